@@ -1,0 +1,164 @@
+/*
+ * mlpcp.h -- multilevel principal component pursuit on AMD MI355X (gfx950).
+ *
+ * C ABI of the hot path of multilevel inexact ALM for robust PCA (PCP) and
+ * for its compressive (masked) form, after Hovhannisyan, Panagakis, Parpas and
+ * Zafeiriou, "Fast Multilevel Algorithms for Compressive Principle Component
+ * Pursuit" (arXiv 2206.13369): every iteration restricts the m x n data to an
+ * m x n_H coarse model, thresholds its singular values there, lifts the result
+ * back with the prolongation and then applies the elementwise soft threshold,
+ * the observation mask and the dual (gradient) step.
+ *
+ * Conventions shared by every entry point
+ *  - Matrices are DEVICE pointers to row-major float32 storage unless noted;
+ *    a leading dimension ld counts elements between consecutive rows and must
+ *    be >= the number of columns.  m counts rows, n columns, m >= n is
+ *    required (the paper assumes n <= m; transpose wide data first).
+ *  - The caller owns every buffer.  The library keeps no per-call state; it
+ *    keeps a per-device cache of the operator constants (restriction stencil
+ *    and the n_H x n_H orthonormalising factor) for each (n, levels) pair it
+ *    has seen, built on first use and kept until the process ends.
+ *  - The restriction used is R = P (P^T P)^{-1/2}, where P is the composite
+ *    linear-interpolation operator of Sec. 3.1, eq. (Rx), read through the
+ *    worked n = 6 example (first row duplicated; last row = last coarse
+ *    point); odd widths use vertex-centred interpolation, n_H = (n + 1) / 2.
+ *    R has orthonormal columns spanning the same range as P.
+ *  - "levels" counts halvings of n (levels = 0: R = I, the plain method).
+ *  - Every call returns an int status (mlpcp_status): 0 = OK, > 0 = warning
+ *    with valid outputs, < 0 = error; outputs are undefined after an error.
+ *    All arguments are validated on the host before anything is launched, so
+ *    a call with invalid arguments touches no GPU state.
+ *  - stream: a hipStream_t passed as void* (NULL = the null stream).
+ *    restrict / prolong / shrink are asynchronous on it.  The solvers and
+ *    svt_prox synchronise it (the host loop reads the feasibility gap and the
+ *    rank every iteration).
+ */
+#ifndef MLPCP_H
+#define MLPCP_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  MLPCP_OK = 0,
+  MLPCP_NOT_CONVERGED = 1,    /* warning: max_iter reached, outputs valid      */
+  MLPCP_E_INVALID_ARG = -1,   /* NULL pointer, non-positive lambda/tol, ...     */
+  MLPCP_E_SHAPE = -2,         /* m < n, ld < columns, non-positive sizes        */
+  MLPCP_E_LEVELS = -3,        /* levels < 0 or too deep for n (n_H < 1)         */
+  MLPCP_E_NONFINITE = -4,     /* the feasibility gap became NaN or Inf          */
+  MLPCP_E_EIG = -5,           /* the Jacobi eigensolver hit its sweep cap       */
+  MLPCP_E_WORKSPACE = -6,     /* caller workspace smaller than required         */
+  MLPCP_E_HIP = -7,           /* a HIP runtime call failed                       */
+  MLPCP_E_UNSUPPORTED = -8    /* option outside the implemented set             */
+} mlpcp_status;
+
+typedef enum { MLPCP_FP32 = 0, MLPCP_BF16 = 1, MLPCP_BF16X3 = 2 } mlpcp_precision;
+
+/* Solver options.  Penalty schedule mu_{k+1} = min(rho mu_k, mu_max_factor * mu_0)
+ * (the paper only asks for an increasing sequence, Alg. 1 and Alg. 4).
+ * Stopping test: feasibility gap FG = ||P_Q(D - L - S)||_F / ||P_Q D||_F <= tol,
+ * the measure of the experiments section, checked every iteration.           */
+typedef struct {
+  int levels;              /* restriction levels (0 = plain inexact ALM)      */
+  double tol;              /* FG tolerance, > 0                               */
+  int max_iter;            /* > 0                                             */
+  double rho;              /* penalty growth factor, >= 1                     */
+  double mu_max_factor;    /* mu_max = mu_max_factor * mu_0, >= 1             */
+  int prec;                /* mlpcp_precision; MLPCP_FP32 is implemented      */
+  int check_every;         /* FG check cadence; 1 is implemented              */
+  int r_norm;              /* restriction normalisation; 0 = orthonormal R    */
+} mlpcp_opts;
+
+/* Per-solve report.  history (optional, caller host memory): if fg_history is
+ * non-NULL it receives the FG of each iteration (history_len entries at most),
+ * rank_history likewise the rank kept by each coarse SVT.                    */
+typedef struct {
+  int iters;               /* iterations performed                            */
+  double fg;               /* final feasibility gap                           */
+  int rank;                /* singular values kept by the last coarse SVT     */
+  double mu_final;         /* penalty used by the last iteration              */
+  double tau_margin;       /* min_i |sigma_i - tau| / tau at the last SVT     */
+  int eig_sweeps;          /* Jacobi sweeps of the last eigensolve            */
+  double* fg_history;      /* in: optional host array                         */
+  int* rank_history;       /* in: optional host array                         */
+  int history_len;         /* in: length of the two arrays                    */
+} mlpcp_info;
+
+/* Fills defaults: levels 0, tol 1e-6, max_iter 500, rho 1.5, mu_max_factor 1e7,
+ * FP32, check_every 1, orthonormal restriction.                              */
+void mlpcp_default_opts(mlpcp_opts* opts);
+
+/* Coarse width n_H after `levels` halvings of n (Sec. 3.1: composite of
+ * interpolation operators); < 0 (mlpcp_status) if levels is invalid.         */
+int mlpcp_coarse_dim(int n, int levels);
+
+/* Device workspace (bytes) a solve of an m x n problem needs with these
+ * options; 0 if the arguments are invalid.  The solvers and svt_prox accept
+ * ws = NULL, in which case they allocate (and free) it themselves.           */
+size_t mlpcp_workspace_bytes(int m, int n, const mlpcp_opts* opts);
+
+/* Robust PCA, eq. (rpca): min ||L||_* + lambda ||S||_1 s.t. D = L + S, by
+ * inexact ALM (Alg. 1, opts->levels = 0) or multilevel inexact ALM (Alg. 4).
+ *  D      m x n input, leading dimension ldd.
+ *  lambda weight of the l1 term, > 0.
+ *  mu0    initial penalty, > 0 (Alg. 1 / Alg. 4 require it).
+ *  S0, Y0 optional m x n (ld = n) initial sparse part and multiplier; NULL =
+ *         zeros.  They may alias the S and Y outputs.
+ *  L, S   outputs, m x n, ld = n.  Y: optional output multiplier (NULL = not
+ *         returned).  L, S, Y must not alias D or each other.
+ *  ws     device workspace of ws_bytes >= mlpcp_workspace_bytes(), or NULL.
+ *  info   optional report (may be NULL).
+ * Returns MLPCP_OK when FG <= tol, MLPCP_NOT_CONVERGED after max_iter.       */
+int mlpcp_pcp_solve(int m, int n, const float* D, int ldd, float lambda, double mu0,
+                    const mlpcp_opts* opts, const float* S0, const float* Y0,
+                    float* L, float* S, float* Y, void* ws, size_t ws_bytes,
+                    mlpcp_info* info, void* stream);
+
+/* Compressive PCP in its constrained form (Sec. 2): find L, S with
+ * P_Q[L + S] = P_Q[D], minimising ||L||_* + lambda ||P_Q S||_1, by the masked
+ * (multilevel) inexact ALM: the sparse part is free off Q, so off Q the dual
+ * stays zero and the coarse data carries the previous L.
+ *  Q  m x n uint8 mask (ld = n): nonzero = observed.  D off Q is never read.
+ * Outputs: L is the completed low-rank estimate (all entries); S and Y are
+ * zero off Q.  Other arguments as mlpcp_pcp_solve; S0 and Y0 off Q are ignored.
+ * With Q all ones the result equals mlpcp_pcp_solve's.                       */
+int mlpcp_cpcp_solve(int m, int n, const float* D, int ldd, const uint8_t* Q,
+                     float lambda, double mu0, const mlpcp_opts* opts,
+                     const float* S0, const float* Y0, float* L, float* S, float* Y,
+                     void* ws, size_t ws_bytes, mlpcp_info* info, void* stream);
+
+/* Coarse singular value thresholding lifted back (Alg. 4, the coarse SVT and
+ * its prolongation, eq. coarse-aug-lagr): L = SVT_tau(M R) R^T, the proximal
+ * map of tau ||.||_* restricted to matrices whose rows lie in range(R).
+ *  M m x n (ldm), tau > 0, L m x n output (ld = n), rank: optional host int
+ *  receiving the number of singular values above tau.                        */
+int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
+                   float* L, int* rank, void* ws, size_t ws_bytes, void* stream);
+
+/* Elementwise soft threshold S_tau[x] = sign(x) max(|x| - tau, 0) (the sparse
+ * step of Alg. 1), on `count` contiguous floats.  Y may alias X.  tau >= 0.
+ * NaN inputs propagate.                                                      */
+int mlpcp_shrink(size_t count, const float* X, float tau, float* Y, void* stream);
+
+/* Restriction XH = X R (m x n -> m x n_H; Alg. 4, coarse data), asynchronous.
+ *  X m x n (ldx >= n), XH m x n_H (ldh >= n_H).                              */
+int mlpcp_restrict(int m, int n, const float* X, int ldx, int levels, float* XH, int ldh,
+                   void* stream);
+
+/* Prolongation X = XH R^T (m x n_H -> m x n; Alg. 4, lift), asynchronous.
+ *  XH m x n_H (ldh >= n_H), X m x n (ldx >= n).                              */
+int mlpcp_prolong(int m, int n, const float* XH, int ldh, int levels, float* X, int ldx,
+                  void* stream);
+
+/* Static description of a status code (never NULL).                          */
+const char* mlpcp_status_string(int status);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* MLPCP_H */

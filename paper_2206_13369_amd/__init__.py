@@ -1,0 +1,277 @@
+"""Python binding of libmlpcp: multilevel PCP / CPCP on AMD MI355X.
+
+Argument marshalling only.  Every step of the solver runs in the HIP kernels of
+libmlpcp.so behind the C ABI declared in include/mlpcp.h; PyTorch supplies
+device memory (tensors, the caching allocator for workspaces) and the current
+HIP stream.  There is no CPU fallback: if the library is missing, importing the
+functions that need it raises.
+
+Entry points (same names as the C ABI, minus the ``mlpcp_`` prefix):
+    pcp_solve, cpcp_solve, svt_prox, shrink, restrict, prolong,
+    coarse_dim, workspace_bytes, default_opts, status_string
+and the raw ctypes handle ``lib()`` for tests that call the C ABI directly.
+"""
+from __future__ import annotations
+
+import ctypes
+import dataclasses
+import os
+from typing import Optional
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libmlpcp.so")
+
+MLPCP_OK = 0
+MLPCP_NOT_CONVERGED = 1
+MLPCP_E_INVALID_ARG = -1
+MLPCP_E_SHAPE = -2
+MLPCP_E_LEVELS = -3
+MLPCP_E_NONFINITE = -4
+MLPCP_E_EIG = -5
+MLPCP_E_WORKSPACE = -6
+MLPCP_E_HIP = -7
+MLPCP_E_UNSUPPORTED = -8
+
+EXPORTED = (
+    "mlpcp_default_opts", "mlpcp_coarse_dim", "mlpcp_workspace_bytes", "mlpcp_pcp_solve",
+    "mlpcp_cpcp_solve", "mlpcp_svt_prox", "mlpcp_shrink", "mlpcp_restrict", "mlpcp_prolong",
+    "mlpcp_status_string",
+)
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("levels", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
+                ("rho", ctypes.c_double), ("mu_max_factor", ctypes.c_double), ("prec", ctypes.c_int),
+                ("check_every", ctypes.c_int), ("r_norm", ctypes.c_int)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("fg", ctypes.c_double), ("rank", ctypes.c_int),
+                ("mu_final", ctypes.c_double), ("tau_margin", ctypes.c_double), ("eig_sweeps", ctypes.c_int),
+                ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
+                ("history_len", ctypes.c_int)]
+
+
+class MLPCPError(RuntimeError):
+    def __init__(self, status: int, where: str):
+        super().__init__(f"{where}: {status_string(status)} (status {status})")
+        self.status = status
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """The loaded libmlpcp.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_2206_13369_amd.build` "
+                          "(there is no CPU fallback)")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i, d, f, sz = ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_float, ctypes.c_size_t
+    L.mlpcp_default_opts.argtypes = [ctypes.POINTER(Opts)]
+    L.mlpcp_default_opts.restype = None
+    L.mlpcp_coarse_dim.argtypes = [i, i]
+    L.mlpcp_coarse_dim.restype = i
+    L.mlpcp_workspace_bytes.argtypes = [i, i, ctypes.POINTER(Opts)]
+    L.mlpcp_workspace_bytes.restype = sz
+    L.mlpcp_pcp_solve.argtypes = [i, i, vp, i, f, d, ctypes.POINTER(Opts), vp, vp, vp, vp, vp, vp, sz,
+                                  ctypes.POINTER(Info), vp]
+    L.mlpcp_pcp_solve.restype = i
+    L.mlpcp_cpcp_solve.argtypes = [i, i, vp, i, vp, f, d, ctypes.POINTER(Opts), vp, vp, vp, vp, vp, vp, sz,
+                                   ctypes.POINTER(Info), vp]
+    L.mlpcp_cpcp_solve.restype = i
+    L.mlpcp_svt_prox.argtypes = [i, i, vp, i, i, f, vp, ctypes.POINTER(i), vp, sz, vp]
+    L.mlpcp_svt_prox.restype = i
+    L.mlpcp_shrink.argtypes = [sz, vp, f, vp, vp]
+    L.mlpcp_shrink.restype = i
+    L.mlpcp_restrict.argtypes = [i, i, vp, i, i, vp, i, vp]
+    L.mlpcp_restrict.restype = i
+    L.mlpcp_prolong.argtypes = [i, i, vp, i, i, vp, i, vp]
+    L.mlpcp_prolong.restype = i
+    L.mlpcp_status_string.argtypes = [i]
+    L.mlpcp_status_string.restype = ctypes.c_char_p
+    _lib = L
+    return L
+
+
+def status_string(status: int) -> str:
+    return lib().mlpcp_status_string(int(status)).decode()
+
+
+def coarse_dim(n: int, levels: int) -> int:
+    r = lib().mlpcp_coarse_dim(int(n), int(levels))
+    if r < 0:
+        raise MLPCPError(r, "coarse_dim")
+    return r
+
+
+def default_opts(**kw) -> Opts:
+    o = Opts()
+    lib().mlpcp_default_opts(ctypes.byref(o))
+    for k, v in kw.items():
+        if not hasattr(o, k):
+            raise TypeError(f"unknown option {k}")
+        setattr(o, k, v)
+    return o
+
+
+def workspace_bytes(m: int, n: int, opts: Optional[Opts] = None) -> int:
+    return int(lib().mlpcp_workspace_bytes(int(m), int(n), ctypes.byref(opts) if opts is not None else None))
+
+
+# ---- torch marshalling -------------------------------------------------------------
+
+def _torch():
+    import torch
+    return torch
+
+
+def _check_dev(t, name, dtype=None):
+    torch = _torch()
+    if not isinstance(t, torch.Tensor) or not t.is_cuda:
+        raise TypeError(f"{name} must be a CUDA (HIP) tensor")
+    if dtype is not None and t.dtype != dtype:
+        raise TypeError(f"{name} must be {dtype}")
+    return t
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _stream(device):
+    return ctypes.c_void_p(_torch().cuda.current_stream(device).cuda_stream)
+
+
+@dataclasses.dataclass
+class SolveResult:
+    L: object
+    S: object
+    Y: object
+    status: int
+    iters: int
+    fg: float
+    rank: int
+    mu_final: float
+    tau_margin: float
+    eig_sweeps: int
+    fg_history: list
+    rank_history: list
+
+
+def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history):
+    torch = _torch()
+    _check_dev(D, "D", torch.float32)
+    if D.dim() != 2 or D.stride(1) != 1:
+        raise ValueError("D must be a 2-D row-major tensor")
+    m, n = D.shape
+    dev = D.device
+    L = torch.empty((m, n), dtype=torch.float32, device=dev)
+    S = torch.empty((m, n), dtype=torch.float32, device=dev)
+    Y = torch.empty((m, n), dtype=torch.float32, device=dev) if want_y else None
+    for name, t in (("S0", S0), ("Y0", Y0)):
+        if t is not None:
+            _check_dev(t, name, torch.float32)
+            if not t.is_contiguous() or tuple(t.shape) != (m, n):
+                raise ValueError(f"{name} must be a contiguous m x n tensor")
+    o = default_opts(levels=levels, tol=tol, max_iter=max_iter, rho=rho, mu_max_factor=mu_max_factor)
+    wsb = workspace_bytes(m, n, o)
+    if workspace is None:
+        ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
+    else:
+        ws = workspace
+        if ws.numel() < wsb:
+            raise ValueError(f"workspace needs {wsb} bytes")
+    info = Info()
+    fh = (ctypes.c_double * history)() if history else None
+    rh = (ctypes.c_int * history)() if history else None
+    if history:
+        info.fg_history = fh
+        info.rank_history = rh
+        info.history_len = history
+    ld = D.stride(0)
+    if Q is None:
+        st = lib().mlpcp_pcp_solve(m, n, _ptr(D), ld, float(lam), float(mu0), ctypes.byref(o), _ptr(S0), _ptr(Y0),
+                                   _ptr(L), _ptr(S), _ptr(Y), _ptr(ws), ws.numel(), ctypes.byref(info),
+                                   _stream(dev))
+    else:
+        _check_dev(Q, "Q", torch.uint8)
+        if not Q.is_contiguous() or tuple(Q.shape) != (m, n):
+            raise ValueError("Q must be a contiguous m x n uint8 tensor")
+        st = lib().mlpcp_cpcp_solve(m, n, _ptr(D), ld, _ptr(Q), float(lam), float(mu0), ctypes.byref(o), _ptr(S0),
+                                    _ptr(Y0), _ptr(L), _ptr(S), _ptr(Y), _ptr(ws), ws.numel(), ctypes.byref(info),
+                                    _stream(dev))
+    if st < 0:
+        raise MLPCPError(st, "cpcp_solve" if Q is not None else "pcp_solve")
+    k = min(info.iters, history) if history else 0
+    return SolveResult(L, S, Y, st, info.iters, info.fg, info.rank, info.mu_final, info.tau_margin, info.eig_sweeps,
+                       [fh[i] for i in range(k)] if history else [], [rh[i] for i in range(k)] if history else [])
+
+
+def pcp_solve(D, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
+              rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
+              workspace=None, history: int = 0) -> SolveResult:
+    """Robust PCA by (multilevel) inexact ALM; D is an m x n float32 tensor on the GPU."""
+    return _solve(D, None, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history)
+
+
+def cpcp_solve(D, Q, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
+               rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
+               workspace=None, history: int = 0) -> SolveResult:
+    """Compressive PCP (constrained form) by masked (multilevel) inexact ALM; Q uint8 mask."""
+    return _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history)
+
+
+def svt_prox(M, tau: float, levels: int = 0, workspace=None):
+    """L = SVT_tau(M R) R^T and the number of singular values kept."""
+    torch = _torch()
+    _check_dev(M, "M", torch.float32)
+    m, n = M.shape
+    L = torch.empty((m, n), dtype=torch.float32, device=M.device)
+    o = default_opts(levels=levels)
+    wsb = workspace_bytes(m, n, o)
+    ws = workspace if workspace is not None else torch.empty(max(wsb, 1), dtype=torch.uint8, device=M.device)
+    r = ctypes.c_int(0)
+    st = lib().mlpcp_svt_prox(m, n, _ptr(M), M.stride(0), levels, float(tau), _ptr(L), ctypes.byref(r), _ptr(ws),
+                              ws.numel(), _stream(M.device))
+    if st < 0:
+        raise MLPCPError(st, "svt_prox")
+    return L, r.value
+
+
+def shrink(X, tau: float, out=None):
+    torch = _torch()
+    _check_dev(X, "X", torch.float32)
+    if not X.is_contiguous():
+        raise ValueError("X must be contiguous")
+    Y = torch.empty_like(X) if out is None else out
+    st = lib().mlpcp_shrink(X.numel(), _ptr(X), float(tau), _ptr(Y), _stream(X.device))
+    if st < 0:
+        raise MLPCPError(st, "shrink")
+    return Y
+
+
+def restrict(X, levels: int):
+    torch = _torch()
+    _check_dev(X, "X", torch.float32)
+    m, n = X.shape
+    nH = coarse_dim(n, levels)
+    XH = torch.empty((m, nH), dtype=torch.float32, device=X.device)
+    st = lib().mlpcp_restrict(m, n, _ptr(X), X.stride(0), levels, _ptr(XH), nH, _stream(X.device))
+    if st < 0:
+        raise MLPCPError(st, "restrict")
+    return XH
+
+
+def prolong(XH, n: int, levels: int):
+    torch = _torch()
+    _check_dev(XH, "XH", torch.float32)
+    m, nH = XH.shape
+    X = torch.empty((m, n), dtype=torch.float32, device=XH.device)
+    st = lib().mlpcp_prolong(m, n, _ptr(XH), XH.stride(0), levels, _ptr(X), n, _stream(XH.device))
+    if st < 0:
+        raise MLPCPError(st, "prolong")
+    return X

@@ -1,0 +1,95 @@
+// Internal declarations shared by the HIP translation units of libmlpcp.
+#pragma once
+
+#include <hip/hip_runtime.h>
+
+#include <cstddef>
+#include <cstdint>
+#include <vector>
+
+#include "../../include/mlpcp.h"
+
+namespace mlpcp {
+
+// Status propagation -----------------------------------------------------------------
+#define MLPCP_HIP(call)                                   \
+  do {                                                    \
+    hipError_t e_ = (call);                               \
+    if (e_ != hipSuccess) return MLPCP_E_HIP;             \
+  } while (0)
+
+#define MLPCP_TRY(call)                                   \
+  do {                                                    \
+    int s_ = (call);                                      \
+    if (s_ < 0) return s_;                                \
+  } while (0)
+
+constexpr int kEigBlock = 16;          // Jacobi block width b; inner problems are 2b x 2b
+constexpr int kEigInner = 2 * kEigBlock;
+constexpr int kPad = 32;               // padding of n_H for the Gram / eigensolver tiles
+constexpr int kMaxStencil = 2;         // nonzeros per fine row of the composite interpolation
+constexpr int kMaxEigSweeps = 40;
+
+inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
+
+// Operator constants of the coarse model for one (n, levels) pair, on one device.
+//  P (n x nH) composite interpolation:
+//   rows  : fine row j -> kMaxStencil (coarse index, weight) pairs (weight 0 pads)
+//   cols  : CSC, coarse column c -> fine rows col_ptr[c] .. col_ptr[c+1]
+//  C = (P^T P)^{-1/2} (nH x nH, float64, row-major ld = nH), identity when levels = 0.
+struct Operator {
+  int n = 0, levels = 0, nH = 0;
+  int max_col_nnz = 0;
+  int* row_idx = nullptr;     // [n * kMaxStencil]
+  float* row_w = nullptr;     // [n * kMaxStencil]
+  int* col_ptr = nullptr;     // [nH + 1]
+  int* col_row = nullptr;     // [nnz]
+  float* col_w = nullptr;     // [nnz]
+  double* C = nullptr;        // [nH * nH] (nullptr when levels == 0)
+};
+
+// Returns the cached operator for (n, levels) on the current device, building it on
+// first use (host stencil tables, then C on the GPU with the Jacobi eigensolver).
+int get_operator(int n, int levels, hipStream_t stream, const Operator** out);
+
+// Builds the composite interpolation stencil on the host (also used by host tests
+// through mlpcp_coarse_dim and by get_operator).
+int coarse_dim_checked(int n, int levels);
+void build_stencil_host(int n, int levels, std::vector<int>& row_idx, std::vector<float>& row_w,
+                        std::vector<int>& col_ptr, std::vector<int>& col_row, std::vector<float>& col_w,
+                        std::vector<double>* dense_P);
+
+// ---- symmetric eigensolver (eig.hip) ---------------------------------------------
+// Workspace for an N x N problem (N multiple of kPad).
+size_t eig_workspace_bytes(int N);
+// A: N x N float64 symmetric (ld = N), overwritten.  On return V (N x N, ld = N) holds
+// the eigenvectors as columns (unsorted), lam[i] = A_ii, perm[k] = index of the k-th
+// largest eigenvalue.  n <= N is the true size (rows/cols >= n must be zero).
+// sweeps_out receives the number of outer sweeps.  Synchronises `stream`.
+int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws,
+            hipStream_t stream, int* sweeps_out);
+
+// ---- Gram (gram.hip) ---------------------------------------------------------------
+// G = A^T A for A m x k (float32, ld = lda, k <= kp, kp multiple of kPad), accumulated
+// in float64; G is kp x kp float64 (ld = kp), rows/cols >= k zero.
+size_t gram_workspace_bytes(int m, int kp);
+int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
+             hipStream_t stream);
+
+// ---- small dense float64 products (dense.hip) ----------------------------------------
+// C(MxN) = alpha * op(A) op(B), float64 row-major with explicit leading dimensions.
+int gemm_f64(bool transA, bool transB, int M, int N, int K, double alpha, const double* A, int lda,
+             const double* B, int ldb, double* C, int ldc, hipStream_t stream);
+// Out(m x k2, float32, ldo) = In(m x k1, float32, ldi) * W(k1 x k2, float64, ldw),
+// accumulated in float64.
+int rmul_f32_by_f64(int m, int k1, int k2, const float* In, int ldi, const double* W, int ldw,
+                    float* Out, int ldo, hipStream_t stream);
+
+// ---- stencil kernels (operators.hip) ---------------------------------------------------
+// XP = X P  (m x n -> m x nH, float32; the interpolation stencil, no C factor).
+int apply_P(const Operator& op, int m, const float* X, int ldx, float* XP, int ldp, hipStream_t s);
+// X = N P^T (m x nH -> m x n).
+int apply_Pt(const Operator& op, int m, const float* N, int ldn, float* X, int ldx, hipStream_t s);
+
+}  // namespace mlpcp

@@ -1,0 +1,131 @@
+// Gram matrix G = A^T A of the (coarse) data, float64 accumulation on MFMA.
+//
+// The singular values of the coarse data (Alg. 4) are taken as square roots of the
+// eigenvalues of its Gram matrix.  Products of float32 operands are exact in float64,
+// so accumulating in float64 keeps the singular values as accurate as the float32
+// data itself (absolute error ~ eps32 * sigma_max) instead of squaring the condition
+// number; this matters for the values just above the threshold 1/mu.
+//
+// Tiling: one 256-thread block computes a 32 x 32 output tile for a slice of rows
+// ("split"), as 2 x 2 wave tiles of v_mfma_f64_16x16x4f64.  Only tiles on or above the
+// diagonal are computed.  Partial tiles of the splits are summed in a fixed order
+// (deterministic), and the lower triangle is mirrored from the upper one so G is
+// exactly symmetric.
+#include "common.h"
+
+namespace mlpcp {
+
+namespace {
+
+constexpr int GT = 32;   // output tile
+constexpr int KC = 16;   // rows per LDS chunk
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+__device__ __forceinline__ void tri_decode(int p, int nt, int& ti, int& tj) {
+  // p enumerates pairs (ti <= tj) row by row
+  ti = 0;
+  int rem = p;
+  while (rem >= nt - ti) {
+    rem -= nt - ti;
+    ++ti;
+  }
+  tj = ti + rem;
+}
+
+__global__ void __launch_bounds__(256) k_gram_partial(const float* __restrict__ A, int m, int k, int lda, int kp,
+                                                      int rows_per_split, int ntile, double* __restrict__ part) {
+  __shared__ double sI[KC][GT + 1];
+  __shared__ double sJ[KC][GT + 1];
+  int ti, tj;
+  tri_decode(blockIdx.x, ntile, ti, tj);
+  const int s = blockIdx.y;
+  const int r0 = s * rows_per_split;
+  const int r1 = min(m, r0 + rows_per_split);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int bi = wave >> 1, bj = wave & 1;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  const int ci0 = ti * GT, cj0 = tj * GT;
+  for (int k0 = r0; k0 < r1; k0 += KC) {
+#pragma unroll
+    for (int x = 0; x < (KC * GT) / 256; ++x) {
+      const int e = tid + 256 * x;
+      const int row = e / GT, col = e % GT;
+      const int gr = k0 + row;
+      const bool rok = gr < r1;
+      const int gi = ci0 + col, gj = cj0 + col;
+      sI[row][col] = (rok && gi < k) ? (double)A[(size_t)gr * lda + gi] : 0.0;
+      sJ[row][col] = (rok && gj < k) ? (double)A[(size_t)gr * lda + gj] : 0.0;
+    }
+    __syncthreads();
+#pragma unroll
+    for (int kk = 0; kk < KC / 4; ++kk) {
+      const double a = sI[kk * 4 + (lane >> 4)][bi * 16 + (lane & 15)];
+      const double b = sJ[kk * 4 + (lane >> 4)][bj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  double* P = part + (size_t)s * kp * kp;
+  const int col = cj0 + bj * 16 + (lane & 15);
+  // v_mfma_f64_16x16x4f64 output: register v of lane l holds row 4v + l/16, column l%16
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = ci0 + bi * 16 + 4 * v + (lane >> 4);
+    P[(size_t)row * kp + col] = acc[v];
+  }
+}
+
+__global__ void k_gram_reduce(const double* __restrict__ part, int splits, int kp, double* __restrict__ G) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)kp * kp) return;
+  const int i = (int)(idx / kp), j = (int)(idx % kp);
+  const int lo = min(i, j), hi = max(i, j);
+  const size_t off = (size_t)lo * kp + hi;
+  double s = 0.0;
+  for (int q = 0; q < splits; ++q) s += part[(size_t)q * kp * kp + off];
+  G[idx] = s;
+}
+
+void gram_plan(int m, int kp, int& splits, int& rows_per_split) {
+  const int nt = kp / GT;
+  const int pairs = nt * (nt + 1) / 2;
+  int sp = (1024 + pairs - 1) / pairs;
+  const int max_by_rows = (m + 63) / 64;
+  if (sp > max_by_rows) sp = max_by_rows;
+  const size_t cap = (size_t)64 << 20;
+  const size_t per = (size_t)kp * kp * sizeof(double);
+  if ((size_t)sp * per > cap) sp = (int)(cap / per);
+  if (sp < 1) sp = 1;
+  int rps = (m + sp - 1) / sp;
+  rps = round_up(rps, KC);
+  sp = (m + rps - 1) / rps;
+  if (sp < 1) sp = 1;
+  splits = sp;
+  rows_per_split = rps;
+}
+
+}  // namespace
+
+size_t gram_workspace_bytes(int m, int kp) {
+  int sp, rps;
+  gram_plan(m, kp, sp, rps);
+  return align256((size_t)sp * kp * kp * sizeof(double));
+}
+
+int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws, hipStream_t stream) {
+  if (kp % GT != 0 || k > kp) return MLPCP_E_INVALID_ARG;
+  int sp, rps;
+  gram_plan(m, kp, sp, rps);
+  const int nt = kp / GT;
+  const int pairs = nt * (nt + 1) / 2;
+  double* part = static_cast<double*>(ws);
+  hipLaunchKernelGGL(k_gram_partial, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
+  const size_t nn = (size_t)kp * kp;
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, stream, part, sp, kp, G);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+}  // namespace mlpcp

@@ -1,0 +1,463 @@
+// Coarse-model operators (Sec. 3.1) and the streaming entry points restrict, prolong
+// and shrink.
+//
+// The interpolation operator P_n of eq. (Rx) is read through the worked n = 6 example:
+// even n -> n/2 coarse points, fine row 0 and fine row 1 both take coarse point 0, odd
+// fine rows 2k+1 take coarse point k, even fine rows 2k (k >= 1) average coarse points
+// k-1 and k.  Odd n (not covered by the paper) uses vertex-centred interpolation:
+// coarse points at even fine rows, midpoints at odd rows, n_H = (n+1)/2.  "levels"
+// composes that many operators.  The composite is piecewise linear, so each fine row
+// has at most two nonzero weights; weights are dyadic, hence exact in float.
+//
+// The coarse model uses R = P C with C = (P^T P)^{-1/2}: orthonormal columns spanning
+// range(P) (the normalisation for which the nuclear-norm gap of Thm. LH-eps vanishes).
+#include "common.h"
+
+#include <cmath>
+#include <cstring>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <tuple>
+#include <utility>
+
+namespace mlpcp {
+
+int coarse_dim_checked(int n, int levels) {
+  if (levels < 0 || n < 1) return MLPCP_E_LEVELS;
+  for (int l = 0; l < levels; ++l) {
+    if (n < 2) return MLPCP_E_LEVELS;
+    n = (n % 2 == 0) ? n / 2 : (n + 1) / 2;
+  }
+  return n;
+}
+
+namespace {
+
+using SparseRow = std::vector<std::pair<int, double>>;
+
+// single-level operator rows: fine j -> (coarse, weight)
+std::vector<SparseRow> level_rows(int n) {
+  std::vector<SparseRow> rows(n);
+  if (n % 2 == 0) {
+    const int nH = n / 2;
+    rows[0] = {{0, 1.0}};
+    for (int k = 0; k < nH; ++k) rows[2 * k + 1] = {{k, 1.0}};
+    for (int k = 1; k < nH; ++k) rows[2 * k] = {{k - 1, 0.5}, {k, 0.5}};
+  } else {
+    const int nH = (n + 1) / 2;
+    for (int k = 0; k < nH; ++k) rows[2 * k] = {{k, 1.0}};
+    for (int k = 0; k + 1 < nH; ++k) rows[2 * k + 1] = {{k, 0.5}, {k + 1, 0.5}};
+  }
+  return rows;
+}
+
+}  // namespace
+
+void build_stencil_host(int n, int levels, std::vector<int>& row_idx, std::vector<float>& row_w,
+                        std::vector<int>& col_ptr, std::vector<int>& col_row, std::vector<float>& col_w,
+                        std::vector<double>* dense_P) {
+  // compose: fine row j of P_n P_{n1} ... as a sparse combination of coarsest points
+  std::vector<SparseRow> cur(n);
+  for (int j = 0; j < n; ++j) cur[j] = {{j, 1.0}};
+  int width = n;
+  for (int l = 0; l < levels; ++l) {
+    const std::vector<SparseRow> lr = level_rows(width);
+    for (int j = 0; j < n; ++j) {
+      std::map<int, double> acc;
+      for (const auto& cw : cur[j])
+        for (const auto& dw : lr[cw.first]) acc[dw.first] += cw.second * dw.second;
+      SparseRow nr;
+      for (const auto& kv : acc)
+        if (kv.second != 0.0) nr.push_back(kv);
+      cur[j] = nr;
+    }
+    width = (width % 2 == 0) ? width / 2 : (width + 1) / 2;
+  }
+  const int nH = width;
+  row_idx.assign((size_t)n * kMaxStencil, 0);
+  row_w.assign((size_t)n * kMaxStencil, 0.0f);
+  std::vector<std::vector<std::pair<int, float>>> cols(nH);
+  for (int j = 0; j < n; ++j) {
+    int s = 0;
+    for (const auto& cw : cur[j]) {
+      if (s < kMaxStencil) {
+        row_idx[(size_t)j * kMaxStencil + s] = cw.first;
+        row_w[(size_t)j * kMaxStencil + s] = (float)cw.second;
+      }
+      ++s;
+      cols[cw.first].push_back({j, (float)cw.second});
+    }
+  }
+  col_ptr.assign(nH + 1, 0);
+  col_row.clear();
+  col_w.clear();
+  for (int c = 0; c < nH; ++c) {
+    col_ptr[c + 1] = col_ptr[c] + (int)cols[c].size();
+    for (const auto& jw : cols[c]) {
+      col_row.push_back(jw.first);
+      col_w.push_back(jw.second);
+    }
+  }
+  if (dense_P) {
+    dense_P->assign((size_t)n * nH, 0.0);
+    for (int j = 0; j < n; ++j)
+      for (const auto& cw : cur[j]) (*dense_P)[(size_t)j * nH + cw.first] = cw.second;
+  }
+}
+
+namespace {
+
+// W[i][k] = V[i][k] / sqrt(lam[k]) for k < nH (i < nH)
+__global__ void k_scale_cols_invsqrt(const double* __restrict__ V, const double* __restrict__ lam, int N, int nH,
+                                     double* __restrict__ W) {
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= (size_t)nH * nH) return;
+  const int i = (int)(idx / nH), k = (int)(idx % nH);
+  W[(size_t)i * N + k] = V[(size_t)i * N + k] / sqrt(lam[k]);
+}
+
+struct OpDeleter {
+  void operator()(Operator* op) const {
+    if (!op) return;
+    (void)hipFree(op->row_idx);
+    (void)hipFree(op->row_w);
+    (void)hipFree(op->col_ptr);
+    (void)hipFree(op->col_row);
+    (void)hipFree(op->col_w);
+    (void)hipFree(op->C);
+    delete op;
+  }
+};
+
+std::mutex g_op_mutex;
+std::map<std::tuple<int, int, int>, std::unique_ptr<Operator, OpDeleter>> g_ops;
+
+template <typename T>
+int upload(const std::vector<T>& h, T** d) {
+  const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
+  MLPCP_HIP(hipMalloc(reinterpret_cast<void**>(d), bytes));
+  if (!h.empty()) MLPCP_HIP(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+  return MLPCP_OK;
+}
+
+int build_operator(int n, int levels, hipStream_t stream, Operator* op) {
+  const int nH = coarse_dim_checked(n, levels);
+  if (nH < 1) return MLPCP_E_LEVELS;
+  op->n = n;
+  op->levels = levels;
+  op->nH = nH;
+  std::vector<int> ri, cp, cr;
+  std::vector<float> rw, cw;
+  build_stencil_host(n, levels, ri, rw, cp, cr, cw, nullptr);
+  int mx = 0;
+  for (int c = 0; c < nH; ++c) mx = std::max(mx, cp[c + 1] - cp[c]);
+  op->max_col_nnz = mx;
+  MLPCP_TRY(upload(ri, &op->row_idx));
+  MLPCP_TRY(upload(rw, &op->row_w));
+  MLPCP_TRY(upload(cp, &op->col_ptr));
+  MLPCP_TRY(upload(cr, &op->col_row));
+  MLPCP_TRY(upload(cw, &op->col_w));
+  if (levels == 0) return MLPCP_OK;
+  // P^T P from the column lists (exact: dyadic weights), then C = (P^T P)^{-1/2}
+  const int N = round_up(nH, kPad);
+  std::vector<double> PtP((size_t)N * N, 0.0);
+  {
+    std::vector<std::vector<std::pair<int, double>>> rowsP(n);
+    for (int c = 0; c < nH; ++c)
+      for (int t = cp[c]; t < cp[c + 1]; ++t) rowsP[cr[t]].push_back({c, (double)cw[t]});
+    for (int j = 0; j < n; ++j)
+      for (const auto& a : rowsP[j])
+        for (const auto& b : rowsP[j]) PtP[(size_t)a.first * N + b.first] += a.second * b.second;
+  }
+  double *dA = nullptr, *dV = nullptr, *dW = nullptr, *dlam = nullptr;
+  int* dperm = nullptr;
+  void* ews = nullptr;
+  int st = MLPCP_OK;
+  const size_t nn = (size_t)N * N;
+  if (hipMalloc(&dA, nn * 8) != hipSuccess || hipMalloc(&dV, nn * 8) != hipSuccess ||
+      hipMalloc(&dW, nn * 8) != hipSuccess || hipMalloc(&dlam, (size_t)N * 8) != hipSuccess ||
+      hipMalloc(&dperm, (size_t)N * 4) != hipSuccess || hipMalloc(&ews, eig_workspace_bytes(N)) != hipSuccess ||
+      hipMalloc(&op->C, (size_t)nH * nH * 8) != hipSuccess) {
+    st = MLPCP_E_HIP;
+  }
+  if (st == MLPCP_OK && hipMemcpyAsync(dA, PtP.data(), nn * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
+    st = MLPCP_E_HIP;
+  int sweeps = 0;
+  if (st == MLPCP_OK) st = eig_sym(nH, N, dA, dV, dlam, dperm, ews, stream, &sweeps);
+  if (st == MLPCP_OK) {
+    const size_t cnt = (size_t)nH * nH;
+    hipLaunchKernelGGL(k_scale_cols_invsqrt, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, dV, dlam,
+                       N, nH, dW);
+    st = gemm_f64(false, true, nH, nH, nH, 1.0, dW, N, dV, N, op->C, nH, stream);
+  }
+  if (st == MLPCP_OK && hipStreamSynchronize(stream) != hipSuccess) st = MLPCP_E_HIP;
+  (void)hipFree(dA);
+  (void)hipFree(dV);
+  (void)hipFree(dW);
+  (void)hipFree(dlam);
+  (void)hipFree(dperm);
+  (void)hipFree(ews);
+  return st;
+}
+
+}  // namespace
+
+int get_operator(int n, int levels, hipStream_t stream, const Operator** out) {
+  int dev = 0;
+  MLPCP_HIP(hipGetDevice(&dev));
+  std::lock_guard<std::mutex> lock(g_op_mutex);
+  auto key = std::make_tuple(dev, n, levels);
+  auto it = g_ops.find(key);
+  if (it != g_ops.end()) {
+    *out = it->second.get();
+    return MLPCP_OK;
+  }
+  std::unique_ptr<Operator, OpDeleter> op(new Operator());
+  const int st = build_operator(n, levels, stream, op.get());
+  if (st != MLPCP_OK) return st;
+  *out = op.get();
+  g_ops.emplace(key, std::move(op));
+  return MLPCP_OK;
+}
+
+namespace {
+
+__global__ void k_apply_P(int m, int n, int nH, const float* __restrict__ X, int ldx, float* __restrict__ XP,
+                          int ldp, const int* __restrict__ col_ptr, const int* __restrict__ col_row,
+                          const float* __restrict__ col_w) {
+  const size_t total = (size_t)m * nH;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / nH;
+    const int c = (int)(idx % nH);
+    const float* x = X + i * ldx;
+    float acc = 0.0f;
+    for (int t = col_ptr[c]; t < col_ptr[c + 1]; ++t) acc = fmaf(col_w[t], x[col_row[t]], acc);
+    XP[i * ldp + c] = acc;
+  }
+}
+
+__global__ void k_apply_Pt(int m, int n, const float* __restrict__ Nm, int ldn, float* __restrict__ X, int ldx,
+                           const int* __restrict__ row_idx, const float* __restrict__ row_w) {
+  const size_t total = (size_t)m * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / n;
+    const int j = (int)(idx % n);
+    const float* y = Nm + i * ldn;
+    float acc = 0.0f;
+#pragma unroll
+    for (int s = 0; s < kMaxStencil; ++s) acc = fmaf(row_w[j * kMaxStencil + s], y[row_idx[j * kMaxStencil + s]], acc);
+    X[i * ldx + j] = acc;
+  }
+}
+
+unsigned stream_grid(size_t total) {
+  size_t b = (total + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// XH rows = (X rows P) C for ROWS rows per block, accumulated in float64.
+constexpr int RROWS = 8;
+__global__ void __launch_bounds__(256) k_restrict_full(int m, int n, int nH, const float* __restrict__ X, int ldx,
+                                                       float* __restrict__ XH, int ldh,
+                                                       const int* __restrict__ col_ptr,
+                                                       const int* __restrict__ col_row,
+                                                       const float* __restrict__ col_w,
+                                                       const double* __restrict__ C) {
+  extern __shared__ double smem[];  // [RROWS][nH]
+  const int i0 = blockIdx.x * RROWS;
+  const int rows = min(RROWS, m - i0);
+  for (int e = threadIdx.x; e < rows * nH; e += blockDim.x) {
+    const int r = e / nH, c = e % nH;
+    const float* x = X + (size_t)(i0 + r) * ldx;
+    double acc = 0.0;
+    for (int t = col_ptr[c]; t < col_ptr[c + 1]; ++t) acc += (double)col_w[t] * (double)x[col_row[t]];
+    smem[r * nH + c] = acc;
+  }
+  __syncthreads();
+  for (int c2 = threadIdx.x; c2 < nH; c2 += blockDim.x) {
+    double acc[RROWS];
+#pragma unroll
+    for (int r = 0; r < RROWS; ++r) acc[r] = 0.0;
+    for (int c1 = 0; c1 < nH; ++c1) {
+      const double w = C[(size_t)c1 * nH + c2];
+#pragma unroll
+      for (int r = 0; r < RROWS; ++r) acc[r] += smem[(r < rows ? r : 0) * nH + c1] * w;
+    }
+    for (int r = 0; r < rows; ++r) XH[(size_t)(i0 + r) * ldh + c2] = (float)acc[r];
+  }
+}
+
+// X rows = (XH rows C) P^T
+__global__ void __launch_bounds__(256) k_prolong_full(int m, int n, int nH, const float* __restrict__ XH, int ldh,
+                                                      float* __restrict__ X, int ldx,
+                                                      const int* __restrict__ row_idx,
+                                                      const float* __restrict__ row_w,
+                                                      const double* __restrict__ C) {
+  extern __shared__ double smem[];  // [2][RROWS][nH]
+  double* sx = smem;
+  double* sn = smem + RROWS * nH;
+  const int i0 = blockIdx.x * RROWS;
+  const int rows = min(RROWS, m - i0);
+  for (int e = threadIdx.x; e < rows * nH; e += blockDim.x) {
+    const int r = e / nH, c = e % nH;
+    sx[r * nH + c] = (double)XH[(size_t)(i0 + r) * ldh + c];
+  }
+  __syncthreads();
+  for (int c2 = threadIdx.x; c2 < nH; c2 += blockDim.x) {
+    double acc[RROWS];
+#pragma unroll
+    for (int r = 0; r < RROWS; ++r) acc[r] = 0.0;
+    for (int c1 = 0; c1 < nH; ++c1) {
+      const double w = C[(size_t)c1 * nH + c2];  // C symmetric
+#pragma unroll
+      for (int r = 0; r < RROWS; ++r) acc[r] += sx[(r < rows ? r : 0) * nH + c1] * w;
+    }
+    for (int r = 0; r < rows; ++r) sn[r * nH + c2] = acc[r];
+  }
+  __syncthreads();
+  for (int e = threadIdx.x; e < rows * n; e += blockDim.x) {
+    const int r = e / n, j = e % n;
+    double acc = 0.0;
+#pragma unroll
+    for (int s = 0; s < kMaxStencil; ++s)
+      acc += (double)row_w[j * kMaxStencil + s] * sn[r * nH + row_idx[j * kMaxStencil + s]];
+    X[(size_t)(i0 + r) * ldx + j] = (float)acc;
+  }
+}
+
+// S_tau[x] = sign(x) max(|x| - tau, 0); NaN propagates.
+__global__ void k_shrink(size_t count, const float* __restrict__ X, float tau, float* __restrict__ Y) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
+    const float x = X[i];
+    const float a = fabsf(x) - tau;
+    Y[i] = (a > 0.0f) ? copysignf(a, x) : ((a == a) ? 0.0f : a);
+  }
+}
+
+__global__ void k_copy_rows(int m, int n, const float* __restrict__ X, int ldx, float* __restrict__ Y, int ldy) {
+  const size_t total = (size_t)m * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / n;
+    const int j = (int)(idx % n);
+    Y[i * ldy + j] = X[i * ldx + j];
+  }
+}
+
+}  // namespace
+
+int apply_P(const Operator& op, int m, const float* X, int ldx, float* XP, int ldp, hipStream_t s) {
+  const size_t total = (size_t)m * op.nH;
+  if (total == 0) return MLPCP_OK;
+  hipLaunchKernelGGL(k_apply_P, dim3(stream_grid(total)), dim3(256), 0, s, m, op.n, op.nH, X, ldx, XP, ldp,
+                     op.col_ptr, op.col_row, op.col_w);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+int apply_Pt(const Operator& op, int m, const float* Nm, int ldn, float* X, int ldx, hipStream_t s) {
+  const size_t total = (size_t)m * op.n;
+  if (total == 0) return MLPCP_OK;
+  hipLaunchKernelGGL(k_apply_Pt, dim3(stream_grid(total)), dim3(256), 0, s, m, op.n, Nm, ldn, X, ldx, op.row_idx,
+                     op.row_w);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+}  // namespace mlpcp
+
+using namespace mlpcp;
+
+extern "C" {
+
+void mlpcp_default_opts(mlpcp_opts* o) {
+  if (!o) return;
+  o->levels = 0;
+  o->tol = 1e-6;
+  o->max_iter = 500;
+  o->rho = 1.5;
+  o->mu_max_factor = 1e7;
+  o->prec = MLPCP_FP32;
+  o->check_every = 1;
+  o->r_norm = 0;
+}
+
+int mlpcp_coarse_dim(int n, int levels) { return coarse_dim_checked(n, levels); }
+
+const char* mlpcp_status_string(int s) {
+  switch (s) {
+    case MLPCP_OK: return "ok";
+    case MLPCP_NOT_CONVERGED: return "not converged: max_iter reached (outputs valid)";
+    case MLPCP_E_INVALID_ARG: return "invalid argument";
+    case MLPCP_E_SHAPE: return "invalid shape or leading dimension";
+    case MLPCP_E_LEVELS: return "invalid number of levels for this width";
+    case MLPCP_E_NONFINITE: return "feasibility gap became non-finite";
+    case MLPCP_E_EIG: return "eigensolver did not converge within its sweep cap";
+    case MLPCP_E_WORKSPACE: return "workspace too small";
+    case MLPCP_E_HIP: return "HIP runtime error";
+    case MLPCP_E_UNSUPPORTED: return "unsupported option";
+    default: return "unknown status";
+  }
+}
+
+int mlpcp_shrink(size_t count, const float* X, float tau, float* Y, void* stream) {
+  if ((count > 0 && (!X || !Y)) || !(tau >= 0.0f) || std::isinf(tau)) return MLPCP_E_INVALID_ARG;
+  if (count == 0) return MLPCP_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  hipLaunchKernelGGL(k_shrink, dim3(stream_grid(count)), dim3(256), 0, s, count, X, tau, Y);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+int mlpcp_restrict(int m, int n, const float* X, int ldx, int levels, float* XH, int ldh, void* stream) {
+  if (m < 0 || n < 1) return MLPCP_E_SHAPE;
+  const int nH = coarse_dim_checked(n, levels);
+  if (nH < 1) return MLPCP_E_LEVELS;
+  if (ldx < n || ldh < nH) return MLPCP_E_SHAPE;
+  if (m > 0 && (!X || !XH)) return MLPCP_E_INVALID_ARG;
+  if (m == 0) return MLPCP_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (levels == 0) {
+    hipLaunchKernelGGL(k_copy_rows, dim3(stream_grid((size_t)m * n)), dim3(256), 0, s, m, n, X, ldx, XH, ldh);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
+  const Operator* op = nullptr;
+  MLPCP_TRY(get_operator(n, levels, s, &op));
+  const size_t sm = (size_t)RROWS * nH * sizeof(double);
+  if (sm > 64 * 1024) return MLPCP_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_restrict_full, dim3((m + RROWS - 1) / RROWS), dim3(256), sm, s, m, n, nH, X, ldx, XH, ldh,
+                     op->col_ptr, op->col_row, op->col_w, op->C);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+int mlpcp_prolong(int m, int n, const float* XH, int ldh, int levels, float* X, int ldx, void* stream) {
+  if (m < 0 || n < 1) return MLPCP_E_SHAPE;
+  const int nH = coarse_dim_checked(n, levels);
+  if (nH < 1) return MLPCP_E_LEVELS;
+  if (ldx < n || ldh < nH) return MLPCP_E_SHAPE;
+  if (m > 0 && (!X || !XH)) return MLPCP_E_INVALID_ARG;
+  if (m == 0) return MLPCP_OK;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  if (levels == 0) {
+    hipLaunchKernelGGL(k_copy_rows, dim3(stream_grid((size_t)m * n)), dim3(256), 0, s, m, n, XH, ldh, X, ldx);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
+  const Operator* op = nullptr;
+  MLPCP_TRY(get_operator(n, levels, s, &op));
+  const size_t sm = (size_t)2 * RROWS * nH * sizeof(double);
+  if (sm > 64 * 1024) return MLPCP_E_UNSUPPORTED;
+  hipLaunchKernelGGL(k_prolong_full, dim3((m + RROWS - 1) / RROWS), dim3(256), sm, s, m, n, nH, XH, ldh, X, ldx,
+                     op->row_idx, op->row_w, op->C);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+}  // extern "C"

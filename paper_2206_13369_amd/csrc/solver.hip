@@ -1,0 +1,674 @@
+// Multilevel inexact ALM (Alg. 4; Alg. 1 when levels = 0) for PCP and its masked
+// (compressive) form, and the standalone coarse SVT.
+//
+// Per iteration t (penalty mu_t, threshold tau = 1/mu_t):
+//   gram      G   = M_P^T M_P, M_P = X_t P                  (coarse data without C)
+//   coarse    G_H = C G C = (X_t R)^T (X_t R),  R = P C     (Gram of the coarse data)
+//   eig       G_H = V diag(lam) V^T (float64 Jacobi)
+//   svt prep  sigma = sqrt(lam), r = #{sigma > tau}, w = (sigma - tau)/sigma,
+//             T = C V_r diag(sqrt w)  (n_H x r)
+//   epilogue  L_{t+1} = M_P T T^T P^T  (= U_H S_tau[Sigma_H] V_H^T R^T, the coarse SVT
+//             lifted back), then per element on Q:
+//                 E = D - L + Y_t/mu_t,  S = S_{lam/mu_t}[E],  Y_{t+1} = clamp(mu_t E, +-lam)
+//             (the dual update Y_t + mu_t (D - L - S) written in closed form), the
+//             feasibility-gap partial sum of (D - L - S)^2, and the next coarse data
+//             X_{t+1} = D - S + Y_{t+1}/mu_{t+1}; off Q, X_{t+1} = L_{t+1} and S = Y = 0.
+//             X_{t+1} is restricted (X_{t+1} P) in the same pass.
+// State between iterations: one m x n float32 matrix Z holding E on Q and L off Q
+// (S and Y are functions of E and mu), kept in the caller's S buffer, plus M_P.  A final
+// pass recomputes L from the last coarse factors and writes L, S and Y.
+#include "common.h"
+
+#include <algorithm>
+#include <cmath>
+#include <vector>
+
+namespace mlpcp {
+
+namespace {
+
+constexpr int kThreads = 256;
+constexpr size_t kLdsBudget = 60 * 1024;
+
+enum Mode { MODE_STEP = 0, MODE_FINAL = 1, MODE_RECON = 2 };
+
+struct IterStats {
+  double fg2;      // sum of squared residuals on Q
+  double nrm2;     // ||P_Q D||_F^2 (init)
+  double margin;   // min |sigma - tau| / tau
+  int rank;
+  int pad;
+};
+
+__device__ __forceinline__ float shrinkf(float e, float thr) {
+  const float a = fabsf(e) - thr;
+  return a > 0.0f ? copysignf(a, e) : 0.0f;
+}
+
+__device__ __forceinline__ bool qbit(const uint32_t* __restrict__ bits, int nw, int i, int j) {
+  return (bits[(size_t)i * nw + (j >> 5)] >> (j & 31)) & 1u;
+}
+
+__device__ double block_sum(double v, double* red) {
+  const int tid = threadIdx.x;
+  red[tid] = v;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double s = red[0];
+  __syncthreads();
+  return s;
+}
+
+// restrict the TM x n panel sX (LDS, ld n) into MP rows i0.. (ld ldp), c < nH
+__device__ __forceinline__ void restrict_panel(const float* sX, int rows, int n, int nH, float* __restrict__ MP,
+                                               int ldp, int i0, const int* __restrict__ col_ptr,
+                                               const int* __restrict__ col_row, const float* __restrict__ col_w) {
+  for (int e = threadIdx.x; e < rows * nH; e += kThreads) {
+    const int i = e / nH, c = e % nH;
+    const float* x = sX + (size_t)i * n;
+    float acc = 0.0f;
+    const int t1 = col_ptr[c + 1];
+    for (int t = col_ptr[c]; t < t1; ++t) acc = fmaf(col_w[t], x[col_row[t]], acc);
+    MP[(size_t)(i0 + i) * ldp + c] = acc;
+  }
+}
+
+__global__ void k_pack_mask(int m, int n, const uint8_t* __restrict__ Q, int nw, uint32_t* __restrict__ bits) {
+  const size_t total = (size_t)m * nw;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / nw;
+    const int w = (int)(idx % nw);
+    uint32_t v = 0;
+    const int j0 = w * 32;
+    const int jn = min(32, n - j0);
+    for (int b = 0; b < jn; ++b) v |= (Q[i * n + j0 + b] != 0 ? 1u : 0u) << b;
+    bits[idx] = v;
+  }
+}
+
+// Initial coarse data: X_0 = P_Q(D - S0 + Y0/mu0) (or X_0 = M for the standalone SVT),
+// M_P = X_0 P (PLAIN: M_P = X_0), and partial sums of ||P_Q D||^2.
+template <bool PLAIN, bool MASKED>
+__global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM, const float* __restrict__ D,
+                                                   int ldd, const uint32_t* __restrict__ bits, int nw,
+                                                   const float* __restrict__ S0, const float* __restrict__ Y0,
+                                                   float inv_mu0, float* __restrict__ MP, int ldp,
+                                                   const int* __restrict__ col_ptr, const int* __restrict__ col_row,
+                                                   const float* __restrict__ col_w, double* __restrict__ partial) {
+  extern __shared__ float sm[];
+  __shared__ double red[kThreads];
+  const int i0 = blockIdx.x * TM;
+  const int rows = min(TM, m - i0);
+  double acc = 0.0;
+  for (int e = threadIdx.x; e < rows * n; e += kThreads) {
+    const int i = e / n, j = e % n;
+    const int gi = i0 + i;
+    float x = 0.0f;
+    if (!MASKED || qbit(bits, nw, gi, j)) {
+      const float d = D[(size_t)gi * ldd + j];
+      acc += (double)d * (double)d;
+      x = d;
+      if (S0) x -= S0[(size_t)gi * n + j];
+      if (Y0) x += Y0[(size_t)gi * n + j] * inv_mu0;
+    }
+    if (PLAIN)
+      MP[(size_t)gi * ldp + j] = x;
+    else
+      sm[(size_t)i * n + j] = x;
+  }
+  if (!PLAIN) {
+    __syncthreads();
+    restrict_panel(sm, rows, n, nH, MP, ldp, i0, col_ptr, col_row, col_w);
+  }
+  const double s = block_sum(acc, red);
+  if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
+}
+
+// sigma_k = sqrt(max(lam_perm[k], 0)), r = #{sigma > tau}, sw[k] = sqrt((sigma-tau)/sigma)
+__global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict__ lam, const int* __restrict__ perm,
+                                                       int nH, double tau, double* __restrict__ sw,
+                                                       IterStats* __restrict__ st) {
+  __shared__ int cnt[kThreads];
+  __shared__ double mg[kThreads];
+  int c = 0;
+  double mgn = 1.0e300;
+  for (int k = threadIdx.x; k < nH; k += kThreads) {
+    const double sg = sqrt(fmax(lam[perm[k]], 0.0));
+    if (sg > tau) {
+      ++c;
+      sw[k] = sqrt((sg - tau) / sg);
+    } else {
+      sw[k] = 0.0;
+    }
+    mgn = fmin(mgn, fabs(sg - tau) / tau);
+  }
+  cnt[threadIdx.x] = c;
+  mg[threadIdx.x] = mgn;
+  __syncthreads();
+  for (int w = kThreads / 2; w > 0; w >>= 1) {
+    if (threadIdx.x < w) {
+      cnt[threadIdx.x] += cnt[threadIdx.x + w];
+      mg[threadIdx.x] = fmin(mg[threadIdx.x], mg[threadIdx.x + w]);
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    st->rank = cnt[0];
+    st->margin = mg[0];
+  }
+}
+
+// T[c][k] = sum_j C[c][j] V[j][perm[k]] * sw[k] (C = I when PLAIN), k < r;  Tt = T^T.
+template <bool PLAIN>
+__global__ void k_build_T(int nH, int N, const double* __restrict__ C, const double* __restrict__ V,
+                          const int* __restrict__ perm, const double* __restrict__ sw,
+                          const IterStats* __restrict__ st, float* __restrict__ T, float* __restrict__ Tt,
+                          int ldT) {
+  const int r = st->rank;
+  const size_t total = (size_t)nH * r;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / r), k = (int)(idx % r);
+    const int col = perm[k];
+    double v;
+    if (PLAIN) {
+      v = V[(size_t)c * N + col];
+    } else {
+      v = 0.0;
+      for (int j = 0; j < nH; ++j) v += C[(size_t)c * nH + j] * V[(size_t)j * N + col];
+    }
+    const float tv = (float)(v * sw[k]);
+    T[(size_t)c * ldT + k] = tv;
+    Tt[(size_t)k * ldT + c] = tv;
+  }
+}
+
+struct EpiArgs {
+  int m, n, nH, TM, ldp, nw, ldT;
+  const float* D;
+  int ldd;
+  const uint32_t* bits;
+  const float* MPcur;
+  float* MPnext;
+  const float* T;
+  const float* Tt;
+  const IterStats* st;
+  const float* Zin;   // state (E on Q, L off Q)
+  float* Zout;        // may equal Zin
+  const float* Y0;    // first iteration: initial multiplier (nullable)
+  float* Lout;        // FINAL / RECON
+  float* Sout;        // FINAL (may equal Zin)
+  float* Yout;        // FINAL (nullable)
+  float mu, inv_mu, mu_prev, inv_mu_next, lam, thr;
+  int first;
+  const int* row_idx;
+  const float* row_w;
+  const int* col_ptr;
+  const int* col_row;
+  const float* col_w;
+  double* partial;
+};
+
+template <int MODE, bool PLAIN, bool MASKED>
+__global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
+  extern __shared__ float sm[];
+  __shared__ double red[kThreads];
+  const int nHp = a.ldp;
+  float* sMP = sm;                              // TM x nHp: M_P panel, then N panel
+  float* sA = sm + (size_t)a.TM * nHp;          // TM x nHp: A = M_P T (r <= nH columns)
+  float* sX = sA + (size_t)a.TM * nHp;          // TM x n  : next coarse data (not PLAIN)
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * a.TM;
+  const int rows = min(a.TM, a.m - i0);
+  const int nH = a.nH, n = a.n;
+  const int r = a.st->rank;
+
+  // 1. M_P panel
+  for (int e = tid; e < rows * nH; e += kThreads) {
+    const int i = e / nH, c = e % nH;
+    sMP[i * nHp + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
+  }
+  __syncthreads();
+  // 2. A = M_P T   (rows x r)
+  for (int e = tid; e < rows * r; e += kThreads) {
+    const int i = e / r, k = e % r;
+    const float* x = sMP + i * nHp;
+    float acc = 0.0f;
+    for (int c = 0; c < nH; ++c) acc = fmaf(x[c], a.T[(size_t)c * a.ldT + k], acc);
+    sA[i * nHp + k] = acc;
+  }
+  __syncthreads();
+  // 3. N = A T^T  (rows x nH), over the M_P panel
+  for (int e = tid; e < rows * nH; e += kThreads) {
+    const int i = e / nH, c = e % nH;
+    const float* y = sA + i * nHp;
+    float acc = 0.0f;
+    for (int k = 0; k < r; ++k) acc = fmaf(y[k], a.Tt[(size_t)k * a.ldT + c], acc);
+    sMP[i * nHp + c] = acc;
+  }
+  __syncthreads();
+  // 4. fine elements
+  double racc = 0.0;
+  for (int e = tid; e < rows * n; e += kThreads) {
+    const int i = e / n, j = e % n;
+    const int gi = i0 + i;
+    float L;
+    if (PLAIN) {
+      L = sMP[i * nHp + j];
+    } else {
+      const int* ri = a.row_idx + j * kMaxStencil;
+      const float* rw = a.row_w + j * kMaxStencil;
+      L = 0.0f;
+#pragma unroll
+      for (int s = 0; s < kMaxStencil; ++s) L = fmaf(rw[s], sMP[i * nHp + ri[s]], L);
+    }
+    const size_t gij = (size_t)gi * n + j;
+    if (MODE == MODE_RECON) {
+      a.Lout[gij] = L;
+      continue;
+    }
+    const bool q = MASKED ? qbit(a.bits, a.nw, gi, j) : true;
+    if (MODE == MODE_FINAL) {
+      a.Lout[gij] = L;
+      if (q) {
+        const float z = a.Zin[gij];
+        a.Sout[gij] = shrinkf(z, a.thr);
+        if (a.Yout) a.Yout[gij] = fminf(fmaxf(a.mu * z, -a.lam), a.lam);
+      } else {
+        a.Sout[gij] = 0.0f;
+        if (a.Yout) a.Yout[gij] = 0.0f;
+      }
+      continue;
+    }
+    float x;
+    if (q) {
+      const float d = a.D[(size_t)gi * a.ldd + j];
+      float ym;
+      if (a.first) {
+        ym = a.Y0 ? a.Y0[gij] * a.inv_mu : 0.0f;
+      } else {
+        ym = fminf(fmaxf(a.mu_prev * a.Zin[gij], -a.lam), a.lam) * a.inv_mu;
+      }
+      const float dl = d - L;
+      const float ev = dl + ym;
+      const float s = shrinkf(ev, a.thr);
+      const float res = dl - s;
+      racc += (double)res * (double)res;
+      a.Zout[gij] = ev;
+      const float ynext = fminf(fmaxf(a.mu * ev, -a.lam), a.lam);
+      x = d - s + ynext * a.inv_mu_next;
+    } else {
+      a.Zout[gij] = L;
+      x = L;
+    }
+    if (PLAIN)
+      a.MPnext[(size_t)gi * a.ldp + j] = x;
+    else
+      sX[(size_t)i * n + j] = x;
+  }
+  if (MODE != MODE_STEP) return;
+  if (!PLAIN) {
+    __syncthreads();
+    restrict_panel(sX, rows, n, nH, a.MPnext, a.ldp, i0, a.col_ptr, a.col_row, a.col_w);
+  }
+  const double s = block_sum(racc, red);
+  if (tid == 0) a.partial[blockIdx.x] = s;
+}
+
+// sums partial[0..cnt) in a fixed order into *out
+__global__ void __launch_bounds__(kThreads) k_reduce(const double* __restrict__ partial, int cnt,
+                                                     double* __restrict__ out) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += kThreads) s += partial[i];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) *out = t;
+}
+
+unsigned grid_for(size_t total) {
+  size_t b = (total + kThreads - 1) / kThreads;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (unsigned)b;
+}
+
+// ---------------------------------------------------------------------------------
+struct Plan {
+  int m, n, nH, nHp, levels, TM, nblk, nw;
+  bool plain, masked;
+  size_t lds_epi, lds_init;
+  size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_perm, off_sw, off_T, off_Tt,
+      off_part, off_gram, off_eig, off_stats, total;
+};
+
+int make_plan(int m, int n, int levels, bool masked, Plan& p) {
+  p.m = m;
+  p.n = n;
+  p.levels = levels;
+  p.nH = coarse_dim_checked(n, levels);
+  if (p.nH < 1) return MLPCP_E_LEVELS;
+  p.nHp = round_up(p.nH, kPad);
+  p.plain = (levels == 0);
+  p.masked = masked;
+  p.nw = (n + 31) / 32;
+  const size_t per_row = (size_t)4 * (2 * p.nHp + (p.plain ? 0 : n));
+  int TM = (int)(kLdsBudget / per_row);
+  if (TM < 1) return MLPCP_E_UNSUPPORTED;
+  if (TM > 64) TM = 64;
+  p.TM = TM;
+  p.nblk = (m + TM - 1) / TM;
+  p.lds_epi = (size_t)TM * per_row;
+  p.lds_init = p.plain ? 0 : (size_t)TM * n * 4;
+  size_t off = 0;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t nn = (size_t)p.nHp * p.nHp;
+  p.off_mp0 = take((size_t)m * p.nHp * 4);
+  p.off_mp1 = take((size_t)m * p.nHp * 4);
+  p.off_bits = take(masked ? (size_t)m * p.nw * 4 : 0);
+  p.off_G = take(nn * 8);
+  p.off_GH = take(p.plain ? 0 : nn * 8);
+  p.off_tmp = take(p.plain ? 0 : nn * 8);
+  p.off_V = take(nn * 8);
+  p.off_lam = take((size_t)p.nHp * 8);
+  p.off_perm = take((size_t)p.nHp * 4);
+  p.off_sw = take((size_t)p.nHp * 8);
+  p.off_T = take(nn * 4);
+  p.off_Tt = take(nn * 4);
+  p.off_part = take((size_t)p.nblk * 8);
+  p.off_gram = take(gram_workspace_bytes(m, p.nHp));
+  p.off_eig = take(eig_workspace_bytes(p.nHp));
+  p.off_stats = take(sizeof(IterStats));
+  p.total = off + 256;  // slack for aligning the caller's base pointer
+  return MLPCP_OK;
+}
+
+struct WS {
+  char* base = nullptr;
+  void* owned = nullptr;
+  ~WS() {
+    if (owned) (void)hipFree(owned);
+  }
+  template <typename T>
+  T* at(size_t off) const {
+    return reinterpret_cast<T*>(base + off);
+  }
+};
+
+int bind_workspace(const Plan& p, void* ws, size_t ws_bytes, WS& w) {
+  if (ws) {
+    if (ws_bytes < p.total) return MLPCP_E_WORKSPACE;
+    w.base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(ws) + 255) & ~uintptr_t(255));
+  } else {
+    MLPCP_HIP(hipMalloc(&w.owned, p.total));
+    w.base = reinterpret_cast<char*>((reinterpret_cast<uintptr_t>(w.owned) + 255) & ~uintptr_t(255));
+  }
+  return MLPCP_OK;
+}
+
+int valid_opts(const mlpcp_opts& o) {
+  if (!(o.tol > 0.0) || !std::isfinite(o.tol) || o.max_iter < 1 || !(o.rho >= 1.0) || !std::isfinite(o.rho) ||
+      !(o.mu_max_factor >= 1.0) || !std::isfinite(o.mu_max_factor))
+    return MLPCP_E_INVALID_ARG;
+  if (o.prec != MLPCP_FP32 || o.check_every != 1 || o.r_norm != 0) return MLPCP_E_UNSUPPORTED;
+  return MLPCP_OK;
+}
+
+// One coarse SVT on M_P (buffer `mp`): Gram, C G C, eigensolve, weights, T.
+int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, double tau, hipStream_t s,
+               int* sweeps) {
+  double* G = w.at<double>(p.off_G);
+  double* V = w.at<double>(p.off_V);
+  double* lam = w.at<double>(p.off_lam);
+  int* perm = w.at<int>(p.off_perm);
+  double* sw = w.at<double>(p.off_sw);
+  float* T = w.at<float>(p.off_T);
+  float* Tt = w.at<float>(p.off_Tt);
+  IterStats* st = w.at<IterStats>(p.off_stats);
+  MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.nHp, G, w.at<void>(p.off_gram), s));
+  double* GH = G;
+  if (!p.plain) {
+    GH = w.at<double>(p.off_GH);
+    double* tmp = w.at<double>(p.off_tmp);
+    MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
+    MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
+  }
+  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps));
+  hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, sw, st);
+  const size_t tot = (size_t)p.nH * p.nH;
+  if (p.plain)
+    hipLaunchKernelGGL(k_build_T<true>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op.C, V, perm, sw,
+                       st, T, Tt, p.nHp);
+  else
+    hipLaunchKernelGGL(k_build_T<false>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op.C, V, perm,
+                       sw, st, T, Tt, p.nHp);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+template <int MODE>
+int launch_epilogue(const Plan& p, const EpiArgs& a, hipStream_t s) {
+  const dim3 g(p.nblk), b(kThreads);
+  if (p.plain) {
+    if (p.masked)
+      hipLaunchKernelGGL((k_epilogue<MODE, true, true>), g, b, p.lds_epi, s, a);
+    else
+      hipLaunchKernelGGL((k_epilogue<MODE, true, false>), g, b, p.lds_epi, s, a);
+  } else {
+    if (p.masked)
+      hipLaunchKernelGGL((k_epilogue<MODE, false, true>), g, b, p.lds_epi, s, a);
+    else
+      hipLaunchKernelGGL((k_epilogue<MODE, false, false>), g, b, p.lds_epi, s, a);
+  }
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+int launch_init(const Plan& p, const Operator& op, const float* D, int ldd, const uint32_t* bits,
+                const float* S0, const float* Y0, float inv_mu0, float* mp, double* partial, hipStream_t s) {
+  const dim3 g(p.nblk), b(kThreads);
+  if (p.plain) {
+    if (p.masked)
+      hipLaunchKernelGGL((k_init<true, true>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
+                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+    else
+      hipLaunchKernelGGL((k_init<true, false>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
+                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+  } else {
+    if (p.masked)
+      hipLaunchKernelGGL((k_init<false, true>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
+                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+    else
+      hipLaunchKernelGGL((k_init<false, false>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
+                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+  }
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda, double mu0,
+          const mlpcp_opts* optp, const float* S0, const float* Y0, float* L, float* S, float* Y, void* ws,
+          size_t ws_bytes, mlpcp_info* info, void* stream, bool masked) {
+  mlpcp_opts o;
+  if (optp)
+    o = *optp;
+  else
+    mlpcp_default_opts(&o);
+  if (m < 1 || n < 1 || m < n || ldd < n) return MLPCP_E_SHAPE;
+  if (!D || !L || !S || (masked && !Q)) return MLPCP_E_INVALID_ARG;
+  if (!(lambda > 0.0f) || !std::isfinite(lambda) || !(mu0 > 0.0) || !std::isfinite(mu0)) return MLPCP_E_INVALID_ARG;
+  MLPCP_TRY(valid_opts(o));
+  if (coarse_dim_checked(n, o.levels) < 1) return MLPCP_E_LEVELS;
+  if (L == S || L == Y || (Y && S == Y) || (const float*)L == D || (const float*)S == D) return MLPCP_E_INVALID_ARG;
+  Plan p;
+  MLPCP_TRY(make_plan(m, n, o.levels, masked, p));
+  if (ws && ws_bytes < p.total) return MLPCP_E_WORKSPACE;
+
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Operator* op = nullptr;
+  MLPCP_TRY(get_operator(n, o.levels, s, &op));
+  WS w;
+  MLPCP_TRY(bind_workspace(p, ws, ws_bytes, w));
+  float* mp[2] = {w.at<float>(p.off_mp0), w.at<float>(p.off_mp1)};
+  uint32_t* bits = masked ? w.at<uint32_t>(p.off_bits) : nullptr;
+  double* part = w.at<double>(p.off_part);
+  IterStats* st = w.at<IterStats>(p.off_stats);
+  if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
+  if (masked) {
+    const size_t words = (size_t)m * p.nw;
+    hipLaunchKernelGGL(k_pack_mask, dim3(grid_for(words)), dim3(kThreads), 0, s, m, n, Q, p.nw, bits);
+  }
+  MLPCP_TRY(launch_init(p, *op, D, ldd, bits, S0, Y0, (float)(1.0 / mu0), mp[0], part, s));
+  hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, p.nblk, &st->nrm2);
+  MLPCP_HIP(hipGetLastError());
+  IterStats hs;
+  MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  MLPCP_HIP(hipStreamSynchronize(s));
+  const double nrmD = std::sqrt(hs.nrm2);
+
+  const double mu_max = o.mu_max_factor * mu0;
+  double mu = mu0, mu_prev = mu0;
+  double fg = INFINITY;
+  int t = 0, rank = 0, sweeps = 0;
+  double margin = 0.0;
+  bool converged = false;
+  int status = MLPCP_OK;
+  for (t = 0; t < o.max_iter; ++t) {
+    const double mu_next = std::min(o.rho * mu, mu_max);
+    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps));
+    EpiArgs a{};
+    a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+    a.D = D; a.ldd = ldd; a.bits = bits;
+    a.MPcur = mp[t & 1]; a.MPnext = mp[(t + 1) & 1];
+    a.T = w.at<float>(p.off_T); a.Tt = w.at<float>(p.off_Tt); a.st = st;
+    a.Zin = S; a.Zout = S; a.Y0 = Y0;
+    a.mu = (float)mu; a.inv_mu = (float)(1.0 / mu); a.mu_prev = (float)mu_prev;
+    a.inv_mu_next = (float)(1.0 / mu_next); a.lam = lambda; a.thr = (float)(lambda / mu);
+    a.first = (t == 0);
+    a.row_idx = op->row_idx; a.row_w = op->row_w;
+    a.col_ptr = op->col_ptr; a.col_row = op->col_row; a.col_w = op->col_w;
+    a.partial = part;
+    MLPCP_TRY(launch_epilogue<MODE_STEP>(p, a, s));
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, p.nblk, &st->fg2);
+    MLPCP_HIP(hipGetLastError());
+    MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    MLPCP_HIP(hipStreamSynchronize(s));
+    fg = std::sqrt(hs.fg2) / nrmD;
+    rank = hs.rank;
+    margin = hs.margin;
+    if (info && info->fg_history && t < info->history_len) info->fg_history[t] = fg;
+    if (info && info->rank_history && t < info->history_len) info->rank_history[t] = rank;
+    if (!std::isfinite(fg)) {
+      status = MLPCP_E_NONFINITE;
+      ++t;
+      break;
+    }
+    if (fg <= o.tol) {
+      converged = true;
+      ++t;
+      break;
+    }
+    mu_prev = mu;
+    mu = mu_next;
+  }
+  if (status == MLPCP_OK) {
+    // t iterations done; the last one used mu (if converged) -- recompute its L
+    const int last = t - 1;
+    const double mu_last = converged ? mu : mu_prev;
+    EpiArgs a{};
+    a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+    a.D = D; a.ldd = ldd; a.bits = bits;
+    a.MPcur = mp[last & 1]; a.MPnext = nullptr;
+    a.T = w.at<float>(p.off_T); a.Tt = w.at<float>(p.off_Tt); a.st = st;
+    a.Zin = S; a.Lout = L; a.Sout = S; a.Yout = Y;
+    a.mu = (float)mu_last; a.lam = lambda; a.thr = (float)(lambda / mu_last);
+    a.row_idx = op->row_idx; a.row_w = op->row_w;
+    MLPCP_TRY(launch_epilogue<MODE_FINAL>(p, a, s));
+    MLPCP_HIP(hipStreamSynchronize(s));
+    if (!converged) status = MLPCP_NOT_CONVERGED;
+    mu = mu_last;
+  }
+  if (info) {
+    info->iters = t;
+    info->fg = fg;
+    info->rank = rank;
+    info->mu_final = mu;
+    info->tau_margin = margin;
+    info->eig_sweeps = sweeps;
+  }
+  return status;
+}
+
+}  // namespace
+
+}  // namespace mlpcp
+
+using namespace mlpcp;
+
+extern "C" {
+
+size_t mlpcp_workspace_bytes(int m, int n, const mlpcp_opts* optp) {
+  mlpcp_opts o;
+  if (optp)
+    o = *optp;
+  else
+    mlpcp_default_opts(&o);
+  if (m < 1 || n < 1 || m < n) return 0;
+  Plan p;
+  if (make_plan(m, n, o.levels, true, p) != MLPCP_OK) return 0;
+  return p.total;
+}
+
+int mlpcp_pcp_solve(int m, int n, const float* D, int ldd, float lambda, double mu0, const mlpcp_opts* opts,
+                    const float* S0, const float* Y0, float* L, float* S, float* Y, void* ws, size_t ws_bytes,
+                    mlpcp_info* info, void* stream) {
+  return solve(m, n, D, ldd, nullptr, lambda, mu0, opts, S0, Y0, L, S, Y, ws, ws_bytes, info, stream, false);
+}
+
+int mlpcp_cpcp_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda, double mu0,
+                     const mlpcp_opts* opts, const float* S0, const float* Y0, float* L, float* S, float* Y,
+                     void* ws, size_t ws_bytes, mlpcp_info* info, void* stream) {
+  return solve(m, n, D, ldd, Q, lambda, mu0, opts, S0, Y0, L, S, Y, ws, ws_bytes, info, stream, true);
+}
+
+int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau, float* L, int* rank, void* ws,
+                   size_t ws_bytes, void* stream) {
+  if (m < 1 || n < 1 || m < n || ldm < n) return MLPCP_E_SHAPE;
+  if (!M || !L) return MLPCP_E_INVALID_ARG;
+  if (!(tau > 0.0f) || !std::isfinite(tau)) return MLPCP_E_INVALID_ARG;
+  if (coarse_dim_checked(n, levels) < 1) return MLPCP_E_LEVELS;
+  Plan p;
+  MLPCP_TRY(make_plan(m, n, levels, false, p));
+  if (ws && ws_bytes < p.total) return MLPCP_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Operator* op = nullptr;
+  MLPCP_TRY(get_operator(n, levels, s, &op));
+  WS w;
+  MLPCP_TRY(bind_workspace(p, ws, ws_bytes, w));
+  float* mp = w.at<float>(p.off_mp0);
+  if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
+  MLPCP_TRY(launch_init(p, *op, M, ldm, nullptr, nullptr, nullptr, 0.0f, mp, nullptr, s));
+  int sweeps = 0;
+  MLPCP_TRY(coarse_svt(p, *op, w, mp, (double)tau, s, &sweeps));
+  EpiArgs a{};
+  a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+  a.MPcur = mp; a.T = w.at<float>(p.off_T); a.Tt = w.at<float>(p.off_Tt);
+  a.st = w.at<IterStats>(p.off_stats);
+  a.Lout = L;
+  a.row_idx = op->row_idx; a.row_w = op->row_w;
+  MLPCP_TRY(launch_epilogue<MODE_RECON>(p, a, s));
+  IterStats hs;
+  MLPCP_HIP(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  MLPCP_HIP(hipStreamSynchronize(s));
+  if (rank) *rank = hs.rank;
+  return MLPCP_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,73 @@
+"""GPU parity of the streaming operators and the coarse SVT against the FP64 oracle,
+called through the C ABI (Python binding).  Sizes span several tiles and ragged
+tails; tolerances follow from float32 arithmetic."""
+import numpy as np
+import pytest
+
+import oracle
+import paper_2206_13369_amd as mlp
+from gpu_util import rel, say, to_dev, to_np, torch_dev
+
+pytestmark = pytest.mark.gpu
+
+
+def test_shrink_matches_float32_formula_exactly():
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(0)
+    x = rng.normal(size=100003).astype(np.float32) * 3
+    x[:6] = [0.0, -0.0, 0.5, -0.5, np.inf, -np.inf]
+    for tau in (0.0, 0.5, 1.0, 2.75):
+        say("shrink", tau)
+        y = to_np(mlp.shrink(to_dev(x), tau))
+        ref = np.sign(x) * np.maximum(np.abs(x) - np.float32(tau), np.float32(0))
+        assert y.dtype == np.float32
+        assert np.array_equal(y, ref.astype(np.float32))
+    # NaN propagates, in place works
+    xn = np.array([np.nan, 1.0, -3.0], dtype=np.float32)
+    t = to_dev(xn)
+    mlp.shrink(t, 0.5, out=t)
+    got = to_np(t)
+    assert np.isnan(got[0]) and got[1] == 0.5 and got[2] == -2.5
+
+
+@pytest.mark.parametrize("m,n,levels", [(37, 50, 2), (130, 200, 4), (65, 25, 1), (9, 300, 2), (300, 2000, 3),
+                                        (64, 64, 0)])
+def test_restrict_prolong(m, n, levels):
+    say("restrict/prolong", m, n, levels)
+    rng = np.random.default_rng(m + n)
+    X = rng.normal(size=(m, n)).astype(np.float32)
+    XH = to_np(mlp.restrict(to_dev(X), levels))
+    ref = oracle.restrict(X.astype(np.float64), levels)
+    assert XH.shape == ref.shape
+    assert rel(XH, ref) < 2e-6
+    Z = rng.normal(size=ref.shape).astype(np.float32)
+    Xf = to_np(mlp.prolong(to_dev(Z), n, levels))
+    ref2 = oracle.prolong(Z.astype(np.float64), n, levels)
+    assert rel(Xf, ref2) < 2e-6
+    if levels == 0:
+        assert np.array_equal(XH, X) and np.array_equal(Xf, Z)
+
+
+@pytest.mark.parametrize("m,n,levels,rank", [(50, 20, 0, 3), (120, 64, 0, 5), (300, 300, 2, 10), (500, 100, 0, 8),
+                                             (400, 200, 4, 6), (257, 250, 1, 12), (90, 33, 0, 4)])
+def test_svt_prox_matches_oracle(m, n, levels, rank):
+    say("svt_prox", m, n, levels, rank)
+    rng = np.random.default_rng(m * 7 + n)
+    M = (rng.normal(size=(m, rank)) @ rng.normal(size=(rank, n)) + 0.05 * rng.normal(size=(m, n))).astype(np.float32)
+    s = np.linalg.svd(oracle.restrict(M.astype(np.float64), levels), compute_uv=False)
+    # threshold in a gap of the coarse spectrum, so the rank is well defined
+    gaps = s[:-1] / s[1:]
+    k = int(np.argmax(gaps[: max(1, min(len(gaps), rank + 2))]))
+    tau = float(np.sqrt(s[k] * s[k + 1]))
+    L, r = mlp.svt_prox(to_dev(M), tau, levels)
+    Lref, rref = oracle.svt_prox(M.astype(np.float64), tau, levels)
+    assert r == rref
+    assert rel(to_np(L), Lref) < 1e-5
+
+
+def test_svt_prox_thresholds_everything():
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(3)
+    M = rng.normal(size=(80, 40)).astype(np.float32)
+    L, r = mlp.svt_prox(to_dev(M), 1e6, 1)
+    assert r == 0 and not to_np(L).any()
