@@ -1,0 +1,235 @@
+#!/usr/bin/env python3
+"""Benchmark: time to feasibility gap <= 1e-6, multilevel vs plain, on one MI355X.
+
+Workload (default): compressive PCP, 2000 x 2000, rank-50 Gaussian low-rank part,
+10% corruptions U[-10, 10], 60% of entries observed, 3 levels (n_H = 250),
+float32 data (Gram accumulated and eigensolved in float64).
+
+One step = one complete multilevel solve from the initial point to FG <= 1e-6
+(every step of the hot path: restriction, coarse Gram, eigensolve, coarse SVT,
+prolongation, fused soft threshold / mask / dual step / feasibility gap).
+The plain method (levels = 0, the same kernels with R = I) is timed on the same
+input for the speedup.  Inputs are resident in HBM before the timed region.
+
+Prints ONE JSON line.  Options: --steps K --warmup W --gpus N (N must be 1)
+--workload {c1,c2,c3,c5} --no-plain --no-cpu.
+"""
+import argparse
+import json
+import math
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+METRIC = "time-to-rel-err 1e-6 (s) & iters/s: multilevel vs plain PCP on 1 MI355X"
+
+HBM_PEAK = 8.0e12          # bytes/s
+FP64_PEAK = 78.6e12        # flop/s, dense FP64 (vector and matrix)
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--workload", default="c2")
+    ap.add_argument("--tol", type=float, default=1e-6)
+    ap.add_argument("--no-plain", action="store_true")
+    ap.add_argument("--no-cpu", action="store_true")
+    ap.add_argument("--plain-steps", type=int, default=1)
+    return ap.parse_args()
+
+
+def describe(w):
+    masked = w.Q is not None
+    kind = "CPCP" if masked else "PCP"
+    obs = f", {w.Q.mean():.0%} observed" if masked else ""
+    return (f"{w.name}: {kind} {w.m}x{w.n}, rank {w.rank}{obs}, {w.levels} levels "
+            f"(n_H={int(__import__('oracle').coarse_dim(w.n, w.levels))}), FG<=1e-6; {w.recipe}")
+
+
+def algorithmic_work(cls, w, nH, plain, launches_per_solve=None):
+    """(bound, amount per launch, unit-kind) of the method's own work for a kernel class."""
+    m, n = w.m, w.n
+    masked = w.Q is not None
+    if cls == "epilogue":
+        k = n if plain else nH
+        b = 12.0 * m * n + 8.0 * m * k + (m * n / 8.0 if masked else 0.0)
+        return "hbm", b
+    if cls == "init_restrict":
+        k = n if plain else nH
+        return "hbm", 4.0 * m * n + 4.0 * m * k + (m * n / 8.0 if masked else 0.0)
+    if cls == "finalize":
+        return "hbm", 4.0 * m * n * (1 + 3) + 4.0 * m * (n if plain else nH)
+    if cls == "gram_f64":
+        k = n if plain else nH
+        return "mfma", 1.0 * m * k * (k + 1)
+    if cls == "jacobi_apply":
+        N = int(math.ceil(k_of(n if plain else nH) / 32.0)) * 32
+        npairs = N // 32
+        return "alu", 4.0 * 32 ** 3 * npairs * npairs + 2.0 * 32 ** 3 * (N // 32) * npairs
+    if cls == "jacobi_pairs":
+        N = int(math.ceil(k_of(n if plain else nH) / 32.0)) * 32
+        npairs = max(1, N // 32)
+        return "alu", 31.0 * (256 * 24 + 512 * 6) * npairs
+    return None, None
+
+
+def k_of(x):
+    return x
+
+
+def main():
+    a = parse()
+    if a.gpus != 1:
+        print(f"bench.py runs on exactly one GPU; --gpus {a.gpus} is not supported (the solver is single-GPU; "
+              "the multi-GPU sharding is a design note only)", file=sys.stderr)
+        sys.exit(2)
+
+    import numpy as np
+    import torch
+
+    import paper_2206_13369_amd as mlp
+    import synth
+
+    if not torch.cuda.is_available():
+        print("bench.py needs a GPU", file=sys.stderr)
+        sys.exit(1)
+    dev = torch.device("cuda:0")
+    t_gen = time.time()
+    w = synth.config(a.workload)
+    t_gen = time.time() - t_gen
+    print(f"[bench] workload {w.name} {w.m}x{w.n} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
+    D = torch.from_numpy(w.D).to(dev)
+    Q = torch.from_numpy(w.Q.astype(np.uint8)).to(dev) if w.Q is not None else None
+    nH = mlp.coarse_dim(w.n, w.levels)
+
+    def run(levels, ws):
+        kw = dict(levels=levels, tol=a.tol, max_iter=500, want_y=False, workspace=ws, history=600)
+        if Q is None:
+            return mlp.pcp_solve(D, w.lam, w.mu0, **kw)
+        return mlp.cpcp_solve(D, Q, w.lam, w.mu0, **kw)
+
+    ws_ml = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=w.levels)), dtype=torch.uint8,
+                        device=dev)
+    for i in range(a.warmup):
+        r = run(w.levels, ws_ml)
+        print(f"[bench] warmup {i}: iters {r.iters} fg {r.fg:.2e}", file=sys.stderr, flush=True)
+    torch.cuda.synchronize()
+    mlp.profile_enable(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for i in range(a.steps):
+        results.append(run(w.levels, ws_ml))
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    prof = mlp.profile_read()
+    mlp.profile_enable(False)
+    ml_s = (t1 - t0) / a.steps
+    r = results[-1]
+    iters = r.iters
+    print(f"[bench] multilevel: {ml_s*1e3:.2f} ms/solve, {iters} iters, fg {r.fg:.2e}, rank {r.rank}",
+          file=sys.stderr, flush=True)
+    kernel_ms = {k: round(v[1] / a.steps, 4) for k, v in prof.items() if v[0] > 0}
+    launches = {k: v[0] // a.steps for k, v in prof.items() if v[0] > 0}
+
+    plain = None
+    if not a.no_plain:
+        ws_pl = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=0)), dtype=torch.uint8,
+                            device=dev)
+        rp = run(0, ws_pl)   # warm-up (operator cache, code objects)
+        torch.cuda.synchronize()
+        mlp.profile_enable(True)
+        tp0 = time.perf_counter()
+        for _ in range(a.plain_steps):
+            rp = run(0, ws_pl)
+        torch.cuda.synchronize()
+        tp1 = time.perf_counter()
+        pprof = mlp.profile_read()
+        mlp.profile_enable(False)
+        plain_s = (tp1 - tp0) / a.plain_steps
+        plain = dict(time_s=plain_s, iters=rp.iters, fg=rp.fg, rank=rp.rank,
+                     kernel_ms={k: round(v[1] / a.plain_steps, 3) for k, v in pprof.items() if v[0] > 0})
+        print(f"[bench] plain: {plain_s*1e3:.1f} ms/solve, {rp.iters} iters, fg {rp.fg:.2e}, rank {rp.rank}",
+              file=sys.stderr, flush=True)
+        del ws_pl
+
+    # dominant kernel of the multilevel solve and its roofline
+    dom = max(kernel_ms.items(), key=lambda kv: kv[1])[0]
+    bound, amount = algorithmic_work(dom, w, nH, False)
+    roof = None
+    if bound is not None and launches.get(dom):
+        avg_s = kernel_ms[dom] / 1e3 / launches[dom]
+        if bound == "hbm":
+            ach = amount / avg_s / 1e9
+            roof = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK / 1e9, unit="GB/s",
+                        frac=round(ach / (HBM_PEAK / 1e9), 4), traffic=None, kernel=dom,
+                        avg_launch_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_launch=amount)
+        else:
+            ach = amount / avg_s / 1e12
+            roof = dict(bound=bound, achieved=round(ach, 4), peak=FP64_PEAK / 1e12, unit="TFLOP/s",
+                        frac=round(ach / (FP64_PEAK / 1e12), 5), traffic=None, kernel=dom,
+                        avg_launch_us=round(avg_s * 1e6, 2), algorithmic_flops_per_launch=amount)
+    # also the epilogue's HBM roofline (the path's streaming kernel)
+    epi = None
+    if launches.get("epilogue"):
+        avg_s = kernel_ms["epilogue"] / 1e3 / launches["epilogue"]
+        _, b = algorithmic_work("epilogue", w, nH, False)
+        epi = dict(achieved_GBps=round(b / avg_s / 1e9, 1), frac=round(b / avg_s / HBM_PEAK, 4),
+                   avg_launch_us=round(avg_s * 1e6, 2), bytes_per_launch=b)
+
+    cpu = None
+    if not a.no_cpu:
+        import oracle
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count()
+        tc0 = time.perf_counter()
+        ref = oracle.ialm(w.D, w.lam, w.mu0, Q=w.Q, levels=w.levels, tol=a.tol, max_iter=60)
+        tc1 = time.perf_counter()
+        cpu = dict(value=round(tc1 - tc0, 3), unit="s", cores=cores, kind="oracle",
+                   sample=f"one full multilevel FP64 oracle solve of the same input to FG<=1e-6 "
+                          f"({ref.iters} iterations, {ref.iters/(tc1-tc0):.2f} iters/s)",
+                   iters=ref.iters)
+        print(f"[bench] oracle: {tc1-tc0:.2f}s, {ref.iters} iters", file=sys.stderr, flush=True)
+
+    out = {
+        "metric": METRIC,
+        "value": round(ml_s, 6),
+        "unit": "s",
+        "n_gpus": 1,
+        "steps": a.steps,
+        "warmup": a.warmup,
+        "ms_per_step": round(ml_s * 1e3, 4),
+        "higher_is_better": False,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f32",
+        "data": "synthetic",
+        "config": {"workload": describe(w)},
+        "iters": iters,
+        "iters_per_s": round(iters / ml_s, 2),
+        "fg": r.fg,
+        "rank": r.rank,
+        "plain_time_s": None if plain is None else round(plain["time_s"], 5),
+        "plain_iters": None if plain is None else plain["iters"],
+        "plain_iters_per_s": None if plain is None else round(plain["iters"] / plain["time_s"], 3),
+        "speedup_vs_plain": None if plain is None else round(plain["time_s"] / ml_s, 2),
+        "kernel_ms_per_solve": kernel_ms,
+        "launches_per_solve": launches,
+        "plain_kernel_ms_per_solve": None if plain is None else plain["kernel_ms"],
+        "epilogue_roofline": epi,
+        "roofline": roof,
+        "cpu_baseline": cpu,
+    }
+    print(json.dumps(out))
+
+
+if __name__ == "__main__":
+    main()

@@ -35,7 +35,7 @@ MLPCP_E_UNSUPPORTED = -8
 EXPORTED = (
     "mlpcp_default_opts", "mlpcp_coarse_dim", "mlpcp_workspace_bytes", "mlpcp_pcp_solve",
     "mlpcp_cpcp_solve", "mlpcp_svt_prox", "mlpcp_shrink", "mlpcp_restrict", "mlpcp_prolong",
-    "mlpcp_status_string",
+    "mlpcp_status_string", "mlpcp_profile_enable", "mlpcp_profile_read",
 )
 
 
@@ -50,6 +50,10 @@ class Info(ctypes.Structure):
                 ("mu_final", ctypes.c_double), ("tau_margin", ctypes.c_double), ("eig_sweeps", ctypes.c_int),
                 ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
                 ("history_len", ctypes.c_int)]
+
+
+class KernelTime(ctypes.Structure):
+    _fields_ = [("name", ctypes.c_char_p), ("launches", ctypes.c_longlong), ("total_ms", ctypes.c_double)]
 
 
 class MLPCPError(RuntimeError):
@@ -93,8 +97,24 @@ def lib() -> ctypes.CDLL:
     L.mlpcp_prolong.restype = i
     L.mlpcp_status_string.argtypes = [i]
     L.mlpcp_status_string.restype = ctypes.c_char_p
+    L.mlpcp_profile_enable.argtypes = [i]
+    L.mlpcp_profile_enable.restype = i
+    L.mlpcp_profile_read.argtypes = [ctypes.POINTER(KernelTime), i]
+    L.mlpcp_profile_read.restype = i
     _lib = L
     return L
+
+
+def profile_enable(on: bool = True) -> None:
+    """Turns per-kernel-class HIP-event timing on or off (and resets it)."""
+    lib().mlpcp_profile_enable(1 if on else 0)
+
+
+def profile_read() -> dict:
+    """{kernel class: (launches, total milliseconds)} accumulated since profile_enable."""
+    buf = (KernelTime * 32)()
+    k = lib().mlpcp_profile_read(buf, 32)
+    return {buf[i].name.decode(): (int(buf[i].launches), float(buf[i].total_ms)) for i in range(min(k, 32))}
 
 
 def status_string(status: int) -> str:

@@ -18,6 +18,7 @@
 //  Grams): rotate (p,q) iff |a_pq| > eps * sqrt(|a_pp a_qq|) and |a_pq| > floor,
 //  floor = 1e-17 * trace(A).
 #include "common.h"
+#include "profile.h"
 
 #include <cmath>
 
@@ -304,26 +305,43 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
   int* flag = reinterpret_cast<int*>(w + 128);
   int* dsweeps = reinterpret_cast<int*>(w + 192);
 
-  hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, stream, A, N, floor_p);
+  {
+    ProfScope ps(KC_JACOBI_MISC, stream);
+    hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, stream, A, N, floor_p);
+  }
   int sweeps = 0;
   if (N == IN) {
-    hipLaunchKernelGGL(k_jacobi_direct, dim3(1), dim3(256), 0, stream, A, V, N, floor_p, kMaxEigSweeps, dsweeps);
+    {
+      ProfScope ps(KC_JACOBI_PAIRS, stream);
+      hipLaunchKernelGGL(k_jacobi_direct, dim3(1), dim3(256), 0, stream, A, V, N, floor_p, kMaxEigSweeps,
+                         dsweeps);
+    }
     MLPCP_HIP(hipGetLastError());
     MLPCP_HIP(hipMemcpyAsync(&sweeps, dsweeps, sizeof(int), hipMemcpyDeviceToHost, stream));
     MLPCP_HIP(hipStreamSynchronize(stream));
     if (sweeps < 0) return MLPCP_E_EIG;
   } else {
     const size_t nn = (size_t)N * N;
-    hipLaunchKernelGGL(k_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, stream, V, N);
+    {
+      ProfScope ps(KC_JACOBI_MISC, stream);
+      hipLaunchKernelGGL(k_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, stream, V, N);
+    }
     const int apply_blocks = npairs * npairs + (N / IN) * npairs;
     bool converged = false;
     int hflag = 0;
     for (sweeps = 1; sweeps <= kMaxEigSweeps; ++sweeps) {
       MLPCP_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
       for (int r = 0; r < nb - 1; ++r) {
-        hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(256), 0, stream, A, N, nb, r, Qblk, floor_p, 1,
-                           flag);
-        hipLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, A, V, N, nb, r, Qblk, flag);
+        {
+          ProfScope ps(KC_JACOBI_PAIRS, stream);
+          hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(256), 0, stream, A, N, nb, r, Qblk, floor_p, 1,
+                             flag);
+        }
+        {
+          ProfScope ps(KC_JACOBI_APPLY, stream);
+          hipLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, A, V, N, nb, r, Qblk,
+                             flag);
+        }
       }
       MLPCP_HIP(hipGetLastError());
       MLPCP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -335,7 +353,10 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
     }
     if (!converged) return MLPCP_E_EIG;
   }
-  hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, stream, A, N, n, lam, perm);
+  {
+    ProfScope ps(KC_JACOBI_MISC, stream);
+    hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, stream, A, N, n, lam, perm);
+  }
   MLPCP_HIP(hipGetLastError());
   if (sweeps_out) *sweeps_out = sweeps;
   return MLPCP_OK;

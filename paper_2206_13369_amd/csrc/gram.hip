@@ -12,6 +12,7 @@
 // (deterministic), and the lower triangle is mirrored from the upper one so G is
 // exactly symmetric.
 #include "common.h"
+#include "profile.h"
 
 namespace mlpcp {
 
@@ -121,6 +122,7 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
   const int nt = kp / GT;
   const int pairs = nt * (nt + 1) / 2;
   double* part = static_cast<double*>(ws);
+  ProfScope ps(KC_GRAM, stream);
   hipLaunchKernelGGL(k_gram_partial, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
   const size_t nn = (size_t)kp * kp;
   hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, stream, part, sp, kp, G);

@@ -18,6 +18,7 @@
 // (S and Y are functions of E and mu), kept in the caller's S buffer, plus M_P.  A final
 // pass recomputes L from the last coarse factors and writes L, S and Y.
 #include "common.h"
+#include "profile.h"
 
 #include <algorithm>
 #include <cmath>
@@ -435,12 +436,14 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.nHp, G, w.at<void>(p.off_gram), s));
   double* GH = G;
   if (!p.plain) {
+    ProfScope ps(KC_COARSE, s);
     GH = w.at<double>(p.off_GH);
     double* tmp = w.at<double>(p.off_tmp);
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
   }
   MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps));
+  ProfScope ps(KC_SVT, s);
   hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, sw, st);
   const size_t tot = (size_t)p.nH * p.nH;
   if (p.plain)
@@ -456,6 +459,7 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
 template <int MODE>
 int launch_epilogue(const Plan& p, const EpiArgs& a, hipStream_t s) {
   const dim3 g(p.nblk), b(kThreads);
+  ProfScope ps(MODE == MODE_STEP ? KC_EPILOGUE : KC_FINAL, s);
   if (p.plain) {
     if (p.masked)
       hipLaunchKernelGGL((k_epilogue<MODE, true, true>), g, b, p.lds_epi, s, a);
@@ -474,6 +478,7 @@ int launch_epilogue(const Plan& p, const EpiArgs& a, hipStream_t s) {
 int launch_init(const Plan& p, const Operator& op, const float* D, int ldd, const uint32_t* bits,
                 const float* S0, const float* Y0, float inv_mu0, float* mp, double* partial, hipStream_t s) {
   const dim3 g(p.nblk), b(kThreads);
+  ProfScope ps(KC_INIT, s);
   if (p.plain) {
     if (p.masked)
       hipLaunchKernelGGL((k_init<true, true>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
@@ -556,10 +561,14 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     a.col_ptr = op->col_ptr; a.col_row = op->col_row; a.col_w = op->col_w;
     a.partial = part;
     MLPCP_TRY(launch_epilogue<MODE_STEP>(p, a, s));
-    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, p.nblk, &st->fg2);
+    {
+      ProfScope ps(KC_REDUCE, s);
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, p.nblk, &st->fg2);
+    }
     MLPCP_HIP(hipGetLastError());
     MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     MLPCP_HIP(hipStreamSynchronize(s));
+    prof_drain();
     fg = std::sqrt(hs.fg2) / nrmD;
     rank = hs.rank;
     margin = hs.margin;
