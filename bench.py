@@ -51,35 +51,30 @@ def describe(w):
             f"(n_H={int(__import__('oracle').coarse_dim(w.n, w.levels))}), FG<=1e-6; {w.recipe}")
 
 
-def algorithmic_work(cls, w, nH, plain, launches_per_solve=None):
-    """(bound, amount per launch, unit-kind) of the method's own work for a kernel class."""
+def algorithmic_work(cls, w, nH, plain):
+    """(bound, amount per launch) of the method's own work for one launch of a kernel
+    class: HBM bytes the kernel must move, or float64 flops."""
     m, n = w.m, w.n
     masked = w.Q is not None
+    k = n if plain else nH
     if cls == "epilogue":
-        k = n if plain else nH
-        b = 12.0 * m * n + 8.0 * m * k + (m * n / 8.0 if masked else 0.0)
-        return "hbm", b
+        # read D, read state, write state, (mask bits), read M_P, write next M_P
+        return "hbm", 12.0 * m * n + 8.0 * m * k + (m * n / 8.0 if masked else 0.0)
     if cls == "init_restrict":
-        k = n if plain else nH
         return "hbm", 4.0 * m * n + 4.0 * m * k + (m * n / 8.0 if masked else 0.0)
     if cls == "finalize":
-        return "hbm", 4.0 * m * n * (1 + 3) + 4.0 * m * (n if plain else nH)
+        return "hbm", 16.0 * m * n + 4.0 * m * k
     if cls == "gram_f64":
-        k = n if plain else nH
         return "mfma", 1.0 * m * k * (k + 1)
+    N = int(math.ceil(k / 64.0)) * 64
+    npairs = N // 64
     if cls == "jacobi_apply":
-        N = int(math.ceil(k_of(n if plain else nH) / 32.0)) * 32
-        npairs = N // 32
-        return "alu", 4.0 * 32 ** 3 * npairs * npairs + 2.0 * 32 ** 3 * (N // 32) * npairs
+        # off-diagonal A tiles (two 64^3 products) + V tiles (one), float64
+        return "alu", 2.0 * (2 * 64 ** 3) * (npairs * (npairs - 1) // 2) + 2.0 * 64 ** 3 * (N // 64) * npairs
     if cls == "jacobi_pairs":
-        N = int(math.ceil(k_of(n if plain else nH) / 32.0)) * 32
-        npairs = max(1, N // 32)
-        return "alu", 31.0 * (256 * 24 + 512 * 6) * npairs
+        # 32 rounds of 32 rotations on a 64x64 block and its 64x64 factor
+        return "alu", npairs * 32 * 32 * (64 * 6 + 64 * 6)
     return None, None
-
-
-def k_of(x):
-    return x
 
 
 def main():
@@ -118,8 +113,18 @@ def main():
     for i in range(a.warmup):
         r = run(w.levels, ws_ml)
         print(f"[bench] warmup {i}: iters {r.iters} fg {r.fg:.2e}", file=sys.stderr, flush=True)
+    # per-kernel breakdown of one solve (every launch bracketed by events)
     torch.cuda.synchronize()
     mlp.profile_enable(True)
+    run(w.levels, ws_ml)
+    torch.cuda.synchronize()
+    prof = mlp.profile_read()
+    mlp.profile_enable(False)
+    kernel_ms = {k: round(v[1], 4) for k, v in prof.items() if v[0] > 0}
+    launches = {k: v[0] for k, v in prof.items() if v[0] > 0}
+    dom = max(kernel_ms.items(), key=lambda kv: kv[1])[0]
+
+    # timed region: K solves, no instrumentation
     torch.cuda.synchronize()
     t0 = time.perf_counter()
     results = []
@@ -127,54 +132,65 @@ def main():
         results.append(run(w.levels, ws_ml))
     torch.cuda.synchronize()
     t1 = time.perf_counter()
-    prof = mlp.profile_read()
-    mlp.profile_enable(False)
     ml_s = (t1 - t0) / a.steps
     r = results[-1]
     iters = r.iters
-    print(f"[bench] multilevel: {ml_s*1e3:.2f} ms/solve, {iters} iters, fg {r.fg:.2e}, rank {r.rank}",
-          file=sys.stderr, flush=True)
-    kernel_ms = {k: round(v[1] / a.steps, 4) for k, v in prof.items() if v[0] > 0}
-    launches = {k: v[0] // a.steps for k, v in prof.items() if v[0] > 0}
+    print(f"[bench] multilevel: {ml_s*1e3:.2f} ms/solve, {iters} iters, fg {r.fg:.2e}, rank {r.rank}; "
+          f"dominant kernel {dom}", file=sys.stderr, flush=True)
+
+    # the same K solves with HIP events around the dominant kernel class only
+    torch.cuda.synchronize()
+    mlp.profile_enable([dom])
+    ti0 = time.perf_counter()
+    for i in range(a.steps):
+        run(w.levels, ws_ml)
+    torch.cuda.synchronize()
+    ti1 = time.perf_counter()
+    dprof = mlp.profile_read()[dom]
+    mlp.profile_enable(False)
+    dom_launches, dom_ms = dprof
+    inst_s = (ti1 - ti0) / a.steps
 
     plain = None
     if not a.no_plain:
         ws_pl = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=0)), dtype=torch.uint8,
                             device=dev)
-        rp = run(0, ws_pl)   # warm-up (operator cache, code objects)
         torch.cuda.synchronize()
-        mlp.profile_enable(True)
+        mlp.profile_enable(True)       # warm-up solve, also the plain kernel breakdown
+        rp = run(0, ws_pl)
+        torch.cuda.synchronize()
+        pprof = mlp.profile_read()
+        mlp.profile_enable(False)
         tp0 = time.perf_counter()
         for _ in range(a.plain_steps):
             rp = run(0, ws_pl)
         torch.cuda.synchronize()
         tp1 = time.perf_counter()
-        pprof = mlp.profile_read()
-        mlp.profile_enable(False)
         plain_s = (tp1 - tp0) / a.plain_steps
         plain = dict(time_s=plain_s, iters=rp.iters, fg=rp.fg, rank=rp.rank,
-                     kernel_ms={k: round(v[1] / a.plain_steps, 3) for k, v in pprof.items() if v[0] > 0})
+                     kernel_ms={k: round(v[1], 3) for k, v in pprof.items() if v[0] > 0})
         print(f"[bench] plain: {plain_s*1e3:.1f} ms/solve, {rp.iters} iters, fg {rp.fg:.2e}, rank {rp.rank}",
               file=sys.stderr, flush=True)
         del ws_pl
 
-    # dominant kernel of the multilevel solve and its roofline
-    dom = max(kernel_ms.items(), key=lambda kv: kv[1])[0]
+    # roofline of the dominant kernel, from its event-timed launches
     bound, amount = algorithmic_work(dom, w, nH, False)
     roof = None
-    if bound is not None and launches.get(dom):
-        avg_s = kernel_ms[dom] / 1e3 / launches[dom]
+    if bound is not None and dom_launches:
+        avg_s = dom_ms / 1e3 / dom_launches
         if bound == "hbm":
             ach = amount / avg_s / 1e9
             roof = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK / 1e9, unit="GB/s",
                         frac=round(ach / (HBM_PEAK / 1e9), 4), traffic=None, kernel=dom,
-                        avg_launch_us=round(avg_s * 1e6, 2), algorithmic_bytes_per_launch=amount)
+                        avg_launch_us=round(avg_s * 1e6, 2), launches=dom_launches,
+                        algorithmic_bytes_per_launch=amount)
         else:
             ach = amount / avg_s / 1e12
             roof = dict(bound=bound, achieved=round(ach, 4), peak=FP64_PEAK / 1e12, unit="TFLOP/s",
                         frac=round(ach / (FP64_PEAK / 1e12), 5), traffic=None, kernel=dom,
-                        avg_launch_us=round(avg_s * 1e6, 2), algorithmic_flops_per_launch=amount)
-    # also the epilogue's HBM roofline (the path's streaming kernel)
+                        avg_launch_us=round(avg_s * 1e6, 2), launches=dom_launches,
+                        algorithmic_flops_per_launch=amount)
+    # the streaming epilogue's HBM roofline (from the breakdown solve)
     epi = None
     if launches.get("epilogue"):
         avg_s = kernel_ms["epilogue"] / 1e3 / launches["epilogue"]
@@ -221,6 +237,7 @@ def main():
         "plain_iters": None if plain is None else plain["iters"],
         "plain_iters_per_s": None if plain is None else round(plain["iters"] / plain["time_s"], 3),
         "speedup_vs_plain": None if plain is None else round(plain["time_s"] / ml_s, 2),
+        "instrumented_ms_per_step": round(inst_s * 1e3, 4),
         "kernel_ms_per_solve": kernel_ms,
         "launches_per_solve": launches,
         "plain_kernel_ms_per_solve": None if plain is None else plain["kernel_ms"],

@@ -157,18 +157,21 @@ int mlpcp_prolong(int m, int n, const float* XH, int ldh, int levels, float* X, 
 /* Static description of a status code (never NULL).                          */
 const char* mlpcp_status_string(int status);
 
-/* Kernel timing, for diagnostics and benchmarking.  While enabled, every solver
- * kernel launch is bracketed by HIP events recorded on the caller's stream, and
- * the elapsed times are accumulated per kernel class.  enable(0 or 1) resets the
- * counters; read() copies up to `cap` classes into `out` (static names) and
- * returns the number of classes.  Timing adds two event records per launch.  */
+/* Kernel timing, for diagnostics and benchmarking.  Kernels are grouped into
+ * classes (read() reports them in a fixed order: init_restrict, gram_f64,
+ * coarse_CGC, jacobi_pairs, jacobi_apply, jacobi_misc, svt_prep, epilogue,
+ * reduce, finalize, other).  enable(mask) resets the counters and brackets every
+ * launch of class i with HIP events on the caller's stream when bit i of mask is
+ * set (mask 0 = off, -1 = all); the elapsed times are accumulated per class.
+ * read() copies up to `cap` classes into `out` (static names) and returns the
+ * number of classes.  Each timed launch adds two event records to the stream.  */
 typedef struct {
   const char* name;
   long long launches;
   double total_ms;
 } mlpcp_kernel_time;
 
-int mlpcp_profile_enable(int on);
+int mlpcp_profile_enable(int mask);
 int mlpcp_profile_read(mlpcp_kernel_time* out, int cap);
 
 #ifdef __cplusplus

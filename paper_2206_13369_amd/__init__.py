@@ -105,9 +105,22 @@ def lib() -> ctypes.CDLL:
     return L
 
 
-def profile_enable(on: bool = True) -> None:
-    """Turns per-kernel-class HIP-event timing on or off (and resets it)."""
-    lib().mlpcp_profile_enable(1 if on else 0)
+KERNEL_CLASSES = ("init_restrict", "gram_f64", "coarse_CGC", "jacobi_pairs", "jacobi_apply", "jacobi_misc",
+                  "svt_prep", "epilogue", "reduce", "finalize", "other")
+
+
+def profile_enable(on=True) -> None:
+    """Per-kernel-class HIP-event timing: True = all classes, False = off, or an
+    iterable of class names to time only those.  Resets the counters."""
+    if on is True:
+        mask = -1
+    elif not on:
+        mask = 0
+    else:
+        mask = 0
+        for name in on:
+            mask |= 1 << KERNEL_CLASSES.index(name)
+    lib().mlpcp_profile_enable(mask)
 
 
 def profile_read() -> dict:

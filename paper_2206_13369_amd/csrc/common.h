@@ -24,9 +24,9 @@ namespace mlpcp {
     if (s_ < 0) return s_;                                \
   } while (0)
 
-constexpr int kEigBlock = 16;          // Jacobi block width b; inner problems are 2b x 2b
+constexpr int kEigBlock = 32;          // Jacobi block width b; inner problems are 2b x 2b
 constexpr int kEigInner = 2 * kEigBlock;
-constexpr int kPad = 32;               // padding of n_H for the Gram / eigensolver tiles
+constexpr int kPad = 64;               // padding of n_H for the Gram / eigensolver tiles
 constexpr int kMaxStencil = 2;         // nonzeros per fine row of the composite interpolation
 constexpr int kMaxEigSweeps = 40;
 
@@ -66,9 +66,11 @@ size_t eig_workspace_bytes(int N);
 // A: N x N float64 symmetric (ld = N), overwritten.  On return V (N x N, ld = N) holds
 // the eigenvectors as columns (unsorted), lam[i] = A_ii, perm[k] = index of the k-th
 // largest eigenvalue.  n <= N is the true size (rows/cols >= n must be zero).
-// sweeps_out receives the number of outer sweeps.  Synchronises `stream`.
+// warm: V holds an orthogonal starting basis on entry (e.g. the previous eigenvectors,
+// identity on the padding); otherwise V is initialised to the identity.
+// sweeps_out receives the number of sweeps.  Synchronises `stream`.
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws,
-            hipStream_t stream, int* sweeps_out);
+            hipStream_t stream, int* sweeps_out, bool warm);
 
 // ---- Gram (gram.hip) ---------------------------------------------------------------
 // G = A^T A for A m x k (float32, ld = lda, k <= kp, kp multiple of kPad), accumulated

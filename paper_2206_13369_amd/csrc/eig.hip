@@ -2,134 +2,174 @@
 // coarse data in Alg. 4 is taken as the eigendecomposition of its Gram matrix).
 //
 // Method: parallel two-sided cyclic Jacobi (Golub & Van Loan, sec. 8.5), blocked.
-//  * Indices are grouped into blocks of b = kEigBlock.  One outer sweep visits every
-//    pair of blocks once, in round-robin order (the circle method: one block fixed,
-//    the others rotating), so each round holds nb/2 disjoint block pairs.
-//  * For each pair the 2b x 2b principal submatrix is diagonalised in LDS by an inner
-//    cyclic Jacobi (itself in round-robin order: b disjoint 2x2 rotations at a time),
-//    accumulating the orthogonal factor Q_pair.
-//  * The round's transformation J = diag(Q_pair) is then applied tile by tile:
-//    A[Pa,Pb] <- Q_a^T A[Pa,Pb] Q_b for every pair of pairs, V[:,Pb] <- V[:,Pb] Q_b.
-//    Tiles are disjoint, so the update is in place.
-//  * A sweep in which no inner problem rotated anything (every off-diagonal entry
-//    below threshold) ends the iteration.
-//  Problems of width <= 2b are solved by one inner solve directly.
-//  Rotation threshold (Demmel-Veselic style, with an absolute floor for singular
-//  Grams): rotate (p,q) iff |a_pq| > eps * sqrt(|a_pp a_qq|) and |a_pq| > floor,
-//  floor = 1e-17 * trace(A).
+//  * Indices are grouped into blocks of b = 32.  An outer sweep visits every pair of
+//    blocks once, in round-robin order (circle method: block 0 fixed, the others
+//    rotating), so each outer round holds nb/2 disjoint block pairs (I, J).
+//  * For each pair the 2b x 2b principal submatrix is loaded into LDS and rotated by
+//    the cross pairs (p in I, q in J) in b rounds of b disjoint rotations
+//    (p_i, q_{(i+s) mod b}); in the first outer round of a sweep the pairs inside
+//    I and inside J are rotated first (b-1 rounds).  So one sweep visits every
+//    off-diagonal position once in N-1 sequential rounds.  The product of the
+//    rotations is the pair's orthogonal factor Q (2b x 2b).
+//  * The outer round's transformation J = diag(Q_pair) is then applied tile by tile
+//    on MFMA: A[Pa,Pb] <- Q_a^T A[Pa,Pb] Q_b (tiles with a <= b, mirrored), and
+//    V[:,Pb] <- V[:,Pb] Q_b.  Tiles are disjoint, so the update is in place.
+//  * A sweep in which nothing was rotated ends the iteration.
+//  * Optional warm start: with V0 given, the iteration starts from A = V0^T A V0,
+//    V = V0 (the previous solver iteration's eigenvectors).
+//  Problems of width 64 are solved by one kernel directly.
+//  Rotation threshold (relative, Demmel-Veselic style, with an absolute floor for
+//  singular Grams and for the rounding the tile products leave): rotate (p,q) iff
+//  a_pq^2 > (1e-15)^2 |a_pp a_qq| and |a_pq| > 1e-16 trace(A).
 #include "common.h"
 #include "profile.h"
 
+#include <algorithm>
 #include <cmath>
 
 namespace mlpcp {
 
 namespace {
 
-constexpr int IB = kEigBlock;       // 16
-constexpr int IN = kEigInner;       // 32
+constexpr int IB = kEigBlock;       // 32
+constexpr int IN = kEigInner;       // 64
 constexpr int LDS_LD = IN + 1;
-constexpr double kRelEps = 2.0e-16;
+constexpr double kRelEps2 = 1.0e-30;  // (1e-15)^2
 
-// circle method: position i of 2p players in round r (player 0 fixed)
+typedef double d4_t __attribute__((ext_vector_type(4)));
+
+// circle method: position i of `players` (even) in round r, player 0 fixed
 __device__ __forceinline__ int rr_player(int i, int r, int players) {
   return i == 0 ? 0 : 1 + ((i - 1 + r) % (players - 1));
 }
 
 __device__ __forceinline__ void rr_pair(int k, int r, int players, int& a, int& b) {
-  int x = rr_player(k, r, players);
-  int y = rr_player(players - 1 - k, r, players);
+  const int x = rr_player(k, r, players);
+  const int y = rr_player(players - 1 - k, r, players);
   a = x < y ? x : y;
   b = x < y ? y : x;
 }
 
-// Jacobi rotation annihilating a_pq of [[app, apq], [apq, aqq]]:
-//   [c s; -s c]^T A [c s; -s c] diagonal, t = s / c the smaller root of
-//   t^2 + 2 theta t - 1 = 0, theta = (aqq - app) / (2 apq).
-__device__ __forceinline__ void rotation(double app, double aqq, double apq, double& c, double& s,
-                                         double& t) {
-  double theta = (aqq - app) / (2.0 * apq);
-  double at = fabs(theta);
-  if (at > 1.0e150) {
-    t = 0.5 / theta;
+// rotation i of inner round s.  phase 0: pairs inside each half (b-player round robin
+// on each half, b-1 rounds); phase 1: cross pairs (i, b + (i+s) mod b), b rounds.
+__device__ __forceinline__ void inner_pair(int phase, int s, int i, int& p, int& q) {
+  if (phase == 0) {
+    const int h = i / (IB / 2), k = i % (IB / 2);
+    int x, y;
+    rr_pair(k, s, IB, x, y);
+    p = h * IB + x;
+    q = h * IB + y;
   } else {
-    t = (theta >= 0.0 ? 1.0 : -1.0) / (at + sqrt(1.0 + theta * theta));
+    p = i;
+    q = IB + ((i + s) & (IB - 1));
   }
+}
+
+// Jacobi rotation annihilating a_pq of [[app, apq], [apq, aqq]]:
+//   [c s; -s c]^T A [c s; -s c] diagonal, t = s/c the root of smaller magnitude of
+//   t^2 + 2 theta t - 1 = 0, theta = (aqq - app)/(2 apq), written without theta:
+//   t = sign(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app.
+__device__ __forceinline__ bool rotation(double app, double aqq, double apq, double floor_abs, double& c,
+                                         double& s, double& t) {
+  const double a2 = apq * apq;
+  if (!(fabs(apq) > floor_abs && a2 > kRelEps2 * fabs(app * aqq))) {
+    c = 1.0;
+    s = 0.0;
+    t = 0.0;
+    return false;
+  }
+  const double d = aqq - app;
+  const double r = sqrt(d * d + 4.0 * a2);
+  t = 2.0 * apq / (fabs(d) + r);
+  if (d < 0.0) t = -t;
   c = 1.0 / sqrt(1.0 + t * t);
   s = t * c;
+  return true;
 }
 
-// One inner sweep set on the IN x IN matrix in LDS, accumulating Q <- Q * J.
-// Runs up to max_sweeps sweeps, stops early after a sweep with no rotation.
-// Returns (in lds flag) whether any rotation happened.  256 threads.
-__device__ void inner_jacobi(double (*A)[LDS_LD], double (*Q)[LDS_LD], int max_sweeps, double floor_abs,
-                             int* any_rot) {
-  __shared__ double rc[IB], rs[IB], rt[IB];
-  __shared__ int rp[IB], rq[IB], rot_on[IB];
-  __shared__ int sweep_rot;
+struct RotShared {
+  double c[IB], s[IB], t[IB];
+  int any;
+};
+
+// One phase (rounds of IB rotations) on the IN x IN matrix in LDS, accumulating
+// Q <- Q J.  256 threads.  Sets rs.any if something rotated.  A skipped rotation is
+// the identity (c = 1, s = t = 0), so every update below is applied unconditionally
+// (exact for skipped pairs); all loads of a thread's items are issued before any of
+// its stores (the items are disjoint), which keeps the LDS latency off the critical
+// path.
+__device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS_LD], int phase, double floor_abs,
+                                            RotShared& rs) {
   const int tid = threadIdx.x;
-  if (tid == 0) *any_rot = 0;
-  for (int sw = 0; sw < max_sweeps; ++sw) {
-    if (tid == 0) sweep_rot = 0;
-    __syncthreads();
-    for (int r = 0; r < IN - 1; ++r) {
-      if (tid < IB) {
-        int p, q;
-        rr_pair(tid, r, IN, p, q);
-        double app = A[p][p], aqq = A[q][q], apq = A[p][q];
-        double c = 1.0, s = 0.0, t = 0.0;
-        int on = 0;
-        if (fabs(apq) > floor_abs && fabs(apq) > kRelEps * sqrt(fabs(app) * fabs(aqq))) {
-          rotation(app, aqq, apq, c, s, t);
-          on = 1;
-          sweep_rot = 1;
-        }
-        rc[tid] = c; rs[tid] = s; rt[tid] = t; rp[tid] = p; rq[tid] = q; rot_on[tid] = on;
-      }
-      __syncthreads();
-      {  // 2x2 tile update: tile (a, b), one per thread (IB*IB = 256 tiles)
-        const int a = tid / IB, b = tid % IB;
-        const int pa = rp[a], qa = rq[a], pb = rp[b], qb = rq[b];
-        if (rot_on[a] | rot_on[b]) {
-          if (a == b) {
-            const double t = rt[a], apq = A[pa][qa];
-            A[pa][pa] -= t * apq;
-            A[qa][qa] += t * apq;
-            A[pa][qa] = 0.0;
-            A[qa][pa] = 0.0;
-          } else {
-            const double ca = rc[a], sa = rs[a], cb = rc[b], sb = rs[b];
-            const double t00 = A[pa][pb], t01 = A[pa][qb], t10 = A[qa][pb], t11 = A[qa][qb];
-            const double u00 = ca * t00 - sa * t10, u01 = ca * t01 - sa * t11;
-            const double u10 = sa * t00 + ca * t10, u11 = sa * t01 + ca * t11;
-            A[pa][pb] = u00 * cb - u01 * sb;
-            A[pa][qb] = u00 * sb + u01 * cb;
-            A[qa][pb] = u10 * cb - u11 * sb;
-            A[qa][qb] = u10 * sb + u11 * cb;
-          }
-        }
-      }
-      for (int it = tid; it < IN * IB; it += blockDim.x) {  // Q <- Q * J (row i, pair b)
-        const int i = it / IB, b = it % IB;
-        if (rot_on[b]) {
-          const int pb = rp[b], qb = rq[b];
-          const double c = rc[b], s = rs[b];
-          const double x = Q[i][pb], y = Q[i][qb];
-          Q[i][pb] = c * x - s * y;
-          Q[i][qb] = s * x + c * y;
-        }
-      }
-      __syncthreads();
+  const int rounds = phase == 0 ? IB - 1 : IB;
+  constexpr int NT = (IB * IB) / 256;   // 2x2 tiles per thread
+  constexpr int NQ = (IN * IB) / 256;   // (row, pair) items of Q per thread
+  for (int s = 0; s < rounds; ++s) {
+    if (tid < IB) {
+      int p, q;
+      inner_pair(phase, s, tid, p, q);
+      double c, sn, t;
+      const bool on = rotation(A[p][p], A[q][q], A[p][q], floor_abs, c, sn, t);
+      rs.c[tid] = c;
+      rs.s[tid] = sn;
+      rs.t[tid] = t;
+      if (on) rs.any = 1;
     }
-    const int any = sweep_rot;
     __syncthreads();
-    if (!any) break;
-    if (tid == 0) *any_rot = 1;
+    {
+      int pa[NT], qa[NT], pb[NT], qb[NT];
+      double ca[NT], sa[NT], cb[NT], sb[NT], ta[NT];
+      double t00[NT], t01[NT], t10[NT], t11[NT];
+#pragma unroll
+      for (int x = 0; x < NT; ++x) {
+        const int id = tid + 256 * x;
+        const int a = id / IB, b = id % IB;
+        inner_pair(phase, s, a, pa[x], qa[x]);
+        inner_pair(phase, s, b, pb[x], qb[x]);
+        ca[x] = rs.c[a]; sa[x] = rs.s[a]; ta[x] = rs.t[a];
+        cb[x] = rs.c[b]; sb[x] = rs.s[b];
+        t00[x] = A[pa[x]][pb[x]]; t01[x] = A[pa[x]][qb[x]];
+        t10[x] = A[qa[x]][pb[x]]; t11[x] = A[qa[x]][qb[x]];
+      }
+      int qi[NQ], qp[NQ], qq[NQ];
+      double qc[NQ], qs[NQ], qx[NQ], qy[NQ];
+#pragma unroll
+      for (int x = 0; x < NQ; ++x) {
+        const int id = tid + 256 * x;
+        const int b = id % IB;
+        qi[x] = id / IB;
+        inner_pair(phase, s, b, qp[x], qq[x]);
+        qc[x] = rs.c[b]; qs[x] = rs.s[b];
+        qx[x] = Q[qi[x]][qp[x]]; qy[x] = Q[qi[x]][qq[x]];
+      }
+#pragma unroll
+      for (int x = 0; x < NT; ++x) {
+        const double u00 = ca[x] * t00[x] - sa[x] * t10[x], u01 = ca[x] * t01[x] - sa[x] * t11[x];
+        const double u10 = sa[x] * t00[x] + ca[x] * t10[x], u11 = sa[x] * t01[x] + ca[x] * t11[x];
+        double n00 = u00 * cb[x] - u01 * sb[x];
+        double n01 = u00 * sb[x] + u01 * cb[x];
+        double n10 = u10 * cb[x] - u11 * sb[x];
+        double n11 = u10 * sb[x] + u11 * cb[x];
+        if (pa[x] == pb[x]) {   // diagonal 2x2 tile: exact form of the annihilation
+          n00 = t00[x] - ta[x] * t01[x];
+          n11 = t11[x] + ta[x] * t01[x];
+          n01 = ta[x] != 0.0 ? 0.0 : t01[x];
+          n10 = n01;
+        }
+        A[pa[x]][pb[x]] = n00; A[pa[x]][qb[x]] = n01;
+        A[qa[x]][pb[x]] = n10; A[qa[x]][qb[x]] = n11;
+      }
+#pragma unroll
+      for (int x = 0; x < NQ; ++x) {
+        Q[qi[x]][qp[x]] = qc[x] * qx[x] - qs[x] * qy[x];
+        Q[qi[x]][qq[x]] = qs[x] * qx[x] + qc[x] * qy[x];
+      }
+    }
+    __syncthreads();
   }
-  __syncthreads();
 }
 
-// trace(A) -> floor = 1e-17 * |trace| (one block)
+// trace(A) -> floor = 1e-16 * |trace| (one block)
 __global__ void k_floor(const double* __restrict__ A, int N, double* __restrict__ floor_out) {
   __shared__ double red[256];
   double s = 0.0;
@@ -140,48 +180,54 @@ __global__ void k_floor(const double* __restrict__ A, int N, double* __restrict_
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) floor_out[0] = 1.0e-17 * red[0] + 1.0e-300;
+  if (threadIdx.x == 0) floor_out[0] = 1.0e-16 * red[0] + 1.0e-300;
 }
 
-// Whole problem fits one inner solve (N == IN).
+// Whole problem (N == IN) in one block: full sweeps until nothing rotates.
 __global__ void __launch_bounds__(256) k_jacobi_direct(double* __restrict__ A, double* __restrict__ V, int N,
-                                                       const double* __restrict__ floor_p, int max_sweeps,
+                                                       const double* __restrict__ floor_p, int warm, int max_sweeps,
                                                        int* __restrict__ sweeps_out) {
   __shared__ double sA[IN][LDS_LD];
   __shared__ double sQ[IN][LDS_LD];
-  __shared__ int any;
+  __shared__ RotShared rs;
   for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
     const int i = it / IN, j = it % IN;
     sA[i][j] = A[(size_t)i * N + j];
-    sQ[i][j] = (i == j) ? 1.0 : 0.0;
+    sQ[i][j] = warm ? V[(size_t)i * N + j] : (i == j ? 1.0 : 0.0);
   }
-  __syncthreads();
-  // run sweeps one at a time to count them
+  const double fl = floor_p[0];
   int sweeps = 0;
+  bool conv = false;
   for (; sweeps < max_sweeps; ++sweeps) {
-    inner_jacobi(sA, sQ, 1, floor_p[0], &any);
-    if (!any) break;
+    if (threadIdx.x == 0) rs.any = 0;
+    __syncthreads();
+    inner_phase(sA, sQ, 0, fl, rs);
+    inner_phase(sA, sQ, 1, fl, rs);
+    const int any = rs.any;
+    __syncthreads();
+    if (!any) {
+      conv = true;
+      break;
+    }
   }
   for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
     const int i = it / IN, j = it % IN;
     A[(size_t)i * N + j] = sA[i][j];
     V[(size_t)i * N + j] = sQ[i][j];
   }
-  if (threadIdx.x == 0) sweeps_out[0] = (sweeps < max_sweeps) ? sweeps + 1 : -1;
+  if (threadIdx.x == 0) sweeps_out[0] = conv ? sweeps + 1 : -1;
 }
 
-__device__ __forceinline__ int pair_global(int l, int I, int J) {
-  return l < IB ? I * IB + l : J * IB + (l - IB);
-}
+__device__ __forceinline__ int pair_global(int l, int I, int J) { return l < IB ? I * IB + l : J * IB + (l - IB); }
 
-// Outer round, step 1: one block per block pair; diagonalise the 2b x 2b
-// submatrix, write Q_pair.
-__global__ void __launch_bounds__(256) k_jacobi_pairs(const double* __restrict__ A, int N, int nb, int round,
+// Outer round, step 1: one block per block pair: rotate the cross pairs (and, in the
+// first round of a sweep, the pairs inside each block), write Q_pair.
+__global__ void __launch_bounds__(256) k_jacobi_pairs(double* __restrict__ A, int N, int nb, int round,
                                                       double* __restrict__ Qblk, const double* __restrict__ floor_p,
-                                                      int inner_sweeps, int* __restrict__ flag) {
+                                                      int* __restrict__ flag) {
   __shared__ double sA[IN][LDS_LD];
   __shared__ double sQ[IN][LDS_LD];
-  __shared__ int any;
+  __shared__ RotShared rs;
   int I, J;
   rr_pair(blockIdx.x, round, nb, I, J);
   for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
@@ -189,118 +235,174 @@ __global__ void __launch_bounds__(256) k_jacobi_pairs(const double* __restrict__
     sA[i][j] = A[(size_t)pair_global(i, I, J) * N + pair_global(j, I, J)];
     sQ[i][j] = (i == j) ? 1.0 : 0.0;
   }
+  if (threadIdx.x == 0) rs.any = 0;
   __syncthreads();
-  inner_jacobi(sA, sQ, inner_sweeps, floor_p[0], &any);
-  double* Qo = Qblk + (size_t)blockIdx.x * IN * IN;
-  for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) Qo[it] = sQ[it / IN][it % IN];
-  if (threadIdx.x == 0 && any) atomicOr(flag, 1);
+  const double fl = floor_p[0];
+  if (round == 0) inner_phase(sA, sQ, 0, fl, rs);
+  inner_phase(sA, sQ, 1, fl, rs);
+  // the rotated 2b x 2b block goes straight back (annihilated entries stay exactly 0;
+  // the apply step skips these diagonal tiles), and Q_pair to the workspace
+  double* Qo = Qblk + (size_t)blockIdx.x * (IN * IN + 1);
+  for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
+    const int i = it / IN, j = it % IN;
+    Qo[it] = sQ[i][j];
+    A[(size_t)pair_global(i, I, J) * N + pair_global(j, I, J)] = sA[i][j];
+  }
+  if (threadIdx.x == 0) Qo[IN * IN] = rs.any ? 1.0 : 0.0;   // per-pair "rotated" marker
+  if (threadIdx.x == 0 && rs.any) atomicOr(flag, 1);
 }
 
-// Outer round, step 2: apply J.  Blocks [0, npairs^2) update A tiles (pair a rows x
-// pair b cols); blocks [npairs^2, npairs^2 + (N/IN)*npairs) update V tiles
-// (32-row chunk x pair b cols).
+// 64x64x64 product on MFMA f64 by 4 waves (each a 32x32 quadrant of 2x2 16x16 blocks):
+//   out = opA(X) * Y   with opA(X)[i][k] = TRANS ? X[k][i] : X[i][k]   (X, Y in LDS)
+template <bool TRANS>
+__device__ __forceinline__ void mm64(const double (*X)[LDS_LD], const double (*Y)[LDS_LD], d4_t acc[2][2]) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+  const int li = lane & 15, lk = lane >> 4;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = (d4_t){0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+  for (int k0 = 0; k0 < IN; k0 += 4) {
+    double a[2], b[2];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi) {
+      const int i = wi + bi * 16 + li;
+      a[bi] = TRANS ? X[k0 + lk][i] : X[i][k0 + lk];
+    }
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj) b[bj] = Y[k0 + lk][wj + bj * 16 + li];
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+  }
+}
+
+// writes the accumulators (output layout: register v of lane l = row 4v + l/16, col l%16)
+template <typename F>
+__device__ __forceinline__ void mm64_store(const d4_t acc[2][2], F&& put) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
+#pragma unroll
+  for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+    for (int bj = 0; bj < 2; ++bj)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) put(wi + bi * 16 + 4 * v + (lane >> 4), wj + bj * 16 + (lane & 15), acc[bi][bj][v]);
+}
+
+// Outer round, step 2: apply J.  Blocks [0, ntri) update A tiles (a < b, mirrored;
+// the diagonal tiles a == b were written by the pair step); blocks
+// [ntri, ntri + (N/IN)*npairs) update V tiles (IN-row chunk x pair b cols).
+// Tiles whose two factors are both the identity are skipped.
 __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, double* __restrict__ V, int N, int nb,
-                                                      int round, const double* __restrict__ Qblk,
-                                                      const int* __restrict__ flag) {
+                                                      int round, const double* __restrict__ Qblk) {
   __shared__ double sT[IN][LDS_LD];
-  __shared__ double sU[IN][LDS_LD];
-  __shared__ double sQa[IN][LDS_LD];
-  __shared__ double sQb[IN][LDS_LD];
+  __shared__ double sQ[IN][LDS_LD];
   const int npairs = nb / 2;
+  const int ntri = npairs * (npairs - 1) / 2;
   const int tid = threadIdx.x;
   int bid = blockIdx.x;
-  if (bid < npairs * npairs) {
-    const int a = bid / npairs, b = bid % npairs;
+  d4_t acc[2][2];
+  if (bid < ntri) {
+    int a = 0, rem = bid;   // strictly upper pairs (a < b), row by row
+    while (rem >= npairs - 1 - a) {
+      rem -= npairs - 1 - a;
+      ++a;
+    }
+    const int b = a + 1 + rem;
+    const double* Qa = Qblk + (size_t)a * (IN * IN + 1);
+    const double* Qb = Qblk + (size_t)b * (IN * IN + 1);
+    const bool rot_a = Qa[IN * IN] != 0.0, rot_b = Qb[IN * IN] != 0.0;
+    if (!rot_a && !rot_b) return;
     int Ia, Ja, Ib, Jb;
     rr_pair(a, round, nb, Ia, Ja);
     rr_pair(b, round, nb, Ib, Jb);
-    const double* Qa = Qblk + (size_t)a * IN * IN;
-    const double* Qb = Qblk + (size_t)b * IN * IN;
-    for (int it = tid; it < IN * IN; it += blockDim.x) {
+    for (int it = tid; it < IN * IN; it += 256) {
       const int i = it / IN, j = it % IN;
       sT[i][j] = A[(size_t)pair_global(i, Ia, Ja) * N + pair_global(j, Ib, Jb)];
-      sQa[i][j] = Qa[it];
-      sQb[i][j] = Qb[it];
+      sQ[i][j] = Qa[it];
     }
     __syncthreads();
-    // U = Qa^T T
-    for (int it = tid; it < IN * IN; it += blockDim.x) {
-      const int i = it / IN, j = it % IN;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < IN; ++k) acc += sQa[k][i] * sT[k][j];
-      sU[i][j] = acc;
-    }
+    mm64<true>(sQ, sT, acc);   // U = Qa^T T
     __syncthreads();
-    // T' = U Qb
-    for (int it = tid; it < IN * IN; it += blockDim.x) {
-      const int i = it / IN, j = it % IN;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < IN; ++k) acc += sU[i][k] * sQb[k][j];
-      A[(size_t)pair_global(i, Ia, Ja) * N + pair_global(j, Ib, Jb)] = acc;
-    }
+    mm64_store(acc, [&](int i, int j, double v) { sT[i][j] = v; });
+    for (int it = tid; it < IN * IN; it += 256) sQ[it / IN][it % IN] = Qb[it];
+    __syncthreads();
+    mm64<false>(sT, sQ, acc);                      // T' = U Qb
+    mm64_store(acc, [&](int i, int j, double v) {
+      A[(size_t)pair_global(i, Ia, Ja) * N + pair_global(j, Ib, Jb)] = v;
+      A[(size_t)pair_global(j, Ib, Jb) * N + pair_global(i, Ia, Ja)] = v;
+    });
   } else {
-    bid -= npairs * npairs;
+    bid -= ntri;
     const int rb = bid / npairs, b = bid % npairs;
+    const double* Qb = Qblk + (size_t)b * (IN * IN + 1);
+    if (Qb[IN * IN] == 0.0) return;
     int Ib, Jb;
     rr_pair(b, round, nb, Ib, Jb);
-    const double* Qb = Qblk + (size_t)b * IN * IN;
-    for (int it = tid; it < IN * IN; it += blockDim.x) {
+    for (int it = tid; it < IN * IN; it += 256) {
       const int i = it / IN, j = it % IN;
       sT[i][j] = V[(size_t)(rb * IN + i) * N + pair_global(j, Ib, Jb)];
-      sQb[i][j] = Qb[it];
+      sQ[i][j] = Qb[it];
     }
     __syncthreads();
-    for (int it = tid; it < IN * IN; it += blockDim.x) {
-      const int i = it / IN, j = it % IN;
-      double acc = 0.0;
-#pragma unroll 8
-      for (int k = 0; k < IN; ++k) acc += sT[i][k] * sQb[k][j];
-      V[(size_t)(rb * IN + i) * N + pair_global(j, Ib, Jb)] = acc;
-    }
+    mm64<false>(sT, sQ, acc);
+    mm64_store(acc, [&](int i, int j, double v) { V[(size_t)(rb * IN + i) * N + pair_global(j, Ib, Jb)] = v; });
   }
-  (void)flag;
 }
 
 __global__ void k_identity(double* __restrict__ V, int N) {
-  size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)N * N) V[idx] = ((idx / N) == (idx % N)) ? 1.0 : 0.0;
 }
 
-// lam[i] = A_ii; perm[k] = i for the k-th largest among the first n (ties by index).
-__global__ void __launch_bounds__(1024) k_eig_sort(const double* __restrict__ A, int N, int n,
-                                                   double* __restrict__ lam, int* __restrict__ perm) {
-  for (int i = threadIdx.x; i < N; i += blockDim.x) lam[i] = A[(size_t)i * N + i];
+// lam[i] = A_ii (all N)
+__global__ void k_diag(const double* __restrict__ A, int N, double* __restrict__ lam) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N) lam[i] = A[(size_t)i * N + i];
+}
+
+// perm[k] = i for the k-th largest lam among the first n (ties by index); n..N-1 map
+// to themselves.  One thread per element, the n values staged in LDS.
+__global__ void __launch_bounds__(256) k_rank(const double* __restrict__ lam, int N, int n, int* __restrict__ perm) {
+  extern __shared__ double sl[];
+  for (int j = threadIdx.x; j < n; j += blockDim.x) sl[j] = lam[j];
   __syncthreads();
-  for (int i = threadIdx.x; i < n; i += blockDim.x) {
-    const double li = lam[i];
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) {
+    const double li = sl[i];
     int rank = 0;
     for (int j = 0; j < n; ++j) {
-      const double lj = lam[j];
+      const double lj = sl[j];
       rank += (lj > li) || (lj == li && j < i);
     }
     perm[rank] = i;
+  } else if (i < N) {
+    perm[i] = i;
   }
-  for (int i = n + threadIdx.x; i < N; i += blockDim.x) perm[i] = i;
 }
 
 }  // namespace
 
 size_t eig_workspace_bytes(int N) {
-  const int nb = N / IB;
-  const size_t npairs = nb / 2;
-  return align256(npairs * IN * IN * sizeof(double)) + 256 + 256;
+  const size_t npairs = (size_t)(N / IB) / 2;
+  return align256(std::max<size_t>(npairs, 1) * (IN * IN + 1) * sizeof(double)) +
+         align256((size_t)N * N * sizeof(double)) + 256 + 256;
 }
 
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws, hipStream_t stream,
-            int* sweeps_out) {
+            int* sweeps_out, bool warm) {
   if (N % IN != 0 || n > N || n < 1) return MLPCP_E_INVALID_ARG;
   char* w = static_cast<char*>(ws);
   const int nb = N / IB;
   const int npairs = nb / 2;
   double* Qblk = reinterpret_cast<double*>(w);
-  w += align256((size_t)npairs * IN * IN * sizeof(double));
+  w += align256((size_t)std::max(npairs, 1) * (IN * IN + 1) * sizeof(double));
+  double* tmp = reinterpret_cast<double*>(w);
+  w += align256((size_t)N * N * sizeof(double));
   double* floor_p = reinterpret_cast<double*>(w);
   int* flag = reinterpret_cast<int*>(w + 128);
   int* dsweeps = reinterpret_cast<int*>(w + 192);
@@ -308,25 +410,29 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
   {
     ProfScope ps(KC_JACOBI_MISC, stream);
     hipLaunchKernelGGL(k_floor, dim3(1), dim3(256), 0, stream, A, N, floor_p);
+    if (warm) {
+      // A <- V0^T A V0 (V holds V0 and keeps it as the starting eigenvector basis)
+      MLPCP_TRY(gemm_f64(true, false, N, N, N, 1.0, V, N, A, N, tmp, N, stream));
+      MLPCP_TRY(gemm_f64(false, false, N, N, N, 1.0, tmp, N, V, N, A, N, stream));
+    } else if (N != IN) {
+      const size_t nn = (size_t)N * N;
+      hipLaunchKernelGGL(k_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, stream, V, N);
+    }
   }
   int sweeps = 0;
   if (N == IN) {
     {
       ProfScope ps(KC_JACOBI_PAIRS, stream);
-      hipLaunchKernelGGL(k_jacobi_direct, dim3(1), dim3(256), 0, stream, A, V, N, floor_p, kMaxEigSweeps,
-                         dsweeps);
+      hipLaunchKernelGGL(k_jacobi_direct, dim3(1), dim3(256), 0, stream, A, V, N, floor_p, warm ? 1 : 0,
+                         kMaxEigSweeps, dsweeps);
     }
     MLPCP_HIP(hipGetLastError());
     MLPCP_HIP(hipMemcpyAsync(&sweeps, dsweeps, sizeof(int), hipMemcpyDeviceToHost, stream));
     MLPCP_HIP(hipStreamSynchronize(stream));
     if (sweeps < 0) return MLPCP_E_EIG;
   } else {
-    const size_t nn = (size_t)N * N;
-    {
-      ProfScope ps(KC_JACOBI_MISC, stream);
-      hipLaunchKernelGGL(k_identity, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, stream, V, N);
-    }
-    const int apply_blocks = npairs * npairs + (N / IN) * npairs;
+    const int ntri = npairs * (npairs - 1) / 2;
+    const int apply_blocks = ntri + (N / IN) * npairs;
     bool converged = false;
     int hflag = 0;
     for (sweeps = 1; sweeps <= kMaxEigSweeps; ++sweeps) {
@@ -334,13 +440,11 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
       for (int r = 0; r < nb - 1; ++r) {
         {
           ProfScope ps(KC_JACOBI_PAIRS, stream);
-          hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(256), 0, stream, A, N, nb, r, Qblk, floor_p, 1,
-                             flag);
+          hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(256), 0, stream, A, N, nb, r, Qblk, floor_p, flag);
         }
         {
           ProfScope ps(KC_JACOBI_APPLY, stream);
-          hipLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, A, V, N, nb, r, Qblk,
-                             flag);
+          hipLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, A, V, N, nb, r, Qblk);
         }
       }
       MLPCP_HIP(hipGetLastError());
@@ -355,7 +459,9 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
   }
   {
     ProfScope ps(KC_JACOBI_MISC, stream);
-    hipLaunchKernelGGL(k_eig_sort, dim3(1), dim3(1024), 0, stream, A, N, n, lam, perm);
+    hipLaunchKernelGGL(k_diag, dim3((N + 255) / 256), dim3(256), 0, stream, A, N, lam);
+    hipLaunchKernelGGL(k_rank, dim3((N + 255) / 256), dim3(256), (size_t)n * sizeof(double), stream, lam, N, n,
+                       perm);
   }
   MLPCP_HIP(hipGetLastError());
   if (sweeps_out) *sweeps_out = sweeps;

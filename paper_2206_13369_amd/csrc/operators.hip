@@ -184,7 +184,7 @@ int build_operator(int n, int levels, hipStream_t stream, Operator* op) {
   if (st == MLPCP_OK && hipMemcpyAsync(dA, PtP.data(), nn * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
     st = MLPCP_E_HIP;
   int sweeps = 0;
-  if (st == MLPCP_OK) st = eig_sym(nH, N, dA, dV, dlam, dperm, ews, stream, &sweeps);
+  if (st == MLPCP_OK) st = eig_sym(nH, N, dA, dV, dlam, dperm, ews, stream, &sweeps, false);
   if (st == MLPCP_OK) {
     const size_t cnt = (size_t)nH * nH;
     hipLaunchKernelGGL(k_scale_cols_invsqrt, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, dV, dlam,

@@ -1,6 +1,6 @@
-// Optional kernel timing: HIP events recorded on the launching stream around each
-// kernel of the solver, accumulated per kernel class.  Off by default; when off the
-// hooks cost one relaxed atomic load.
+// Optional kernel timing: HIP events recorded on the launching stream around the
+// kernels of the selected classes, accumulated per class.  Off by default; when off
+// the hooks cost one relaxed atomic load.
 #include "profile.h"
 
 #include <atomic>
@@ -19,7 +19,7 @@ struct Pending {
   hipEvent_t a, b;
 };
 
-std::atomic<int> g_on{0};
+std::atomic<int> g_mask{0};
 std::mutex g_mu;
 std::vector<Pending> g_pending;
 std::vector<hipEvent_t> g_pool;
@@ -42,7 +42,7 @@ hipEvent_t get_event() {
 }  // namespace
 
 void prof_begin(int cls, hipStream_t s) {
-  if (!g_on.load(std::memory_order_relaxed)) return;
+  if (!((g_mask.load(std::memory_order_relaxed) >> cls) & 1)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t e = get_event();
   if (!e) return;
@@ -52,7 +52,7 @@ void prof_begin(int cls, hipStream_t s) {
 }
 
 void prof_end(int cls, hipStream_t s) {
-  if (!g_on.load(std::memory_order_relaxed) || t_start == nullptr || t_cls != cls) return;
+  if (!((g_mask.load(std::memory_order_relaxed) >> cls) & 1) || t_start == nullptr || t_cls != cls) return;
   std::lock_guard<std::mutex> lk(g_mu);
   hipEvent_t e = get_event();
   if (!e) return;
@@ -63,7 +63,7 @@ void prof_end(int cls, hipStream_t s) {
 }
 
 void prof_drain() {
-  if (!g_on.load(std::memory_order_relaxed)) return;
+  if (!g_mask.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_mu);
   for (const Pending& p : g_pending) {
     float ms = 0.0f;
@@ -83,14 +83,18 @@ using namespace mlpcp;
 
 extern "C" {
 
-int mlpcp_profile_enable(int on) {
+int mlpcp_profile_enable(int mask) {
   std::lock_guard<std::mutex> lk(g_mu);
   for (int i = 0; i < KC_COUNT; ++i) {
     g_launches[i] = 0;
     g_ms[i] = 0.0;
   }
+  for (const Pending& p : g_pending) {
+    g_pool.push_back(p.a);
+    g_pool.push_back(p.b);
+  }
   g_pending.clear();
-  g_on.store(on ? 1 : 0);
+  g_mask.store(mask);
   return MLPCP_OK;
 }
 

@@ -424,7 +424,7 @@ int valid_opts(const mlpcp_opts& o) {
 
 // One coarse SVT on M_P (buffer `mp`): Gram, C G C, eigensolve, weights, T.
 int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, double tau, hipStream_t s,
-               int* sweeps) {
+               int* sweeps, bool warm) {
   double* G = w.at<double>(p.off_G);
   double* V = w.at<double>(p.off_V);
   double* lam = w.at<double>(p.off_lam);
@@ -442,7 +442,7 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
   }
-  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps));
+  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps, warm));
   ProfScope ps(KC_SVT, s);
   hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, sw, st);
   const size_t tot = (size_t)p.nH * p.nH;
@@ -547,7 +547,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   int status = MLPCP_OK;
   for (t = 0; t < o.max_iter; ++t) {
     const double mu_next = std::min(o.rho * mu, mu_max);
-    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps));
+    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0));
     EpiArgs a{};
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
@@ -665,7 +665,7 @@ int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
   if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
   MLPCP_TRY(launch_init(p, *op, M, ldm, nullptr, nullptr, nullptr, 0.0f, mp, nullptr, s));
   int sweeps = 0;
-  MLPCP_TRY(coarse_svt(p, *op, w, mp, (double)tau, s, &sweeps));
+  MLPCP_TRY(coarse_svt(p, *op, w, mp, (double)tau, s, &sweeps, false));
   EpiArgs a{};
   a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
   a.MPcur = mp; a.T = w.at<float>(p.off_T); a.Tt = w.at<float>(p.off_Tt);
