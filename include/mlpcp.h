@@ -122,7 +122,8 @@ int mlpcp_pcp_solve(int m, int n, const float* D, int ldd, float lambda, double 
  * P_Q[L + S] = P_Q[D], minimising ||L||_* + lambda ||P_Q S||_1, by the masked
  * (multilevel) inexact ALM: the sparse part is free off Q, so off Q the dual
  * stays zero and the coarse data carries the previous L.
- *  Q  m x n uint8 mask (ld = n): nonzero = observed.  D off Q is never read.
+ *  Q  m x n uint8 mask (ld = n): nonzero = observed.  D off Q is ignored (its
+ *     values never reach the result; the memory must still be readable).
  * Outputs: L is the completed low-rank estimate (all entries); S and Y are
  * zero off Q.  Other arguments as mlpcp_pcp_solve; S0 and Y0 off Q are ignored.
  * With Q all ones the result equals mlpcp_pcp_solve's.                       */

@@ -41,6 +41,7 @@ inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 struct Operator {
   int n = 0, levels = 0, nH = 0;
   int max_col_nnz = 0;
+  int nnz = 0;                // nonzeros of P
   int* row_idx = nullptr;     // [n * kMaxStencil]
   float* row_w = nullptr;     // [n * kMaxStencil]
   int* col_ptr = nullptr;     // [nH + 1]

@@ -117,52 +117,55 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
     }
     __syncthreads();
     {
-      int pa[NT], qa[NT], pb[NT], qb[NT];
-      double ca[NT], sa[NT], cb[NT], sb[NT], ta[NT];
+      // tiles: this thread's NT tiles share the row pair a (params loaded once)
+      const int a = tid / (IB / NT);
+      int pa, qa;
+      inner_pair(phase, s, a, pa, qa);
+      const double ca = rs.c[a], sa = rs.s[a], ta = rs.t[a];
+      int pb[NT], qb[NT];
+      double cb[NT], sb[NT];
       double t00[NT], t01[NT], t10[NT], t11[NT];
 #pragma unroll
       for (int x = 0; x < NT; ++x) {
-        const int id = tid + 256 * x;
-        const int a = id / IB, b = id % IB;
-        inner_pair(phase, s, a, pa[x], qa[x]);
+        const int b = (tid % (IB / NT)) * NT + x;
         inner_pair(phase, s, b, pb[x], qb[x]);
-        ca[x] = rs.c[a]; sa[x] = rs.s[a]; ta[x] = rs.t[a];
         cb[x] = rs.c[b]; sb[x] = rs.s[b];
-        t00[x] = A[pa[x]][pb[x]]; t01[x] = A[pa[x]][qb[x]];
-        t10[x] = A[qa[x]][pb[x]]; t11[x] = A[qa[x]][qb[x]];
+        t00[x] = A[pa][pb[x]]; t01[x] = A[pa][qb[x]];
+        t10[x] = A[qa][pb[x]]; t11[x] = A[qa][qb[x]];
       }
-      int qi[NQ], qp[NQ], qq[NQ];
-      double qc[NQ], qs[NQ], qx[NQ], qy[NQ];
+      // Q items: this thread's NQ rows share the column pair b
+      const int bq = tid % IB;
+      int qp, qq;
+      inner_pair(phase, s, bq, qp, qq);
+      const double qc = rs.c[bq], qs = rs.s[bq];
+      double qx[NQ], qy[NQ];
 #pragma unroll
       for (int x = 0; x < NQ; ++x) {
-        const int id = tid + 256 * x;
-        const int b = id % IB;
-        qi[x] = id / IB;
-        inner_pair(phase, s, b, qp[x], qq[x]);
-        qc[x] = rs.c[b]; qs[x] = rs.s[b];
-        qx[x] = Q[qi[x]][qp[x]]; qy[x] = Q[qi[x]][qq[x]];
+        const int i = x * (256 / IB) + tid / IB;
+        qx[x] = Q[i][qp]; qy[x] = Q[i][qq];
       }
 #pragma unroll
       for (int x = 0; x < NT; ++x) {
-        const double u00 = ca[x] * t00[x] - sa[x] * t10[x], u01 = ca[x] * t01[x] - sa[x] * t11[x];
-        const double u10 = sa[x] * t00[x] + ca[x] * t10[x], u11 = sa[x] * t01[x] + ca[x] * t11[x];
+        const double u00 = ca * t00[x] - sa * t10[x], u01 = ca * t01[x] - sa * t11[x];
+        const double u10 = sa * t00[x] + ca * t10[x], u11 = sa * t01[x] + ca * t11[x];
         double n00 = u00 * cb[x] - u01 * sb[x];
         double n01 = u00 * sb[x] + u01 * cb[x];
         double n10 = u10 * cb[x] - u11 * sb[x];
         double n11 = u10 * sb[x] + u11 * cb[x];
-        if (pa[x] == pb[x]) {   // diagonal 2x2 tile: exact form of the annihilation
-          n00 = t00[x] - ta[x] * t01[x];
-          n11 = t11[x] + ta[x] * t01[x];
-          n01 = ta[x] != 0.0 ? 0.0 : t01[x];
+        if (pa == pb[x]) {   // diagonal 2x2 tile: exact form of the annihilation
+          n00 = t00[x] - ta * t01[x];
+          n11 = t11[x] + ta * t01[x];
+          n01 = ta != 0.0 ? 0.0 : t01[x];
           n10 = n01;
         }
-        A[pa[x]][pb[x]] = n00; A[pa[x]][qb[x]] = n01;
-        A[qa[x]][pb[x]] = n10; A[qa[x]][qb[x]] = n11;
+        A[pa][pb[x]] = n00; A[pa][qb[x]] = n01;
+        A[qa][pb[x]] = n10; A[qa][qb[x]] = n11;
       }
 #pragma unroll
       for (int x = 0; x < NQ; ++x) {
-        Q[qi[x]][qp[x]] = qc[x] * qx[x] - qs[x] * qy[x];
-        Q[qi[x]][qq[x]] = qs[x] * qx[x] + qc[x] * qy[x];
+        const int i = x * (256 / IB) + tid / IB;
+        Q[i][qp] = qc * qx[x] - qs * qy[x];
+        Q[i][qq] = qs * qx[x] + qc * qy[x];
       }
     }
     __syncthreads();

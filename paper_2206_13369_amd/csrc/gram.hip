@@ -78,22 +78,31 @@ __global__ void __launch_bounds__(256) k_gram_partial(const float* __restrict__ 
   }
 }
 
-__global__ void k_gram_reduce(const double* __restrict__ part, int splits, int kp, double* __restrict__ G) {
-  const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (idx >= (size_t)kp * kp) return;
-  const int i = (int)(idx / kp), j = (int)(idx % kp);
-  const int lo = min(i, j), hi = max(i, j);
-  const size_t off = (size_t)lo * kp + hi;
+// G[i][j] = sum over splits of the upper-triangle partial (i<=j mirrored), in a fixed
+// order: 64 outputs per block, 4 thread groups each summing every 4th split, then the
+// 4 group sums added in order.
+__global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ part, int splits, int kp,
+                                                     double* __restrict__ G) {
+  __shared__ double red[4][64];
+  const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const size_t idx = (size_t)blockIdx.x * 64 + e;
+  const size_t total = (size_t)kp * kp;
   double s = 0.0;
-  for (int q = 0; q < splits; ++q) s += part[(size_t)q * kp * kp + off];
-  G[idx] = s;
+  if (idx < total) {
+    const int i = (int)(idx / kp), j = (int)(idx % kp);
+    const size_t off = (size_t)min(i, j) * kp + max(i, j);
+    for (int q = g; q < splits; q += 4) s += part[(size_t)q * total + off];
+  }
+  red[g][e] = s;
+  __syncthreads();
+  if (g == 0 && idx < total) G[idx] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
 void gram_plan(int m, int kp, int& splits, int& rows_per_split) {
   const int nt = kp / GT;
   const int pairs = nt * (nt + 1) / 2;
-  int sp = (1024 + pairs - 1) / pairs;
-  const int max_by_rows = (m + 63) / 64;
+  int sp = (768 + pairs - 1) / pairs;
+  const int max_by_rows = (m + 511) / 512;
   if (sp > max_by_rows) sp = max_by_rows;
   const size_t cap = (size_t)64 << 20;
   const size_t per = (size_t)kp * kp * sizeof(double);
@@ -125,7 +134,7 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
   ProfScope ps(KC_GRAM, stream);
   hipLaunchKernelGGL(k_gram_partial, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
   const size_t nn = (size_t)kp * kp;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 255) / 256)), dim3(256), 0, stream, part, sp, kp, G);
+  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, stream, part, sp, kp, G);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }

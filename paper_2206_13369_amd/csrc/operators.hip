@@ -153,6 +153,13 @@ int build_operator(int n, int levels, hipStream_t stream, Operator* op) {
   int mx = 0;
   for (int c = 0; c < nH; ++c) mx = std::max(mx, cp[c + 1] - cp[c]);
   op->max_col_nnz = mx;
+  op->nnz = cp[nH];
+  {  // the kernels read exactly kMaxStencil weights per fine row
+    std::vector<int> row_cnt(n, 0);
+    for (int t = 0; t < op->nnz; ++t) ++row_cnt[cr[t]];
+    for (int j = 0; j < n; ++j)
+      if (row_cnt[j] > kMaxStencil) return MLPCP_E_UNSUPPORTED;
+  }
   MLPCP_TRY(upload(ri, &op->row_idx));
   MLPCP_TRY(upload(rw, &op->row_w));
   MLPCP_TRY(upload(cp, &op->col_ptr));

@@ -8,15 +8,18 @@
 //   svt prep  sigma = sqrt(lam), r = #{sigma > tau}, w = (sigma - tau)/sigma,
 //             T = C V_r diag(sqrt w)  (n_H x r)
 //   epilogue  L_{t+1} = M_P T T^T P^T  (= U_H S_tau[Sigma_H] V_H^T R^T, the coarse SVT
-//             lifted back), then per element on Q:
-//                 E = D - L + Y_t/mu_t,  S = S_{lam/mu_t}[E],  Y_{t+1} = clamp(mu_t E, +-lam)
-//             (the dual update Y_t + mu_t (D - L - S) written in closed form), the
-//             feasibility-gap partial sum of (D - L - S)^2, and the next coarse data
-//             X_{t+1} = D - S + Y_{t+1}/mu_{t+1}; off Q, X_{t+1} = L_{t+1} and S = Y = 0.
-//             X_{t+1} is restricted (X_{t+1} P) in the same pass.
-// State between iterations: one m x n float32 matrix Z holding E on Q and L off Q
-// (S and Y are functions of E and mu), kept in the caller's S buffer, plus M_P.  A final
-// pass recomputes L from the last coarse factors and writes L, S and Y.
+//             lifted back), then per element on Q, with E = D - L + Y_t/mu_t:
+//                 S = S_{lam/mu_t}[E],  Y_{t+1} = mu_t clip(E, lam/mu_t)
+//             (the dual update Y_t + mu_t (D - L - S) in closed form), the
+//             feasibility-gap partial sum of (D - L - S)^2 = (clip(E) - Y_t/mu_t)^2, and
+//             the next coarse data X_{t+1} = D - S + Y_{t+1}/mu_{t+1}; off Q,
+//             X_{t+1} = L_{t+1} and S = Y = 0.  X_{t+1} is restricted (X_{t+1} P) in the
+//             same pass.
+// State between iterations: one m x n float32 matrix holding W = E - D = -L + Y_t/mu_t
+// on Q and L off Q, kept in the caller's S buffer, plus M_P.  W is small where D carries
+// large corruptions, so the updates are written in terms of W and clip(D + W) and never
+// subtract two large float32 numbers.  A final pass recomputes L from the last coarse
+// factors and writes L, S = S[D + W] and Y.
 #include "common.h"
 #include "profile.h"
 
@@ -164,10 +167,12 @@ __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict_
 }
 
 // T[c][k] = sum_j C[c][j] V[j][perm[k]] * sw[k] (C = I when PLAIN), k < r;  Tt = T^T.
+// Kept in float64: L = (M_P T) T^T extracts a part of the coarse data that can be far
+// smaller than the data itself, so both the factor and the sums stay in float64.
 template <bool PLAIN>
 __global__ void k_build_T(int nH, int N, const double* __restrict__ C, const double* __restrict__ V,
                           const int* __restrict__ perm, const double* __restrict__ sw,
-                          const IterStats* __restrict__ st, float* __restrict__ T, float* __restrict__ Tt,
+                          const IterStats* __restrict__ st, double* __restrict__ T, double* __restrict__ Tt,
                           int ldT) {
   const int r = st->rank;
   const size_t total = (size_t)nH * r;
@@ -182,7 +187,7 @@ __global__ void k_build_T(int nH, int N, const double* __restrict__ C, const dou
       v = 0.0;
       for (int j = 0; j < nH; ++j) v += C[(size_t)c * nH + j] * V[(size_t)j * N + col];
     }
-    const float tv = (float)(v * sw[k]);
+    const double tv = v * sw[k];
     T[(size_t)c * ldT + k] = tv;
     Tt[(size_t)k * ldT + c] = tv;
   }
@@ -195,8 +200,8 @@ struct EpiArgs {
   const uint32_t* bits;
   const float* MPcur;
   float* MPnext;
-  const float* T;
-  const float* Tt;
+  const double* T;
+  const double* Tt;
   const IterStats* st;
   const float* Zin;   // state (E on Q, L off Q)
   float* Zout;        // may equal Zin
@@ -205,6 +210,9 @@ struct EpiArgs {
   float* Sout;        // FINAL (may equal Zin)
   float* Yout;        // FINAL (nullable)
   float mu, inv_mu, mu_prev, inv_mu_next, lam, thr;
+  float thr_prev;     // lam / mu_{t-1}
+  float ratio_prev;   // mu_{t-1} / mu_t
+  float grow;         // 1 + mu_t / mu_{t+1}
   int first;
   const int* row_idx;
   const float* row_w;
@@ -234,22 +242,22 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
     sMP[i * nHp + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
   }
   __syncthreads();
-  // 2. A = M_P T   (rows x r)
+  // 2. A = M_P T   (rows x r), float64 sums rounded once
   for (int e = tid; e < rows * r; e += kThreads) {
     const int i = e / r, k = e % r;
     const float* x = sMP + i * nHp;
-    float acc = 0.0f;
-    for (int c = 0; c < nH; ++c) acc = fmaf(x[c], a.T[(size_t)c * a.ldT + k], acc);
-    sA[i * nHp + k] = acc;
+    double acc = 0.0;
+    for (int c = 0; c < nH; ++c) acc = fma((double)x[c], a.T[(size_t)c * a.ldT + k], acc);
+    sA[i * nHp + k] = (float)acc;
   }
   __syncthreads();
   // 3. N = A T^T  (rows x nH), over the M_P panel
   for (int e = tid; e < rows * nH; e += kThreads) {
     const int i = e / nH, c = e % nH;
     const float* y = sA + i * nHp;
-    float acc = 0.0f;
-    for (int k = 0; k < r; ++k) acc = fmaf(y[k], a.Tt[(size_t)k * a.ldT + c], acc);
-    sMP[i * nHp + c] = acc;
+    double acc = 0.0;
+    for (int k = 0; k < r; ++k) acc = fma((double)y[k], a.Tt[(size_t)k * a.ldT + c], acc);
+    sMP[i * nHp + c] = (float)acc;
   }
   __syncthreads();
   // 4. fine elements
@@ -276,9 +284,9 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
     if (MODE == MODE_FINAL) {
       a.Lout[gij] = L;
       if (q) {
-        const float z = a.Zin[gij];
-        a.Sout[gij] = shrinkf(z, a.thr);
-        if (a.Yout) a.Yout[gij] = fminf(fmaxf(a.mu * z, -a.lam), a.lam);
+        const float e = a.D[(size_t)gi * a.ldd + j] + a.Zin[gij];   // E = D + W
+        a.Sout[gij] = shrinkf(e, a.thr);
+        if (a.Yout) a.Yout[gij] = fminf(fmaxf(a.mu * e, -a.lam), a.lam);
       } else {
         a.Sout[gij] = 0.0f;
         if (a.Yout) a.Yout[gij] = 0.0f;
@@ -287,21 +295,21 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
     }
     float x;
     if (q) {
+      // state W = E - D = -L + Y/mu (small), so no update below cancels large terms
       const float d = a.D[(size_t)gi * a.ldd + j];
-      float ym;
+      float ym;   // Y_t / mu_t
       if (a.first) {
         ym = a.Y0 ? a.Y0[gij] * a.inv_mu : 0.0f;
       } else {
-        ym = fminf(fmaxf(a.mu_prev * a.Zin[gij], -a.lam), a.lam) * a.inv_mu;
+        const float et = d + a.Zin[gij];                          // E_t
+        ym = fminf(fmaxf(et, -a.thr_prev), a.thr_prev) * a.ratio_prev;   // clip(E_t) mu_{t-1}/mu_t
       }
-      const float dl = d - L;
-      const float ev = dl + ym;
-      const float s = shrinkf(ev, a.thr);
-      const float res = dl - s;
+      const float wv = ym - L;                                    // W_{t+1}
+      const float c = fminf(fmaxf(d + wv, -a.thr), a.thr);        // clip(E_{t+1}, lam/mu_t)
+      const float res = c - ym;                                   // D - L - S
       racc += (double)res * (double)res;
-      a.Zout[gij] = ev;
-      const float ynext = fminf(fmaxf(a.mu * ev, -a.lam), a.lam);
-      x = d - s + ynext * a.inv_mu_next;
+      a.Zout[gij] = wv;
+      x = c * a.grow - wv;                                        // D - S + Y_{t+1}/mu_{t+1}
     } else {
       a.Zout[gij] = L;
       x = L;
@@ -318,6 +326,172 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
   }
   const double s = block_sum(racc, red);
   if (tid == 0) a.partial[blockIdx.x] = s;
+}
+
+// K = T T^T (n_H x n_H, float64, ld = ldK), the coarse SVT operator of the tall path:
+// L = M_P K P^T.  Entries beyond n_H are zero.
+__global__ void k_build_K(int nH, int ldK, const double* __restrict__ T, int ldT, const IterStats* __restrict__ st,
+                          double* __restrict__ K) {
+  const int r = st->rank;
+  const int idx = blockIdx.x * blockDim.x + threadIdx.x;
+  if (idx >= ldK * ldK) return;
+  const int c = idx / ldK, d = idx % ldK;
+  double acc = 0.0;
+  if (c < nH && d < nH)
+    for (int k = 0; k < r; ++k) acc = fma(T[(size_t)c * ldT + k], T[(size_t)d * ldT + k], acc);
+  K[idx] = acc;
+}
+
+// Epilogue for coarse widths n_H <= kTallNH (the tall, HBM-bound workloads).  A
+// persistent grid: each block stages K (float64) and the interpolation stencil in LDS
+// once, then loops over TM-row tiles: N = M_P K (float64 sums), L = N P^T, the
+// elementwise update (float4 accesses when VEC), and the restriction of the next
+// coarse data.  Same arithmetic as k_epilogue.
+constexpr int kTallNH = 64;
+
+template <int MODE, bool MASKED, bool VEC>
+__global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const double* __restrict__ K, int ntiles,
+                                                           int nnz) {
+  extern __shared__ double smd[];
+  __shared__ double red[kThreads];
+  const int n = a.n, nH = a.nH, TM = a.TM;
+  double* sK = smd;                                         // 64 x 64
+  float* sMP = reinterpret_cast<float*>(sK + kTallNH * kTallNH);   // TM x 64
+  float* sN = sMP + TM * kTallNH;                           // TM x 64
+  float* sX = sN + TM * kTallNH;                            // TM x n
+  int* sRi = reinterpret_cast<int*>(sX + (size_t)TM * n);   // n x 2
+  float* sRw = reinterpret_cast<float*>(sRi + 2 * n);       // n x 2
+  int* sCp = reinterpret_cast<int*>(sRw + 2 * n);           // nH + 1
+  int* sCr = sCp + (nH + 1);                                // nnz
+  float* sCw = reinterpret_cast<float*>(sCr + nnz);         // nnz
+  const int tid = threadIdx.x;
+  for (int e = tid; e < kTallNH * kTallNH; e += kThreads) sK[e] = K[e];
+  for (int e = tid; e < 2 * n; e += kThreads) {
+    sRi[e] = a.row_idx[e];
+    sRw[e] = a.row_w[e];
+  }
+  if (MODE == MODE_STEP) {
+    for (int e = tid; e <= nH; e += kThreads) sCp[e] = a.col_ptr[e];
+    for (int e = tid; e < nnz; e += kThreads) {
+      sCr[e] = a.col_row[e];
+      sCw[e] = a.col_w[e];
+    }
+  }
+  double racc = 0.0;
+  for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
+    const int i0 = tile * TM;
+    const int rows = min(TM, a.m - i0);
+    __syncthreads();
+    for (int e = tid; e < rows * nH; e += kThreads) {
+      const int i = e / nH, c = e % nH;
+      sMP[i * kTallNH + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
+    }
+    __syncthreads();
+    for (int e = tid; e < rows * nH; e += kThreads) {       // N = M_P K
+      const int i = e / nH, c = e % nH;
+      const float* x = sMP + i * kTallNH;
+      double acc = 0.0;
+      for (int cc = 0; cc < nH; ++cc) acc = fma((double)x[cc], sK[cc * kTallNH + c], acc);
+      sN[i * kTallNH + c] = (float)acc;
+    }
+    __syncthreads();
+    constexpr int V = VEC ? 4 : 1;
+    const int groups = rows * n / V;
+    for (int g = tid; g < groups; g += kThreads) {
+      const int e = g * V;
+      const int i = e / n, j0 = e % n;
+      const int gi = i0 + i;
+      float Lv[V], dv[V], zv[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const int j = j0 + v;
+        const float* nrow = sN + i * kTallNH;
+        Lv[v] = fmaf(sRw[2 * j + 1], nrow[sRi[2 * j + 1]], sRw[2 * j] * nrow[sRi[2 * j]]);
+      }
+      const size_t gij = (size_t)gi * n + j0;
+      if (MODE == MODE_RECON) {
+        if (VEC) {
+          *reinterpret_cast<float4*>(a.Lout + gij) = make_float4(Lv[0], Lv[V > 1 ? 1 : 0], Lv[V > 2 ? 2 : 0], Lv[V > 3 ? 3 : 0]);
+        } else {
+          a.Lout[gij] = Lv[0];
+        }
+        continue;
+      }
+      uint32_t qb = 0xFu;
+      if (MASKED) qb = (a.bits[(size_t)gi * a.nw + (j0 >> 5)] >> (j0 & 31)) & (VEC ? 0xFu : 1u);
+      if (VEC) {
+        const float4 d4 = *reinterpret_cast<const float4*>(a.D + (size_t)gi * a.ldd + j0);
+        dv[0] = d4.x; dv[V > 1 ? 1 : 0] = d4.y; dv[V > 2 ? 2 : 0] = d4.z; dv[V > 3 ? 3 : 0] = d4.w;
+        if (MODE == MODE_FINAL || !a.first) {
+          const float4 z4 = *reinterpret_cast<const float4*>(a.Zin + gij);
+          zv[0] = z4.x; zv[V > 1 ? 1 : 0] = z4.y; zv[V > 2 ? 2 : 0] = z4.z; zv[V > 3 ? 3 : 0] = z4.w;
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) zv[v] = 0.0f;
+        }
+      } else {
+        dv[0] = a.D[(size_t)gi * a.ldd + j0];
+        zv[0] = (MODE == MODE_FINAL || !a.first) ? a.Zin[gij] : 0.0f;
+      }
+      float o1[V], o2[V], o3[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const bool q = (qb >> v) & 1u;
+        if (MODE == MODE_FINAL) {
+          const float ev = dv[v] + zv[v];
+          o1[v] = Lv[v];
+          o2[v] = q ? shrinkf(ev, a.thr) : 0.0f;
+          o3[v] = q ? fminf(fmaxf(a.mu * ev, -a.lam), a.lam) : 0.0f;
+        } else {
+          float ym;
+          if (a.first) {
+            ym = a.Y0 ? a.Y0[gij + v] * a.inv_mu : 0.0f;
+          } else {
+            ym = fminf(fmaxf(dv[v] + zv[v], -a.thr_prev), a.thr_prev) * a.ratio_prev;
+          }
+          const float wv = ym - Lv[v];
+          const float c = fminf(fmaxf(dv[v] + wv, -a.thr), a.thr);
+          const float res = c - ym;
+          if (q) racc += (double)res * (double)res;
+          o1[v] = q ? wv : Lv[v];                   // next state
+          o2[v] = q ? c * a.grow - wv : Lv[v];      // next coarse data X_{t+1}
+        }
+      }
+      if (MODE == MODE_FINAL) {
+        if (VEC) {
+          *reinterpret_cast<float4*>(a.Lout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
+          *reinterpret_cast<float4*>(a.Sout + gij) = make_float4(o2[0], o2[V > 1 ? 1 : 0], o2[V > 2 ? 2 : 0], o2[V > 3 ? 3 : 0]);
+          if (a.Yout)
+            *reinterpret_cast<float4*>(a.Yout + gij) = make_float4(o3[0], o3[V > 1 ? 1 : 0], o3[V > 2 ? 2 : 0], o3[V > 3 ? 3 : 0]);
+        } else {
+          a.Lout[gij] = o1[0];
+          a.Sout[gij] = o2[0];
+          if (a.Yout) a.Yout[gij] = o3[0];
+        }
+      } else {
+        if (VEC)
+          *reinterpret_cast<float4*>(a.Zout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
+        else
+          a.Zout[gij] = o1[0];
+#pragma unroll
+        for (int v = 0; v < V; ++v) sX[(size_t)i * n + j0 + v] = o2[v];
+      }
+    }
+    if (MODE == MODE_STEP) {
+      __syncthreads();
+      for (int e = tid; e < rows * nH; e += kThreads) {    // restrict X_{t+1}
+        const int i = e / nH, c = e % nH;
+        const float* x = sX + (size_t)i * n;
+        float acc = 0.0f;
+        const int t1 = sCp[c + 1];
+        for (int t = sCp[c]; t < t1; ++t) acc = fmaf(sCw[t], x[sCr[t]], acc);
+        a.MPnext[(size_t)(i0 + i) * a.ldp + c] = acc;
+      }
+    }
+  }
+  if (MODE != MODE_STEP) return;
+  const double sum = block_sum(racc, red);
+  if (tid == 0) a.partial[blockIdx.x] = sum;
 }
 
 // sums partial[0..cnt) in a fixed order into *out
@@ -342,9 +516,25 @@ struct Plan {
   int m, n, nH, nHp, levels, TM, nblk, nw;
   bool plain, masked;
   size_t lds_epi, lds_init;
+  // tall path (n_H <= kTallNH, not plain): persistent grid over TM_tall-row tiles
+  bool tall;
+  int TM_tall, ntiles_tall, grid_tall, nnz;
+  size_t lds_tall;
   size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_perm, off_sw, off_T, off_Tt,
-      off_part, off_gram, off_eig, off_stats, total;
+      off_K, off_part, off_gram, off_eig, off_stats, total;
 };
+
+int device_cus() {
+  static int cached[64] = {0};
+  int dev = 0;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
+  if (!cached[dev]) {
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
+    cached[dev] = cus;
+  }
+  return cached[dev];
+}
 
 int make_plan(int m, int n, int levels, bool masked, Plan& p) {
   p.m = m;
@@ -364,6 +554,27 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p) {
   p.nblk = (m + TM - 1) / TM;
   p.lds_epi = (size_t)TM * per_row;
   p.lds_init = p.plain ? 0 : (size_t)TM * n * 4;
+  p.tall = !p.plain && p.nHp <= kTallNH;
+  p.nnz = 0;
+  p.TM_tall = 0;
+  p.ntiles_tall = 0;
+  p.grid_tall = 0;
+  p.lds_tall = 0;
+  if (p.tall) {
+    p.nnz = 2 * n;   // upper bound: at most two weights per fine row
+    const size_t fixed = (size_t)kTallNH * kTallNH * 8 + (size_t)16 * n + (size_t)4 * (p.nH + 1) + (size_t)8 * p.nnz;
+    const size_t per = (size_t)4 * (2 * kTallNH + n);
+    const size_t budget = 76 * 1024;   // two blocks per 160 KB CU
+    int tm = budget > fixed ? (int)((budget - fixed) / per) : 0;
+    if (tm > 16) tm = 16;
+    if (tm < 1) {
+      p.tall = false;
+    } else {
+      p.TM_tall = tm;
+      p.ntiles_tall = (m + tm - 1) / tm;
+      p.lds_tall = fixed + (size_t)tm * per;
+    }
+  }
   size_t off = 0;
   auto take = [&](size_t bytes) {
     const size_t o = off;
@@ -381,9 +592,10 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p) {
   p.off_lam = take((size_t)p.nHp * 8);
   p.off_perm = take((size_t)p.nHp * 4);
   p.off_sw = take((size_t)p.nHp * 8);
-  p.off_T = take(nn * 4);
-  p.off_Tt = take(nn * 4);
-  p.off_part = take((size_t)p.nblk * 8);
+  p.off_T = take(nn * 8);
+  p.off_Tt = take(nn * 8);
+  p.off_K = take(p.tall ? (size_t)kTallNH * kTallNH * 8 : 0);
+  p.off_part = take((size_t)std::max(p.nblk, 4096) * 8);
   p.off_gram = take(gram_workspace_bytes(m, p.nHp));
   p.off_eig = take(eig_workspace_bytes(p.nHp));
   p.off_stats = take(sizeof(IterStats));
@@ -430,8 +642,8 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   double* lam = w.at<double>(p.off_lam);
   int* perm = w.at<int>(p.off_perm);
   double* sw = w.at<double>(p.off_sw);
-  float* T = w.at<float>(p.off_T);
-  float* Tt = w.at<float>(p.off_Tt);
+  double* T = w.at<double>(p.off_T);
+  double* Tt = w.at<double>(p.off_Tt);
   IterStats* st = w.at<IterStats>(p.off_stats);
   MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.nHp, G, w.at<void>(p.off_gram), s));
   double* GH = G;
@@ -452,14 +664,45 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   else
     hipLaunchKernelGGL(k_build_T<false>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op.C, V, perm,
                        sw, st, T, Tt, p.nHp);
+  if (p.tall)
+    hipLaunchKernelGGL(k_build_K, dim3((kTallNH * kTallNH + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p.nH,
+                       kTallNH, T, p.nHp, st, w.at<double>(p.off_K));
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }
 
+bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
+
+template <int MODE, bool MASKED, bool VEC>
+int launch_tall_one(const Plan& p, const EpiArgs& a, const double* K, int nnz, int grid, hipStream_t s) {
+  auto fn = k_epilogue_tall<MODE, MASKED, VEC>;
+  MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                (int)p.lds_tall));
+  hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), p.lds_tall, s, a, K, p.ntiles_tall, nnz);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+// Launches the epilogue of the given mode; returns the number of FG partials written.
 template <int MODE>
-int launch_epilogue(const Plan& p, const EpiArgs& a, hipStream_t s) {
-  const dim3 g(p.nblk), b(kThreads);
+int launch_epilogue(const Plan& p, const EpiArgs& a, const double* K, int nnz, hipStream_t s, int* partials) {
   ProfScope ps(MODE == MODE_STEP ? KC_EPILOGUE : KC_FINAL, s);
+  if (p.tall) {
+    const int grid = std::min(p.ntiles_tall, 2 * device_cus());
+    *partials = grid;
+    const bool vec = (p.n % 4 == 0) && aligned16(a.Lout) && aligned16(a.Zin) && aligned16(a.Zout) &&
+                     aligned16(a.Sout) && aligned16(a.Yout) && (MODE == MODE_RECON || (a.ldd % 4 == 0 && aligned16(a.D)));
+    EpiArgs b = a;
+    b.TM = p.TM_tall;
+    if (vec) {
+      if (p.masked) return launch_tall_one<MODE, true, true>(p, b, K, nnz, grid, s);
+      return launch_tall_one<MODE, false, true>(p, b, K, nnz, grid, s);
+    }
+    if (p.masked) return launch_tall_one<MODE, true, false>(p, b, K, nnz, grid, s);
+    return launch_tall_one<MODE, false, false>(p, b, K, nnz, grid, s);
+  }
+  *partials = p.nblk;
+  const dim3 g(p.nblk), b(kThreads);
   if (p.plain) {
     if (p.masked)
       hipLaunchKernelGGL((k_epilogue<MODE, true, true>), g, b, p.lds_epi, s, a);
@@ -552,18 +795,20 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
     a.MPcur = mp[t & 1]; a.MPnext = mp[(t + 1) & 1];
-    a.T = w.at<float>(p.off_T); a.Tt = w.at<float>(p.off_Tt); a.st = st;
+    a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt); a.st = st;
     a.Zin = S; a.Zout = S; a.Y0 = Y0;
     a.mu = (float)mu; a.inv_mu = (float)(1.0 / mu); a.mu_prev = (float)mu_prev;
     a.inv_mu_next = (float)(1.0 / mu_next); a.lam = lambda; a.thr = (float)(lambda / mu);
+    a.thr_prev = (float)(lambda / mu_prev); a.ratio_prev = (float)(mu_prev / mu); a.grow = (float)(1.0 + mu / mu_next);
     a.first = (t == 0);
     a.row_idx = op->row_idx; a.row_w = op->row_w;
     a.col_ptr = op->col_ptr; a.col_row = op->col_row; a.col_w = op->col_w;
     a.partial = part;
-    MLPCP_TRY(launch_epilogue<MODE_STEP>(p, a, s));
+    int nparts = 0;
+    MLPCP_TRY(launch_epilogue<MODE_STEP>(p, a, w.at<double>(p.off_K), op->nnz, s, &nparts));
     {
       ProfScope ps(KC_REDUCE, s);
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, p.nblk, &st->fg2);
+      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, nparts, &st->fg2);
     }
     MLPCP_HIP(hipGetLastError());
     MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
@@ -595,11 +840,12 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
     a.MPcur = mp[last & 1]; a.MPnext = nullptr;
-    a.T = w.at<float>(p.off_T); a.Tt = w.at<float>(p.off_Tt); a.st = st;
+    a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt); a.st = st;
     a.Zin = S; a.Lout = L; a.Sout = S; a.Yout = Y;
     a.mu = (float)mu_last; a.lam = lambda; a.thr = (float)(lambda / mu_last);
     a.row_idx = op->row_idx; a.row_w = op->row_w;
-    MLPCP_TRY(launch_epilogue<MODE_FINAL>(p, a, s));
+    int nparts = 0;
+    MLPCP_TRY(launch_epilogue<MODE_FINAL>(p, a, w.at<double>(p.off_K), op->nnz, s, &nparts));
     MLPCP_HIP(hipStreamSynchronize(s));
     if (!converged) status = MLPCP_NOT_CONVERGED;
     mu = mu_last;
@@ -668,11 +914,12 @@ int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
   MLPCP_TRY(coarse_svt(p, *op, w, mp, (double)tau, s, &sweeps, false));
   EpiArgs a{};
   a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
-  a.MPcur = mp; a.T = w.at<float>(p.off_T); a.Tt = w.at<float>(p.off_Tt);
+  a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
   a.st = w.at<IterStats>(p.off_stats);
   a.Lout = L;
   a.row_idx = op->row_idx; a.row_w = op->row_w;
-  MLPCP_TRY(launch_epilogue<MODE_RECON>(p, a, s));
+  int nparts = 0;
+  MLPCP_TRY(launch_epilogue<MODE_RECON>(p, a, w.at<double>(p.off_K), op->nnz, s, &nparts));
   IterStats hs;
   MLPCP_HIP(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
   MLPCP_HIP(hipStreamSynchronize(s));
