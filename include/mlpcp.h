@@ -155,6 +155,34 @@ int mlpcp_restrict(int m, int n, const float* X, int ldx, int levels, float* XH,
 int mlpcp_prolong(int m, int n, const float* XH, int ldh, int levels, float* X, int ldx,
                   void* stream);
 
+/* ---- Differentiation form: one explicit iteration and its adjoint -------------
+ * One iteration of multilevel inexact ALM (Alg. 4; Alg. 1 at levels = 0) in the
+ * paper's explicit form, for unrolled (differentiable) solvers:
+ *   M = D - S + Y/mu;  L = SVT_{1/mu}(M R) R^T;  S' = S_{lam/mu}[D - L + Y/mu];
+ *   Y' = Y + mu (D - L - S').
+ *  D m x n (ldd); S, Y m x n (ld = n), NULL = zeros; L, S_next, Y_next outputs
+ *  m x n (ld = n); rank: optional host int.  Synchronises the stream.          */
+size_t mlpcp_step_workspace_bytes(int m, int n, int levels);
+int mlpcp_ialm_step(int m, int n, int levels, const float* D, int ldd, const float* S, const float* Y,
+                    float lambda, double mu, float* L, float* S_next, float* Y_next, int* rank,
+                    void* ws, size_t ws_bytes, void* stream);
+
+/* Vector-Jacobian product of mlpcp_ialm_step at (D, S, Y, lambda), mu held fixed.
+ * Recomputes the step internally (checkpoint/recompute), then propagates the output
+ * adjoints L_bar, S_bar, Y_bar (m x n, ld = n, NULL = zero) back:
+ *   D_bar      (m x n, ldd)  += dLoss/dD contribution of this step (accumulated),
+ *   S_bar_prev (m x n, ld n)  = dLoss/dS,   Y_bar_prev (m x n, ld n) = dLoss/dY,
+ *   *lambda_bar (host)       += dLoss/dlambda contribution (NULL = not wanted).
+ * The SVT adjoint is the derivative of the singular value thresholding map written
+ * in the coarse singular basis; dropped singular directions enter only through
+ * A v_j, so no coefficient divides by a small singular value and every coefficient
+ * is bounded (sigma_i > tau >= sigma_j).  The soft-threshold adjoint is the mask
+ * 1[|E| > lambda/mu] and, for lambda, -sign(E)/mu on that mask.  Synchronises.   */
+int mlpcp_ialm_step_vjp(int m, int n, int levels, const float* D, int ldd, const float* S, const float* Y,
+                        float lambda, double mu, const float* L_bar, const float* S_bar, const float* Y_bar,
+                        float* D_bar, float* S_bar_prev, float* Y_bar_prev, double* lambda_bar,
+                        void* ws, size_t ws_bytes, void* stream);
+
 /* Static description of a status code (never NULL).                          */
 const char* mlpcp_status_string(int status);
 

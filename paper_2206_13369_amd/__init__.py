@@ -35,7 +35,8 @@ MLPCP_E_UNSUPPORTED = -8
 EXPORTED = (
     "mlpcp_default_opts", "mlpcp_coarse_dim", "mlpcp_workspace_bytes", "mlpcp_pcp_solve",
     "mlpcp_cpcp_solve", "mlpcp_svt_prox", "mlpcp_shrink", "mlpcp_restrict", "mlpcp_prolong",
-    "mlpcp_status_string", "mlpcp_profile_enable", "mlpcp_profile_read",
+    "mlpcp_status_string", "mlpcp_profile_enable", "mlpcp_profile_read", "mlpcp_step_workspace_bytes",
+    "mlpcp_ialm_step", "mlpcp_ialm_step_vjp",
 )
 
 
@@ -101,6 +102,13 @@ def lib() -> ctypes.CDLL:
     L.mlpcp_profile_enable.restype = i
     L.mlpcp_profile_read.argtypes = [ctypes.POINTER(KernelTime), i]
     L.mlpcp_profile_read.restype = i
+    L.mlpcp_step_workspace_bytes.argtypes = [i, i, i]
+    L.mlpcp_step_workspace_bytes.restype = sz
+    L.mlpcp_ialm_step.argtypes = [i, i, i, vp, i, vp, vp, f, d, vp, vp, vp, ctypes.POINTER(i), vp, sz, vp]
+    L.mlpcp_ialm_step.restype = i
+    L.mlpcp_ialm_step_vjp.argtypes = [i, i, i, vp, i, vp, vp, f, d, vp, vp, vp, vp, vp, vp,
+                                      ctypes.POINTER(d), vp, sz, vp]
+    L.mlpcp_ialm_step_vjp.restype = i
     _lib = L
     return L
 
@@ -308,3 +316,52 @@ def prolong(XH, n: int, levels: int):
     if st < 0:
         raise MLPCPError(st, "prolong")
     return X
+
+
+# ---- differentiation form ------------------------------------------------------------
+
+def step_workspace(m: int, n: int, levels: int, device):
+    torch = _torch()
+    return torch.empty(max(int(lib().mlpcp_step_workspace_bytes(m, n, levels)), 1), dtype=torch.uint8,
+                       device=device)
+
+
+def ialm_step(D, S, Y, lam: float, mu: float, levels: int, workspace=None):
+    """One explicit (multilevel) inexact-ALM iteration; S, Y may be None (zeros).
+    Returns (L, S_next, Y_next, rank)."""
+    torch = _torch()
+    _check_dev(D, "D", torch.float32)
+    m, n = D.shape
+    L = torch.empty((m, n), dtype=torch.float32, device=D.device)
+    Sn = torch.empty_like(L)
+    Yn = torch.empty_like(L)
+    ws = workspace if workspace is not None else step_workspace(m, n, levels, D.device)
+    r = ctypes.c_int(0)
+    st = lib().mlpcp_ialm_step(m, n, levels, _ptr(D), D.stride(0), _ptr(S), _ptr(Y), float(lam), float(mu), _ptr(L),
+                               _ptr(Sn), _ptr(Yn), ctypes.byref(r), _ptr(ws), ws.numel(), _stream(D.device))
+    if st < 0:
+        raise MLPCPError(st, "ialm_step")
+    return L, Sn, Yn, r.value
+
+
+def ialm_step_vjp(D, S, Y, lam: float, mu: float, levels: int, L_bar, S_bar, Y_bar, D_bar, workspace=None):
+    """Adjoint of ialm_step: accumulates into D_bar, returns (S_bar_prev, Y_bar_prev, lambda_bar)."""
+    torch = _torch()
+    m, n = D.shape
+    Sbp = torch.empty((m, n), dtype=torch.float32, device=D.device)
+    Ybp = torch.empty_like(Sbp)
+    ws = workspace if workspace is not None else step_workspace(m, n, levels, D.device)
+    lb = ctypes.c_double(0.0)
+    st = lib().mlpcp_ialm_step_vjp(m, n, levels, _ptr(D), D.stride(0), _ptr(S), _ptr(Y), float(lam), float(mu),
+                                   _ptr(L_bar), _ptr(S_bar), _ptr(Y_bar), _ptr(D_bar), _ptr(Sbp), _ptr(Ybp),
+                                   ctypes.byref(lb), _ptr(ws), ws.numel(), _stream(D.device))
+    if st < 0:
+        raise MLPCPError(st, "ialm_step_vjp")
+    return Sbp, Ybp, lb.value
+
+
+def penalty_schedule(mu0: float, iters: int, rho: float = 1.5, mu_max_factor: float = 1e7):
+    mus = [float(mu0)]
+    for _ in range(iters - 1):
+        mus.append(min(rho * mus[-1], mu_max_factor * mu0))
+    return mus

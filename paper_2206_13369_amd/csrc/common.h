@@ -79,6 +79,10 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
 size_t gram_workspace_bytes(int m, int kp);
 int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
              hipStream_t stream);
+// G = A^T B (A, B m x k float32), float64 accumulation; uses at most
+// gram_workspace_bytes(m, kp) of workspace.
+int cross_f64(int m, int k, int kp, const float* A, int lda, const float* B, int ldb, double* G, void* ws,
+              hipStream_t stream);
 
 // ---- small dense float64 products (dense.hip) ----------------------------------------
 // C(MxN) = alpha * op(A) op(B), float64 row-major with explicit leading dimensions.

@@ -34,12 +34,20 @@ __device__ __forceinline__ void tri_decode(int p, int nt, int& ti, int& tj) {
   tj = ti + rem;
 }
 
+// CROSS = false: G = A^T A, tiles on/above the diagonal; CROSS = true: G = A^T B, all tiles
+template <bool CROSS>
 __global__ void __launch_bounds__(256) k_gram_partial(const float* __restrict__ A, int m, int k, int lda, int kp,
-                                                      int rows_per_split, int ntile, double* __restrict__ part) {
+                                                      int rows_per_split, int ntile, double* __restrict__ part,
+                                                      const float* __restrict__ B, int ldb) {
   __shared__ double sI[KC][GT + 1];
   __shared__ double sJ[KC][GT + 1];
   int ti, tj;
-  tri_decode(blockIdx.x, ntile, ti, tj);
+  if (CROSS) {
+    ti = blockIdx.x / ntile;
+    tj = blockIdx.x % ntile;
+  } else {
+    tri_decode(blockIdx.x, ntile, ti, tj);
+  }
   const int s = blockIdx.y;
   const int r0 = s * rows_per_split;
   const int r1 = min(m, r0 + rows_per_split);
@@ -57,7 +65,10 @@ __global__ void __launch_bounds__(256) k_gram_partial(const float* __restrict__ 
       const bool rok = gr < r1;
       const int gi = ci0 + col, gj = cj0 + col;
       sI[row][col] = (rok && gi < k) ? (double)A[(size_t)gr * lda + gi] : 0.0;
-      sJ[row][col] = (rok && gj < k) ? (double)A[(size_t)gr * lda + gj] : 0.0;
+      if (CROSS)
+        sJ[row][col] = (rok && gj < k) ? (double)B[(size_t)gr * ldb + gj] : 0.0;
+      else
+        sJ[row][col] = (rok && gj < k) ? (double)A[(size_t)gr * lda + gj] : 0.0;
     }
     __syncthreads();
 #pragma unroll
@@ -81,6 +92,7 @@ __global__ void __launch_bounds__(256) k_gram_partial(const float* __restrict__ 
 // G[i][j] = sum over splits of the upper-triangle partial (i<=j mirrored), in a fixed
 // order: 64 outputs per block, 4 thread groups each summing every 4th split, then the
 // 4 group sums added in order.
+template <bool CROSS>
 __global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ part, int splits, int kp,
                                                      double* __restrict__ G) {
   __shared__ double red[4][64];
@@ -90,7 +102,7 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ 
   double s = 0.0;
   if (idx < total) {
     const int i = (int)(idx / kp), j = (int)(idx % kp);
-    const size_t off = (size_t)min(i, j) * kp + max(i, j);
+    const size_t off = CROSS ? idx : (size_t)min(i, j) * kp + max(i, j);
     for (int q = g; q < splits; q += 4) s += part[(size_t)q * total + off];
   }
   red[g][e] = s;
@@ -98,9 +110,9 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ 
   if (g == 0 && idx < total) G[idx] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
-void gram_plan(int m, int kp, int& splits, int& rows_per_split) {
+void gram_plan(int m, int kp, int& splits, int& rows_per_split, bool cross = false) {
   const int nt = kp / GT;
-  const int pairs = nt * (nt + 1) / 2;
+  const int pairs = cross ? nt * nt : nt * (nt + 1) / 2;
   int sp = (768 + pairs - 1) / pairs;
   const int max_by_rows = (m + 511) / 512;
   if (sp > max_by_rows) sp = max_by_rows;
@@ -132,9 +144,26 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
   const int pairs = nt * (nt + 1) / 2;
   double* part = static_cast<double*>(ws);
   ProfScope ps(KC_GRAM, stream);
-  hipLaunchKernelGGL(k_gram_partial, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
+  hipLaunchKernelGGL(k_gram_partial<false>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part,
+                     nullptr, 0);
   const size_t nn = (size_t)kp * kp;
-  hipLaunchKernelGGL(k_gram_reduce, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, stream, part, sp, kp, G);
+  hipLaunchKernelGGL(k_gram_reduce<false>, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, stream, part, sp, kp, G);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+int cross_f64(int m, int k, int kp, const float* A, int lda, const float* B, int ldb, double* G, void* ws,
+              hipStream_t stream) {
+  if (kp % GT != 0 || k > kp) return MLPCP_E_INVALID_ARG;
+  int sp, rps;
+  gram_plan(m, kp, sp, rps, true);
+  const int nt = kp / GT;
+  double* part = static_cast<double*>(ws);
+  ProfScope ps(KC_OTHER, stream);
+  hipLaunchKernelGGL(k_gram_partial<true>, dim3(nt * nt, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part,
+                     B, ldb);
+  const size_t nn = (size_t)kp * kp;
+  hipLaunchKernelGGL(k_gram_reduce<true>, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, stream, part, sp, kp, G);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }

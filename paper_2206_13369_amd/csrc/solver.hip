@@ -861,6 +861,227 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   return status;
 }
 
+
+// ===================================================================================
+// Differentiation form: one explicit iteration of Alg. 4 (Alg. 1 at levels = 0) and
+// its vector-Jacobian product, for unrolled solvers.
+//
+// Step (penalty mu, tau = 1/mu, theta = lam/mu):
+//   M = D - S + Y/mu;  A = M R;  F = SVT_tau(A);  L = F R^T;
+//   E = D - L + Y/mu;  S' = S_theta[E];  Y' = Y + mu (D - L - S').
+// Adjoint, given Lb, S'b, Y'b:
+//   Yb += Y'b;  Db += mu Y'b;  Lb -= mu Y'b;  S'b -= mu Y'b
+//   Eb = S'b 1[|E| > theta];  lam_b -= sum(S'b sign(E) 1[|E| > theta]) / mu
+//   Db += Eb;  Lb -= Eb;  Yb += Eb/mu
+//   Fb = Lb R;  Ab = SVT-VJP(A, Fb);  Mb = Ab R^T
+//   Db += Mb;  Sb = -Mb;  Yb += Mb/mu
+// SVT-VJP with A = U diag(sigma) V^T, f = (sigma - tau)_+, kept set K = {sigma > tau},
+// dropped set D: with Phat = V^T A^T Fb V (so that U_i^T Fb V_j = Phat_ij / sigma_i),
+//   Ab = A V Omega V^T + Fb V diag(w) V^T,  w = f / sigma,
+//   Omega_ij (i, j in K)     = (M_ij - Gb_ij w_j) / sigma_i,
+//       Gb_ij = Phat_ij / sigma_i,  M_ij = sym(Gb)_ij + skew(Gb)_ij (f_i + f_j)/(sigma_i + sigma_j)
+//   Omega_ij (i in K, j in D) = Omega_ji = (sigma_i - tau)(Phat_ij + Phat_ji) / (sigma_i (sigma_i^2 - sigma_j^2))
+//   Omega_ij (i, j in D)     = 0.
+// This is the singular-value-function derivative (the SVT Jacobian) with every term in
+// a dropped left singular vector u_j rewritten through sigma_j u_j = A v_j: no division
+// by a small or zero sigma_j remains, and every coefficient is bounded because
+// sigma_i > tau >= sigma_j (the gap guard holds exactly).  With A = M_P C and
+// Fb = Fb_P C (Fb_P = Lb P), Phat = Tf^T (M_P^T Fb_P) Tf and
+// Mb P-side = M_P (Tf Omega Tf^T) + Fb_P (Tf diag(w) Tf^T), Tf = C V.
+
+__global__ void k_step_elem(int m, int n, const float* __restrict__ D, int ldd, const float* __restrict__ L,
+                            const float* __restrict__ Y, float mu, float inv_mu, float thr,
+                            float* __restrict__ Sn, float* __restrict__ Yn) {
+  const size_t total = (size_t)m * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / n;
+    const int j = (int)(idx % n);
+    const float d = D[i * ldd + j];
+    const float y = Y ? Y[idx] : 0.0f;
+    const float e = d - L[idx] + y * inv_mu;
+    const float sv = shrinkf(e, thr);
+    Sn[idx] = sv;
+    Yn[idx] = y + mu * (d - L[idx] - sv);
+  }
+}
+
+__global__ void __launch_bounds__(kThreads) k_vjp_elem1(int m, int n, const float* __restrict__ D, int ldd,
+                                                        const float* __restrict__ L, const float* __restrict__ Y,
+                                                        const float* __restrict__ Lb, const float* __restrict__ Sb,
+                                                        const float* __restrict__ Yb, float mu, float inv_mu,
+                                                        float thr, float* __restrict__ Ltot,
+                                                        float* __restrict__ Db, float* __restrict__ Yacc,
+                                                        double* __restrict__ lam_part) {
+  __shared__ double red[kThreads];
+  const size_t total = (size_t)m * n;
+  double lacc = 0.0;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / n;
+    const int j = (int)(idx % n);
+    const float d = D[i * ldd + j];
+    const float y = Y ? Y[idx] : 0.0f;
+    const float e = d - L[idx] + y * inv_mu;
+    const float yb = Yb ? Yb[idx] : 0.0f;
+    const float sb = (Sb ? Sb[idx] : 0.0f) - mu * yb;
+    const bool on = fabsf(e) > thr;
+    const float eb = on ? sb : 0.0f;
+    if (on) lacc -= (double)sb * (e > 0.0f ? 1.0 : -1.0) * (double)inv_mu;
+    Ltot[idx] = (Lb ? Lb[idx] : 0.0f) - mu * yb - eb;
+    Db[i * ldd + j] += mu * yb + eb;
+    Yacc[idx] = yb + eb * inv_mu;
+  }
+  const double t = block_sum(lacc, red);
+  if (threadIdx.x == 0) lam_part[blockIdx.x] = t;
+}
+
+__global__ void k_vjp_elem2(int m, int n, const float* __restrict__ Xb, float inv_mu, float* __restrict__ Db, int ldd,
+                            float* __restrict__ Sbp, float* __restrict__ Ybp) {
+  const size_t total = (size_t)m * n;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const size_t i = idx / n;
+    const int j = (int)(idx % n);
+    const float xb = Xb[idx];
+    Db[i * ldd + j] += xb;
+    Sbp[idx] = -xb;
+    Ybp[idx] = Ybp[idx] + xb * inv_mu;   // Ybp holds the accumulated Y adjoint on entry
+  }
+}
+
+// Tf[c][k] = sum_j C[c][j] V[j][perm[k]] (C = I when PLAIN), all k < nH; Tw = Tf diag(w)
+template <bool PLAIN>
+__global__ void k_build_Tf(int nH, int N, const double* __restrict__ C, const double* __restrict__ V,
+                           const int* __restrict__ perm, const double* __restrict__ lam, double tau,
+                           const IterStats* __restrict__ st, double* __restrict__ Tf, double* __restrict__ Tw) {
+  const int r = st->rank;
+  const size_t total = (size_t)nH * nH;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / nH), k = (int)(idx % nH);
+    const int col = perm[k];
+    double v;
+    if (PLAIN) {
+      v = V[(size_t)c * N + col];
+    } else {
+      v = 0.0;
+      for (int j = 0; j < nH; ++j) v += C[(size_t)c * nH + j] * V[(size_t)j * N + col];
+    }
+    const double sg = sqrt(fmax(lam[col], 0.0));
+    const double wk = (k < r && sg > 0.0) ? (sg - tau) / sg : 0.0;
+    Tf[(size_t)c * N + k] = v;
+    Tw[(size_t)c * N + k] = v * wk;
+  }
+}
+
+// Omega (sorted basis, nH x nH, ld N) from Phat, the singular values and tau.
+__global__ void k_vjp_coef(int nH, int N, const double* __restrict__ lam, const int* __restrict__ perm, double tau,
+                           const IterStats* __restrict__ st, const double* __restrict__ Ph,
+                           double* __restrict__ Om) {
+  const int r = st->rank;
+  const size_t total = (size_t)nH * nH;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / nH), j = (int)(idx % nH);
+    const double si = sqrt(fmax(lam[perm[i]], 0.0)), sj = sqrt(fmax(lam[perm[j]], 0.0));
+    const bool ki = i < r, kj = j < r;
+    const double pij = Ph[(size_t)i * N + j], pji = Ph[(size_t)j * N + i];
+    double o = 0.0;
+    if (ki && kj) {
+      const double gij = pij / si, gji = pji / sj;
+      const double fi = si - tau, fj = sj - tau;
+      const double cp = (fi + fj) / (si + sj);
+      const double mij = (i == j) ? gij : 0.5 * (gij + gji) + 0.5 * (gij - gji) * cp;
+      o = (mij - gij * (fj / sj)) / si;
+    } else if (ki) {
+      o = (si - tau) * (pij + pji) / (si * (si - sj) * (si + sj));
+    } else if (kj) {
+      o = (sj - tau) * (pij + pji) / (sj * (sj - si) * (sj + si));
+    }
+    Om[(size_t)i * N + j] = o;
+  }
+}
+
+// Out(m x k2) = In1 W1 + In2 W2 (float32 inputs, float64 weights and sums), one row per block
+__global__ void k_rmul2(int m, int k1, int k2, const float* __restrict__ In1, int ld1, const double* __restrict__ W1,
+                        const float* __restrict__ In2, int ld2, const double* __restrict__ W2, int ldw,
+                        float* __restrict__ Out, int ldo) {
+  const int row = blockIdx.x;
+  if (row >= m) return;
+  const float* x1 = In1 + (size_t)row * ld1;
+  const float* x2 = In2 + (size_t)row * ld2;
+  for (int col = threadIdx.x; col < k2; col += blockDim.x) {
+    double acc = 0.0;
+    for (int c = 0; c < k1; ++c)
+      acc += (double)x1[c] * W1[(size_t)c * ldw + col] + (double)x2[c] * W2[(size_t)c * ldw + col];
+    Out[(size_t)row * ldo + col] = (float)acc;
+  }
+}
+
+struct StepPlan {
+  Plan p;
+  size_t off_L, off_Ltot, off_Fb, off_Xbp, off_Xb, off_Z, off_Ph, off_Om, off_Tf, off_Tw, off_t1, off_WA, off_WF,
+      off_lp, total;
+  int lp_blocks;
+};
+
+int make_step_plan(int m, int n, int levels, StepPlan& sp) {
+  MLPCP_TRY(make_plan(m, n, levels, false, sp.p));
+  size_t off = sp.p.total;
+  auto take = [&](size_t bytes) {
+    const size_t o = off;
+    off += align256(bytes);
+    return o;
+  };
+  const size_t mn = (size_t)m * n, mh = (size_t)m * sp.p.nHp, nn = (size_t)sp.p.nHp * sp.p.nHp;
+  sp.off_L = take(mn * 4);
+  sp.off_Ltot = take(mn * 4);
+  sp.off_Fb = take(mh * 4);
+  sp.off_Xbp = take(mh * 4);
+  sp.off_Xb = take(mn * 4);
+  sp.off_Z = take(nn * 8);
+  sp.off_Ph = take(nn * 8);
+  sp.off_Om = take(nn * 8);
+  sp.off_Tf = take(nn * 8);
+  sp.off_Tw = take(nn * 8);
+  sp.off_t1 = take(nn * 8);
+  sp.off_WA = take(nn * 8);
+  sp.off_WF = take(nn * 8);
+  sp.lp_blocks = (int)grid_for(mn);
+  sp.off_lp = take((size_t)sp.lp_blocks * 8);
+  sp.total = off + 256;
+  return MLPCP_OK;
+}
+
+// Forward part shared by step and step_vjp: M_P, coarse SVT, L (into Lout).
+int step_forward_core(const StepPlan& sp, const Operator& op, const WS& w, const float* D, int ldd, const float* S,
+                      const float* Y, double mu, float* Lout, hipStream_t s) {
+  const Plan& p = sp.p;
+  float* mp = w.at<float>(p.off_mp0);
+  if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
+  MLPCP_TRY(launch_init(p, op, D, ldd, nullptr, S, Y, (float)(1.0 / mu), mp, nullptr, s));
+  int sweeps = 0;
+  MLPCP_TRY(coarse_svt(p, op, w, mp, 1.0 / mu, s, &sweeps, false));
+  EpiArgs a{};
+  a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+  a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
+  a.st = w.at<IterStats>(p.off_stats);
+  a.Lout = Lout;
+  a.row_idx = op.row_idx; a.row_w = op.row_w;
+  int nparts = 0;
+  MLPCP_TRY(launch_epilogue<MODE_RECON>(p, a, w.at<double>(p.off_K), op.nnz, s, &nparts));
+  return MLPCP_OK;
+}
+
+int step_args_ok(int m, int n, int levels, const float* D, int ldd, float lambda, double mu) {
+  if (m < 1 || n < 1 || m < n || ldd < n) return MLPCP_E_SHAPE;
+  if (!D) return MLPCP_E_INVALID_ARG;
+  if (!(lambda > 0.0f) || !std::isfinite(lambda) || !(mu > 0.0) || !std::isfinite(mu)) return MLPCP_E_INVALID_ARG;
+  if (coarse_dim_checked(n, levels) < 1) return MLPCP_E_LEVELS;
+  return MLPCP_OK;
+}
+
 }  // namespace
 
 }  // namespace mlpcp
@@ -924,6 +1145,131 @@ int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
   MLPCP_HIP(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
   MLPCP_HIP(hipStreamSynchronize(s));
   if (rank) *rank = hs.rank;
+  return MLPCP_OK;
+}
+
+}  // extern "C"
+
+extern "C" {
+
+size_t mlpcp_step_workspace_bytes(int m, int n, int levels) {
+  if (m < 1 || n < 1 || m < n) return 0;
+  StepPlan sp;
+  if (make_step_plan(m, n, levels, sp) != MLPCP_OK) return 0;
+  return sp.total;
+}
+
+int mlpcp_ialm_step(int m, int n, int levels, const float* D, int ldd, const float* S, const float* Y, float lambda,
+                    double mu, float* L, float* S_next, float* Y_next, int* rank, void* ws, size_t ws_bytes,
+                    void* stream) {
+  MLPCP_TRY(step_args_ok(m, n, levels, D, ldd, lambda, mu));
+  if (!L || !S_next || !Y_next) return MLPCP_E_INVALID_ARG;
+  StepPlan sp;
+  MLPCP_TRY(make_step_plan(m, n, levels, sp));
+  if (ws && ws_bytes < sp.total) return MLPCP_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Operator* op = nullptr;
+  MLPCP_TRY(get_operator(n, levels, s, &op));
+  WS w;
+  Plan tmp = sp.p;
+  tmp.total = sp.total;
+  MLPCP_TRY(bind_workspace(tmp, ws, ws_bytes, w));
+  MLPCP_TRY(step_forward_core(sp, *op, w, D, ldd, S, Y, mu, L, s));
+  hipLaunchKernelGGL(k_step_elem, dim3(grid_for((size_t)m * n)), dim3(kThreads), 0, s, m, n, D, ldd, L, Y,
+                     (float)mu, (float)(1.0 / mu), (float)(lambda / mu), S_next, Y_next);
+  MLPCP_HIP(hipGetLastError());
+  IterStats hs;
+  MLPCP_HIP(hipMemcpyAsync(&hs, w.at<IterStats>(sp.p.off_stats), sizeof(hs), hipMemcpyDeviceToHost, s));
+  MLPCP_HIP(hipStreamSynchronize(s));
+  if (rank) *rank = hs.rank;
+  return MLPCP_OK;
+}
+
+int mlpcp_ialm_step_vjp(int m, int n, int levels, const float* D, int ldd, const float* S, const float* Y,
+                        float lambda, double mu, const float* L_bar, const float* S_bar, const float* Y_bar,
+                        float* D_bar, float* S_bar_prev, float* Y_bar_prev, double* lambda_bar, void* ws,
+                        size_t ws_bytes, void* stream) {
+  MLPCP_TRY(step_args_ok(m, n, levels, D, ldd, lambda, mu));
+  if (!D_bar || !S_bar_prev || !Y_bar_prev) return MLPCP_E_INVALID_ARG;
+  StepPlan sp;
+  MLPCP_TRY(make_step_plan(m, n, levels, sp));
+  if (ws && ws_bytes < sp.total) return MLPCP_E_WORKSPACE;
+  const Plan& p = sp.p;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  const Operator* op = nullptr;
+  MLPCP_TRY(get_operator(n, levels, s, &op));
+  WS w;
+  Plan tmp = sp.p;
+  tmp.total = sp.total;
+  MLPCP_TRY(bind_workspace(tmp, ws, ws_bytes, w));
+  float* Lw = w.at<float>(sp.off_L);
+  // recompute the forward step
+  MLPCP_TRY(step_forward_core(sp, *op, w, D, ldd, S, Y, mu, Lw, s));
+  ProfScope ps(KC_OTHER, s);
+  const float inv_mu = (float)(1.0 / mu), thr = (float)(lambda / mu);
+  float* Ltot = w.at<float>(sp.off_Ltot);
+  double* lp = w.at<double>(sp.off_lp);
+  hipLaunchKernelGGL(k_vjp_elem1, dim3(sp.lp_blocks), dim3(kThreads), 0, s, m, n, D, ldd, Lw, Y, L_bar, S_bar, Y_bar,
+                     (float)mu, inv_mu, thr, Ltot, D_bar, Y_bar_prev, lp);
+  // Fb_P = Ltot P
+  const float* FbP = Ltot;
+  int ldF = n;
+  if (!p.plain) {
+    float* fb = w.at<float>(sp.off_Fb);
+    MLPCP_TRY(apply_P(*op, m, Ltot, n, fb, p.nHp, s));
+    FbP = fb;
+    ldF = p.nHp;
+  }
+  const float* MP = w.at<float>(p.off_mp0);
+  double* Z = w.at<double>(sp.off_Z);
+  MLPCP_HIP(hipMemsetAsync(Z, 0, (size_t)p.nHp * p.nHp * 8, s));
+  MLPCP_TRY(cross_f64(m, p.nH, p.nHp, MP, p.nHp, FbP, ldF, Z, w.at<void>(p.off_gram), s));
+  double* V = w.at<double>(p.off_V);
+  double* lam = w.at<double>(p.off_lam);
+  int* perm = w.at<int>(p.off_perm);
+  const IterStats* st = w.at<IterStats>(p.off_stats);
+  double* Tf = w.at<double>(sp.off_Tf);
+  double* Tw = w.at<double>(sp.off_Tw);
+  const size_t tot = (size_t)p.nH * p.nH;
+  if (p.plain)
+    hipLaunchKernelGGL(k_build_Tf<true>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op->C, V, perm, lam,
+                       1.0 / mu, st, Tf, Tw);
+  else
+    hipLaunchKernelGGL(k_build_Tf<false>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op->C, V, perm,
+                       lam, 1.0 / mu, st, Tf, Tw);
+  double* t1 = w.at<double>(sp.off_t1);
+  double* Ph = w.at<double>(sp.off_Ph);
+  const int h = p.nH, N = p.nHp;
+  MLPCP_TRY(gemm_f64(true, false, h, h, h, 1.0, Tf, N, Z, N, t1, N, s));     // Tf^T Z
+  MLPCP_TRY(gemm_f64(false, false, h, h, h, 1.0, t1, N, Tf, N, Ph, N, s));   // (Tf^T Z) Tf
+  double* Om = w.at<double>(sp.off_Om);
+  hipLaunchKernelGGL(k_vjp_coef, dim3(grid_for(tot)), dim3(kThreads), 0, s, h, N, lam, perm, 1.0 / mu, st, Ph, Om);
+  double* WA = w.at<double>(sp.off_WA);
+  double* WF = w.at<double>(sp.off_WF);
+  MLPCP_TRY(gemm_f64(false, false, h, h, h, 1.0, Tf, N, Om, N, t1, N, s));   // Tf Omega
+  MLPCP_TRY(gemm_f64(false, true, h, h, h, 1.0, t1, N, Tf, N, WA, N, s));    // (Tf Omega) Tf^T
+  MLPCP_TRY(gemm_f64(false, true, h, h, h, 1.0, Tw, N, Tf, N, WF, N, s));    // Tf diag(w) Tf^T
+  float* Xb = w.at<float>(sp.off_Xb);
+  if (p.plain) {
+    hipLaunchKernelGGL(k_rmul2, dim3(m), dim3(kThreads), 0, s, m, h, h, MP, p.nHp, WA, FbP, ldF, WF, N, Xb, n);
+  } else {
+    float* Xbp = w.at<float>(sp.off_Xbp);
+    hipLaunchKernelGGL(k_rmul2, dim3(m), dim3(kThreads), 0, s, m, h, h, MP, p.nHp, WA, FbP, ldF, WF, N, Xbp, p.nHp);
+    MLPCP_TRY(apply_Pt(*op, m, Xbp, p.nHp, Xb, n, s));
+  }
+  hipLaunchKernelGGL(k_vjp_elem2, dim3(grid_for((size_t)m * n)), dim3(kThreads), 0, s, m, n, Xb, inv_mu, D_bar, ldd,
+                     S_bar_prev, Y_bar_prev);
+  MLPCP_HIP(hipGetLastError());
+  if (lambda_bar) {
+    double* lsum = w.at<double>(p.off_part);
+    hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, lp, sp.lp_blocks, lsum);
+    double hl = 0.0;
+    MLPCP_HIP(hipMemcpyAsync(&hl, lsum, sizeof(double), hipMemcpyDeviceToHost, s));
+    MLPCP_HIP(hipStreamSynchronize(s));
+    *lambda_bar += hl;
+  } else {
+    MLPCP_HIP(hipStreamSynchronize(s));
+  }
   return MLPCP_OK;
 }
 
