@@ -56,6 +56,22 @@ typedef enum {
   MLPCP_E_UNSUPPORTED = -8    /* option outside the implemented set             */
 } mlpcp_status;
 
+/* Arithmetic of the two products of the coarse SVT (the precision form):
+ *   MLPCP_FP32    Gram M_P^T M_P from float32 operands with float64 products and sums;
+ *                 reconstruction N = M_P K summed in float64.
+ *   MLPCP_BF16X3  reconstruction in split bfloat16: x = hi + lo, each product taken
+ *                 as hi*hi + hi*lo + lo*hi on MFMA with float32 accumulation.  The
+ *                 Gram is split the same way while the threshold tau is far enough
+ *                 above the rounding floor of the split product (tau^2 / trace of the
+ *                 coarse Gram above a bound set by the unit roundoff and m, n_H), and
+ *                 takes the MLPCP_FP32 path below it, so the singular values near
+ *                 tau, which decide the rank, keep float32-data accuracy.
+ *   MLPCP_BF16    as MLPCP_BF16X3, with one more tier on top: the Gram operands are
+ *                 rounded to plain bfloat16 while tau is far above that rounding.
+ * The eigensolve, the threshold and the rank decision stay in float64, the
+ * elementwise update in float32.  The split reconstruction applies on the tall path
+ * (n_H <= 64, multilevel); wider coarse models keep float64 sums there.
+ * mlpcp_info reports how many iterations ran each reduced-precision Gram.       */
 typedef enum { MLPCP_FP32 = 0, MLPCP_BF16 = 1, MLPCP_BF16X3 = 2 } mlpcp_precision;
 
 /* Solver options.  Penalty schedule mu_{k+1} = min(rho mu_k, mu_max_factor * mu_0)
@@ -68,7 +84,7 @@ typedef struct {
   int max_iter;            /* > 0                                             */
   double rho;              /* penalty growth factor, >= 1                     */
   double mu_max_factor;    /* mu_max = mu_max_factor * mu_0, >= 1             */
-  int prec;                /* mlpcp_precision; MLPCP_FP32 is implemented      */
+  int prec;                /* mlpcp_precision (other values: E_INVALID_ARG)   */
   int check_every;         /* FG check cadence; 1 is implemented              */
   int r_norm;              /* restriction normalisation; 0 = orthonormal R    */
 } mlpcp_opts;
@@ -86,6 +102,8 @@ typedef struct {
   double* fg_history;      /* in: optional host array                         */
   int* rank_history;       /* in: optional host array                         */
   int history_len;         /* in: length of the two arrays                    */
+  int gram_bf16_iters;     /* iterations whose Gram ran in plain bfloat16     */
+  int gram_split_iters;    /* iterations whose Gram ran in split bfloat16     */
 } mlpcp_info;
 
 /* Fills defaults: levels 0, tol 1e-6, max_iter 500, rho 1.5, mu_max_factor 1e7,

@@ -50,7 +50,8 @@ class Info(ctypes.Structure):
     _fields_ = [("iters", ctypes.c_int), ("fg", ctypes.c_double), ("rank", ctypes.c_int),
                 ("mu_final", ctypes.c_double), ("tau_margin", ctypes.c_double), ("eig_sweeps", ctypes.c_int),
                 ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
-                ("history_len", ctypes.c_int)]
+                ("history_len", ctypes.c_int), ("gram_bf16_iters", ctypes.c_int),
+                ("gram_split_iters", ctypes.c_int)]
 
 
 class KernelTime(ctypes.Structure):
@@ -201,9 +202,23 @@ class SolveResult:
     eig_sweeps: int
     fg_history: list
     rank_history: list
+    gram_bf16_iters: int = 0
+    gram_split_iters: int = 0
 
 
-def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history):
+PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
+
+
+def _prec(p) -> int:
+    if isinstance(p, str):
+        if p not in PRECISIONS:
+            raise ValueError(f"precision must be one of {sorted(PRECISIONS)}")
+        return PRECISIONS[p]
+    return int(p)
+
+
+def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
+           prec="fp32"):
     torch = _torch()
     _check_dev(D, "D", torch.float32)
     if D.dim() != 2 or D.stride(1) != 1:
@@ -218,7 +233,8 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
             _check_dev(t, name, torch.float32)
             if not t.is_contiguous() or tuple(t.shape) != (m, n):
                 raise ValueError(f"{name} must be a contiguous m x n tensor")
-    o = default_opts(levels=levels, tol=tol, max_iter=max_iter, rho=rho, mu_max_factor=mu_max_factor)
+    o = default_opts(levels=levels, tol=tol, max_iter=max_iter, rho=rho, mu_max_factor=mu_max_factor,
+                     prec=_prec(prec))
     wsb = workspace_bytes(m, n, o)
     if workspace is None:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
@@ -249,21 +265,26 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
         raise MLPCPError(st, "cpcp_solve" if Q is not None else "pcp_solve")
     k = min(info.iters, history) if history else 0
     return SolveResult(L, S, Y, st, info.iters, info.fg, info.rank, info.mu_final, info.tau_margin, info.eig_sweeps,
-                       [fh[i] for i in range(k)] if history else [], [rh[i] for i in range(k)] if history else [])
+                       [fh[i] for i in range(k)] if history else [], [rh[i] for i in range(k)] if history else [],
+                       info.gram_bf16_iters, info.gram_split_iters)
 
 
 def pcp_solve(D, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
               rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
-              workspace=None, history: int = 0) -> SolveResult:
-    """Robust PCA by (multilevel) inexact ALM; D is an m x n float32 tensor on the GPU."""
-    return _solve(D, None, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history)
+              workspace=None, history: int = 0, prec="fp32") -> SolveResult:
+    """Robust PCA by (multilevel) inexact ALM; D is an m x n float32 tensor on the GPU.
+    prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products)."""
+    return _solve(D, None, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
+                  prec)
 
 
 def cpcp_solve(D, Q, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
                rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
-               workspace=None, history: int = 0) -> SolveResult:
-    """Compressive PCP (constrained form) by masked (multilevel) inexact ALM; Q uint8 mask."""
-    return _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history)
+               workspace=None, history: int = 0, prec="fp32") -> SolveResult:
+    """Compressive PCP (constrained form) by masked (multilevel) inexact ALM; Q uint8 mask.
+    prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products)."""
+    return _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
+                  prec)
 
 
 def svt_prox(M, tau: float, levels: int = 0, workspace=None):

@@ -31,6 +31,16 @@ constexpr int kMaxStencil = 2;         // nonzeros per fine row of the composite
 constexpr int kMaxEigSweeps = 40;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
+
+// bfloat16 helpers for the precision form: round-to-nearest-even split x = hi + lo
+__device__ __forceinline__ unsigned short f2bf(float x) {
+  uint32_t u = __float_as_uint(x);
+  u += 0x7FFFu + ((u >> 16) & 1u);
+  return (unsigned short)(u >> 16);
+}
+__device__ __forceinline__ float bf2f(unsigned short h) { return __uint_as_float((uint32_t)h << 16); }
+typedef __bf16 bf16x8_t __attribute__((ext_vector_type(8)));
+typedef float f32x4_t __attribute__((ext_vector_type(4)));
 inline size_t align256(size_t x) { return (x + 255) & ~size_t(255); }
 
 // Operator constants of the coarse model for one (n, levels) pair, on one device.
@@ -78,7 +88,7 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
 // in float64; G is kp x kp float64 (ld = kp), rows/cols >= k zero.
 size_t gram_workspace_bytes(int m, int kp);
 int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
-             hipStream_t stream);
+             hipStream_t stream, int prec = 0);
 // G = A^T B (A, B m x k float32), float64 accumulation; uses at most
 // gram_workspace_bytes(m, kp) of workspace.
 int cross_f64(int m, int k, int kp, const float* A, int lda, const float* B, int ldb, double* G, void* ws,

@@ -89,6 +89,75 @@ __global__ void __launch_bounds__(256) k_gram_partial(const float* __restrict__ 
   }
 }
 
+// Precision form of the Gram: operands rounded to bfloat16 (PREC 1) or split into
+// bfloat16 hi + lo parts with three products hi*hi + hi*lo + lo*hi (PREC 2), on
+// v_mfma_f32_16x16x32_bf16 with float32 accumulation over one 32-row chunk; the
+// chunk sums are added in float64 (the Gram's smallest eigenvalues are what a long
+// float32 running sum would lose), and the split partials by k_gram_reduce.  Operand layout of the
+// instruction: lane l holds A[l%16][8(l/16)+q] and B[8(l/16)+q][l%16], q < 8; the
+// output register v of lane l is row 4(l/16)+v, column l%16.
+constexpr int KB = 32;  // rows per LDS chunk (one MFMA k-step)
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_gram_partial_bf16(const float* __restrict__ A, int m, int k, int lda, int kp,
+                                                           int rows_per_split, int ntile, double* __restrict__ part) {
+  __shared__ float sI[KB][GT + 1];
+  __shared__ float sJ[KB][GT + 1];
+  int ti, tj;
+  tri_decode(blockIdx.x, ntile, ti, tj);
+  const int s = blockIdx.y;
+  const int r0 = s * rows_per_split;
+  const int r1 = min(m, r0 + rows_per_split);
+  const int tid = threadIdx.x;
+  const int wave = tid >> 6, lane = tid & 63;
+  const int bi = wave >> 1, bj = wave & 1;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  const int ci0 = ti * GT, cj0 = tj * GT;
+  for (int k0 = r0; k0 < r1; k0 += KB) {
+#pragma unroll
+    for (int x = 0; x < (KB * GT) / 256; ++x) {
+      const int e = tid + 256 * x;
+      const int row = e / GT, col = e % GT;
+      const int gr = k0 + row;
+      const bool rok = gr < r1;
+      const int gi = ci0 + col, gj = cj0 + col;
+      sI[row][col] = (rok && gi < k) ? A[(size_t)gr * lda + gi] : 0.0f;
+      sJ[row][col] = (rok && gj < k) ? A[(size_t)gr * lda + gj] : 0.0f;
+    }
+    __syncthreads();
+    bf16x8_t ah, bh, al, bl;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int kk = 8 * (lane >> 4) + q;
+      const float xa = sI[kk][bi * 16 + (lane & 15)];
+      const float xb = sJ[kk][bj * 16 + (lane & 15)];
+      const unsigned short ha = f2bf(xa), hb = f2bf(xb);
+      ah[q] = __builtin_bit_cast(__bf16, ha);
+      bh[q] = __builtin_bit_cast(__bf16, hb);
+      if (PREC == 2) {
+        al[q] = __builtin_bit_cast(__bf16, f2bf(xa - bf2f(ha)));
+        bl[q] = __builtin_bit_cast(__bf16, f2bf(xb - bf2f(hb)));
+      }
+    }
+    f32x4_t c = {0.0f, 0.0f, 0.0f, 0.0f};
+    if (PREC == 2) {
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, bh, c, 0, 0, 0);
+      c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bl, c, 0, 0, 0);
+    }
+    c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, bh, c, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) acc[v] += (double)c[v];
+    __syncthreads();
+  }
+  double* P = part + (size_t)s * kp * kp;
+  const int col = cj0 + bj * 16 + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int row = ci0 + bi * 16 + 4 * (lane >> 4) + v;
+    P[(size_t)row * kp + col] = acc[v];
+  }
+}
+
 // G[i][j] = sum over splits of the upper-triangle partial (i<=j mirrored), in a fixed
 // order: 64 outputs per block, 4 thread groups each summing every 4th split, then the
 // 4 group sums added in order.
@@ -136,7 +205,7 @@ size_t gram_workspace_bytes(int m, int kp) {
   return align256((size_t)sp * kp * kp * sizeof(double));
 }
 
-int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws, hipStream_t stream) {
+int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws, hipStream_t stream, int prec) {
   if (kp % GT != 0 || k > kp) return MLPCP_E_INVALID_ARG;
   int sp, rps;
   gram_plan(m, kp, sp, rps);
@@ -144,8 +213,13 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
   const int pairs = nt * (nt + 1) / 2;
   double* part = static_cast<double*>(ws);
   ProfScope ps(KC_GRAM, stream);
-  hipLaunchKernelGGL(k_gram_partial<false>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part,
-                     nullptr, 0);
+  if (prec == MLPCP_BF16)
+    hipLaunchKernelGGL(k_gram_partial_bf16<1>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
+  else if (prec == MLPCP_BF16X3)
+    hipLaunchKernelGGL(k_gram_partial_bf16<2>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
+  else
+    hipLaunchKernelGGL(k_gram_partial<false>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part,
+                       nullptr, 0);
   const size_t nn = (size_t)kp * kp;
   hipLaunchKernelGGL(k_gram_reduce<false>, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, stream, part, sp, kp, G);
   MLPCP_HIP(hipGetLastError());

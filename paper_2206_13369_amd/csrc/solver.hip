@@ -40,6 +40,7 @@ struct IterStats {
   double fg2;      // sum of squared residuals on Q
   double nrm2;     // ||P_Q D||_F^2 (init)
   double margin;   // min |sigma - tau| / tau
+  double trace;    // sum of the coarse eigenvalues (||M_H||_F^2)
   int rank;
   int pad;
 };
@@ -138,9 +139,11 @@ __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict_
                                                        IterStats* __restrict__ st) {
   __shared__ int cnt[kThreads];
   __shared__ double mg[kThreads];
+  __shared__ double tr[kThreads];
   int c = 0;
-  double mgn = 1.0e300;
+  double mgn = 1.0e300, trc = 0.0;
   for (int k = threadIdx.x; k < nH; k += kThreads) {
+    trc += fmax(lam[perm[k]], 0.0);
     const double sg = sqrt(fmax(lam[perm[k]], 0.0));
     if (sg > tau) {
       ++c;
@@ -152,17 +155,20 @@ __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict_
   }
   cnt[threadIdx.x] = c;
   mg[threadIdx.x] = mgn;
+  tr[threadIdx.x] = trc;
   __syncthreads();
   for (int w = kThreads / 2; w > 0; w >>= 1) {
     if (threadIdx.x < w) {
       cnt[threadIdx.x] += cnt[threadIdx.x + w];
       mg[threadIdx.x] = fmin(mg[threadIdx.x], mg[threadIdx.x + w]);
+      tr[threadIdx.x] += tr[threadIdx.x + w];
     }
     __syncthreads();
   }
   if (threadIdx.x == 0) {
     st->rank = cnt[0];
     st->margin = mg[0];
+    st->trace = tr[0];
   }
 }
 
@@ -343,29 +349,43 @@ __global__ void k_build_K(int nH, int ldK, const double* __restrict__ T, int ldT
 }
 
 // Epilogue for coarse widths n_H <= kTallNH (the tall, HBM-bound workloads).  A
-// persistent grid: each block stages K (float64) and the interpolation stencil in LDS
-// once, then loops over TM-row tiles: N = M_P K (float64 sums), L = N P^T, the
-// elementwise update (float4 accesses when VEC), and the restriction of the next
-// coarse data.  Same arithmetic as k_epilogue.
+// persistent grid: each block stages the interpolation stencil (and, at PREC 0, K in
+// float64) in LDS once, then loops over tiles of at most kTallRows rows: N = M_P K,
+// L = N P^T, the elementwise update (float4 accesses when VEC), and the restriction
+// of the next coarse data.  Same arithmetic as k_epilogue.
+//
+// N = M_P K by precision: PREC 0 sums float32 M_P times float64 K in float64 (VALU);
+// PREC 1 rounds both to bfloat16 and PREC 2 splits both into bfloat16 hi + lo with the
+// three products hi*hi + hi*lo + lo*hi, on v_mfma_f32_16x16x32_bf16 with float32
+// accumulation.  For PREC > 0 wave w owns output columns 16w..16w+15 and keeps its
+// K fragments (B operand: lane l holds K[32s + 8(l/16) + q][16w + l%16]) in registers
+// for the whole grid-stride loop; the A operand is row l%16 of the M_P tile.
 constexpr int kTallNH = 64;
+constexpr int kTallRows = 16;          // rows per tile (one MFMA row block)
+constexpr int kLdA = kTallNH + 8;      // padded LDS row of the M_P tile
+constexpr int kLdN = kTallNH + 4;      // padded LDS row of the N tile
 
-template <int MODE, bool MASKED, bool VEC>
+template <int MODE, bool MASKED, bool VEC, int PREC>
 __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const double* __restrict__ K, int ntiles,
                                                            int nnz) {
   extern __shared__ double smd[];
   __shared__ double red[kThreads];
   const int n = a.n, nH = a.nH, TM = a.TM;
-  double* sK = smd;                                         // 64 x 64
-  float* sMP = reinterpret_cast<float*>(sK + kTallNH * kTallNH);   // TM x 64
-  float* sN = sMP + TM * kTallNH;                           // TM x 64
-  float* sX = sN + TM * kTallNH;                            // TM x n
+  double* sK = smd;                                                          // 64 x 64 (PREC 0)
+  float* sMP = reinterpret_cast<float*>(smd + (PREC == 0 ? kTallNH * kTallNH : 0));   // 16 x kLdA
+  float* sN = sMP + kTallRows * kLdA;                                        // 16 x kLdN
+  float* sX = sN + kTallRows * kLdN;                                         // TM x n
   int* sRi = reinterpret_cast<int*>(sX + (size_t)TM * n);   // n x 2
   float* sRw = reinterpret_cast<float*>(sRi + 2 * n);       // n x 2
   int* sCp = reinterpret_cast<int*>(sRw + 2 * n);           // nH + 1
   int* sCr = sCp + (nH + 1);                                // nnz
   float* sCw = reinterpret_cast<float*>(sCr + nnz);         // nnz
   const int tid = threadIdx.x;
-  for (int e = tid; e < kTallNH * kTallNH; e += kThreads) sK[e] = K[e];
+  const int wave = tid >> 6, lane = tid & 63;
+  if (PREC == 0)
+    for (int e = tid; e < kTallNH * kTallNH; e += kThreads) sK[e] = K[e];
+  // the M_P tile beyond column nH (and rows never loaded) must hold finite zeros
+  for (int e = tid; e < kTallRows * kLdA; e += kThreads) sMP[e] = 0.0f;
   for (int e = tid; e < 2 * n; e += kThreads) {
     sRi[e] = a.row_idx[e];
     sRw[e] = a.row_w[e];
@@ -377,6 +397,20 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
       sCw[e] = a.col_w[e];
     }
   }
+  const int ksteps = nH > 32 ? 2 : 1;
+  const bool wave_on = 16 * wave < nH;
+  bf16x8_t kh[2], kl[2];
+  if (PREC > 0) {
+#pragma unroll
+    for (int s = 0; s < 2; ++s)
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        const double kv = K[(32 * s + 8 * (lane >> 4) + q) * kTallNH + 16 * wave + (lane & 15)];
+        const unsigned short h = f2bf((float)kv);
+        kh[s][q] = __builtin_bit_cast(__bf16, h);
+        kl[s][q] = __builtin_bit_cast(__bf16, f2bf((float)(kv - (double)bf2f(h))));
+      }
+  }
   double racc = 0.0;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int i0 = tile * TM;
@@ -384,15 +418,42 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     __syncthreads();
     for (int e = tid; e < rows * nH; e += kThreads) {
       const int i = e / nH, c = e % nH;
-      sMP[i * kTallNH + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
+      sMP[i * kLdA + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
     }
     __syncthreads();
-    for (int e = tid; e < rows * nH; e += kThreads) {       // N = M_P K
-      const int i = e / nH, c = e % nH;
-      const float* x = sMP + i * kTallNH;
-      double acc = 0.0;
-      for (int cc = 0; cc < nH; ++cc) acc = fma((double)x[cc], sK[cc * kTallNH + c], acc);
-      sN[i * kTallNH + c] = (float)acc;
+    if (PREC == 0) {
+      for (int e = tid; e < rows * nH; e += kThreads) {       // N = M_P K
+        const int i = e / nH, c = e % nH;
+        const float* x = sMP + i * kLdA;
+        double acc = 0.0;
+        for (int cc = 0; cc < nH; ++cc) acc = fma((double)x[cc], sK[cc * kTallNH + c], acc);
+        sN[i * kLdN + c] = (float)acc;
+      }
+    } else if (wave_on) {
+      f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s = 0; s < 2; ++s) {
+        if (s < ksteps) {
+          const float* ap = sMP + (lane & 15) * kLdA + 32 * s + 8 * (lane >> 4);
+          const float4 x0 = *reinterpret_cast<const float4*>(ap);
+          const float4 x1 = *reinterpret_cast<const float4*>(ap + 4);
+          const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+          bf16x8_t ah, al;
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const unsigned short h = f2bf(xv[q]);
+            ah[q] = __builtin_bit_cast(__bf16, h);
+            if (PREC == 2) al[q] = __builtin_bit_cast(__bf16, f2bf(xv[q] - bf2f(h)));
+          }
+          if (PREC == 2) {
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, kh[s], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, kl[s], acc, 0, 0, 0);
+          }
+          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, kh[s], acc, 0, 0, 0);
+        }
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sN[(4 * (lane >> 4) + v) * kLdN + 16 * wave + (lane & 15)] = acc[v];
     }
     __syncthreads();
     constexpr int V = VEC ? 4 : 1;
@@ -405,7 +466,7 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
 #pragma unroll
       for (int v = 0; v < V; ++v) {
         const int j = j0 + v;
-        const float* nrow = sN + i * kTallNH;
+        const float* nrow = sN + i * kLdN;
         Lv[v] = fmaf(sRw[2 * j + 1], nrow[sRi[2 * j + 1]], sRw[2 * j] * nrow[sRi[2 * j]]);
       }
       const size_t gij = (size_t)gi * n + j0;
@@ -520,6 +581,9 @@ struct Plan {
   bool tall;
   int TM_tall, ntiles_tall, grid_tall, nnz;
   size_t lds_tall;
+  // precision of the Gram and of the tall reconstruction N = M_P K (0 float64 sums,
+  // 1 bfloat16, 2 split bfloat16) -- see prec_split
+  int gram_prec, recon_prec;
   size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_perm, off_sw, off_T, off_Tt,
       off_K, off_part, off_gram, off_eig, off_stats, total;
 };
@@ -536,8 +600,49 @@ int device_cus() {
   return cached[dev];
 }
 
-int make_plan(int m, int n, int levels, bool masked, Plan& p) {
+// Precision form (mlpcp_opts.prec) -> (Gram, reconstruction) kernel precisions.  The
+// Gram's precision is chosen per iteration (gram_prec_for; this is the first
+// iteration's).  The reconstruction is always split: N = M_P K is a short
+// (n_H-term) sum whose bfloat16 rounding would reach L directly at ~3e-3.
+void prec_split(int prec, int& gram, int& recon) {
+  gram = prec == MLPCP_BF16 ? 1 : prec == MLPCP_BF16X3 ? 2 : 0;
+  recon = prec == MLPCP_FP32 ? 0 : 2;
+}
+
+// Gram precision of one iteration of a precision-form solve, from rho = tau^2 / trace
+// (trace of the previous iteration's coarse Gram; the first iteration has rho = inf).
+// A Gram in reduced precision moves the singular values it yields; the iteration may
+// use it while that shift stays below 1% of the threshold tau, so that the values
+// near tau -- the ones that decide the rank and carry the weights (sigma - tau) --
+// are those of the float32 data:
+//  * bfloat16 operands are the exact Gram of A + E, |E_ij| <= u |A_ij| (u = 2^-8,
+//    independent errors), which moves each sigma by at most ||E||_2 ~
+//    (u / sqrt 3)(1/sqrt(n_H) + 1/sqrt(m)) ||A||_F:  rho >= (u^2/3)(..)^2 / 0.01^2;
+//  * split operands leave a symmetric error of order u^4 trace plus the float32
+//    rounding of the 32-row chunk sums, ~2^-24 trace / sqrt(m / 32); an eigenvalue
+//    error d moves sigma ~ tau by d / (2 tau):  rho >= d / (2 * 0.01 trace);
+//  * below both, the Gram takes the float64-product path of the float32 solver.
+// tau falls geometrically with mu, so a solve walks down the tiers: the first
+// iterations in bfloat16, the middle ones split, the last ones, which fix the result
+// and the rank, exact.  MLPCP_BF16X3 skips the bfloat16 tier.
+int gram_prec_for(int prec, double tau, double trace_prev, int m, int nH) {
+  if (prec == MLPCP_FP32) return 0;
+  if (std::isinf(trace_prev)) return prec == MLPCP_BF16 ? 1 : 2;
+  if (!(trace_prev > 0.0)) return 0;
+  constexpr double u = 1.0 / 256.0, eta = 0.01;
+  const double rho = tau * tau / trace_prev;
+  const double e1 = 1.0 / std::sqrt((double)nH) + 1.0 / std::sqrt((double)m);
+  const double rho_bf16 = (u * u / 3.0) * e1 * e1 / (eta * eta);
+  const double d_split = u * u * u * u + std::ldexp(1.0, -24) / std::sqrt(std::max(1.0, m / 32.0));
+  const double rho_split = d_split / (2.0 * eta);
+  if (prec == MLPCP_BF16 && rho >= rho_bf16) return 1;
+  if (rho >= rho_split) return 2;
+  return 0;
+}
+
+int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_FP32) {
   p.m = m;
+  prec_split(prec, p.gram_prec, p.recon_prec);
   p.n = n;
   p.levels = levels;
   p.nH = coarse_dim_checked(n, levels);
@@ -562,17 +667,22 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p) {
   p.lds_tall = 0;
   if (p.tall) {
     p.nnz = 2 * n;   // upper bound: at most two weights per fine row
-    const size_t fixed = (size_t)kTallNH * kTallNH * 8 + (size_t)16 * n + (size_t)4 * (p.nH + 1) + (size_t)8 * p.nnz;
-    const size_t per = (size_t)4 * (2 * kTallNH + n);
-    const size_t budget = 76 * 1024;   // two blocks per 160 KB CU
+    const size_t fixed = (p.recon_prec == 0 ? (size_t)kTallNH * kTallNH * 8 : 0) +
+                         (size_t)4 * kTallRows * (kLdA + kLdN) + (size_t)16 * n + (size_t)4 * (p.nH + 1) +
+                         (size_t)8 * p.nnz;
+    const size_t per = (size_t)4 * n;
+    const size_t budget = 76 * 1024;   // at least two blocks per 160 KB CU
     int tm = budget > fixed ? (int)((budget - fixed) / per) : 0;
-    if (tm > 16) tm = 16;
+    if (tm > kTallRows) tm = kTallRows;
     if (tm < 1) {
       p.tall = false;
     } else {
       p.TM_tall = tm;
       p.ntiles_tall = (m + tm - 1) / tm;
       p.lds_tall = fixed + (size_t)tm * per;
+      // resident blocks per CU from LDS (160 KB, plus the static reduction array)
+      const int per_cu = (int)std::min<size_t>(4, (160 * 1024) / (p.lds_tall + kThreads * 8 + 256));
+      p.grid_tall = std::min(p.ntiles_tall, std::max(per_cu, 1) * device_cus());
     }
   }
   size_t off = 0;
@@ -630,13 +740,15 @@ int valid_opts(const mlpcp_opts& o) {
   if (!(o.tol > 0.0) || !std::isfinite(o.tol) || o.max_iter < 1 || !(o.rho >= 1.0) || !std::isfinite(o.rho) ||
       !(o.mu_max_factor >= 1.0) || !std::isfinite(o.mu_max_factor))
     return MLPCP_E_INVALID_ARG;
-  if (o.prec != MLPCP_FP32 || o.check_every != 1 || o.r_norm != 0) return MLPCP_E_UNSUPPORTED;
+  if (o.prec != MLPCP_FP32 && o.prec != MLPCP_BF16 && o.prec != MLPCP_BF16X3) return MLPCP_E_INVALID_ARG;
+  if (o.check_every != 1 || o.r_norm != 0) return MLPCP_E_UNSUPPORTED;
   return MLPCP_OK;
 }
 
 // One coarse SVT on M_P (buffer `mp`): Gram, C G C, eigensolve, weights, T.
 int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, double tau, hipStream_t s,
-               int* sweeps, bool warm) {
+               int* sweeps, bool warm, int gram_prec = -1) {
+  if (gram_prec < 0) gram_prec = p.gram_prec;
   double* G = w.at<double>(p.off_G);
   double* V = w.at<double>(p.off_V);
   double* lam = w.at<double>(p.off_lam);
@@ -645,7 +757,7 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   double* T = w.at<double>(p.off_T);
   double* Tt = w.at<double>(p.off_Tt);
   IterStats* st = w.at<IterStats>(p.off_stats);
-  MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.nHp, G, w.at<void>(p.off_gram), s));
+  MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.nHp, G, w.at<void>(p.off_gram), s, gram_prec));
   double* GH = G;
   if (!p.plain) {
     ProfScope ps(KC_COARSE, s);
@@ -675,7 +787,9 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 template <int MODE, bool MASKED, bool VEC>
 int launch_tall_one(const Plan& p, const EpiArgs& a, const double* K, int nnz, int grid, hipStream_t s) {
-  auto fn = k_epilogue_tall<MODE, MASKED, VEC>;
+  auto fn = p.recon_prec == 2   ? k_epilogue_tall<MODE, MASKED, VEC, 2>
+            : p.recon_prec == 1 ? k_epilogue_tall<MODE, MASKED, VEC, 1>
+                                : k_epilogue_tall<MODE, MASKED, VEC, 0>;
   MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)p.lds_tall));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), p.lds_tall, s, a, K, p.ntiles_tall, nnz);
@@ -688,7 +802,7 @@ template <int MODE>
 int launch_epilogue(const Plan& p, const EpiArgs& a, const double* K, int nnz, hipStream_t s, int* partials) {
   ProfScope ps(MODE == MODE_STEP ? KC_EPILOGUE : KC_FINAL, s);
   if (p.tall) {
-    const int grid = std::min(p.ntiles_tall, 2 * device_cus());
+    const int grid = p.grid_tall;
     *partials = grid;
     const bool vec = (p.n % 4 == 0) && aligned16(a.Lout) && aligned16(a.Zin) && aligned16(a.Zout) &&
                      aligned16(a.Sout) && aligned16(a.Yout) && (MODE == MODE_RECON || (a.ldd % 4 == 0 && aligned16(a.D)));
@@ -756,7 +870,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   if (coarse_dim_checked(n, o.levels) < 1) return MLPCP_E_LEVELS;
   if (L == S || L == Y || (Y && S == Y) || (const float*)L == D || (const float*)S == D) return MLPCP_E_INVALID_ARG;
   Plan p;
-  MLPCP_TRY(make_plan(m, n, o.levels, masked, p));
+  MLPCP_TRY(make_plan(m, n, o.levels, masked, p, o.prec));
   if (ws && ws_bytes < p.total) return MLPCP_E_WORKSPACE;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
@@ -788,9 +902,14 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   double margin = 0.0;
   bool converged = false;
   int status = MLPCP_OK;
+  double trace_prev = INFINITY;
+  int bf16_iters = 0, split_iters = 0;
   for (t = 0; t < o.max_iter; ++t) {
     const double mu_next = std::min(o.rho * mu, mu_max);
-    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0));
+    const int gp = gram_prec_for(o.prec, 1.0 / mu, trace_prev, m, p.nH);
+    bf16_iters += gp == 1;
+    split_iters += gp == 2;
+    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0, gp));
     EpiArgs a{};
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
@@ -817,6 +936,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     fg = std::sqrt(hs.fg2) / nrmD;
     rank = hs.rank;
     margin = hs.margin;
+    trace_prev = hs.trace;
     if (info && info->fg_history && t < info->history_len) info->fg_history[t] = fg;
     if (info && info->rank_history && t < info->history_len) info->rank_history[t] = rank;
     if (!std::isfinite(fg)) {
@@ -857,6 +977,8 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     info->mu_final = mu;
     info->tau_margin = margin;
     info->eig_sweeps = sweeps;
+    info->gram_bf16_iters = bf16_iters;
+    info->gram_split_iters = split_iters;
   }
   return status;
 }
