@@ -12,7 +12,7 @@ The plain method (levels = 0, the same kernels with R = I) is timed on the same
 input for the speedup.  Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus N (N must be 1)
---workload {c1,c2,c3,c5} --no-plain --no-cpu.
+--workload {c1,c2,c3,c5} --no-plain --no-cpu --prec {fp32,bf16,bf16x3}.
 """
 import argparse
 import json
@@ -40,6 +40,8 @@ def parse():
     ap.add_argument("--no-plain", action="store_true")
     ap.add_argument("--no-cpu", action="store_true")
     ap.add_argument("--plain-steps", type=int, default=1)
+    ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "bf16x3"],
+                    help="arithmetic of the coarse SVT's Gram and reconstruction products")
     return ap.parse_args()
 
 
@@ -64,7 +66,7 @@ def algorithmic_work(cls, w, nH, plain):
         return "hbm", 4.0 * m * n + 4.0 * m * k + (m * n / 8.0 if masked else 0.0)
     if cls == "finalize":
         return "hbm", 16.0 * m * n + 4.0 * m * k
-    if cls == "gram_f64":
+    if cls == "gram":
         return "mfma", 1.0 * m * k * (k + 1)
     N = int(math.ceil(k / 64.0)) * 64
     npairs = N // 64
@@ -103,7 +105,7 @@ def main():
     nH = mlp.coarse_dim(w.n, w.levels)
 
     def run(levels, ws):
-        kw = dict(levels=levels, tol=a.tol, max_iter=500, want_y=False, workspace=ws, history=600)
+        kw = dict(levels=levels, tol=a.tol, max_iter=500, want_y=False, workspace=ws, history=600, prec=a.prec)
         if Q is None:
             return mlp.pcp_solve(D, w.lam, w.mu0, **kw)
         return mlp.cpcp_solve(D, Q, w.lam, w.mu0, **kw)
@@ -136,7 +138,8 @@ def main():
     r = results[-1]
     iters = r.iters
     print(f"[bench] multilevel: {ml_s*1e3:.2f} ms/solve, {iters} iters, fg {r.fg:.2e}, rank {r.rank}; "
-          f"dominant kernel {dom}", file=sys.stderr, flush=True)
+          f"dominant kernel {dom}; Gram bf16/split iters {r.gram_bf16_iters}/{r.gram_split_iters}",
+          file=sys.stderr, flush=True)
 
     # the same K solves with HIP events around the dominant kernel class only
     torch.cuda.synchronize()
@@ -226,7 +229,8 @@ def main():
         "higher_is_better": False,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f32",
+        "dtype": "f32" if a.prec == "fp32" else a.prec + "/f32",
+        "precision": {"mode": a.prec, "gram_bf16_iters": r.gram_bf16_iters, "gram_split_iters": r.gram_split_iters},
         "data": "synthetic",
         "config": {"workload": describe(w)},
         "iters": iters,

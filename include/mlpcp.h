@@ -58,7 +58,8 @@ typedef enum {
 
 /* Arithmetic of the two products of the coarse SVT (the precision form):
  *   MLPCP_FP32    Gram M_P^T M_P from float32 operands with float64 products and sums;
- *                 reconstruction N = M_P K summed in float64.
+ *                 reconstruction N = M_P K on float32 MFMA (tall path) or with
+ *                 float64 sums (wider coarse models).
  *   MLPCP_BF16X3  reconstruction in split bfloat16: x = hi + lo, each product taken
  *                 as hi*hi + hi*lo + lo*hi on MFMA with float32 accumulation.  The
  *                 Gram is split the same way while the threshold tau is far enough
@@ -70,7 +71,7 @@ typedef enum {
  *                 rounded to plain bfloat16 while tau is far above that rounding.
  * The eigensolve, the threshold and the rank decision stay in float64, the
  * elementwise update in float32.  The split reconstruction applies on the tall path
- * (n_H <= 64, multilevel); wider coarse models keep float64 sums there.
+ * (n_H <= 64, multilevel); wider coarse models keep their float64 sums.
  * mlpcp_info reports how many iterations ran each reduced-precision Gram.       */
 typedef enum { MLPCP_FP32 = 0, MLPCP_BF16 = 1, MLPCP_BF16X3 = 2 } mlpcp_precision;
 

@@ -114,7 +114,7 @@ def lib() -> ctypes.CDLL:
     return L
 
 
-KERNEL_CLASSES = ("init_restrict", "gram_f64", "coarse_CGC", "jacobi_pairs", "jacobi_apply", "jacobi_misc",
+KERNEL_CLASSES = ("init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply", "jacobi_misc",
                   "svt_prep", "epilogue", "reduce", "finalize", "other")
 
 

@@ -11,7 +11,7 @@ namespace mlpcp {
 
 namespace {
 
-const char* kNames[KC_COUNT] = {"init_restrict", "gram_f64", "coarse_CGC", "jacobi_pairs", "jacobi_apply",
+const char* kNames[KC_COUNT] = {"init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply",
                                 "jacobi_misc", "svt_prep", "epilogue", "reduce", "finalize", "other"};
 
 struct Pending {

@@ -354,12 +354,15 @@ __global__ void k_build_K(int nH, int ldK, const double* __restrict__ T, int ldT
 // L = N P^T, the elementwise update (float4 accesses when VEC), and the restriction
 // of the next coarse data.  Same arithmetic as k_epilogue.
 //
-// N = M_P K by precision: PREC 0 sums float32 M_P times float64 K in float64 (VALU);
-// PREC 1 rounds both to bfloat16 and PREC 2 splits both into bfloat16 hi + lo with the
-// three products hi*hi + hi*lo + lo*hi, on v_mfma_f32_16x16x32_bf16 with float32
-// accumulation.  For PREC > 0 wave w owns output columns 16w..16w+15 and keeps its
-// K fragments (B operand: lane l holds K[32s + 8(l/16) + q][16w + l%16]) in registers
-// for the whole grid-stride loop; the A operand is row l%16 of the M_P tile.
+// N = M_P K on MFMA, wave w owning output columns 16w..16w+15 and keeping its K
+// fragments in registers for the whole grid-stride loop:
+//  * PREC 0: v_mfma_f32_16x16x4_f32 on float32 M_P and K (K rounded from float64);
+//    lane l holds A[l%16][4s + l/16] and B[4s + l/16][16w + l%16] at step s;
+//  * PREC 2: both split into bfloat16 hi + lo with the three products hi*hi + hi*lo +
+//    lo*hi on v_mfma_f32_16x16x32_bf16; lane l holds A[l%16][32s + 8(l/16) + q] and
+//    B[32s + 8(l/16) + q][16w + l%16], q < 8.
+// Both accumulate in float32; the output register v of lane l is row 4(l/16) + v,
+// column 16w + l%16.  PREC 0 serves the float32 solver, PREC 2 the precision form.
 constexpr int kTallNH = 64;
 constexpr int kTallRows = 16;          // rows per tile (one MFMA row block)
 constexpr int kLdA = kTallNH + 8;      // padded LDS row of the M_P tile
@@ -370,11 +373,11 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
                                                            int nnz) {
   extern __shared__ double smd[];
   __shared__ double red[kThreads];
+  static_assert(PREC == 0 || PREC == 2, "reconstruction precision");
   const int n = a.n, nH = a.nH, TM = a.TM;
-  double* sK = smd;                                                          // 64 x 64 (PREC 0)
-  float* sMP = reinterpret_cast<float*>(smd + (PREC == 0 ? kTallNH * kTallNH : 0));   // 16 x kLdA
-  float* sN = sMP + kTallRows * kLdA;                                        // 16 x kLdN
-  float* sX = sN + kTallRows * kLdN;                                         // TM x n
+  float* sMP = reinterpret_cast<float*>(smd);                // 16 x kLdA
+  float* sN = sMP + kTallRows * kLdA;                        // 16 x kLdN
+  float* sX = sN + kTallRows * kLdN;                         // TM x n
   int* sRi = reinterpret_cast<int*>(sX + (size_t)TM * n);   // n x 2
   float* sRw = reinterpret_cast<float*>(sRi + 2 * n);       // n x 2
   int* sCp = reinterpret_cast<int*>(sRw + 2 * n);           // nH + 1
@@ -382,8 +385,6 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
   float* sCw = reinterpret_cast<float*>(sCr + nnz);         // nnz
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  if (PREC == 0)
-    for (int e = tid; e < kTallNH * kTallNH; e += kThreads) sK[e] = K[e];
   // the M_P tile beyond column nH (and rows never loaded) must hold finite zeros
   for (int e = tid; e < kTallRows * kLdA; e += kThreads) sMP[e] = 0.0f;
   for (int e = tid; e < 2 * n; e += kThreads) {
@@ -397,20 +398,25 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
       sCw[e] = a.col_w[e];
     }
   }
-  const int ksteps = nH > 32 ? 2 : 1;
   const bool wave_on = 16 * wave < nH;
-  bf16x8_t kh[2], kl[2];
-  if (PREC > 0) {
+  const int kcol = 16 * wave + (lane & 15);
+  float kf[16];                // PREC 0: B fragments, k = 4s + l/16
+  bf16x8_t kh[2], kl[2];       // PREC 2: B fragments, k = 32s + 8(l/16) + q
+  if (PREC == 0) {
+#pragma unroll
+    for (int s = 0; s < 16; ++s) kf[s] = (float)K[(4 * s + (lane >> 4)) * kTallNH + kcol];
+  } else {
 #pragma unroll
     for (int s = 0; s < 2; ++s)
 #pragma unroll
       for (int q = 0; q < 8; ++q) {
-        const double kv = K[(32 * s + 8 * (lane >> 4) + q) * kTallNH + 16 * wave + (lane & 15)];
+        const double kv = K[(32 * s + 8 * (lane >> 4) + q) * kTallNH + kcol];
         const unsigned short h = f2bf((float)kv);
         kh[s][q] = __builtin_bit_cast(__bf16, h);
         kl[s][q] = __builtin_bit_cast(__bf16, f2bf((float)(kv - (double)bf2f(h))));
       }
   }
+  const int ksteps = PREC == 0 ? (nH + 3) / 4 : (nH > 32 ? 2 : 1);
   double racc = 0.0;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int i0 = tile * TM;
@@ -421,39 +427,36 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
       sMP[i * kLdA + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
     }
     __syncthreads();
-    if (PREC == 0) {
-      for (int e = tid; e < rows * nH; e += kThreads) {       // N = M_P K
-        const int i = e / nH, c = e % nH;
-        const float* x = sMP + i * kLdA;
-        double acc = 0.0;
-        for (int cc = 0; cc < nH; ++cc) acc = fma((double)x[cc], sK[cc * kTallNH + c], acc);
-        sN[i * kLdN + c] = (float)acc;
-      }
-    } else if (wave_on) {
+    if (wave_on) {                                          // N = M_P K
       f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+      if (PREC == 0) {
+        const float* ap = sMP + (lane & 15) * kLdA + (lane >> 4);
 #pragma unroll
-      for (int s = 0; s < 2; ++s) {
-        if (s < ksteps) {
-          const float* ap = sMP + (lane & 15) * kLdA + 32 * s + 8 * (lane >> 4);
-          const float4 x0 = *reinterpret_cast<const float4*>(ap);
-          const float4 x1 = *reinterpret_cast<const float4*>(ap + 4);
-          const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
-          bf16x8_t ah, al;
+        for (int s = 0; s < 16; ++s)
+          if (s < ksteps) acc = __builtin_amdgcn_mfma_f32_16x16x4f32(ap[4 * s], kf[s], acc, 0, 0, 0);
+      } else {
 #pragma unroll
-          for (int q = 0; q < 8; ++q) {
-            const unsigned short h = f2bf(xv[q]);
-            ah[q] = __builtin_bit_cast(__bf16, h);
-            if (PREC == 2) al[q] = __builtin_bit_cast(__bf16, f2bf(xv[q] - bf2f(h)));
-          }
-          if (PREC == 2) {
+        for (int s = 0; s < 2; ++s) {
+          if (s < ksteps) {
+            const float* ap = sMP + (lane & 15) * kLdA + 32 * s + 8 * (lane >> 4);
+            const float4 x0 = *reinterpret_cast<const float4*>(ap);
+            const float4 x1 = *reinterpret_cast<const float4*>(ap + 4);
+            const float xv[8] = {x0.x, x0.y, x0.z, x0.w, x1.x, x1.y, x1.z, x1.w};
+            bf16x8_t ah, al;
+#pragma unroll
+            for (int q = 0; q < 8; ++q) {
+              const unsigned short h = f2bf(xv[q]);
+              ah[q] = __builtin_bit_cast(__bf16, h);
+              al[q] = __builtin_bit_cast(__bf16, f2bf(xv[q] - bf2f(h)));
+            }
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al, kh[s], acc, 0, 0, 0);
             acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, kl[s], acc, 0, 0, 0);
+            acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, kh[s], acc, 0, 0, 0);
           }
-          acc = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah, kh[s], acc, 0, 0, 0);
         }
       }
 #pragma unroll
-      for (int v = 0; v < 4; ++v) sN[(4 * (lane >> 4) + v) * kLdN + 16 * wave + (lane & 15)] = acc[v];
+      for (int v = 0; v < 4; ++v) sN[(4 * (lane >> 4) + v) * kLdN + kcol] = acc[v];
     }
     __syncthreads();
     constexpr int V = VEC ? 4 : 1;
@@ -581,8 +584,8 @@ struct Plan {
   bool tall;
   int TM_tall, ntiles_tall, grid_tall, nnz;
   size_t lds_tall;
-  // precision of the Gram and of the tall reconstruction N = M_P K (0 float64 sums,
-  // 1 bfloat16, 2 split bfloat16) -- see prec_split
+  // precision of the Gram (0 float64 products, 1 bfloat16, 2 split bfloat16) and of
+  // the tall reconstruction N = M_P K (0 float32 MFMA, 2 split bfloat16)
   int gram_prec, recon_prec;
   size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_perm, off_sw, off_T, off_Tt,
       off_K, off_part, off_gram, off_eig, off_stats, total;
@@ -618,9 +621,10 @@ void prec_split(int prec, int& gram, int& recon) {
 //  * bfloat16 operands are the exact Gram of A + E, |E_ij| <= u |A_ij| (u = 2^-8,
 //    independent errors), which moves each sigma by at most ||E||_2 ~
 //    (u / sqrt 3)(1/sqrt(n_H) + 1/sqrt(m)) ||A||_F:  rho >= (u^2/3)(..)^2 / 0.01^2;
-//  * split operands leave a symmetric error of order u^4 trace plus the float32
-//    rounding of the 32-row chunk sums, ~2^-24 trace / sqrt(m / 32); an eigenvalue
-//    error d moves sigma ~ tau by d / (2 tau):  rho >= d / (2 * 0.01 trace);
+//  * split operands drop the lo*lo products: the Gram of A + E minus Lo^T Lo, with
+//    |Lo_ij| <= u |A_ij|, a symmetric error of norm ~ (u^2/3)(..)^2 trace, plus the
+//    float32 rounding of the 32-row chunk sums, ~2^-24 trace / sqrt(m / 32); an
+//    eigenvalue error d moves sigma ~ tau by d / (2 tau):  rho >= d / (2 * 0.01 trace);
 //  * below both, the Gram takes the float64-product path of the float32 solver.
 // tau falls geometrically with mu, so a solve walks down the tiers: the first
 // iterations in bfloat16, the middle ones split, the last ones, which fix the result
@@ -633,7 +637,7 @@ int gram_prec_for(int prec, double tau, double trace_prev, int m, int nH) {
   const double rho = tau * tau / trace_prev;
   const double e1 = 1.0 / std::sqrt((double)nH) + 1.0 / std::sqrt((double)m);
   const double rho_bf16 = (u * u / 3.0) * e1 * e1 / (eta * eta);
-  const double d_split = u * u * u * u + std::ldexp(1.0, -24) / std::sqrt(std::max(1.0, m / 32.0));
+  const double d_split = (u * u / 3.0) * e1 * e1 + std::ldexp(1.0, -24) / std::sqrt(std::max(1.0, m / 32.0));
   const double rho_split = d_split / (2.0 * eta);
   if (prec == MLPCP_BF16 && rho >= rho_bf16) return 1;
   if (rho >= rho_split) return 2;
@@ -667,8 +671,7 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
   p.lds_tall = 0;
   if (p.tall) {
     p.nnz = 2 * n;   // upper bound: at most two weights per fine row
-    const size_t fixed = (p.recon_prec == 0 ? (size_t)kTallNH * kTallNH * 8 : 0) +
-                         (size_t)4 * kTallRows * (kLdA + kLdN) + (size_t)16 * n + (size_t)4 * (p.nH + 1) +
+    const size_t fixed = (size_t)4 * kTallRows * (kLdA + kLdN) + (size_t)16 * n + (size_t)4 * (p.nH + 1) +
                          (size_t)8 * p.nnz;
     const size_t per = (size_t)4 * n;
     const size_t budget = 76 * 1024;   // at least two blocks per 160 KB CU
@@ -787,9 +790,7 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 template <int MODE, bool MASKED, bool VEC>
 int launch_tall_one(const Plan& p, const EpiArgs& a, const double* K, int nnz, int grid, hipStream_t s) {
-  auto fn = p.recon_prec == 2   ? k_epilogue_tall<MODE, MASKED, VEC, 2>
-            : p.recon_prec == 1 ? k_epilogue_tall<MODE, MASKED, VEC, 1>
-                                : k_epilogue_tall<MODE, MASKED, VEC, 0>;
+  auto fn = p.recon_prec == 2 ? k_epilogue_tall<MODE, MASKED, VEC, 2> : k_epilogue_tall<MODE, MASKED, VEC, 0>;
   MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)p.lds_tall));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), p.lds_tall, s, a, K, p.ntiles_tall, nnz);
