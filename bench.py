@@ -138,7 +138,8 @@ def main():
     r = results[-1]
     iters = r.iters
     print(f"[bench] multilevel: {ml_s*1e3:.2f} ms/solve, {iters} iters, fg {r.fg:.2e}, rank {r.rank}; "
-          f"dominant kernel {dom}; Gram bf16/split iters {r.gram_bf16_iters}/{r.gram_split_iters}",
+          f"dominant kernel {dom}; Gram bf16/split iters {r.gram_bf16_iters}/{r.gram_split_iters}; "
+          f"last eigensolve sweeps {r.eig_sweeps}",
           file=sys.stderr, flush=True)
 
     # the same K solves with HIP events around the dominant kernel class only

@@ -115,7 +115,7 @@ def lib() -> ctypes.CDLL:
 
 
 KERNEL_CLASSES = ("init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply", "jacobi_misc",
-                  "svt_prep", "epilogue", "reduce", "finalize", "other")
+                  "svt_prep", "epilogue", "reduce", "finalize", "coarse_svt_small", "other")
 
 
 def profile_enable(on=True) -> None:

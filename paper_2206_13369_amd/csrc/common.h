@@ -80,6 +80,28 @@ size_t eig_workspace_bytes(int N);
 // warm: V holds an orthogonal starting basis on entry (e.g. the previous eigenvectors,
 // identity on the padding); otherwise V is initialised to the identity.
 // sweeps_out receives the number of sweeps.  Synchronises `stream`.
+// Per-iteration statistics written on the device, read by the host once per iteration.
+struct IterStats {
+  double fg2;      // sum of squared residuals on Q
+  double nrm2;     // ||P_Q D||_F^2 (init)
+  double margin;   // min |sigma - tau| / tau
+  double trace;    // sum of the coarse eigenvalues (||M_H||_F^2)
+  int rank;
+  int sweeps;      // Jacobi sweeps of the one-workgroup coarse SVT (-1: sweep cap hit)
+};
+
+// Sweep count placeholder: the count is in IterStats::sweeps after the next sync.
+constexpr int kSweepsOnDevice = -100;
+
+// The whole coarse SVT of a coarse model of width n_H <= kEigInner in one workgroup:
+// G_H = C G C (C null: plain, G_H = G), optional warm start from V, Jacobi, ordering,
+// weights sw, T = C V_sorted diag(sw), Tt, and K = T T^T (if K is non-null); writes V,
+// lam (diagonal), perm, sw and the rank / margin / trace / sweeps fields of st.
+// Buffers are kEigInner x kEigInner with leading dimension ld (= kEigInner).
+int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V, bool warm, double tau,
+                     double* lam, int* perm, double* sw, double* T, double* Tt, double* K, IterStats* st,
+                     hipStream_t stream);
+
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws,
             hipStream_t stream, int* sweeps_out, bool warm);
 

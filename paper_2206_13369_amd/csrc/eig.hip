@@ -357,6 +357,262 @@ __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, do
   }
 }
 
+// ---------------------------------------------------------------------------------
+// The coarse SVT of a width-<=64 coarse model in one workgroup (the tall workloads):
+// every step from the Gram to the reconstruction factors stays in LDS, and the
+// Jacobi iteration runs over the n_e = n_H rounded up to even indices only (circle
+// method, n_e - 1 rounds of n_e / 2 disjoint rotations per sweep).  Before each sweep
+// the rotation test is evaluated on every pair; a sweep starts only if some pair
+// passes it (a sweep in which no pair passes rotates nothing), so the final sweep of
+// the plain iteration, which only confirms convergence, is replaced by that test.
+typedef double LdsRow[LDS_LD];
+
+__device__ __forceinline__ bool rotates(double app, double aqq, double apq, double floor_abs) {
+  return fabs(apq) > floor_abs && apq * apq > kRelEps2 * fabs(app * aqq);
+}
+
+__global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const double* __restrict__ G,
+                                                      const double* __restrict__ C, double* __restrict__ V,
+                                                      int warm, double tau, int max_sweeps,
+                                                      double* __restrict__ lam, int* __restrict__ perm,
+                                                      double* __restrict__ sw, double* __restrict__ T,
+                                                      double* __restrict__ Tt, double* __restrict__ K,
+                                                      IterStats* __restrict__ st) {
+  extern __shared__ double dsm[];
+  LdsRow* sA = reinterpret_cast<LdsRow*>(dsm);
+  LdsRow* sQ = sA + IN;
+  LdsRow* sC = sQ + IN;
+  LdsRow* sW = sC + IN;
+  __shared__ double pc[IB], ps[IB], pt[IB], swv[IN], red[256];
+  __shared__ int pp[IB], pq[IB], prm[IN], redi[256];
+  const int tid = threadIdx.x;
+  d4_t acc[2][2];
+  for (int it = tid; it < IN * IN; it += 256) {
+    const int i = it / IN, j = it % IN;
+    const bool in = i < nH && j < nH;
+    sA[i][j] = in ? G[(size_t)i * ld + j] : 0.0;
+    if (C) sC[i][j] = in ? C[(size_t)i * nH + j] : 0.0;
+    sQ[i][j] = (warm && in) ? V[(size_t)i * ld + j] : (i == j ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  if (C) {                                   // G_H = C G C
+    mm64<false>(sA, sC, acc);
+    mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+    __syncthreads();
+    mm64<false>(sC, sW, acc);
+    __syncthreads();
+    mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    __syncthreads();
+  }
+  if (warm) {                                // A <- V0^T A V0, Q = V0
+    mm64<true>(sQ, sA, acc);
+    mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+    __syncthreads();
+    mm64<false>(sW, sQ, acc);
+    __syncthreads();
+    mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    __syncthreads();
+  }
+  // exact symmetry (the products above round each triangle separately)
+  for (int it = tid; it < IN * IN; it += 256) {
+    const int i = it / IN, j = it % IN;
+    if (i < j) {
+      const double v = 0.5 * (sA[i][j] + sA[j][i]);
+      sA[i][j] = v;
+      sA[j][i] = v;
+    }
+  }
+  // absolute floor of the rotation test: 1e-16 trace
+  red[tid] = tid < nH ? fabs(sA[tid][tid]) : 0.0;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double fl = 1.0e-16 * red[0] + 1.0e-300;
+  const int ne = nH + (nH & 1), np = ne / 2;
+  // this thread's 2x2 tiles (pair a rows, pair b columns) and (row, pair) items of
+  // Q, fixed for the whole iteration (only the pairs' indices change per round)
+  constexpr int MT = (IB * IB) / 256, MQ = (IN * IB) / 256;
+  int ta_[MT], tb_[MT], qi_[MQ], qb_[MQ];
+#pragma unroll
+  for (int x = 0; x < MT; ++x) {
+    const int e = tid + 256 * x;
+    ta_[x] = e < np * np ? e / np : -1;
+    tb_[x] = e < np * np ? e % np : 0;
+  }
+#pragma unroll
+  for (int x = 0; x < MQ; ++x) {
+    const int e = tid + 256 * x;
+    qi_[x] = e < ne * np ? e / np : -1;
+    qb_[x] = e < ne * np ? e % np : 0;
+  }
+  int sweeps = 0;
+  bool conv = false;
+  for (;; ++sweeps) {
+    int want = 0;
+    for (int it = tid; it < ne * ne; it += 256) {
+      const int i = it / ne, j = it % ne;
+      if (i < j && rotates(sA[i][i], sA[j][j], sA[i][j], fl)) want = 1;
+    }
+    if (!__syncthreads_or(want)) {
+      conv = true;
+      break;
+    }
+    if (sweeps == max_sweeps) break;
+    for (int r = 0; r < ne - 1; ++r) {
+      if (tid < np) {
+        int p, q;
+        rr_pair(tid, r, ne, p, q);
+        double c, sn, t;
+        rotation(sA[p][p], sA[q][q], sA[p][q], fl, c, sn, t);
+        pp[tid] = p; pq[tid] = q;
+        pc[tid] = c; ps[tid] = sn; pt[tid] = t;
+      }
+      __syncthreads();
+      // all loads of a thread first, then the stores (the items are disjoint)
+      double t00[MT], t01[MT], t10[MT], t11[MT], qx[MQ], qy[MQ];
+      int rp[MT], rq[MT], cp[MT], cq[MT], qp[MQ], qq[MQ];
+#pragma unroll
+      for (int x = 0; x < MT; ++x) {
+        if (ta_[x] >= 0) {
+          rp[x] = pp[ta_[x]]; rq[x] = pq[ta_[x]]; cp[x] = pp[tb_[x]]; cq[x] = pq[tb_[x]];
+          t00[x] = sA[rp[x]][cp[x]]; t01[x] = sA[rp[x]][cq[x]];
+          t10[x] = sA[rq[x]][cp[x]]; t11[x] = sA[rq[x]][cq[x]];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < MQ; ++x) {
+        if (qi_[x] >= 0) {
+          qp[x] = pp[qb_[x]]; qq[x] = pq[qb_[x]];
+          qx[x] = sQ[qi_[x]][qp[x]]; qy[x] = sQ[qi_[x]][qq[x]];
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < MT; ++x) {
+        if (ta_[x] >= 0) {
+          const int a = ta_[x], b = tb_[x];
+          const double ca = pc[a], sa = ps[a], cb = pc[b], sb = ps[b];
+          const double u00 = ca * t00[x] - sa * t10[x], u01 = ca * t01[x] - sa * t11[x];
+          const double u10 = sa * t00[x] + ca * t10[x], u11 = sa * t01[x] + ca * t11[x];
+          double n00 = u00 * cb - u01 * sb;
+          double n01 = u00 * sb + u01 * cb;
+          double n10 = u10 * cb - u11 * sb;
+          double n11 = u10 * sb + u11 * cb;
+          if (a == b) {   // diagonal 2x2 tile: exact form of the annihilation
+            const double ta = pt[a];
+            n00 = t00[x] - ta * t01[x];
+            n11 = t11[x] + ta * t01[x];
+            n01 = ta != 0.0 ? 0.0 : t01[x];
+            n10 = n01;
+          }
+          sA[rp[x]][cp[x]] = n00; sA[rp[x]][cq[x]] = n01;
+          sA[rq[x]][cp[x]] = n10; sA[rq[x]][cq[x]] = n11;
+        }
+      }
+#pragma unroll
+      for (int x = 0; x < MQ; ++x) {
+        if (qi_[x] >= 0) {
+          const double c = pc[qb_[x]], sn = ps[qb_[x]];
+          sQ[qi_[x]][qp[x]] = c * qx[x] - sn * qy[x];
+          sQ[qi_[x]][qq[x]] = sn * qx[x] + c * qy[x];
+        }
+      }
+      __syncthreads();
+    }
+  }
+  // eigenvalues, descending order (ties by index), weights, rank, margin, trace
+  double li = 0.0;
+  if (tid < IN) {
+    li = sA[tid][tid];
+    lam[tid] = tid < nH ? li : 0.0;
+  }
+  if (tid < nH) {
+    int rk = 0;
+    for (int j = 0; j < nH; ++j) {
+      const double lj = sA[j][j];
+      rk += (lj > li) || (lj == li && j < tid);
+    }
+    prm[rk] = tid;
+  } else if (tid < IN) {
+    prm[tid] = tid;
+  }
+  __syncthreads();
+  int kept = 0;
+  double mg = 1.0e300, trc = 0.0;
+  if (tid < nH) {
+    const double lk = fmax(sA[prm[tid]][prm[tid]], 0.0);
+    const double sg = sqrt(lk);
+    double wk = 0.0;
+    if (sg > tau) {
+      kept = 1;
+      wk = sqrt((sg - tau) / sg);
+    }
+    swv[tid] = wk;
+    sw[tid] = wk;
+    mg = fabs(sg - tau) / tau;
+    trc = lk;
+  } else if (tid < IN) {
+    swv[tid] = 0.0;
+  }
+  if (tid < IN) perm[tid] = prm[tid];
+  red[tid] = trc;
+  redi[tid] = kept;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[tid] += red[tid + w];
+      redi[tid] += redi[tid + w];
+    }
+    __syncthreads();
+  }
+  const double trace = red[0];
+  const int rank = redi[0];
+  __syncthreads();
+  red[tid] = mg;
+  __syncthreads();
+  for (int w = 128; w > 0; w >>= 1) {
+    if (tid < w) red[tid] = fmin(red[tid], red[tid + w]);
+    __syncthreads();
+  }
+  if (tid == 0) {
+    st->rank = rank;
+    st->margin = red[0];
+    st->trace = trace;
+    st->sweeps = conv ? sweeps : -1;
+  }
+  // W = V_sorted diag(sw) (columns k < rank), T = C W, Tt, K = T T^T
+  for (int it = tid; it < IN * IN; it += 256) {
+    const int j = it / IN, k = it % IN;
+    sW[j][k] = k < rank ? sQ[j][prm[k]] * swv[k] : 0.0;
+  }
+  __syncthreads();
+  LdsRow* sT = sW;
+  if (C) {
+    mm64<false>(sC, sW, acc);
+    mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    __syncthreads();
+    sT = sA;
+  }
+  for (int it = tid; it < IN * IN; it += 256) {
+    const int i = it / IN, j = it % IN;
+    T[(size_t)i * ld + j] = sT[i][j];
+    Tt[(size_t)j * ld + i] = sT[i][j];
+    V[(size_t)i * ld + j] = sQ[i][j];
+  }
+  if (K) {
+    // K = T T^T = X^T X with X = T^T staged in the Q buffer (V is already written)
+    __syncthreads();
+    for (int it = tid; it < IN * IN; it += 256) {
+      const int i = it / IN, j = it % IN;
+      sQ[j][i] = sT[i][j];
+    }
+    __syncthreads();
+    mm64<true>(sQ, sQ, acc);
+    mm64_store(acc, [&](int i, int j, double v) { K[(size_t)i * IN + j] = v; });
+  }
+}
+
 __global__ void k_identity(double* __restrict__ V, int N) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)N * N) V[idx] = ((idx / N) == (idx % N)) ? 1.0 : 0.0;
@@ -389,6 +645,20 @@ __global__ void __launch_bounds__(256) k_rank(const double* __restrict__ lam, in
 }
 
 }  // namespace
+
+int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V, bool warm, double tau,
+                     double* lam, int* perm, double* sw, double* T, double* Tt, double* K, IterStats* st,
+                     hipStream_t stream) {
+  if (nH < 1 || nH > IN || ld != IN) return MLPCP_E_INVALID_ARG;
+  const size_t lds = (size_t)4 * IN * LDS_LD * sizeof(double);
+  MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse_small),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  ProfScope ps(KC_COARSE_SMALL, stream);
+  hipLaunchKernelGGL(k_coarse_small, dim3(1), dim3(256), lds, stream, nH, ld, G, C, V, warm ? 1 : 0, tau,
+                     kMaxEigSweeps, lam, perm, sw, T, Tt, K, st);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
 
 size_t eig_workspace_bytes(int N) {
   const size_t npairs = (size_t)(N / IB) / 2;

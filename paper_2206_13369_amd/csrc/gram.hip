@@ -14,6 +14,8 @@
 #include "common.h"
 #include "profile.h"
 
+#include <algorithm>
+
 namespace mlpcp {
 
 namespace {
@@ -179,6 +181,157 @@ __global__ void __launch_bounds__(256) k_gram_reduce(const double* __restrict__ 
   if (g == 0 && idx < total) G[idx] = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
 }
 
+// ---------------------------------------------------------------------------------
+// Tall-skinny Gram for coarse widths k <= 64 (kp == 64): each block owns a row range
+// and computes every upper 16 x 16 tile of the (k rounded up to 16)-wide Gram from
+// 64-row chunks staged in LDS, the next chunk's loads in flight while the current one
+// is multiplied.  Wave w owns tiles w, w + 4, w + 8.  PREC 0: float32 operands
+// widened to float64 on v_mfma_f64_16x16x4f64 (exact products, float64 sums);
+// PREC 1 / 2: bfloat16 / split bfloat16 on v_mfma_f32_16x16x32_bf16, chunk sums in
+// float32 added in float64.  Partials: per split, tile u, 16 x 16 row-major.
+constexpr int TALL_ROWS = 64;
+constexpr int TALL_LD = 64 + 4;
+
+// upper tile u of an nt x nt tile grid, row by row -> (ti, tj), ti <= tj
+__device__ __forceinline__ void tall_tile(int u, int nt, int& ti, int& tj) {
+  ti = 0;
+  while (u >= nt - ti) {
+    u -= nt - ti;
+    ++ti;
+  }
+  tj = ti + u;
+}
+
+template <int PREC>
+__global__ void __launch_bounds__(256) k_gram_tall(const float* __restrict__ A, int m, int k, int lda,
+                                                   int rows_per_split, int nt, double* __restrict__ part) {
+  __shared__ float sX[TALL_ROWS][TALL_LD];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int U = nt * (nt + 1) / 2;
+  const int r0 = blockIdx.x * rows_per_split;
+  const int r1 = min(m, r0 + rows_per_split);
+  int ti[3], tj[3];
+  bool own[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    const int u = wave + 4 * x;
+    own[x] = u < U;
+    tall_tile(own[x] ? u : 0, nt, ti[x], tj[x]);
+  }
+  d4_t acc[3];
+#pragma unroll
+  for (int x = 0; x < 3; ++x) acc[x] = (d4_t){0.0, 0.0, 0.0, 0.0};
+  constexpr int PER = TALL_ROWS * 64 / 256;
+  const int kc = nt * 16;
+  float pre[PER];
+  auto fetch = [&](int c0) {
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int e = tid + 256 * x;
+      const int row = e >> 6, col = e & 63;
+      const int gr = c0 + row;
+      pre[x] = (gr < r1 && col < k) ? A[(size_t)gr * lda + col] : 0.0f;
+    }
+  };
+  fetch(r0);
+  for (int c0 = r0; c0 < r1; c0 += TALL_ROWS) {
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int e = tid + 256 * x;
+      const int col = e & 63;
+      if (col < kc) sX[e >> 6][col] = pre[x];
+    }
+    __syncthreads();
+    if (c0 + TALL_ROWS < r1) fetch(c0 + TALL_ROWS);
+#pragma unroll
+    for (int x = 0; x < 3; ++x) {
+      if (!own[x]) continue;
+      const int ci = ti[x] * 16 + (lane & 15), cj = tj[x] * 16 + (lane & 15);
+      if (PREC == 0) {
+#pragma unroll
+        for (int s = 0; s < TALL_ROWS / 4; ++s) {
+          const int kk = 4 * s + (lane >> 4);
+          acc[x] = __builtin_amdgcn_mfma_f64_16x16x4f64((double)sX[kk][ci], (double)sX[kk][cj], acc[x], 0, 0, 0);
+        }
+      } else {
+        constexpr int KS = TALL_ROWS / 32;
+        bf16x8_t ah[KS], bh[KS], al[KS], bl[KS];
+#pragma unroll
+        for (int s = 0; s < KS; ++s)
+#pragma unroll
+          for (int q = 0; q < 8; ++q) {
+            const int kk = 32 * s + 8 * (lane >> 4) + q;
+            const float xa = sX[kk][ci], xb = sX[kk][cj];
+            const unsigned short ha = f2bf(xa), hb = f2bf(xb);
+            ah[s][q] = __builtin_bit_cast(__bf16, ha);
+            bh[s][q] = __builtin_bit_cast(__bf16, hb);
+            al[s][q] = __builtin_bit_cast(__bf16, f2bf(xa - bf2f(ha)));
+            bl[s][q] = __builtin_bit_cast(__bf16, f2bf(xb - bf2f(hb)));
+          }
+        f32x4_t c = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+        for (int s = 0; s < KS; ++s) {
+          if (PREC == 2) {
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(al[s], bh[s], c, 0, 0, 0);
+            c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bl[s], c, 0, 0, 0);
+          }
+          c = __builtin_amdgcn_mfma_f32_16x16x32_bf16(ah[s], bh[s], c, 0, 0, 0);
+        }
+#pragma unroll
+        for (int v = 0; v < 4; ++v) acc[x][v] += (double)c[v];
+      }
+    }
+    __syncthreads();
+  }
+#pragma unroll
+  for (int x = 0; x < 3; ++x) {
+    if (!own[x]) continue;
+    double* P = part + ((size_t)blockIdx.x * U + (wave + 4 * x)) * 256;
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      // f64 output: register v of lane l is row 4v + l/16; bf16: row 4(l/16) + v
+      const int row = PREC == 0 ? 4 * v + (lane >> 4) : 4 * (lane >> 4) + v;
+      P[row * 16 + (lane & 15)] = acc[x][v];
+    }
+  }
+}
+
+// G from the tall partials: 64 tile entries per block, 4 thread groups each summing
+// every 4th split, then the group sums in order; each entry written to both halves.
+// In a diagonal tile only the upper triangle is used: the split product sums (i, j)
+// and (j, i) in different orders, so the two can differ in the last bits.
+__global__ void __launch_bounds__(256) k_gram_tall_reduce(const double* __restrict__ part, int splits, int nt,
+                                                          double* __restrict__ G, int ldg) {
+  __shared__ double red[4][64];
+  const int U = nt * (nt + 1) / 2;
+  const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
+  const int idx = blockIdx.x * 64 + e;
+  const int total = U * 256;
+  double s = 0.0;
+  if (idx < total)
+    for (int q = g; q < splits; q += 4) s += part[(size_t)q * total + idx];
+  red[g][e] = s;
+  __syncthreads();
+  if (g == 0 && idx < total) {
+    int a, b;
+    tall_tile(idx >> 8, nt, a, b);
+    const int r = (idx & 255) >> 4, c = idx & 15;
+    if (a == b && r > c) return;
+    const int i = a * 16 + r, j = b * 16 + c;
+    const double v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    G[(size_t)i * ldg + j] = v;
+    G[(size_t)j * ldg + i] = v;
+  }
+}
+
+void gram_tall_plan(int m, int nt, int& splits, int& rows_per_split) {
+  const int U = nt * (nt + 1) / 2;
+  const int target = U > 3 ? 256 : 512;
+  int rps = round_up((m + target - 1) / target, TALL_ROWS);
+  splits = (m + rps - 1) / rps;
+  rows_per_split = rps;
+}
+
 void gram_plan(int m, int kp, int& splits, int& rows_per_split, bool cross = false) {
   const int nt = kp / GT;
   const int pairs = cross ? nt * nt : nt * (nt + 1) / 2;
@@ -202,7 +355,13 @@ void gram_plan(int m, int kp, int& splits, int& rows_per_split, bool cross = fal
 size_t gram_workspace_bytes(int m, int kp) {
   int sp, rps;
   gram_plan(m, kp, sp, rps);
-  return align256((size_t)sp * kp * kp * sizeof(double));
+  size_t b = (size_t)sp * kp * kp * sizeof(double);
+  if (kp == 64)
+    for (int nt = 1; nt <= 4; ++nt) {
+      gram_tall_plan(m, nt, sp, rps);
+      b = std::max(b, (size_t)sp * (nt * (nt + 1) / 2) * 256 * sizeof(double));
+    }
+  return align256(b);
 }
 
 int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws, hipStream_t stream, int prec) {
@@ -213,6 +372,20 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
   const int pairs = nt * (nt + 1) / 2;
   double* part = static_cast<double*>(ws);
   ProfScope ps(KC_GRAM, stream);
+  if (kp == 64) {
+    const int nt = (k + 15) / 16;
+    gram_tall_plan(m, nt, sp, rps);
+    if (prec == MLPCP_BF16)
+      hipLaunchKernelGGL(k_gram_tall<1>, dim3(sp), dim3(256), 0, stream, A, m, k, lda, rps, nt, part);
+    else if (prec == MLPCP_BF16X3)
+      hipLaunchKernelGGL(k_gram_tall<2>, dim3(sp), dim3(256), 0, stream, A, m, k, lda, rps, nt, part);
+    else
+      hipLaunchKernelGGL(k_gram_tall<0>, dim3(sp), dim3(256), 0, stream, A, m, k, lda, rps, nt, part);
+    const int total = nt * (nt + 1) / 2 * 256;
+    hipLaunchKernelGGL(k_gram_tall_reduce, dim3((total + 63) / 64), dim3(256), 0, stream, part, sp, nt, G, kp);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
   if (prec == MLPCP_BF16)
     hipLaunchKernelGGL(k_gram_partial_bf16<1>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
   else if (prec == MLPCP_BF16X3)

@@ -16,6 +16,7 @@ enum KernelClass {
   KC_EPILOGUE,
   KC_REDUCE,
   KC_FINAL,
+  KC_COARSE_SMALL,
   KC_OTHER,
   KC_COUNT
 };

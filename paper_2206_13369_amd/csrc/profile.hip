@@ -12,7 +12,8 @@ namespace mlpcp {
 namespace {
 
 const char* kNames[KC_COUNT] = {"init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply",
-                                "jacobi_misc", "svt_prep", "epilogue", "reduce", "finalize", "other"};
+                                "jacobi_misc", "svt_prep", "epilogue", "reduce", "finalize", "coarse_svt_small",
+                                "other"};
 
 struct Pending {
   int cls;

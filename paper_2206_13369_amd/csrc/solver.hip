@@ -36,15 +36,6 @@ constexpr size_t kLdsBudget = 60 * 1024;
 
 enum Mode { MODE_STEP = 0, MODE_FINAL = 1, MODE_RECON = 2 };
 
-struct IterStats {
-  double fg2;      // sum of squared residuals on Q
-  double nrm2;     // ||P_Q D||_F^2 (init)
-  double margin;   // min |sigma - tau| / tau
-  double trace;    // sum of the coarse eigenvalues (||M_H||_F^2)
-  int rank;
-  int pad;
-};
-
 __device__ __forceinline__ float shrinkf(float e, float thr) {
   const float a = fabsf(e) - thr;
   return a > 0.0f ? copysignf(a, e) : 0.0f;
@@ -460,85 +451,105 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     }
     __syncthreads();
     constexpr int V = VEC ? 4 : 1;
+    constexpr int B = 4;   // groups per thread whose loads are issued together
     const int groups = rows * n / V;
-    for (int g = tid; g < groups; g += kThreads) {
-      const int e = g * V;
-      const int i = e / n, j0 = e % n;
-      const int gi = i0 + i;
-      float Lv[V], dv[V], zv[V];
+    for (int g0 = tid; g0 < groups; g0 += B * kThreads) {
+      float dv[B][V], zv[B][V];
+      uint32_t qbv[B];
+      int gib[B], j0b[B], ib[B];
 #pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const int j = j0 + v;
-        const float* nrow = sN + i * kLdN;
-        Lv[v] = fmaf(sRw[2 * j + 1], nrow[sRi[2 * j + 1]], sRw[2 * j] * nrow[sRi[2 * j]]);
-      }
-      const size_t gij = (size_t)gi * n + j0;
-      if (MODE == MODE_RECON) {
+      for (int b = 0; b < B; ++b) {
+        const int g = g0 + b * kThreads;
+        ib[b] = -1;
+        if (g >= groups) continue;
+        const int e = g * V;
+        const int i = e / n, j0 = e % n;
+        const int gi = i0 + i;
+        ib[b] = i; j0b[b] = j0; gib[b] = gi;
+        if (MODE == MODE_RECON) continue;
+        qbv[b] = 0xFu;
+        if (MASKED) qbv[b] = (a.bits[(size_t)gi * a.nw + (j0 >> 5)] >> (j0 & 31)) & (VEC ? 0xFu : 1u);
+        const size_t gij = (size_t)gi * n + j0;
         if (VEC) {
-          *reinterpret_cast<float4*>(a.Lout + gij) = make_float4(Lv[0], Lv[V > 1 ? 1 : 0], Lv[V > 2 ? 2 : 0], Lv[V > 3 ? 3 : 0]);
-        } else {
-          a.Lout[gij] = Lv[0];
-        }
-        continue;
-      }
-      uint32_t qb = 0xFu;
-      if (MASKED) qb = (a.bits[(size_t)gi * a.nw + (j0 >> 5)] >> (j0 & 31)) & (VEC ? 0xFu : 1u);
-      if (VEC) {
-        const float4 d4 = *reinterpret_cast<const float4*>(a.D + (size_t)gi * a.ldd + j0);
-        dv[0] = d4.x; dv[V > 1 ? 1 : 0] = d4.y; dv[V > 2 ? 2 : 0] = d4.z; dv[V > 3 ? 3 : 0] = d4.w;
-        if (MODE == MODE_FINAL || !a.first) {
-          const float4 z4 = *reinterpret_cast<const float4*>(a.Zin + gij);
-          zv[0] = z4.x; zv[V > 1 ? 1 : 0] = z4.y; zv[V > 2 ? 2 : 0] = z4.z; zv[V > 3 ? 3 : 0] = z4.w;
-        } else {
-#pragma unroll
-          for (int v = 0; v < V; ++v) zv[v] = 0.0f;
-        }
-      } else {
-        dv[0] = a.D[(size_t)gi * a.ldd + j0];
-        zv[0] = (MODE == MODE_FINAL || !a.first) ? a.Zin[gij] : 0.0f;
-      }
-      float o1[V], o2[V], o3[V];
-#pragma unroll
-      for (int v = 0; v < V; ++v) {
-        const bool q = (qb >> v) & 1u;
-        if (MODE == MODE_FINAL) {
-          const float ev = dv[v] + zv[v];
-          o1[v] = Lv[v];
-          o2[v] = q ? shrinkf(ev, a.thr) : 0.0f;
-          o3[v] = q ? fminf(fmaxf(a.mu * ev, -a.lam), a.lam) : 0.0f;
-        } else {
-          float ym;
-          if (a.first) {
-            ym = a.Y0 ? a.Y0[gij + v] * a.inv_mu : 0.0f;
+          const float4 d4 = *reinterpret_cast<const float4*>(a.D + (size_t)gi * a.ldd + j0);
+          dv[b][0] = d4.x; dv[b][V > 1 ? 1 : 0] = d4.y; dv[b][V > 2 ? 2 : 0] = d4.z; dv[b][V > 3 ? 3 : 0] = d4.w;
+          if (MODE == MODE_FINAL || !a.first) {
+            const float4 z4 = *reinterpret_cast<const float4*>(a.Zin + gij);
+            zv[b][0] = z4.x; zv[b][V > 1 ? 1 : 0] = z4.y; zv[b][V > 2 ? 2 : 0] = z4.z; zv[b][V > 3 ? 3 : 0] = z4.w;
           } else {
-            ym = fminf(fmaxf(dv[v] + zv[v], -a.thr_prev), a.thr_prev) * a.ratio_prev;
+#pragma unroll
+            for (int v = 0; v < V; ++v) zv[b][v] = 0.0f;
           }
-          const float wv = ym - Lv[v];
-          const float c = fminf(fmaxf(dv[v] + wv, -a.thr), a.thr);
-          const float res = c - ym;
-          if (q) racc += (double)res * (double)res;
-          o1[v] = q ? wv : Lv[v];                   // next state
-          o2[v] = q ? c * a.grow - wv : Lv[v];      // next coarse data X_{t+1}
+        } else {
+          dv[b][0] = a.D[(size_t)gi * a.ldd + j0];
+          zv[b][0] = (MODE == MODE_FINAL || !a.first) ? a.Zin[gij] : 0.0f;
         }
       }
-      if (MODE == MODE_FINAL) {
-        if (VEC) {
-          *reinterpret_cast<float4*>(a.Lout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
-          *reinterpret_cast<float4*>(a.Sout + gij) = make_float4(o2[0], o2[V > 1 ? 1 : 0], o2[V > 2 ? 2 : 0], o2[V > 3 ? 3 : 0]);
-          if (a.Yout)
-            *reinterpret_cast<float4*>(a.Yout + gij) = make_float4(o3[0], o3[V > 1 ? 1 : 0], o3[V > 2 ? 2 : 0], o3[V > 3 ? 3 : 0]);
-        } else {
-          a.Lout[gij] = o1[0];
-          a.Sout[gij] = o2[0];
-          if (a.Yout) a.Yout[gij] = o3[0];
-        }
-      } else {
-        if (VEC)
-          *reinterpret_cast<float4*>(a.Zout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
-        else
-          a.Zout[gij] = o1[0];
 #pragma unroll
-        for (int v = 0; v < V; ++v) sX[(size_t)i * n + j0 + v] = o2[v];
+      for (int b = 0; b < B; ++b) {
+        if (ib[b] < 0) continue;
+        const int i = ib[b], j0 = j0b[b];
+        float Lv[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const int j = j0 + v;
+          const float* nrow = sN + i * kLdN;
+          Lv[v] = fmaf(sRw[2 * j + 1], nrow[sRi[2 * j + 1]], sRw[2 * j] * nrow[sRi[2 * j]]);
+        }
+        const size_t gij = (size_t)gib[b] * n + j0;
+        if (MODE == MODE_RECON) {
+          if (VEC) {
+            *reinterpret_cast<float4*>(a.Lout + gij) =
+                make_float4(Lv[0], Lv[V > 1 ? 1 : 0], Lv[V > 2 ? 2 : 0], Lv[V > 3 ? 3 : 0]);
+          } else {
+            a.Lout[gij] = Lv[0];
+          }
+          continue;
+        }
+        const uint32_t qb = qbv[b];
+        float o1[V], o2[V], o3[V];
+#pragma unroll
+        for (int v = 0; v < V; ++v) {
+          const bool q = (qb >> v) & 1u;
+          if (MODE == MODE_FINAL) {
+            const float ev = dv[b][v] + zv[b][v];
+            o1[v] = Lv[v];
+            o2[v] = q ? shrinkf(ev, a.thr) : 0.0f;
+            o3[v] = q ? fminf(fmaxf(a.mu * ev, -a.lam), a.lam) : 0.0f;
+          } else {
+            float ym;
+            if (a.first) {
+              ym = a.Y0 ? a.Y0[gij + v] * a.inv_mu : 0.0f;
+            } else {
+              ym = fminf(fmaxf(dv[b][v] + zv[b][v], -a.thr_prev), a.thr_prev) * a.ratio_prev;
+            }
+            const float wv = ym - Lv[v];
+            const float c = fminf(fmaxf(dv[b][v] + wv, -a.thr), a.thr);
+            const float res = c - ym;
+            if (q) racc += (double)res * (double)res;
+            o1[v] = q ? wv : Lv[v];                   // next state
+            o2[v] = q ? c * a.grow - wv : Lv[v];      // next coarse data X_{t+1}
+          }
+        }
+        if (MODE == MODE_FINAL) {
+          if (VEC) {
+            *reinterpret_cast<float4*>(a.Lout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
+            *reinterpret_cast<float4*>(a.Sout + gij) = make_float4(o2[0], o2[V > 1 ? 1 : 0], o2[V > 2 ? 2 : 0], o2[V > 3 ? 3 : 0]);
+            if (a.Yout)
+              *reinterpret_cast<float4*>(a.Yout + gij) = make_float4(o3[0], o3[V > 1 ? 1 : 0], o3[V > 2 ? 2 : 0], o3[V > 3 ? 3 : 0]);
+          } else {
+            a.Lout[gij] = o1[0];
+            a.Sout[gij] = o2[0];
+            if (a.Yout) a.Yout[gij] = o3[0];
+          }
+        } else {
+          if (VEC)
+            *reinterpret_cast<float4*>(a.Zout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
+          else
+            a.Zout[gij] = o1[0];
+#pragma unroll
+          for (int v = 0; v < V; ++v) sX[(size_t)i * n + j0 + v] = o2[v];
+        }
       }
     }
     if (MODE == MODE_STEP) {
@@ -761,6 +772,12 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   double* Tt = w.at<double>(p.off_Tt);
   IterStats* st = w.at<IterStats>(p.off_stats);
   MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.nHp, G, w.at<void>(p.off_gram), s, gram_prec));
+  if (p.nHp == kEigInner) {
+    // one workgroup from the Gram to the reconstruction factors; sweeps come back in st
+    *sweeps = kSweepsOnDevice;
+    return coarse_svt_small(p.nH, p.nHp, G, p.plain ? nullptr : op.C, V, warm, tau, lam, perm, sw, T, Tt,
+                            p.tall ? w.at<double>(p.off_K) : nullptr, st, s);
+  }
   double* GH = G;
   if (!p.plain) {
     ProfScope ps(KC_COARSE, s);
@@ -784,6 +801,13 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
                        kTallNH, T, p.nHp, st, w.at<double>(p.off_K));
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
+}
+
+// After the stream sync that read `hs`: the sweep count of the last coarse SVT (from
+// the device when the one-workgroup path ran) and MLPCP_E_EIG if it hit the cap.
+int resolve_sweeps(int& sweeps, const IterStats& hs) {
+  if (sweeps == kSweepsOnDevice) sweeps = hs.sweeps;
+  return sweeps < 0 ? MLPCP_E_EIG : MLPCP_OK;
 }
 
 bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) == 0; }
@@ -934,6 +958,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
     MLPCP_HIP(hipStreamSynchronize(s));
     prof_drain();
+    MLPCP_TRY(resolve_sweeps(sweeps, hs));
     fg = std::sqrt(hs.fg2) / nrmD;
     rank = hs.rank;
     margin = hs.margin;
@@ -1267,6 +1292,7 @@ int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
   IterStats hs;
   MLPCP_HIP(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
   MLPCP_HIP(hipStreamSynchronize(s));
+  MLPCP_TRY(resolve_sweeps(sweeps, hs));
   if (rank) *rank = hs.rank;
   return MLPCP_OK;
 }
@@ -1304,6 +1330,7 @@ int mlpcp_ialm_step(int m, int n, int levels, const float* D, int ldd, const flo
   IterStats hs;
   MLPCP_HIP(hipMemcpyAsync(&hs, w.at<IterStats>(sp.p.off_stats), sizeof(hs), hipMemcpyDeviceToHost, s));
   MLPCP_HIP(hipStreamSynchronize(s));
+  if (sp.p.nHp == kEigInner && hs.sweeps < 0) return MLPCP_E_EIG;
   if (rank) *rank = hs.rank;
   return MLPCP_OK;
 }
@@ -1392,6 +1419,12 @@ int mlpcp_ialm_step_vjp(int m, int n, int levels, const float* D, int ldd, const
     *lambda_bar += hl;
   } else {
     MLPCP_HIP(hipStreamSynchronize(s));
+  }
+  if (p.nHp == kEigInner) {
+    IterStats hs;
+    MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+    MLPCP_HIP(hipStreamSynchronize(s));
+    if (hs.sweeps < 0) return MLPCP_E_EIG;
   }
   return MLPCP_OK;
 }
