@@ -35,6 +35,12 @@ constexpr int IB = kEigBlock;       // 32
 constexpr int IN = kEigInner;       // 64
 constexpr int LDS_LD = IN + 1;
 constexpr double kRelEps2 = 1.0e-30;  // (1e-15)^2
+// Absolute rotation floor of the one-workgroup solver, relative to trace(A): an
+// off-diagonal entry below it moves an eigenvalue by less than that share of the
+// trace and the reconstruction L = M_P C V diag(w) V^T C by a comparable share of
+// its norm, far below float32 resolution; it stops sweeps that would only refine
+// eigenvectors of clusters of tiny eigenvalues to their own relative precision.
+constexpr double kSmallAbsTol = 1.0e-14;
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -83,6 +89,42 @@ __device__ __forceinline__ bool rotation(double app, double aqq, double apq, dou
   t = 2.0 * apq / (fabs(d) + r);
   if (d < 0.0) t = -t;
   c = 1.0 / sqrt(1.0 + t * t);
+  s = t * c;
+  return true;
+}
+
+// The rotation of `rotation` with the square roots and quotients taken from the
+// hardware reciprocal (square root) estimates and two Newton steps each, which
+// leaves them within a few units of the last place: c^2 + s^2 = 1 holds to that
+// accuracy, which is what keeps the accumulated factor orthogonal.  Used by the
+// one-workgroup solver, whose rounds are bound by this latency.
+__device__ __forceinline__ double rsq_nr(double x) {
+  double y = __builtin_amdgcn_rsq(x);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  y = y * fma(-0.5 * x * y, y, 1.5);
+  return y;
+}
+__device__ __forceinline__ double rcp_nr(double x) {
+  double y = __builtin_amdgcn_rcp(x);
+  y = y * fma(-x, y, 2.0);
+  y = y * fma(-x, y, 2.0);
+  return y;
+}
+__device__ __forceinline__ bool rotation_fast(double app, double aqq, double apq, double floor_abs, double& c,
+                                              double& s, double& t) {
+  const double a2 = apq * apq;
+  if (!(fabs(apq) > floor_abs && a2 > kRelEps2 * fabs(app * aqq))) {
+    c = 1.0;
+    s = 0.0;
+    t = 0.0;
+    return false;
+  }
+  const double d = aqq - app;
+  const double r2 = fma(d, d, 4.0 * a2);
+  const double r = r2 * rsq_nr(r2);
+  t = 2.0 * apq * rcp_nr(fabs(d) + r);
+  if (d < 0.0) t = -t;
+  c = rsq_nr(fma(t, t, 1.0));
   s = t * c;
   return true;
 }
@@ -371,6 +413,118 @@ __device__ __forceinline__ bool rotates(double app, double aqq, double apq, doub
   return fabs(apq) > floor_abs && apq * apq > kRelEps2 * fabs(app * aqq);
 }
 
+// pair k of round r of the circle method on ne players (player 0 fixed), p < q
+__device__ __forceinline__ void pair_at(int ne, int k, int r, int& p, int& q) {
+  const int m1 = ne - 1;
+  int x = k - 1 + r;
+  x = x >= m1 ? x - m1 : x;
+  const int px = k == 0 ? 0 : 1 + x;
+  int y = ne - 2 - k + r;
+  y = y >= m1 ? y - m1 : y;
+  const int py = 1 + y;
+  p = min(px, py);
+  q = max(px, py);
+}
+
+// Jacobi sweeps on the leading ne x ne block of A (LDS), Q <- Q J, until the rotation
+// test passes for no pair (returns true) or max_sweeps sweeps ran.  ACTIVE threads
+// take part in the rounds, each owning MT 2x2 tiles (pair a rows, pair b columns) and
+// MQ (row, pair) items of Q for the whole iteration; the pairs' indices per round
+// follow from the circle method arithmetically, so all loads of a round are issued
+// at once, without branches.  Slots beyond the item counts point at the padding
+// column IN of the thread's own lane row, which no result ever reads.
+template <int ACTIVE, int MT, int MQ>
+__device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, int max_sweeps, double* pc, double* ps,
+                             double* pt, int& sweeps) {
+  constexpr int kPadCol = IN;
+  const int tid = threadIdx.x, lane = tid & 63;
+  const int np = ne / 2;
+  int ta_[MT], tb_[MT], qi_[MQ], qb_[MQ];
+  bool tv_[MT], qv_[MQ];
+#pragma unroll
+  for (int x = 0; x < MT; ++x) {
+    const int e = tid + ACTIVE * x;
+    tv_[x] = e < np * np;
+    ta_[x] = tv_[x] ? e / np : 0;
+    tb_[x] = tv_[x] ? e % np : 0;
+  }
+#pragma unroll
+  for (int x = 0; x < MQ; ++x) {
+    const int e = tid + ACTIVE * x;
+    qv_[x] = e < ne * np;
+    qi_[x] = qv_[x] ? e / np : lane;
+    qb_[x] = qv_[x] ? e % np : 0;
+  }
+  for (sweeps = 0;; ++sweeps) {
+    int want = 0;
+    for (int it = tid; it < ne * ne; it += blockDim.x) {
+      const int i = it / ne, j = it % ne;
+      if (i < j && rotates(sA[i][i], sA[j][j], sA[i][j], fl)) want = 1;
+    }
+    if (!__syncthreads_or(want)) return true;
+    if (sweeps == max_sweeps) return false;
+    for (int r = 0; r < ne - 1; ++r) {
+      if (tid < np) {
+        int p, q;
+        pair_at(ne, tid, r, p, q);
+        double c, sn, t;
+        rotation_fast(sA[p][p], sA[q][q], sA[p][q], fl, c, sn, t);
+        pc[tid] = c; ps[tid] = sn; pt[tid] = t;
+      }
+      __syncthreads();
+      if (tid < ACTIVE) {
+        double t00[MT], t01[MT], t10[MT], t11[MT], qx[MQ], qy[MQ];
+        int rp[MT], rq[MT], cp[MT], cq[MT], qp[MQ], qq[MQ];
+#pragma unroll
+        for (int x = 0; x < MT; ++x) {
+          pair_at(ne, ta_[x], r, rp[x], rq[x]);
+          pair_at(ne, tb_[x], r, cp[x], cq[x]);
+          if (!tv_[x]) {
+            rp[x] = lane; rq[x] = lane;
+            cp[x] = kPadCol; cq[x] = kPadCol;
+          }
+          t00[x] = sA[rp[x]][cp[x]]; t01[x] = sA[rp[x]][cq[x]];
+          t10[x] = sA[rq[x]][cp[x]]; t11[x] = sA[rq[x]][cq[x]];
+        }
+#pragma unroll
+        for (int x = 0; x < MQ; ++x) {
+          pair_at(ne, qb_[x], r, qp[x], qq[x]);
+          if (!qv_[x]) {
+            qp[x] = kPadCol; qq[x] = kPadCol;
+          }
+          qx[x] = sQ[qi_[x]][qp[x]]; qy[x] = sQ[qi_[x]][qq[x]];
+        }
+#pragma unroll
+        for (int x = 0; x < MT; ++x) {
+          const int a = ta_[x], b = tb_[x];
+          const double ca = pc[a], sa = ps[a], cb = pc[b], sb = ps[b], ta = pt[a];
+          const double u00 = ca * t00[x] - sa * t10[x], u01 = ca * t01[x] - sa * t11[x];
+          const double u10 = sa * t00[x] + ca * t10[x], u11 = sa * t01[x] + ca * t11[x];
+          double n00 = u00 * cb - u01 * sb;
+          double n01 = u00 * sb + u01 * cb;
+          double n10 = u10 * cb - u11 * sb;
+          double n11 = u10 * sb + u11 * cb;
+          if (a == b) {   // diagonal 2x2 tile: exact form of the annihilation
+            n00 = t00[x] - ta * t01[x];
+            n11 = t11[x] + ta * t01[x];
+            n01 = ta != 0.0 ? 0.0 : t01[x];
+            n10 = n01;
+          }
+          sA[rp[x]][cp[x]] = n00; sA[rp[x]][cq[x]] = n01;
+          sA[rq[x]][cp[x]] = n10; sA[rq[x]][cq[x]] = n11;
+        }
+#pragma unroll
+        for (int x = 0; x < MQ; ++x) {
+          const double c = pc[qb_[x]], sn = ps[qb_[x]];
+          sQ[qi_[x]][qp[x]] = c * qx[x] - sn * qy[x];
+          sQ[qi_[x]][qq[x]] = sn * qx[x] + c * qy[x];
+        }
+      }
+      __syncthreads();
+    }
+  }
+}
+
 __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const double* __restrict__ G,
                                                       const double* __restrict__ C, double* __restrict__ V,
                                                       int warm, double tau, int max_sweeps,
@@ -384,7 +538,7 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
   LdsRow* sC = sQ + IN;
   LdsRow* sW = sC + IN;
   __shared__ double pc[IB], ps[IB], pt[IB], swv[IN], red[256];
-  __shared__ int pp[IB], pq[IB], prm[IN], redi[256];
+  __shared__ int prm[IN], redi[256];
   const int tid = threadIdx.x;
   d4_t acc[2][2];
   for (int it = tid; it < IN * IN; it += 256) {
@@ -429,98 +583,20 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
     if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
-  const double fl = 1.0e-16 * red[0] + 1.0e-300;
+  const double fl = kSmallAbsTol * red[0] + 1.0e-300;
   const int ne = nH + (nH & 1), np = ne / 2;
-  // this thread's 2x2 tiles (pair a rows, pair b columns) and (row, pair) items of
-  // Q, fixed for the whole iteration (only the pairs' indices change per round)
-  constexpr int MT = (IB * IB) / 256, MQ = (IN * IB) / 256;
-  int ta_[MT], tb_[MT], qi_[MQ], qb_[MQ];
-#pragma unroll
-  for (int x = 0; x < MT; ++x) {
-    const int e = tid + 256 * x;
-    ta_[x] = e < np * np ? e / np : -1;
-    tb_[x] = e < np * np ? e % np : 0;
-  }
-#pragma unroll
-  for (int x = 0; x < MQ; ++x) {
-    const int e = tid + 256 * x;
-    qi_[x] = e < ne * np ? e / np : -1;
-    qb_[x] = e < ne * np ? e % np : 0;
-  }
   int sweeps = 0;
   bool conv = false;
-  for (;; ++sweeps) {
-    int want = 0;
-    for (int it = tid; it < ne * ne; it += 256) {
-      const int i = it / ne, j = it % ne;
-      if (i < j && rotates(sA[i][i], sA[j][j], sA[i][j], fl)) want = 1;
-    }
-    if (!__syncthreads_or(want)) {
-      conv = true;
-      break;
-    }
-    if (sweeps == max_sweeps) break;
-    for (int r = 0; r < ne - 1; ++r) {
-      if (tid < np) {
-        int p, q;
-        rr_pair(tid, r, ne, p, q);
-        double c, sn, t;
-        rotation(sA[p][p], sA[q][q], sA[p][q], fl, c, sn, t);
-        pp[tid] = p; pq[tid] = q;
-        pc[tid] = c; ps[tid] = sn; pt[tid] = t;
-      }
-      __syncthreads();
-      // all loads of a thread first, then the stores (the items are disjoint)
-      double t00[MT], t01[MT], t10[MT], t11[MT], qx[MQ], qy[MQ];
-      int rp[MT], rq[MT], cp[MT], cq[MT], qp[MQ], qq[MQ];
-#pragma unroll
-      for (int x = 0; x < MT; ++x) {
-        if (ta_[x] >= 0) {
-          rp[x] = pp[ta_[x]]; rq[x] = pq[ta_[x]]; cp[x] = pp[tb_[x]]; cq[x] = pq[tb_[x]];
-          t00[x] = sA[rp[x]][cp[x]]; t01[x] = sA[rp[x]][cq[x]];
-          t10[x] = sA[rq[x]][cp[x]]; t11[x] = sA[rq[x]][cq[x]];
-        }
-      }
-#pragma unroll
-      for (int x = 0; x < MQ; ++x) {
-        if (qi_[x] >= 0) {
-          qp[x] = pp[qb_[x]]; qq[x] = pq[qb_[x]];
-          qx[x] = sQ[qi_[x]][qp[x]]; qy[x] = sQ[qi_[x]][qq[x]];
-        }
-      }
-#pragma unroll
-      for (int x = 0; x < MT; ++x) {
-        if (ta_[x] >= 0) {
-          const int a = ta_[x], b = tb_[x];
-          const double ca = pc[a], sa = ps[a], cb = pc[b], sb = ps[b];
-          const double u00 = ca * t00[x] - sa * t10[x], u01 = ca * t01[x] - sa * t11[x];
-          const double u10 = sa * t00[x] + ca * t10[x], u11 = sa * t01[x] + ca * t11[x];
-          double n00 = u00 * cb - u01 * sb;
-          double n01 = u00 * sb + u01 * cb;
-          double n10 = u10 * cb - u11 * sb;
-          double n11 = u10 * sb + u11 * cb;
-          if (a == b) {   // diagonal 2x2 tile: exact form of the annihilation
-            const double ta = pt[a];
-            n00 = t00[x] - ta * t01[x];
-            n11 = t11[x] + ta * t01[x];
-            n01 = ta != 0.0 ? 0.0 : t01[x];
-            n10 = n01;
-          }
-          sA[rp[x]][cp[x]] = n00; sA[rp[x]][cq[x]] = n01;
-          sA[rq[x]][cp[x]] = n10; sA[rq[x]][cq[x]] = n11;
-        }
-      }
-#pragma unroll
-      for (int x = 0; x < MQ; ++x) {
-        if (qi_[x] >= 0) {
-          const double c = pc[qb_[x]], sn = ps[qb_[x]];
-          sQ[qi_[x]][qp[x]] = c * qx[x] - sn * qy[x];
-          sQ[qi_[x]][qq[x]] = sn * qx[x] + c * qy[x];
-        }
-      }
-      __syncthreads();
-    }
-  }
+  if (ne <= 16)
+    conv = small_sweeps<64, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+  else if (ne <= 32)
+    conv = small_sweeps<256, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+  else if (ne <= 44)
+    conv = small_sweeps<256, 2, 4>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+  else if (ne <= 54)
+    conv = small_sweeps<256, 3, 6>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+  else
+    conv = small_sweeps<256, 4, 8>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
   // eigenvalues, descending order (ties by index), weights, rank, margin, trace
   double li = 0.0;
   if (tid < IN) {
