@@ -15,6 +15,7 @@ Prints ONE JSON line.  Options: --steps K --warmup W --gpus N (N must be 1)
 --workload {c1,c2,c3,c5} --no-plain --no-cpu --prec {fp32,bf16,bf16x3}.
 """
 import argparse
+import hashlib
 import json
 import math
 import os
@@ -42,6 +43,9 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "bf16x3"],
                     help="arithmetic of the coarse SVT's Gram and reconstruction products")
+    ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
+                    help="run one elementwise copy of MIB MiB (read MIB, write MIB) before the solves, "
+                         "the reference kernel for scaling HBM byte counters")
     return ap.parse_args()
 
 
@@ -53,9 +57,11 @@ def describe(w):
             f"(n_H={int(__import__('oracle').coarse_dim(w.n, w.levels))}), FG<=1e-6; {w.recipe}")
 
 
-def algorithmic_work(cls, w, nH, plain):
+def algorithmic_work(cls, w, nH, plain, sweeps):
     """(bound, amount per launch) of the method's own work for one launch of a kernel
-    class: HBM bytes the kernel must move, or float64 flops."""
+    class: HBM bytes the kernel must move ("hbm"), or float64 flops ("mfma" for the
+    matrix-core products, "alu" for the latency-bound Jacobi rounds).  `sweeps` is the
+    per-iteration Jacobi sweep count of the solve."""
     m, n = w.m, w.n
     masked = w.Q is not None
     k = n if plain else nH
@@ -67,16 +73,65 @@ def algorithmic_work(cls, w, nH, plain):
     if cls == "finalize":
         return "hbm", 16.0 * m * n + 4.0 * m * k
     if cls == "gram":
-        return "mfma", 1.0 * m * k * (k + 1)
+        # G = M_P^T M_P on float64 MFMA: 2 m k^2 flops over 4 m k bytes; the bound is
+        # whichever side of the float64 ridge (9.8 flop/B) the intensity k/2 falls on
+        flops, byts = 2.0 * m * k * k, 4.0 * m * k
+        return ("mfma", flops) if flops / byts > FP64_PEAK / HBM_PEAK else ("hbm", byts)
+    sw = (sum(sweeps) / len(sweeps)) if sweeps else 0.0
+    if cls == "coarse_svt_small":
+        # rounds of the circle method: ne/2 rotations; each 2x2 tile of A (ne/2)^2 tiles,
+        # 24 flops; each (row, pair) of the factor ne * ne/2 items, 6 flops; plus six
+        # 64^3 float64 MFMA products (C G C, warm start, T = C W, K = T T^T)
+        ne = k + (k & 1)
+        per_round = (ne // 2) ** 2 * 24.0 + ne * (ne // 2) * 6.0
+        return "alu", sw * (ne - 1) * per_round + 6 * 2.0 * 64 ** 3
     N = int(math.ceil(k / 64.0)) * 64
     npairs = N // 64
     if cls == "jacobi_apply":
         # off-diagonal A tiles (two 64^3 products) + V tiles (one), float64
-        return "alu", 2.0 * (2 * 64 ** 3) * (npairs * (npairs - 1) // 2) + 2.0 * 64 ** 3 * (N // 64) * npairs
+        return "mfma", 2.0 * (2 * 64 ** 3) * (npairs * (npairs - 1) // 2) + 2.0 * 64 ** 3 * (N // 64) * npairs
     if cls == "jacobi_pairs":
         # 32 rounds of 32 rotations on a 64x64 block and its 64x64 factor
         return "alu", npairs * 32 * 32 * (64 * 6 + 64 * 6)
     return None, None
+
+
+def sources_sha256():
+    """Hash of the kernel sources: HBM traffic measured for other sources is not reused."""
+    h = hashlib.sha256()
+    csrc = os.path.join(ROOT, "paper_2206_13369_amd", "csrc")
+    for name in sorted(os.listdir(csrc)):
+        if name.endswith((".hip", ".h")):
+            h.update(name.encode())
+            h.update(open(os.path.join(csrc, name), "rb").read())
+    h.update(open(os.path.join(ROOT, "include", "mlpcp.h"), "rb").read())
+    return h.hexdigest()
+
+
+def measured_traffic(workload, cls):
+    """HBM bytes per launch of a kernel class from the rocprofv3 FETCH_SIZE / WRITE_SIZE
+    runs recorded in profiles/hbm_traffic.json, if they were taken on these sources."""
+    path = os.path.join(ROOT, "profiles", "hbm_traffic.json")
+    if not os.path.exists(path):
+        return None
+    data = json.load(open(path))
+    if data.get("sources_sha256") != sources_sha256():
+        return None
+    return data.get("workloads", {}).get(workload, {}).get(cls)
+
+
+def roofline(cls, bound, amount, avg_s, launches):
+    if bound is None or not launches:
+        return None
+    if bound == "hbm":
+        ach = amount / avg_s / 1e9
+        return dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK / 1e9, unit="GB/s",
+                    frac=round(ach / (HBM_PEAK / 1e9), 4), traffic=None, kernel=cls,
+                    avg_launch_us=round(avg_s * 1e6, 2), launches=launches, algorithmic_bytes_per_launch=amount)
+    ach = amount / avg_s / 1e12
+    return dict(bound=bound, achieved=round(ach, 4), peak=FP64_PEAK / 1e12, unit="TFLOP/s",
+                frac=round(ach / (FP64_PEAK / 1e12), 5), traffic=None, kernel=cls,
+                avg_launch_us=round(avg_s * 1e6, 2), launches=launches, algorithmic_flops_per_launch=amount)
 
 
 def main():
@@ -102,6 +157,12 @@ def main():
     print(f"[bench] workload {w.name} {w.m}x{w.n} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
     D = torch.from_numpy(w.D).to(dev)
     Q = torch.from_numpy(w.Q.astype(np.uint8)).to(dev) if w.Q is not None else None
+    if a.calib_copy:
+        src = torch.ones(a.calib_copy << 18, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        torch.mul(src, 1.0, out=dst)
+        torch.cuda.synchronize()
+        del src, dst
     nH = mlp.coarse_dim(w.n, w.levels)
 
     def run(levels, ws):
@@ -177,30 +238,20 @@ def main():
               file=sys.stderr, flush=True)
         del ws_pl
 
-    # roofline of the dominant kernel, from its event-timed launches
-    bound, amount = algorithmic_work(dom, w, nH, False)
-    roof = None
-    if bound is not None and dom_launches:
-        avg_s = dom_ms / 1e3 / dom_launches
-        if bound == "hbm":
-            ach = amount / avg_s / 1e9
-            roof = dict(bound="hbm", achieved=round(ach, 2), peak=HBM_PEAK / 1e9, unit="GB/s",
-                        frac=round(ach / (HBM_PEAK / 1e9), 4), traffic=None, kernel=dom,
-                        avg_launch_us=round(avg_s * 1e6, 2), launches=dom_launches,
-                        algorithmic_bytes_per_launch=amount)
-        else:
-            ach = amount / avg_s / 1e12
-            roof = dict(bound=bound, achieved=round(ach, 4), peak=FP64_PEAK / 1e12, unit="TFLOP/s",
-                        frac=round(ach / (FP64_PEAK / 1e12), 5), traffic=None, kernel=dom,
-                        avg_launch_us=round(avg_s * 1e6, 2), launches=dom_launches,
-                        algorithmic_flops_per_launch=amount)
-    # the streaming epilogue's HBM roofline (from the breakdown solve)
-    epi = None
-    if launches.get("epilogue"):
-        avg_s = kernel_ms["epilogue"] / 1e3 / launches["epilogue"]
-        _, b = algorithmic_work("epilogue", w, nH, False)
-        epi = dict(achieved_GBps=round(b / avg_s / 1e9, 1), frac=round(b / avg_s / HBM_PEAK, 4),
-                   avg_launch_us=round(avg_s * 1e6, 2), bytes_per_launch=b)
+    # roofline of the dominant kernel, from its event-timed launches; the other kernel
+    # classes from the all-class breakdown solve
+    sweeps = r.sweeps_history
+    bound, amount = algorithmic_work(dom, w, nH, False, sweeps)
+    roof = roofline(dom, bound, amount, dom_ms / 1e3 / max(dom_launches, 1), dom_launches)
+    if roof is not None:
+        roof["traffic"] = measured_traffic(w.name, dom)
+    others = {}
+    for cls in kernel_ms:
+        bd, am = algorithmic_work(cls, w, nH, False, sweeps)
+        rf = roofline(cls, bd, am, kernel_ms[cls] / 1e3 / launches[cls], launches[cls])
+        if rf is not None:
+            others[cls] = {k: rf[k] for k in ("bound", "achieved", "unit", "frac", "avg_launch_us")}
+            others[cls]["traffic"] = measured_traffic(w.name, cls)
 
     cpu = None
     if not a.no_cpu:
@@ -246,7 +297,8 @@ def main():
         "kernel_ms_per_solve": kernel_ms,
         "launches_per_solve": launches,
         "plain_kernel_ms_per_solve": None if plain is None else plain["kernel_ms"],
-        "epilogue_roofline": epi,
+        "sweeps_per_iteration": sweeps,
+        "kernel_rooflines": others,
         "roofline": roof,
         "cpu_baseline": cpu,
     }

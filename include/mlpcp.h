@@ -105,6 +105,8 @@ typedef struct {
   int history_len;         /* in: length of the two arrays                    */
   int gram_bf16_iters;     /* iterations whose Gram ran in plain bfloat16     */
   int gram_split_iters;    /* iterations whose Gram ran in split bfloat16     */
+  int* sweeps_history;     /* in: optional host array (history_len entries):  */
+                           /* Jacobi sweeps of each iteration's eigensolve    */
 } mlpcp_info;
 
 /* Fills defaults: levels 0, tol 1e-6, max_iter 500, rho 1.5, mu_max_factor 1e7,

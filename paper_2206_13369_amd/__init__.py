@@ -51,7 +51,7 @@ class Info(ctypes.Structure):
                 ("mu_final", ctypes.c_double), ("tau_margin", ctypes.c_double), ("eig_sweeps", ctypes.c_int),
                 ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
                 ("history_len", ctypes.c_int), ("gram_bf16_iters", ctypes.c_int),
-                ("gram_split_iters", ctypes.c_int)]
+                ("gram_split_iters", ctypes.c_int), ("sweeps_history", ctypes.POINTER(ctypes.c_int))]
 
 
 class KernelTime(ctypes.Structure):
@@ -204,6 +204,7 @@ class SolveResult:
     rank_history: list
     gram_bf16_iters: int = 0
     gram_split_iters: int = 0
+    sweeps_history: list = dataclasses.field(default_factory=list)
 
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
@@ -245,9 +246,11 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
     info = Info()
     fh = (ctypes.c_double * history)() if history else None
     rh = (ctypes.c_int * history)() if history else None
+    sh = (ctypes.c_int * history)() if history else None
     if history:
         info.fg_history = fh
         info.rank_history = rh
+        info.sweeps_history = sh
         info.history_len = history
     ld = D.stride(0)
     if Q is None:
@@ -266,7 +269,8 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
     k = min(info.iters, history) if history else 0
     return SolveResult(L, S, Y, st, info.iters, info.fg, info.rank, info.mu_final, info.tau_margin, info.eig_sweeps,
                        [fh[i] for i in range(k)] if history else [], [rh[i] for i in range(k)] if history else [],
-                       info.gram_bf16_iters, info.gram_split_iters)
+                       info.gram_bf16_iters, info.gram_split_iters,
+                       [sh[i] for i in range(k)] if history else [])
 
 
 def pcp_solve(D, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,

@@ -20,7 +20,7 @@
 //  Problems of width 64 are solved by one kernel directly.
 //  Rotation threshold (relative, Demmel-Veselic style, with an absolute floor for
 //  singular Grams and for the rounding the tile products leave): rotate (p,q) iff
-//  a_pq^2 > (1e-15)^2 |a_pp a_qq| and |a_pq| > 1e-16 trace(A).
+//  a_pq^2 > (1e-15)^2 |a_pp a_qq| and |a_pq| > 1e-14 trace(A) (kAbsTol).
 #include "common.h"
 #include "profile.h"
 
@@ -35,12 +35,12 @@ constexpr int IB = kEigBlock;       // 32
 constexpr int IN = kEigInner;       // 64
 constexpr int LDS_LD = IN + 1;
 constexpr double kRelEps2 = 1.0e-30;  // (1e-15)^2
-// Absolute rotation floor of the one-workgroup solver, relative to trace(A): an
-// off-diagonal entry below it moves an eigenvalue by less than that share of the
-// trace and the reconstruction L = M_P C V diag(w) V^T C by a comparable share of
-// its norm, far below float32 resolution; it stops sweeps that would only refine
-// eigenvectors of clusters of tiny eigenvalues to their own relative precision.
-constexpr double kSmallAbsTol = 1.0e-14;
+// Absolute rotation floor, relative to trace(A): an off-diagonal entry below it moves
+// an eigenvalue by less than that share of the trace and the reconstruction
+// L = M_P C V diag(w) V^T C by a comparable share of its norm, far below float32
+// resolution; it stops sweeps that would only refine eigenvectors of clusters of
+// tiny eigenvalues to their own relative precision.
+constexpr double kAbsTol = 1.0e-14;
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -151,7 +151,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       int p, q;
       inner_pair(phase, s, tid, p, q);
       double c, sn, t;
-      const bool on = rotation(A[p][p], A[q][q], A[p][q], floor_abs, c, sn, t);
+      const bool on = rotation_fast(A[p][p], A[q][q], A[p][q], floor_abs, c, sn, t);
       rs.c[tid] = c;
       rs.s[tid] = sn;
       rs.t[tid] = t;
@@ -214,7 +214,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
   }
 }
 
-// trace(A) -> floor = 1e-16 * |trace| (one block)
+// trace(A) -> floor = kAbsTol * |trace| (one block)
 __global__ void k_floor(const double* __restrict__ A, int N, double* __restrict__ floor_out) {
   __shared__ double red[256];
   double s = 0.0;
@@ -225,7 +225,7 @@ __global__ void k_floor(const double* __restrict__ A, int N, double* __restrict_
     if (threadIdx.x < w) red[threadIdx.x] += red[threadIdx.x + w];
     __syncthreads();
   }
-  if (threadIdx.x == 0) floor_out[0] = 1.0e-16 * red[0] + 1.0e-300;
+  if (threadIdx.x == 0) floor_out[0] = kAbsTol * red[0] + 1.0e-300;
 }
 
 // Whole problem (N == IN) in one block: full sweeps until nothing rotates.
@@ -576,14 +576,14 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
       sA[j][i] = v;
     }
   }
-  // absolute floor of the rotation test: 1e-16 trace
+  // absolute floor of the rotation test: kAbsTol trace
   red[tid] = tid < nH ? fabs(sA[tid][tid]) : 0.0;
   __syncthreads();
   for (int w = 128; w > 0; w >>= 1) {
     if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
-  const double fl = kSmallAbsTol * red[0] + 1.0e-300;
+  const double fl = kAbsTol * red[0] + 1.0e-300;
   const int ne = nH + (nH & 1), np = ne / 2;
   int sweeps = 0;
   bool conv = false;

@@ -408,6 +408,29 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
       }
   }
   const int ksteps = PREC == 0 ? (nH + 3) / 4 : (nH > 32 ? 2 : 1);
+  // fixed-column assignment of the elementwise pass (vector path, n / 4 <= kThreads):
+  // thread -> column group ec_j0, rows ec_r0, ec_r0 + ec_rstep, ...
+  const int grow = n / 4;
+  const bool fixed_cols = VEC && grow <= kThreads;
+  const int ec_rstep = fixed_cols ? kThreads / grow : 1;
+  const int ec_r0 = fixed_cols ? tid / grow : 0;
+  const int ec_j0 = fixed_cols ? 4 * (tid % grow) : 0;
+  const bool ec_on = fixed_cols && ec_r0 < ec_rstep;
+  int st_i0[4], st_i1[4];
+  float st_w0[4], st_w1[4];
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int j = ec_on ? ec_j0 + v : 0;
+    st_i0[v] = a.row_idx[2 * j];
+    st_i1[v] = a.row_idx[2 * j + 1];
+    st_w0[v] = a.row_w[2 * j];
+    st_w1[v] = a.row_w[2 * j + 1];
+  }
+  // restriction: thread -> coarse column rc_c, rows rc_r0 + k rc_rstep (n_H <= 64, so
+  // at least 4 rows per pass and at most kTallRows / 4 rows per thread)
+  const int rc_rstep = kThreads / nH;
+  const int rc_r0 = tid / nH, rc_c = tid % nH;
+  const bool rc_on = rc_r0 < rc_rstep;
   double racc = 0.0;
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int i0 = tile * TM;
@@ -451,116 +474,128 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     }
     __syncthreads();
     constexpr int V = VEC ? 4 : 1;
-    constexpr int B = 4;   // groups per thread whose loads are issued together
-    const int groups = rows * n / V;
-    for (int g0 = tid; g0 < groups; g0 += B * kThreads) {
-      float dv[B][V], zv[B][V];
-      uint32_t qbv[B];
-      int gib[B], j0b[B], ib[B];
-#pragma unroll
-      for (int b = 0; b < B; ++b) {
-        const int g = g0 + b * kThreads;
-        ib[b] = -1;
-        if (g >= groups) continue;
-        const int e = g * V;
-        const int i = e / n, j0 = e % n;
-        const int gi = i0 + i;
-        ib[b] = i; j0b[b] = j0; gib[b] = gi;
-        if (MODE == MODE_RECON) continue;
-        qbv[b] = 0xFu;
-        if (MASKED) qbv[b] = (a.bits[(size_t)gi * a.nw + (j0 >> 5)] >> (j0 & 31)) & (VEC ? 0xFu : 1u);
-        const size_t gij = (size_t)gi * n + j0;
+    // one element group (V consecutive columns of one row): N -> L through the row
+    // stencil, then the elementwise update
+    auto element_group = [&](int i, int j0, const float (&Lv)[V]) {
+      const int gi = i0 + i;
+      const size_t gij = (size_t)gi * n + j0;
+      if (MODE == MODE_RECON) {
         if (VEC) {
-          const float4 d4 = *reinterpret_cast<const float4*>(a.D + (size_t)gi * a.ldd + j0);
-          dv[b][0] = d4.x; dv[b][V > 1 ? 1 : 0] = d4.y; dv[b][V > 2 ? 2 : 0] = d4.z; dv[b][V > 3 ? 3 : 0] = d4.w;
-          if (MODE == MODE_FINAL || !a.first) {
-            const float4 z4 = *reinterpret_cast<const float4*>(a.Zin + gij);
-            zv[b][0] = z4.x; zv[b][V > 1 ? 1 : 0] = z4.y; zv[b][V > 2 ? 2 : 0] = z4.z; zv[b][V > 3 ? 3 : 0] = z4.w;
-          } else {
-#pragma unroll
-            for (int v = 0; v < V; ++v) zv[b][v] = 0.0f;
-          }
+          *reinterpret_cast<float4*>(a.Lout + gij) =
+              make_float4(Lv[0], Lv[V > 1 ? 1 : 0], Lv[V > 2 ? 2 : 0], Lv[V > 3 ? 3 : 0]);
         } else {
-          dv[b][0] = a.D[(size_t)gi * a.ldd + j0];
-          zv[b][0] = (MODE == MODE_FINAL || !a.first) ? a.Zin[gij] : 0.0f;
+          a.Lout[gij] = Lv[0];
+        }
+        return;
+      }
+      uint32_t qb = 0xFu;
+      if (MASKED) qb = (a.bits[(size_t)gi * a.nw + (j0 >> 5)] >> (j0 & 31)) & (VEC ? 0xFu : 1u);
+      float dv[V], zv[V];
+      if (VEC) {
+        const float4 d4 = *reinterpret_cast<const float4*>(a.D + (size_t)gi * a.ldd + j0);
+        dv[0] = d4.x; dv[V > 1 ? 1 : 0] = d4.y; dv[V > 2 ? 2 : 0] = d4.z; dv[V > 3 ? 3 : 0] = d4.w;
+        if (MODE == MODE_FINAL || !a.first) {
+          const float4 z4 = *reinterpret_cast<const float4*>(a.Zin + gij);
+          zv[0] = z4.x; zv[V > 1 ? 1 : 0] = z4.y; zv[V > 2 ? 2 : 0] = z4.z; zv[V > 3 ? 3 : 0] = z4.w;
+        } else {
+#pragma unroll
+          for (int v = 0; v < V; ++v) zv[v] = 0.0f;
+        }
+      } else {
+        dv[0] = a.D[(size_t)gi * a.ldd + j0];
+        zv[0] = (MODE == MODE_FINAL || !a.first) ? a.Zin[gij] : 0.0f;
+      }
+      float o1[V], o2[V], o3[V];
+#pragma unroll
+      for (int v = 0; v < V; ++v) {
+        const bool q = (qb >> v) & 1u;
+        if (MODE == MODE_FINAL) {
+          const float ev = dv[v] + zv[v];
+          o1[v] = Lv[v];
+          o2[v] = q ? shrinkf(ev, a.thr) : 0.0f;
+          o3[v] = q ? fminf(fmaxf(a.mu * ev, -a.lam), a.lam) : 0.0f;
+        } else {
+          float ym;
+          if (a.first) {
+            ym = a.Y0 ? a.Y0[gij + v] * a.inv_mu : 0.0f;
+          } else {
+            ym = fminf(fmaxf(dv[v] + zv[v], -a.thr_prev), a.thr_prev) * a.ratio_prev;
+          }
+          const float wv = ym - Lv[v];
+          const float c = fminf(fmaxf(dv[v] + wv, -a.thr), a.thr);
+          const float res = c - ym;
+          if (q) racc += (double)res * (double)res;
+          o1[v] = q ? wv : Lv[v];                   // next state
+          o2[v] = q ? c * a.grow - wv : Lv[v];      // next coarse data X_{t+1}
         }
       }
+      if (MODE == MODE_FINAL) {
+        if (VEC) {
+          *reinterpret_cast<float4*>(a.Lout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
+          *reinterpret_cast<float4*>(a.Sout + gij) = make_float4(o2[0], o2[V > 1 ? 1 : 0], o2[V > 2 ? 2 : 0], o2[V > 3 ? 3 : 0]);
+          if (a.Yout)
+            *reinterpret_cast<float4*>(a.Yout + gij) = make_float4(o3[0], o3[V > 1 ? 1 : 0], o3[V > 2 ? 2 : 0], o3[V > 3 ? 3 : 0]);
+        } else {
+          a.Lout[gij] = o1[0];
+          a.Sout[gij] = o2[0];
+          if (a.Yout) a.Yout[gij] = o3[0];
+        }
+      } else {
+        if (VEC)
+          *reinterpret_cast<float4*>(a.Zout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
+        else
+          a.Zout[gij] = o1[0];
 #pragma unroll
-      for (int b = 0; b < B; ++b) {
-        if (ib[b] < 0) continue;
-        const int i = ib[b], j0 = j0b[b];
+        for (int v = 0; v < V; ++v) sX[(size_t)i * n + j0 + v] = o2[v];
+      }
+    };
+    if (fixed_cols) {
+      // every thread keeps the same V columns for all rows of the tile (stencil in
+      // registers, no index arithmetic per element)
+      if (ec_on)
+        for (int i = ec_r0; i < rows; i += ec_rstep) {
+          const float* nrow = sN + i * kLdN;
+          float Lv[V];
+#pragma unroll
+          for (int v = 0; v < V; ++v) Lv[v] = fmaf(st_w1[v], nrow[st_i1[v]], st_w0[v] * nrow[st_i0[v]]);
+          element_group(i, ec_j0, Lv);
+        }
+    } else {
+      const int groups = rows * n / V;
+      for (int g = tid; g < groups; g += kThreads) {
+        const int e = g * V;
+        const int i = e / n, j0 = e % n;
+        const float* nrow = sN + i * kLdN;
         float Lv[V];
 #pragma unroll
         for (int v = 0; v < V; ++v) {
           const int j = j0 + v;
-          const float* nrow = sN + i * kLdN;
           Lv[v] = fmaf(sRw[2 * j + 1], nrow[sRi[2 * j + 1]], sRw[2 * j] * nrow[sRi[2 * j]]);
         }
-        const size_t gij = (size_t)gib[b] * n + j0;
-        if (MODE == MODE_RECON) {
-          if (VEC) {
-            *reinterpret_cast<float4*>(a.Lout + gij) =
-                make_float4(Lv[0], Lv[V > 1 ? 1 : 0], Lv[V > 2 ? 2 : 0], Lv[V > 3 ? 3 : 0]);
-          } else {
-            a.Lout[gij] = Lv[0];
-          }
-          continue;
-        }
-        const uint32_t qb = qbv[b];
-        float o1[V], o2[V], o3[V];
-#pragma unroll
-        for (int v = 0; v < V; ++v) {
-          const bool q = (qb >> v) & 1u;
-          if (MODE == MODE_FINAL) {
-            const float ev = dv[b][v] + zv[b][v];
-            o1[v] = Lv[v];
-            o2[v] = q ? shrinkf(ev, a.thr) : 0.0f;
-            o3[v] = q ? fminf(fmaxf(a.mu * ev, -a.lam), a.lam) : 0.0f;
-          } else {
-            float ym;
-            if (a.first) {
-              ym = a.Y0 ? a.Y0[gij + v] * a.inv_mu : 0.0f;
-            } else {
-              ym = fminf(fmaxf(dv[b][v] + zv[b][v], -a.thr_prev), a.thr_prev) * a.ratio_prev;
-            }
-            const float wv = ym - Lv[v];
-            const float c = fminf(fmaxf(dv[b][v] + wv, -a.thr), a.thr);
-            const float res = c - ym;
-            if (q) racc += (double)res * (double)res;
-            o1[v] = q ? wv : Lv[v];                   // next state
-            o2[v] = q ? c * a.grow - wv : Lv[v];      // next coarse data X_{t+1}
-          }
-        }
-        if (MODE == MODE_FINAL) {
-          if (VEC) {
-            *reinterpret_cast<float4*>(a.Lout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
-            *reinterpret_cast<float4*>(a.Sout + gij) = make_float4(o2[0], o2[V > 1 ? 1 : 0], o2[V > 2 ? 2 : 0], o2[V > 3 ? 3 : 0]);
-            if (a.Yout)
-              *reinterpret_cast<float4*>(a.Yout + gij) = make_float4(o3[0], o3[V > 1 ? 1 : 0], o3[V > 2 ? 2 : 0], o3[V > 3 ? 3 : 0]);
-          } else {
-            a.Lout[gij] = o1[0];
-            a.Sout[gij] = o2[0];
-            if (a.Yout) a.Yout[gij] = o3[0];
-          }
-        } else {
-          if (VEC)
-            *reinterpret_cast<float4*>(a.Zout + gij) = make_float4(o1[0], o1[V > 1 ? 1 : 0], o1[V > 2 ? 2 : 0], o1[V > 3 ? 3 : 0]);
-          else
-            a.Zout[gij] = o1[0];
-#pragma unroll
-          for (int v = 0; v < V; ++v) sX[(size_t)i * n + j0 + v] = o2[v];
-        }
+        element_group(i, j0, Lv);
       }
     }
     if (MODE == MODE_STEP) {
       __syncthreads();
-      for (int e = tid; e < rows * nH; e += kThreads) {    // restrict X_{t+1}
-        const int i = e / nH, c = e % nH;
-        const float* x = sX + (size_t)i * n;
-        float acc = 0.0f;
-        const int t1 = sCp[c + 1];
-        for (int t = sCp[c]; t < t1; ++t) acc = fmaf(sCw[t], x[sCr[t]], acc);
-        a.MPnext[(size_t)(i0 + i) * a.ldp + c] = acc;
+      // restrict X_{t+1}: thread -> coarse column rc_c, rows rc_r0 + k rc_rstep; each
+      // tap's index and weight are read once for all of the thread's rows
+      if (rc_on) {
+        float acc[kTallRows / 4] = {};
+        const int t0 = sCp[rc_c], t1 = sCp[rc_c + 1];
+        for (int t = t0; t < t1; ++t) {
+          const int col = sCr[t];
+          const float w = sCw[t];
+#pragma unroll
+          for (int k = 0; k < kTallRows / 4; ++k) {
+            const int i = rc_r0 + k * rc_rstep;
+            if (i < rows) acc[k] = fmaf(w, sX[(size_t)i * n + col], acc[k]);
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kTallRows / 4; ++k) {
+          const int i = rc_r0 + k * rc_rstep;
+          if (i < rows) a.MPnext[(size_t)(i0 + i) * a.ldp + rc_c] = acc[k];
+        }
       }
     }
   }
@@ -965,6 +1000,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     trace_prev = hs.trace;
     if (info && info->fg_history && t < info->history_len) info->fg_history[t] = fg;
     if (info && info->rank_history && t < info->history_len) info->rank_history[t] = rank;
+    if (info && info->sweeps_history && t < info->history_len) info->sweeps_history[t] = sweeps;
     if (!std::isfinite(fg)) {
       status = MLPCP_E_NONFINITE;
       ++t;
