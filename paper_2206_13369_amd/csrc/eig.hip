@@ -140,12 +140,13 @@ struct RotShared {
 // (exact for skipped pairs); all loads of a thread's items are issued before any of
 // its stores (the items are disjoint), which keeps the LDS latency off the critical
 // path.
+template <int THREADS>
 __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS_LD], int phase, double floor_abs,
                                             RotShared& rs) {
   const int tid = threadIdx.x;
   const int rounds = phase == 0 ? IB - 1 : IB;
-  constexpr int NT = (IB * IB) / 256;   // 2x2 tiles per thread
-  constexpr int NQ = (IN * IB) / 256;   // (row, pair) items of Q per thread
+  constexpr int NT = (IB * IB) / THREADS;   // 2x2 tiles per thread
+  constexpr int NQ = (IN * IB) / THREADS;   // (row, pair) items of Q per thread
   for (int s = 0; s < rounds; ++s) {
     if (tid < IB) {
       int p, q;
@@ -183,7 +184,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       double qx[NQ], qy[NQ];
 #pragma unroll
       for (int x = 0; x < NQ; ++x) {
-        const int i = x * (256 / IB) + tid / IB;
+        const int i = x * (THREADS / IB) + tid / IB;
         qx[x] = Q[i][qp]; qy[x] = Q[i][qq];
       }
 #pragma unroll
@@ -205,7 +206,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       }
 #pragma unroll
       for (int x = 0; x < NQ; ++x) {
-        const int i = x * (256 / IB) + tid / IB;
+        const int i = x * (THREADS / IB) + tid / IB;
         Q[i][qp] = qc * qx[x] - qs * qy[x];
         Q[i][qq] = qs * qx[x] + qc * qy[x];
       }
@@ -246,8 +247,8 @@ __global__ void __launch_bounds__(256) k_jacobi_direct(double* __restrict__ A, d
   for (; sweeps < max_sweeps; ++sweeps) {
     if (threadIdx.x == 0) rs.any = 0;
     __syncthreads();
-    inner_phase(sA, sQ, 0, fl, rs);
-    inner_phase(sA, sQ, 1, fl, rs);
+    inner_phase<256>(sA, sQ, 0, fl, rs);
+    inner_phase<256>(sA, sQ, 1, fl, rs);
     const int any = rs.any;
     __syncthreads();
     if (!any) {
@@ -267,7 +268,10 @@ __device__ __forceinline__ int pair_global(int l, int I, int J) { return l < IB 
 
 // Outer round, step 1: one block per block pair: rotate the cross pairs (and, in the
 // first round of a sweep, the pairs inside each block), write Q_pair.
-__global__ void __launch_bounds__(256) k_jacobi_pairs(double* __restrict__ A, int N, int nb, int round,
+// kPairThreads threads: a round is bound by LDS latency, which sixteen waves hide
+// better than four (one 2x2 tile and two factor items per thread).
+constexpr int kPairThreads = 1024;
+__global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restrict__ A, int N, int nb, int round,
                                                       double* __restrict__ Qblk, const double* __restrict__ floor_p,
                                                       int* __restrict__ flag) {
   __shared__ double sA[IN][LDS_LD];
@@ -283,8 +287,8 @@ __global__ void __launch_bounds__(256) k_jacobi_pairs(double* __restrict__ A, in
   if (threadIdx.x == 0) rs.any = 0;
   __syncthreads();
   const double fl = floor_p[0];
-  if (round == 0) inner_phase(sA, sQ, 0, fl, rs);
-  inner_phase(sA, sQ, 1, fl, rs);
+  if (round == 0) inner_phase<kPairThreads>(sA, sQ, 0, fl, rs);
+  inner_phase<kPairThreads>(sA, sQ, 1, fl, rs);
   // the rotated 2b x 2b block goes straight back (annihilated entries stay exactly 0;
   // the apply step skips these diagonal tiles), and Q_pair to the workspace
   double* Qo = Qblk + (size_t)blockIdx.x * (IN * IN + 1);
@@ -408,6 +412,10 @@ __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, do
 // passes it (a sweep in which no pair passes rotates nothing), so the final sweep of
 // the plain iteration, which only confirms convergence, is replaced by that test.
 typedef double LdsRow[LDS_LD];
+// threads of the one-workgroup solver: a round of a 64-wide problem is bound by LDS
+// latency, and sixteen waves hide it better than four (one 2x2 tile and two factor
+// items per thread)
+constexpr int kSmallThreads = 1024;
 
 __device__ __forceinline__ bool rotates(double app, double aqq, double apq, double floor_abs) {
   return fabs(apq) > floor_abs && apq * apq > kRelEps2 * fabs(app * aqq);
@@ -525,7 +533,7 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, int max_
   }
 }
 
-__global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const double* __restrict__ G,
+__global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, const double* __restrict__ G,
                                                       const double* __restrict__ C, double* __restrict__ V,
                                                       int warm, double tau, int max_sweeps,
                                                       double* __restrict__ lam, int* __restrict__ perm,
@@ -537,11 +545,12 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
   LdsRow* sQ = sA + IN;
   LdsRow* sC = sQ + IN;
   LdsRow* sW = sC + IN;
-  __shared__ double pc[IB], ps[IB], pt[IB], swv[IN], red[256];
-  __shared__ int prm[IN], redi[256];
+  __shared__ double pc[IB], ps[IB], pt[IB], swv[IN], red[kSmallThreads];
+  __shared__ int prm[IN], redi[kSmallThreads];
   const int tid = threadIdx.x;
+  const bool mm_on = tid < 256;   // the 64^3 products run on the first four waves
   d4_t acc[2][2];
-  for (int it = tid; it < IN * IN; it += 256) {
+  for (int it = tid; it < IN * IN; it += kSmallThreads) {
     const int i = it / IN, j = it % IN;
     const bool in = i < nH && j < nH;
     sA[i][j] = in ? G[(size_t)i * ld + j] : 0.0;
@@ -550,25 +559,29 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
   }
   __syncthreads();
   if (C) {                                   // G_H = C G C
-    mm64<false>(sA, sC, acc);
-    mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+    if (mm_on) {
+      mm64<false>(sA, sC, acc);
+      mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+    }
     __syncthreads();
-    mm64<false>(sC, sW, acc);
+    if (mm_on) mm64<false>(sC, sW, acc);
     __syncthreads();
-    mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
     __syncthreads();
   }
   if (warm) {                                // A <- V0^T A V0, Q = V0
-    mm64<true>(sQ, sA, acc);
-    mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+    if (mm_on) {
+      mm64<true>(sQ, sA, acc);
+      mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+    }
     __syncthreads();
-    mm64<false>(sW, sQ, acc);
+    if (mm_on) mm64<false>(sW, sQ, acc);
     __syncthreads();
-    mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
     __syncthreads();
   }
   // exact symmetry (the products above round each triangle separately)
-  for (int it = tid; it < IN * IN; it += 256) {
+  for (int it = tid; it < IN * IN; it += kSmallThreads) {
     const int i = it / IN, j = it % IN;
     if (i < j) {
       const double v = 0.5 * (sA[i][j] + sA[j][i]);
@@ -579,7 +592,7 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
   // absolute floor of the rotation test: kAbsTol trace
   red[tid] = tid < nH ? fabs(sA[tid][tid]) : 0.0;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] += red[tid + w];
     __syncthreads();
   }
@@ -591,12 +604,8 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
     conv = small_sweeps<64, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
   else if (ne <= 32)
     conv = small_sweeps<256, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
-  else if (ne <= 44)
-    conv = small_sweeps<256, 2, 4>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
-  else if (ne <= 54)
-    conv = small_sweeps<256, 3, 6>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
   else
-    conv = small_sweeps<256, 4, 8>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+    conv = small_sweeps<kSmallThreads, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
   // eigenvalues, descending order (ties by index), weights, rank, margin, trace
   double li = 0.0;
   if (tid < IN) {
@@ -635,7 +644,7 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
   red[tid] = trc;
   redi[tid] = kept;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
     if (tid < w) {
       red[tid] += red[tid + w];
       redi[tid] += redi[tid + w];
@@ -647,7 +656,7 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
   __syncthreads();
   red[tid] = mg;
   __syncthreads();
-  for (int w = 128; w > 0; w >>= 1) {
+  for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] = fmin(red[tid], red[tid + w]);
     __syncthreads();
   }
@@ -658,19 +667,21 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
     st->sweeps = conv ? sweeps : -1;
   }
   // W = V_sorted diag(sw) (columns k < rank), T = C W, Tt, K = T T^T
-  for (int it = tid; it < IN * IN; it += 256) {
+  for (int it = tid; it < IN * IN; it += kSmallThreads) {
     const int j = it / IN, k = it % IN;
     sW[j][k] = k < rank ? sQ[j][prm[k]] * swv[k] : 0.0;
   }
   __syncthreads();
   LdsRow* sT = sW;
   if (C) {
-    mm64<false>(sC, sW, acc);
-    mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    if (mm_on) {
+      mm64<false>(sC, sW, acc);
+      mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    }
     __syncthreads();
     sT = sA;
   }
-  for (int it = tid; it < IN * IN; it += 256) {
+  for (int it = tid; it < IN * IN; it += kSmallThreads) {
     const int i = it / IN, j = it % IN;
     T[(size_t)i * ld + j] = sT[i][j];
     Tt[(size_t)j * ld + i] = sT[i][j];
@@ -679,13 +690,15 @@ __global__ void __launch_bounds__(256) k_coarse_small(int nH, int ld, const doub
   if (K) {
     // K = T T^T = X^T X with X = T^T staged in the Q buffer (V is already written)
     __syncthreads();
-    for (int it = tid; it < IN * IN; it += 256) {
+    for (int it = tid; it < IN * IN; it += kSmallThreads) {
       const int i = it / IN, j = it % IN;
       sQ[j][i] = sT[i][j];
     }
     __syncthreads();
-    mm64<true>(sQ, sQ, acc);
-    mm64_store(acc, [&](int i, int j, double v) { K[(size_t)i * IN + j] = v; });
+    if (mm_on) {
+      mm64<true>(sQ, sQ, acc);
+      mm64_store(acc, [&](int i, int j, double v) { K[(size_t)i * IN + j] = v; });
+    }
   }
 }
 
@@ -730,7 +743,7 @@ int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V
   MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse_small),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   ProfScope ps(KC_COARSE_SMALL, stream);
-  hipLaunchKernelGGL(k_coarse_small, dim3(1), dim3(256), lds, stream, nH, ld, G, C, V, warm ? 1 : 0, tau,
+  hipLaunchKernelGGL(k_coarse_small, dim3(1), dim3(kSmallThreads), lds, stream, nH, ld, G, C, V, warm ? 1 : 0, tau,
                      kMaxEigSweeps, lam, perm, sw, T, Tt, K, st);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
@@ -789,7 +802,8 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
       for (int r = 0; r < nb - 1; ++r) {
         {
           ProfScope ps(KC_JACOBI_PAIRS, stream);
-          hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(256), 0, stream, A, N, nb, r, Qblk, floor_p, flag);
+          hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, A, N, nb, r, Qblk, floor_p,
+                             flag);
         }
         {
           ProfScope ps(KC_JACOBI_APPLY, stream);
