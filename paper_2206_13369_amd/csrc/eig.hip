@@ -14,7 +14,9 @@
 //  * The outer round's transformation J = diag(Q_pair) is then applied tile by tile
 //    on MFMA: A[Pa,Pb] <- Q_a^T A[Pa,Pb] Q_b (tiles with a <= b, mirrored), and
 //    V[:,Pb] <- V[:,Pb] Q_b.  Tiles are disjoint, so the update is in place.
-//  * A sweep in which nothing was rotated ends the iteration.
+//  * A sweep starts only if some pair passes the rotation test (a sweep in which no
+//    pair passes it rotates nothing), and a block pair with nothing to rotate is
+//    skipped, its factor marked as the identity.
 //  * Optional warm start: with V0 given, the iteration starts from A = V0^T A V0,
 //    V = V0 (the previous solver iteration's eigenvectors).
 //  Problems of width 64 are solved by one kernel directly.
@@ -127,6 +129,10 @@ __device__ __forceinline__ bool rotation_fast(double app, double aqq, double apq
   c = rsq_nr(fma(t, t, 1.0));
   s = t * c;
   return true;
+}
+
+__device__ __forceinline__ bool rotates(double app, double aqq, double apq, double floor_abs) {
+  return fabs(apq) > floor_abs && apq * apq > kRelEps2 * fabs(app * aqq);
 }
 
 struct RotShared {
@@ -287,6 +293,19 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
   if (threadIdx.x == 0) rs.any = 0;
   __syncthreads();
   const double fl = floor_p[0];
+  // nothing to rotate in this block pair (round 0: any pair; later rounds: the cross
+  // pairs): leave A as it is and mark the factor as the identity, which the apply
+  // step then neither reads nor applies
+  int want = 0;
+  for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
+    const int i = it / IN, j = it % IN;
+    const bool cand = round == 0 ? i < j : (i < IB && j >= IB);
+    if (cand && rotates(sA[i][i], sA[j][j], sA[i][j], fl)) want = 1;
+  }
+  if (!__syncthreads_or(want)) {
+    if (threadIdx.x == 0) Qblk[(size_t)blockIdx.x * (IN * IN + 1) + IN * IN] = 0.0;
+    return;
+  }
   if (round == 0) inner_phase<kPairThreads>(sA, sQ, 0, fl, rs);
   inner_phase<kPairThreads>(sA, sQ, 1, fl, rs);
   // the rotated 2b x 2b block goes straight back (annihilated entries stay exactly 0;
@@ -372,13 +391,13 @@ __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, do
     for (int it = tid; it < IN * IN; it += 256) {
       const int i = it / IN, j = it % IN;
       sT[i][j] = A[(size_t)pair_global(i, Ia, Ja) * N + pair_global(j, Ib, Jb)];
-      sQ[i][j] = Qa[it];
+      sQ[i][j] = rot_a ? Qa[it] : (i == j ? 1.0 : 0.0);
     }
     __syncthreads();
     mm64<true>(sQ, sT, acc);   // U = Qa^T T
     __syncthreads();
     mm64_store(acc, [&](int i, int j, double v) { sT[i][j] = v; });
-    for (int it = tid; it < IN * IN; it += 256) sQ[it / IN][it % IN] = Qb[it];
+    for (int it = tid; it < IN * IN; it += 256) sQ[it / IN][it % IN] = rot_b ? Qb[it] : (it / IN == it % IN ? 1.0 : 0.0);
     __syncthreads();
     mm64<false>(sT, sQ, acc);                      // T' = U Qb
     mm64_store(acc, [&](int i, int j, double v) {
@@ -417,9 +436,6 @@ typedef double LdsRow[LDS_LD];
 // items per thread)
 constexpr int kSmallThreads = 1024;
 
-__device__ __forceinline__ bool rotates(double app, double aqq, double apq, double floor_abs) {
-  return fabs(apq) > floor_abs && apq * apq > kRelEps2 * fabs(app * aqq);
-}
 
 // pair k of round r of the circle method on ne players (player 0 fixed), p < q
 __device__ __forceinline__ void pair_at(int ne, int k, int r, int& p, int& q) {
@@ -702,6 +718,19 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   }
 }
 
+// flag = 1 if any pair (p < q) of A passes the rotation test
+__global__ void __launch_bounds__(256) k_any_rotation(const double* __restrict__ A, int N,
+                                                      const double* __restrict__ floor_p, int* __restrict__ flag) {
+  const double fl = floor_p[0];
+  int want = 0;
+  const size_t total = (size_t)N * N;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    if (i < j && rotates(A[(size_t)i * N + i], A[(size_t)j * N + j], A[idx], fl)) want = 1;
+  }
+  if (__syncthreads_or(want) && threadIdx.x == 0) atomicOr(flag, 1);
+}
+
 __global__ void k_identity(double* __restrict__ V, int N) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)N * N) V[idx] = ((idx / N) == (idx % N)) ? 1.0 : 0.0;
@@ -797,8 +826,22 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
     const int apply_blocks = ntri + (N / IN) * npairs;
     bool converged = false;
     int hflag = 0;
-    for (sweeps = 1; sweeps <= kMaxEigSweeps; ++sweeps) {
+    // a sweep starts only if some pair passes the rotation test (a sweep in which none
+    // does rotates nothing), so convergence costs one test, not one more sweep
+    for (sweeps = 0;; ++sweeps) {
       MLPCP_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
+      {
+        ProfScope ps(KC_JACOBI_MISC, stream);
+        hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, A, N, floor_p, flag);
+      }
+      MLPCP_HIP(hipGetLastError());
+      MLPCP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+      MLPCP_HIP(hipStreamSynchronize(stream));
+      if (!hflag) {
+        converged = true;
+        break;
+      }
+      if (sweeps == kMaxEigSweeps) break;
       for (int r = 0; r < nb - 1; ++r) {
         {
           ProfScope ps(KC_JACOBI_PAIRS, stream);
@@ -811,12 +854,6 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
         }
       }
       MLPCP_HIP(hipGetLastError());
-      MLPCP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
-      MLPCP_HIP(hipStreamSynchronize(stream));
-      if (!hflag) {
-        converged = true;
-        break;
-      }
     }
     if (!converged) return MLPCP_E_EIG;
   }
