@@ -1,6 +1,7 @@
 // Small dense float64 helpers used around the eigensolver: C = op(A) op(B) for the
-// n_H x n_H products (C G C and the orthonormalising factor) and a right
-// multiplication of a tall float32 matrix by a small float64 matrix.
+// n_H x n_H products (C G C, the warm start V^T A V, the orthonormalising factor) on
+// float64 MFMA, and a right multiplication of a tall float32 matrix by a small
+// float64 matrix.
 #include "common.h"
 
 namespace mlpcp {
@@ -8,6 +9,8 @@ namespace mlpcp {
 namespace {
 
 constexpr int T = 32;
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
 
 __global__ void __launch_bounds__(256) k_gemm_f64(int transA, int transB, int M, int N, int K, double alpha,
                                                   const double* __restrict__ A, int lda,
@@ -17,8 +20,9 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int transA, int transB, int M,
   __shared__ double sB[T][T + 1];
   const int i0 = blockIdx.y * T, j0 = blockIdx.x * T;
   const int tid = threadIdx.x;
-  const int ti = tid / 8, tj = (tid % 8) * 4;  // each thread: 1 row x 4 cols
-  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  const int lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
   for (int k0 = 0; k0 < K; k0 += T) {
     for (int e = tid; e < T * T; e += 256) {
       const int r = e / T, c = e % T;
@@ -32,21 +36,22 @@ __global__ void __launch_bounds__(256) k_gemm_f64(int transA, int transB, int M,
       sB[r][c] = vb;
     }
     __syncthreads();
-#pragma unroll 8
-    for (int k = 0; k < T; ++k) {
-      const double a = sA[ti][k];
+    // wave (wi, wj) owns the 16 x 16 sub-tile; v_mfma_f64_16x16x4f64: lane l holds
+    // op(A)[l%16][k0 + l/16] and op(B)[k0 + l/16][l%16]
 #pragma unroll
-      for (int q = 0; q < 4; ++q) acc[q] += a * sB[k][tj + q];
+    for (int ks = 0; ks < T / 4; ++ks) {
+      const double a = sA[wi * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+      const double b = sB[ks * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
     }
     __syncthreads();
   }
-  const int gi = i0 + ti;
-  if (gi < M) {
+  // output register v of lane l: row 4v + l/16, column l%16
+  const int gj = j0 + wj * 16 + (lane & 15);
 #pragma unroll
-    for (int q = 0; q < 4; ++q) {
-      const int gj = j0 + tj + q;
-      if (gj < N) C[(size_t)gi * ldc + gj] = alpha * acc[q];
-    }
+  for (int v = 0; v < 4; ++v) {
+    const int gi = i0 + wi * 16 + 4 * v + (lane >> 4);
+    if (gi < M && gj < N) C[(size_t)gi * ldc + gj] = alpha * acc[v];
   }
 }
 

@@ -613,7 +613,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
     __syncthreads();
   }
   const double fl = kAbsTol * red[0] + 1.0e-300;
-  const int ne = nH + (nH & 1), np = ne / 2;
+  const int ne = nH + (nH & 1);
   int sweeps = 0;
   bool conv = false;
   if (ne <= 16)

@@ -325,6 +325,29 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
   if (tid == 0) a.partial[blockIdx.x] = s;
 }
 
+// W[j][k] = V[j][perm[k]] * sw[k] for k < r (zero beyond): the right factor of
+// T = C W, formed on MFMA by gemm_f64.
+__global__ void k_build_W(int nH, int N, const double* __restrict__ V, const int* __restrict__ perm,
+                          const double* __restrict__ sw, const IterStats* __restrict__ st, double* __restrict__ W) {
+  const int r = st->rank;
+  const size_t total = (size_t)nH * nH;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int j = (int)(idx / nH), k = (int)(idx % nH);
+    W[(size_t)j * N + k] = k < r ? V[(size_t)j * N + perm[k]] * sw[k] : 0.0;
+  }
+}
+
+// Tt = T^T (n_H x n_H block, ld N)
+__global__ void k_transpose(int nH, int N, const double* __restrict__ T, double* __restrict__ Tt) {
+  const size_t total = (size_t)nH * nH;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
+       idx += (size_t)gridDim.x * blockDim.x) {
+    const int c = (int)(idx / nH), k = (int)(idx % nH);
+    Tt[(size_t)k * N + c] = T[(size_t)c * N + k];
+  }
+}
+
 // K = T T^T (n_H x n_H, float64, ld = ldK), the coarse SVT operator of the tall path:
 // L = M_P K P^T.  Entries beyond n_H are zero.
 __global__ void k_build_K(int nH, int ldK, const double* __restrict__ T, int ldT, const IterStats* __restrict__ st,
@@ -828,9 +851,13 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   if (p.plain)
     hipLaunchKernelGGL(k_build_T<true>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op.C, V, perm, sw,
                        st, T, Tt, p.nHp);
-  else
-    hipLaunchKernelGGL(k_build_T<false>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op.C, V, perm,
-                       sw, st, T, Tt, p.nHp);
+  else {
+    // T = C W on MFMA, W = V_sorted diag(sw) (columns beyond the rank zero)
+    double* W = w.at<double>(p.off_tmp);
+    hipLaunchKernelGGL(k_build_W, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, V, perm, sw, st, W);
+    MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, W, p.nHp, T, p.nHp, s));
+    hipLaunchKernelGGL(k_transpose, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, T, Tt);
+  }
   if (p.tall)
     hipLaunchKernelGGL(k_build_K, dim3((kTallNH * kTallNH + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p.nH,
                        kTallNH, T, p.nHp, st, w.at<double>(p.off_K));
