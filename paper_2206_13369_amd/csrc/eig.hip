@@ -388,16 +388,32 @@ __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, do
     int Ia, Ja, Ib, Jb;
     rr_pair(a, round, nb, Ia, Ja);
     rr_pair(b, round, nb, Ib, Jb);
-    for (int it = tid; it < IN * IN; it += 256) {
+    // all global loads of the block are issued up front (tile, both factors)
+    constexpr int PER = IN * IN / 256;
+    double ra[PER], rqa[PER], rqb[PER];
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int it = tid + 256 * x;
       const int i = it / IN, j = it % IN;
-      sT[i][j] = A[(size_t)pair_global(i, Ia, Ja) * N + pair_global(j, Ib, Jb)];
-      sQ[i][j] = rot_a ? Qa[it] : (i == j ? 1.0 : 0.0);
+      ra[x] = A[(size_t)pair_global(i, Ia, Ja) * N + pair_global(j, Ib, Jb)];
+      rqa[x] = rot_a ? Qa[it] : (i == j ? 1.0 : 0.0);
+      rqb[x] = rot_b ? Qb[it] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int it = tid + 256 * x;
+      sT[it / IN][it % IN] = ra[x];
+      sQ[it / IN][it % IN] = rqa[x];
     }
     __syncthreads();
     mm64<true>(sQ, sT, acc);   // U = Qa^T T
     __syncthreads();
     mm64_store(acc, [&](int i, int j, double v) { sT[i][j] = v; });
-    for (int it = tid; it < IN * IN; it += 256) sQ[it / IN][it % IN] = rot_b ? Qb[it] : (it / IN == it % IN ? 1.0 : 0.0);
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int it = tid + 256 * x;
+      sQ[it / IN][it % IN] = rqb[x];
+    }
     __syncthreads();
     mm64<false>(sT, sQ, acc);                      // T' = U Qb
     mm64_store(acc, [&](int i, int j, double v) {
@@ -411,10 +427,19 @@ __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, do
     if (Qb[IN * IN] == 0.0) return;
     int Ib, Jb;
     rr_pair(b, round, nb, Ib, Jb);
-    for (int it = tid; it < IN * IN; it += 256) {
-      const int i = it / IN, j = it % IN;
-      sT[i][j] = V[(size_t)(rb * IN + i) * N + pair_global(j, Ib, Jb)];
-      sQ[i][j] = Qb[it];
+    constexpr int PER = IN * IN / 256;
+    double rv[PER], rq[PER];
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int it = tid + 256 * x;
+      rv[x] = V[(size_t)(rb * IN + it / IN) * N + pair_global(it % IN, Ib, Jb)];
+      rq[x] = Qb[it];
+    }
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int it = tid + 256 * x;
+      sT[it / IN][it % IN] = rv[x];
+      sQ[it / IN][it % IN] = rq[x];
     }
     __syncthreads();
     mm64<false>(sT, sQ, acc);
