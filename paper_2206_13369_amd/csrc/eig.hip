@@ -285,9 +285,18 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
   __shared__ RotShared rs;
   int I, J;
   rr_pair(blockIdx.x, round, nb, I, J);
-  for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
+  constexpr int PER = IN * IN / kPairThreads;
+  double ra[PER];
+#pragma unroll
+  for (int x = 0; x < PER; ++x) {
+    const int it = threadIdx.x + kPairThreads * x;
+    ra[x] = A[(size_t)pair_global(it / IN, I, J) * N + pair_global(it % IN, I, J)];
+  }
+#pragma unroll
+  for (int x = 0; x < PER; ++x) {
+    const int it = threadIdx.x + kPairThreads * x;
     const int i = it / IN, j = it % IN;
-    sA[i][j] = A[(size_t)pair_global(i, I, J) * N + pair_global(j, I, J)];
+    sA[i][j] = ra[x];
     sQ[i][j] = (i == j) ? 1.0 : 0.0;
   }
   if (threadIdx.x == 0) rs.any = 0;
@@ -311,7 +320,9 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
   // the rotated 2b x 2b block goes straight back (annihilated entries stay exactly 0;
   // the apply step skips these diagonal tiles), and Q_pair to the workspace
   double* Qo = Qblk + (size_t)blockIdx.x * (IN * IN + 1);
-  for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
+#pragma unroll
+  for (int x = 0; x < PER; ++x) {
+    const int it = threadIdx.x + kPairThreads * x;
     const int i = it / IN, j = it % IN;
     Qo[it] = sQ[i][j];
     A[(size_t)pair_global(i, I, J) * N + pair_global(j, I, J)] = sA[i][j];
@@ -591,12 +602,26 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   const int tid = threadIdx.x;
   const bool mm_on = tid < 256;   // the 64^3 products run on the first four waves
   d4_t acc[2][2];
-  for (int it = tid; it < IN * IN; it += kSmallThreads) {
-    const int i = it / IN, j = it % IN;
-    const bool in = i < nH && j < nH;
-    sA[i][j] = in ? G[(size_t)i * ld + j] : 0.0;
-    if (C) sC[i][j] = in ? C[(size_t)i * nH + j] : 0.0;
-    sQ[i][j] = (warm && in) ? V[(size_t)i * ld + j] : (i == j ? 1.0 : 0.0);
+  {
+    constexpr int PER = IN * IN / kSmallThreads;
+    double rg[PER], rc[PER], rv[PER];
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int it = tid + kSmallThreads * x;
+      const int i = it / IN, j = it % IN;
+      const bool in = i < nH && j < nH;
+      rg[x] = in ? G[(size_t)i * ld + j] : 0.0;
+      rc[x] = (C && in) ? C[(size_t)i * nH + j] : 0.0;
+      rv[x] = (warm && in) ? V[(size_t)i * ld + j] : (i == j ? 1.0 : 0.0);
+    }
+#pragma unroll
+    for (int x = 0; x < PER; ++x) {
+      const int it = tid + kSmallThreads * x;
+      const int i = it / IN, j = it % IN;
+      sA[i][j] = rg[x];
+      sC[i][j] = rc[x];
+      sQ[i][j] = rv[x];
+    }
   }
   __syncthreads();
   if (C) {                                   // G_H = C G C
