@@ -22,7 +22,7 @@
 //  Problems of width 64 are solved by one kernel directly.
 //  Rotation threshold (relative, Demmel-Veselic style, with an absolute floor for
 //  singular Grams and for the rounding the tile products leave): rotate (p,q) iff
-//  a_pq^2 > (1e-15)^2 |a_pp a_qq| and |a_pq| > 1e-14 trace(A) (kAbsTol).
+//  a_pq^2 > (1e-12)^2 |a_pp a_qq| (kRelEps2) and |a_pq| > 1e-14 trace(A) (kAbsTol).
 #include "common.h"
 #include "profile.h"
 
@@ -36,7 +36,12 @@ namespace {
 constexpr int IB = kEigBlock;       // 32
 constexpr int IN = kEigInner;       // 64
 constexpr int LDS_LD = IN + 1;
-constexpr double kRelEps2 = 1.0e-30;  // (1e-15)^2
+// Relative rotation threshold (squared).  An entry left at eps sqrt(a_pp a_qq) moves
+// the eigenvalues by O(eps^2) and the eigenvectors by eps over the relative gap; the
+// reconstruction is float32, so eps = 1e-12 leaves far more accuracy than the result
+// carries, and it saves the last sweep of the quadratic convergence (the one that
+// takes the off-diagonal from ~1e-8 to ~1e-16).
+constexpr double kRelEps2 = 1.0e-24;  // (1e-12)^2
 // Absolute rotation floor, relative to trace(A): an off-diagonal entry below it moves
 // an eigenvalue by less than that share of the trace and the reconstruction
 // L = M_P C V diag(w) V^T C by a comparable share of its norm, far below float32
