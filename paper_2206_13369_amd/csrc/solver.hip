@@ -379,6 +379,7 @@ __global__ void k_build_K(int nH, int ldK, const double* __restrict__ T, int ldT
 // column 16w + l%16.  PREC 0 serves the float32 solver, PREC 2 the precision form.
 constexpr int kTallNH = 64;
 constexpr int kTallRows = 16;          // rows per tile (one MFMA row block)
+constexpr int kRowBatch = 2;           // rows whose loads a thread issues together
 constexpr int kLdA = kTallNH + 8;      // padded LDS row of the M_P tile
 constexpr int kLdN = kTallNH + 4;      // padded LDS row of the N tile
 
@@ -499,21 +500,13 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     constexpr int V = VEC ? 4 : 1;
     // one element group (V consecutive columns of one row): N -> L through the row
     // stencil, then the elementwise update
-    auto element_group = [&](int i, int j0, const float (&Lv)[V]) {
+    // the loads of one element group (V consecutive columns of row i), then its update
+    auto load_group = [&](int i, int j0, float (&dv)[V], float (&zv)[V], uint32_t& qb) {
+      if (MODE == MODE_RECON) return;
       const int gi = i0 + i;
       const size_t gij = (size_t)gi * n + j0;
-      if (MODE == MODE_RECON) {
-        if (VEC) {
-          *reinterpret_cast<float4*>(a.Lout + gij) =
-              make_float4(Lv[0], Lv[V > 1 ? 1 : 0], Lv[V > 2 ? 2 : 0], Lv[V > 3 ? 3 : 0]);
-        } else {
-          a.Lout[gij] = Lv[0];
-        }
-        return;
-      }
-      uint32_t qb = 0xFu;
+      qb = 0xFu;
       if (MASKED) qb = (a.bits[(size_t)gi * a.nw + (j0 >> 5)] >> (j0 & 31)) & (VEC ? 0xFu : 1u);
-      float dv[V], zv[V];
       if (VEC) {
         const float4 d4 = *reinterpret_cast<const float4*>(a.D + (size_t)gi * a.ldd + j0);
         dv[0] = d4.x; dv[V > 1 ? 1 : 0] = d4.y; dv[V > 2 ? 2 : 0] = d4.z; dv[V > 3 ? 3 : 0] = d4.w;
@@ -527,6 +520,20 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
       } else {
         dv[0] = a.D[(size_t)gi * a.ldd + j0];
         zv[0] = (MODE == MODE_FINAL || !a.first) ? a.Zin[gij] : 0.0f;
+      }
+    };
+    auto element_group = [&](int i, int j0, const float (&Lv)[V], const float (&dv)[V], const float (&zv)[V],
+                             uint32_t qb) {
+      const int gi = i0 + i;
+      const size_t gij = (size_t)gi * n + j0;
+      if (MODE == MODE_RECON) {
+        if (VEC) {
+          *reinterpret_cast<float4*>(a.Lout + gij) =
+              make_float4(Lv[0], Lv[V > 1 ? 1 : 0], Lv[V > 2 ? 2 : 0], Lv[V > 3 ? 3 : 0]);
+        } else {
+          a.Lout[gij] = Lv[0];
+        }
+        return;
       }
       float o1[V], o2[V], o3[V];
 #pragma unroll
@@ -574,20 +581,35 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     };
     if (fixed_cols) {
       // every thread keeps the same V columns for all rows of the tile (stencil in
-      // registers, no index arithmetic per element)
+      // registers, no index arithmetic per element); the loads of kRowBatch rows are
+      // issued together
+      constexpr int RB = kRowBatch;
       if (ec_on)
-        for (int i = ec_r0; i < rows; i += ec_rstep) {
-          const float* nrow = sN + i * kLdN;
-          float Lv[V];
+        for (int i = ec_r0; i < rows; i += RB * ec_rstep) {
+          float dv[RB][V], zv[RB][V];
+          uint32_t qb[RB];
 #pragma unroll
-          for (int v = 0; v < V; ++v) Lv[v] = fmaf(st_w1[v], nrow[st_i1[v]], st_w0[v] * nrow[st_i0[v]]);
-          element_group(i, ec_j0, Lv);
+          for (int u = 0; u < RB; ++u)
+            if (i + u * ec_rstep < rows) load_group(i + u * ec_rstep, ec_j0, dv[u], zv[u], qb[u]);
+#pragma unroll
+          for (int u = 0; u < RB; ++u) {
+            const int ii = i + u * ec_rstep;
+            if (ii >= rows) break;
+            const float* nrow = sN + ii * kLdN;
+            float Lv[V];
+#pragma unroll
+            for (int v = 0; v < V; ++v) Lv[v] = fmaf(st_w1[v], nrow[st_i1[v]], st_w0[v] * nrow[st_i0[v]]);
+            element_group(ii, ec_j0, Lv, dv[u], zv[u], qb[u]);
+          }
         }
     } else {
       const int groups = rows * n / V;
       for (int g = tid; g < groups; g += kThreads) {
         const int e = g * V;
         const int i = e / n, j0 = e % n;
+        float dv[V], zv[V];
+        uint32_t qb = 0;
+        load_group(i, j0, dv, zv, qb);
         const float* nrow = sN + i * kLdN;
         float Lv[V];
 #pragma unroll
@@ -595,7 +617,7 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
           const int j = j0 + v;
           Lv[v] = fmaf(sRw[2 * j + 1], nrow[sRi[2 * j + 1]], sRw[2 * j] * nrow[sRi[2 * j]]);
         }
-        element_group(i, j0, Lv);
+        element_group(i, j0, Lv, dv, zv, qb);
       }
     }
     if (MODE == MODE_STEP) {
