@@ -627,13 +627,25 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
       if (rc_on) {
         float acc[kTallRows / 4] = {};
         const int t0 = sCp[rc_c], t1 = sCp[rc_c + 1];
-        for (int t = t0; t < t1; ++t) {
-          const int col = sCr[t];
-          const float w = sCw[t];
+        // taps in chunks of 8: their indices and weights are read together, then the
+        // data (same accumulation order as one tap at a time)
+        for (int t = t0; t < t1; t += 8) {
+          int cols[8];
+          float ws[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            cols[u] = t + u < t1 ? sCr[t + u] : 0;
+            ws[u] = t + u < t1 ? sCw[t + u] : 0.0f;
+          }
 #pragma unroll
           for (int k = 0; k < kTallRows / 4; ++k) {
             const int i = rc_r0 + k * rc_rstep;
-            if (i < rows) acc[k] = fmaf(w, sX[(size_t)i * n + col], acc[k]);
+            if (i < rows) {
+              const float* x = sX + (size_t)i * n;
+#pragma unroll
+              for (int u = 0; u < 8; ++u)
+                if (t + u < t1) acc[k] = fmaf(ws[u], x[cols[u]], acc[k]);
+            }
           }
         }
 #pragma unroll
