@@ -400,8 +400,6 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
   float* sCw = reinterpret_cast<float*>(sCr + nnz);         // nnz
   const int tid = threadIdx.x;
   const int wave = tid >> 6, lane = tid & 63;
-  // the M_P tile beyond column nH (and rows never loaded) must hold finite zeros
-  for (int e = tid; e < kTallRows * kLdA; e += kThreads) sMP[e] = 0.0f;
   for (int e = tid; e < 2 * n; e += kThreads) {
     sRi[e] = a.row_idx[e];
     sRw[e] = a.row_w[e];
@@ -456,14 +454,29 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
   const int rc_r0 = tid / nH, rc_c = tid % nH;
   const bool rc_on = rc_r0 < rc_rstep;
   double racc = 0.0;
+  // the M_P rows of the block's next tile are fetched into registers one tile ahead
+  constexpr int MPR = kTallRows * kTallNH / kThreads;
+  float mpv[MPR];
+  auto fetch_mp = [&](int tile) {
+    const int r0 = tile * TM, nr = min(TM, a.m - r0);
+#pragma unroll
+    for (int e = 0; e < MPR; ++e) {
+      const int x = tid + kThreads * e;
+      const int i = x / kTallNH, c = x % kTallNH;
+      mpv[e] = (i < nr && c < nH) ? a.MPcur[(size_t)(r0 + i) * a.ldp + c] : 0.0f;
+    }
+  };
+  if (blockIdx.x < ntiles) fetch_mp(blockIdx.x);
   for (int tile = blockIdx.x; tile < ntiles; tile += gridDim.x) {
     const int i0 = tile * TM;
     const int rows = min(TM, a.m - i0);
     __syncthreads();
-    for (int e = tid; e < rows * nH; e += kThreads) {
-      const int i = e / nH, c = e % nH;
-      sMP[i * kLdA + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
+#pragma unroll
+    for (int e = 0; e < MPR; ++e) {
+      const int x = tid + kThreads * e;
+      sMP[(x / kTallNH) * kLdA + x % kTallNH] = mpv[e];
     }
+    if (tile + (int)gridDim.x < ntiles) fetch_mp(tile + gridDim.x);
     __syncthreads();
     if (wave_on) {                                          // N = M_P K
       f32x4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
