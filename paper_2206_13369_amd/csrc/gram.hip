@@ -296,20 +296,20 @@ __global__ void __launch_bounds__(256) k_gram_tall(const float* __restrict__ A, 
   }
 }
 
-// G from the tall partials: 64 tile entries per block, 4 thread groups each summing
-// every 4th split, then the group sums in order; each entry written to both halves.
+// G from the tall partials: 16 tile entries per block, 16 thread groups each summing
+// every 16th split, then the group sums in order; each entry written to both halves.
 // In a diagonal tile only the upper triangle is used: the split product sums (i, j)
 // and (j, i) in different orders, so the two can differ in the last bits.
 __global__ void __launch_bounds__(256) k_gram_tall_reduce(const double* __restrict__ part, int splits, int nt,
                                                           double* __restrict__ G, int ldg) {
-  __shared__ double red[4][64];
+  __shared__ double red[16][17];
   const int U = nt * (nt + 1) / 2;
-  const int e = threadIdx.x & 63, g = threadIdx.x >> 6;
-  const int idx = blockIdx.x * 64 + e;
+  const int e = threadIdx.x & 15, g = threadIdx.x >> 4;
+  const int idx = blockIdx.x * 16 + e;
   const int total = U * 256;
   double s = 0.0;
   if (idx < total)
-    for (int q = g; q < splits; q += 4) s += part[(size_t)q * total + idx];
+    for (int q = g; q < splits; q += 16) s += part[(size_t)q * total + idx];
   red[g][e] = s;
   __syncthreads();
   if (g == 0 && idx < total) {
@@ -318,7 +318,9 @@ __global__ void __launch_bounds__(256) k_gram_tall_reduce(const double* __restri
     const int r = (idx & 255) >> 4, c = idx & 15;
     if (a == b && r > c) return;
     const int i = a * 16 + r, j = b * 16 + c;
-    const double v = ((red[0][e] + red[1][e]) + red[2][e]) + red[3][e];
+    double v = 0.0;
+#pragma unroll
+    for (int k = 0; k < 16; ++k) v += red[k][e];
     G[(size_t)i * ldg + j] = v;
     G[(size_t)j * ldg + i] = v;
   }
@@ -326,7 +328,7 @@ __global__ void __launch_bounds__(256) k_gram_tall_reduce(const double* __restri
 
 void gram_tall_plan(int m, int nt, int& splits, int& rows_per_split) {
   const int U = nt * (nt + 1) / 2;
-  const int target = U > 3 ? 256 : 512;
+  const int target = U > 3 ? 512 : 1024;
   int rps = round_up((m + target - 1) / target, TALL_ROWS);
   splits = (m + rps - 1) / rps;
   rows_per_split = rps;
@@ -382,7 +384,7 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
     else
       hipLaunchKernelGGL(k_gram_tall<0>, dim3(sp), dim3(256), 0, stream, A, m, k, lda, rps, nt, part);
     const int total = nt * (nt + 1) / 2 * 256;
-    hipLaunchKernelGGL(k_gram_tall_reduce, dim3((total + 63) / 64), dim3(256), 0, stream, part, sp, nt, G, kp);
+    hipLaunchKernelGGL(k_gram_tall_reduce, dim3((total + 15) / 16), dim3(256), 0, stream, part, sp, nt, G, kp);
     MLPCP_HIP(hipGetLastError());
     return MLPCP_OK;
   }
