@@ -103,7 +103,7 @@ int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V
                      hipStream_t stream);
 
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws,
-            hipStream_t stream, int* sweeps_out, bool warm);
+            hipStream_t stream, int* sweeps_out, bool warm, int sweep_hint = 0);
 
 // ---- Gram (gram.hip) ---------------------------------------------------------------
 // G = A^T A for A m x k (float32, ld = lda, k <= kp, kp multiple of kPad), accumulated

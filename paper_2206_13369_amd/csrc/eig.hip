@@ -284,10 +284,11 @@ __device__ __forceinline__ int pair_global(int l, int I, int J) { return l < IB 
 constexpr int kPairThreads = 1024;
 __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restrict__ A, int N, int nb, int round,
                                                       double* __restrict__ Qblk, const double* __restrict__ floor_p,
-                                                      int* __restrict__ flag) {
+                                                      const int* __restrict__ active) {
   __shared__ double sA[IN][LDS_LD];
   __shared__ double sQ[IN][LDS_LD];
   __shared__ RotShared rs;
+  if (!*active) return;   // the sweep's pre-test found nothing to rotate
   int I, J;
   rr_pair(blockIdx.x, round, nb, I, J);
   constexpr int PER = IN * IN / kPairThreads;
@@ -333,7 +334,6 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
     A[(size_t)pair_global(i, I, J) * N + pair_global(j, I, J)] = sA[i][j];
   }
   if (threadIdx.x == 0) Qo[IN * IN] = rs.any ? 1.0 : 0.0;   // per-pair "rotated" marker
-  if (threadIdx.x == 0 && rs.any) atomicOr(flag, 1);
 }
 
 // 64x64x64 product on MFMA f64 by 4 waves (each a 32x32 quadrant of 2x2 16x16 blocks):
@@ -382,9 +382,11 @@ __device__ __forceinline__ void mm64_store(const d4_t acc[2][2], F&& put) {
 // [ntri, ntri + (N/IN)*npairs) update V tiles (IN-row chunk x pair b cols).
 // Tiles whose two factors are both the identity are skipped.
 __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, double* __restrict__ V, int N, int nb,
-                                                      int round, const double* __restrict__ Qblk) {
+                                                      int round, const double* __restrict__ Qblk,
+                                                      const int* __restrict__ active) {
   __shared__ double sT[IN][LDS_LD];
   __shared__ double sQ[IN][LDS_LD];
+  if (!*active) return;
   const int npairs = nb / 2;
   const int ntri = npairs * (npairs - 1) / 2;
   const int tid = threadIdx.x;
@@ -786,6 +788,11 @@ __global__ void __launch_bounds__(256) k_any_rotation(const double* __restrict__
   if (__syncthreads_or(want) && threadIdx.x == 0) atomicOr(flag, 1);
 }
 
+// counts the sweeps whose pre-test found something to rotate
+__global__ void k_count_sweep(const int* __restrict__ active, int* __restrict__ count) {
+  if (threadIdx.x == 0 && *active) count[0] += 1;
+}
+
 __global__ void k_identity(double* __restrict__ V, int N) {
   const size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (idx < (size_t)N * N) V[idx] = ((idx / N) == (idx % N)) ? 1.0 : 0.0;
@@ -840,7 +847,7 @@ size_t eig_workspace_bytes(int N) {
 }
 
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws, hipStream_t stream,
-            int* sweeps_out, bool warm) {
+            int* sweeps_out, bool warm, int sweep_hint) {
   if (N % IN != 0 || n > N || n < 1) return MLPCP_E_INVALID_ARG;
   char* w = static_cast<char*>(ws);
   const int nb = N / IB;
@@ -880,35 +887,49 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
     const int ntri = npairs * (npairs - 1) / 2;
     const int apply_blocks = ntri + (N / IN) * npairs;
     bool converged = false;
-    int hflag = 0;
-    // a sweep starts only if some pair passes the rotation test (a sweep in which none
-    // does rotates nothing), so convergence costs one test, not one more sweep
-    for (sweeps = 0;; ++sweeps) {
-      MLPCP_HIP(hipMemsetAsync(flag, 0, sizeof(int), stream));
-      {
-        ProfScope ps(KC_JACOBI_MISC, stream);
-        hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, A, N, floor_p, flag);
+    // Each sweep starts with a device-side test (any pair passing the rotation test?)
+    // whose result gates every kernel of the sweep, so sweeps can be queued without a
+    // host round trip: a sweep after convergence costs its empty launches only.  The
+    // first batch is one sweep less than the caller's hint (the previous solve's
+    // count); then one sweep per host check until the test finds nothing.
+    int* active = flag;
+    MLPCP_HIP(hipMemsetAsync(dsweeps, 0, sizeof(int), stream));
+    int queued = 0, batch = std::max(1, std::min(sweep_hint - 1, kMaxEigSweeps));
+    int hstate[2] = {0, 0};
+    for (;;) {
+      for (int b = 0; b < batch; ++b) {
+        MLPCP_HIP(hipMemsetAsync(active, 0, sizeof(int), stream));
+        {
+          ProfScope ps(KC_JACOBI_MISC, stream);
+          hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, A, N, floor_p, active);
+          hipLaunchKernelGGL(k_count_sweep, dim3(1), dim3(64), 0, stream, active, dsweeps);
+        }
+        for (int r = 0; r < nb - 1; ++r) {
+          {
+            ProfScope ps(KC_JACOBI_PAIRS, stream);
+            hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, A, N, nb, r, Qblk,
+                               floor_p, active);
+          }
+          {
+            ProfScope ps(KC_JACOBI_APPLY, stream);
+            hipLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, A, V, N, nb, r, Qblk,
+                               active);
+          }
+        }
       }
       MLPCP_HIP(hipGetLastError());
-      MLPCP_HIP(hipMemcpyAsync(&hflag, flag, sizeof(int), hipMemcpyDeviceToHost, stream));
+      queued += batch;
+      // active and the sweep count are adjacent in the workspace
+      MLPCP_HIP(hipMemcpyAsync(&hstate[0], active, sizeof(int), hipMemcpyDeviceToHost, stream));
+      MLPCP_HIP(hipMemcpyAsync(&hstate[1], dsweeps, sizeof(int), hipMemcpyDeviceToHost, stream));
       MLPCP_HIP(hipStreamSynchronize(stream));
-      if (!hflag) {
+      sweeps = hstate[1];
+      if (!hstate[0]) {   // the last pre-test found nothing: converged
         converged = true;
         break;
       }
-      if (sweeps == kMaxEigSweeps) break;
-      for (int r = 0; r < nb - 1; ++r) {
-        {
-          ProfScope ps(KC_JACOBI_PAIRS, stream);
-          hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, A, N, nb, r, Qblk, floor_p,
-                             flag);
-        }
-        {
-          ProfScope ps(KC_JACOBI_APPLY, stream);
-          hipLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, A, V, N, nb, r, Qblk);
-        }
-      }
-      MLPCP_HIP(hipGetLastError());
+      if (sweeps >= kMaxEigSweeps || queued > 2 * kMaxEigSweeps) break;
+      batch = 1;
     }
     if (!converged) return MLPCP_E_EIG;
   }

@@ -891,7 +891,8 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
   }
-  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps, warm));
+  // the previous eigensolve's sweep count (in *sweeps on entry) sizes the first batch
+  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps, warm, warm ? *sweeps : 0));
   ProfScope ps(KC_SVT, s);
   hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, sw, st);
   const size_t tot = (size_t)p.nH * p.nH;
