@@ -20,6 +20,8 @@ float64 copy of the unrolled solver for reference gradients:
                    their masked (compressive) form.
 * ``unrolled``     K unrolled multilevel iterations with a fixed penalty
                    schedule, differentiated by torch.autograd in float64.
+* ``fwt``          Frank-Wolfe Thresholding (Alg. 3) and its multilevel form
+                   (Alg. 6) for the unconstrained CPCP problem, eq. (cpcp).
 
 Every reading of a passage that is silent, garbled or ambiguous is listed in
 the module where it is taken.
@@ -29,8 +31,10 @@ from .restriction import (interp_level, composite_interp, coarse_dim, orthonorma
 from .prox import shrink, svt, svt_prox
 from .ialm import IALMResult, ialm, default_schedule
 from .power import spectral_norm
+from .fwt import FWTResult, fwt
 
 __all__ = [
     "interp_level", "composite_interp", "coarse_dim", "orthonormal_restriction", "restrict", "prolong",
     "shrink", "svt", "svt_prox", "IALMResult", "ialm", "default_schedule", "spectral_norm",
+    "FWTResult", "fwt",
 ]

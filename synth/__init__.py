@@ -32,6 +32,9 @@ __all__ = [
     "config",
     "CONFIG_NAMES",
     "mu0_for",
+    "fw_cpcp",
+    "fw_config",
+    "FW_CONFIG_NAMES",
 ]
 
 
@@ -48,6 +51,8 @@ class Workload:
     mu0: float
     tol: float = 1e-6
     recipe: str = ""
+    lam_L: Optional[float] = None  # weight of the nuclear term (unconstrained CPCP only;
+                                   # ``lam`` then weighs the l1 term)
 
     @property
     def m(self) -> int:
@@ -251,3 +256,59 @@ def config(name: str, scale: float = 1.0) -> Workload:
         side = max(16, int(round(512 * math.sqrt(scale))))
         return hyperspectral_like(side=side, bands=200, levels=4, name="c5")
     raise KeyError(name)
+
+
+def fw_cpcp(m: int, n: int, rank: int, *, seed: int, levels: int, sparse_frac: float = 0.05,
+            sparse_amp: float = 5.0, observed_frac: float = 0.8, delta: float = 0.02,
+            name: str = "fw") -> Workload:
+    """Synthetic unconstrained-CPCP data after the synthetic experiments of Sec. 4.1
+    (D = L^ + S^ with rank-r L^ whose singular values decay as 1/k^2, sparse S^, part
+    of the entries observed).  Sizes the paper leaves open are fixed here:
+
+    L0 = U diag(s0 / k^2) V^T, U (m x r) orthonormal from a Gaussian, V (n x r)
+    orthonormalised smooth curves cos(pi k t + phi_k), t in [0, 1], k = 0..r-1 (rows of
+    L0 vary slowly along n, as the coarse model presumes); s0 gives L0 unit RMS.
+    S0: ``sparse_frac`` of the entries, exact uniform support, values U[-amp, amp].
+    Q: ``observed_frac`` of the entries, exact uniform support.
+    lam_L = delta * observed_frac * s0 (a fraction of the top singular value of the
+    observed low-rank part), lam_S = lam_L / sqrt(max(m, n)); both rounded to float32
+    so that every solver sees the same values.  ``lam`` holds lam_S."""
+    rng = np.random.Generator(np.random.PCG64(seed))
+    U, _ = np.linalg.qr(rng.normal(size=(m, rank)))
+    t = np.linspace(0.0, 1.0, n)
+    phases = rng.uniform(0.0, 2.0 * math.pi, size=rank)
+    V = np.stack([np.cos(math.pi * k * t + phases[k]) for k in range(rank)], axis=1)
+    V, _ = np.linalg.qr(V)
+    decay = 1.0 / np.arange(1, rank + 1, dtype=np.float64) ** 2
+    s0 = math.sqrt(m * n / float(np.sum(decay ** 2)))
+    L0 = (U * (s0 * decay)) @ V.T
+    S0 = np.zeros(m * n)
+    idx = _exact_support(rng, m * n, sparse_frac)
+    S0[idx] = rng.uniform(-sparse_amp, sparse_amp, size=idx.size)
+    S0 = S0.reshape(m, n)
+    Q = _mask(rng, m, n, observed_frac)
+    D = np.ascontiguousarray((L0 + S0).astype(np.float32))
+    lam_L = float(np.float32(delta * observed_frac * s0))
+    lam_S = float(np.float32(lam_L / math.sqrt(max(m, n))))
+    return Workload(name, D, Q, L0, S0, lam_S, levels, rank, 0.0, tol=1e-3, lam_L=lam_L,
+                    recipe=f"L0 rank {rank}, sigma_k = s0/k^2, smooth right factors; S0 {sparse_frac:.0%} "
+                           f"U[-{sparse_amp},{sparse_amp}]; observed {observed_frac:.0%}; lam_L {lam_L:.4g} "
+                           f"lam_S {lam_S:.4g}; seed {seed}")
+
+
+FW_CONFIG_NAMES = ("fw1", "fw2", "fw3", "fw4")
+
+
+def fw_config(name: str, scale: float = 1.0) -> Workload:
+    """The four synthetic CPCP problems of the Frank-Wolfe comparison (Table 2 sizes):
+
+    fw1  10000 x 500,  rank 2, 3 levels (n_H = 63)
+    fw2  10000 x 5000, rank 2, 7 levels (n_H = 40)
+    fw3  10000 x 500,  rank 5, 3 levels
+    fw4  10000 x 5000, rank 5, 7 levels
+
+    ``scale`` < 1 shrinks m (for quick tests)."""
+    sizes = {"fw1": (500, 2, 3, 11), "fw2": (5000, 2, 7, 12), "fw3": (500, 5, 3, 13), "fw4": (5000, 5, 7, 14)}
+    n, rank, levels, seed = sizes[name]
+    m = max(n, int(round(10000 * scale)))
+    return fw_cpcp(m, n, rank, seed=seed, levels=levels, name=name)
