@@ -31,10 +31,10 @@ from .restriction import (interp_level, composite_interp, coarse_dim, orthonorma
 from .prox import shrink, svt, svt_prox
 from .ialm import IALMResult, ialm, default_schedule
 from .power import spectral_norm
-from .fwt import FWTResult, fwt
+from . import fwt
 
 __all__ = [
     "interp_level", "composite_interp", "coarse_dim", "orthonormal_restriction", "restrict", "prolong",
     "shrink", "svt", "svt_prox", "IALMResult", "ialm", "default_schedule", "spectral_norm",
-    "FWTResult", "fwt",
+    "fwt",
 ]
