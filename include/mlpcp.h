@@ -204,13 +204,58 @@ int mlpcp_ialm_step_vjp(int m, int n, int levels, const float* D, int ldd, const
                         float* D_bar, float* S_bar_prev, float* Y_bar_prev, double* lambda_bar,
                         void* ws, size_t ws_bytes, void* stream);
 
+/* ---- Unconstrained CPCP by Frank-Wolfe Thresholding ---------------------------
+ * eq. (cpcp):  min 1/2 ||P_Q[L + S - D]||_F^2 + lam_L ||L||_* + lam_S ||S||_1,
+ * by FW-T (Alg. 3, levels = 0) or multilevel FW-T (Alg. 6, levels > 0) on the
+ * epigraph form eq. (cpcp-fw): L = S = 0, t_L = t_S = 0, U = f / lam at start;
+ * each iteration takes the nuclear linear oracle -u w^T (top singular pair of the
+ * gradient G = P_Q[L + S - D]; ML-FWT: of the coarse gradient G R, lifted by R^T,
+ * radius 1/||R||_2 = 1), the l1 oracle at the largest |G_ij|, the gates
+ * lam >= -<G, M>, the exact line search over both segments (a convex quadratic
+ * on the unit square), the threshold S = S_{lam_S}[S_half - P_Q[L + S_half - D]]
+ * with t_S = ||S||_1, and the bounds U = f / lam.
+ * Stopping: relative objective change |f_{k-1} - f_k| / f_{k-1} <= tol (the paper
+ * runs to a 1e-3 tolerance without defining it).
+ *  D    m x n (ldd >= n), m >= n, m * n < 2^31.
+ *  Q    m x n uint8 mask (ld = n), nonzero = observed; NULL = fully observed.
+ *  lam_L, lam_S > 0 (the arithmetic uses these float values).
+ *  levels  0 = FW-T (power iteration for the top pair, n <= 8192 with
+ *          16-byte-aligned D and L and ldd % 4 == 0, else n <= 2048);
+ *          > 0 = ML-FWT, n_H <= 64.  Other shapes: MLPCP_E_UNSUPPORTED.
+ *  L, S outputs m x n (ld = n): the last iterate; S is zero off Q.
+ *  ws   device workspace >= mlpcp_fwt_workspace_bytes(m, n, levels, Q != NULL),
+ *       or NULL (allocated and freed inside).
+ *  info optional report; its history arrays (host, optional) receive per
+ *       iteration f, the step sizes alpha, beta and the top singular value.
+ * Returns MLPCP_OK when the stopping test holds (also when P_Q D = 0: zero
+ * iterations, L = S = 0), MLPCP_NOT_CONVERGED after max_iter.  Synchronises.   */
+typedef struct {
+  int iters;               /* iterations performed                            */
+  int converged;           /* 1 if the stopping test held                     */
+  double f;                /* objective f(L, S, t_L, t_S) of the last iterate */
+  double t_L, t_S;         /* its epigraph variables (t_S = ||S||_1)          */
+  double rel_change;       /* last |f_{k-1} - f_k| / f_{k-1}                  */
+  double gap;              /* Frank-Wolfe gap <grad f, x - v> of the last step */
+  long long power_steps;   /* power-iteration steps in total (FW-T)          */
+  double* f_history;       /* in: optional host arrays of history_len entries */
+  double* alpha_history;
+  double* beta_history;
+  double* sigma_history;
+  int history_len;
+} mlpcp_fwt_info;
+
+size_t mlpcp_fwt_workspace_bytes(int m, int n, int levels, int masked);
+int mlpcp_cpcp_fwt(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam_L, float lam_S,
+                   int levels, double tol, int max_iter, float* L, float* S, void* ws, size_t ws_bytes,
+                   mlpcp_fwt_info* info, void* stream);
+
 /* Static description of a status code (never NULL).                          */
 const char* mlpcp_status_string(int status);
 
 /* Kernel timing, for diagnostics and benchmarking.  Kernels are grouped into
- * classes (read() reports them in a fixed order: init_restrict, gram_f64,
+ * classes (read() reports them in a fixed order: init_restrict, gram,
  * coarse_CGC, jacobi_pairs, jacobi_apply, jacobi_misc, svt_prep, epilogue,
- * reduce, finalize, other).  enable(mask) resets the counters and brackets every
+ * reduce, finalize, coarse_svt_small, fw_pass, fw_power, fw_small, other).  enable(mask) resets the counters and brackets every
  * launch of class i with HIP events on the caller's stream when bit i of mask is
  * set (mask 0 = off, -1 = all); the elapsed times are accumulated per class.
  * read() copies up to `cap` classes into `out` (static names) and returns the

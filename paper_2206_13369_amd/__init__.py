@@ -8,7 +8,8 @@ functions that need it raises.
 
 Entry points (same names as the C ABI, minus the ``mlpcp_`` prefix):
     pcp_solve, cpcp_solve, svt_prox, shrink, restrict, prolong,
-    coarse_dim, workspace_bytes, default_opts, status_string
+    coarse_dim, workspace_bytes, default_opts, status_string,
+    cpcp_fwt, fwt_workspace_bytes
 and the raw ctypes handle ``lib()`` for tests that call the C ABI directly.
 """
 from __future__ import annotations
@@ -36,7 +37,7 @@ EXPORTED = (
     "mlpcp_default_opts", "mlpcp_coarse_dim", "mlpcp_workspace_bytes", "mlpcp_pcp_solve",
     "mlpcp_cpcp_solve", "mlpcp_svt_prox", "mlpcp_shrink", "mlpcp_restrict", "mlpcp_prolong",
     "mlpcp_status_string", "mlpcp_profile_enable", "mlpcp_profile_read", "mlpcp_step_workspace_bytes",
-    "mlpcp_ialm_step", "mlpcp_ialm_step_vjp",
+    "mlpcp_ialm_step", "mlpcp_ialm_step_vjp", "mlpcp_fwt_workspace_bytes", "mlpcp_cpcp_fwt",
 )
 
 
@@ -52,6 +53,15 @@ class Info(ctypes.Structure):
                 ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
                 ("history_len", ctypes.c_int), ("gram_bf16_iters", ctypes.c_int),
                 ("gram_split_iters", ctypes.c_int), ("sweeps_history", ctypes.POINTER(ctypes.c_int))]
+
+
+class FwtInfo(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int), ("converged", ctypes.c_int), ("f", ctypes.c_double),
+                ("t_L", ctypes.c_double), ("t_S", ctypes.c_double), ("rel_change", ctypes.c_double),
+                ("gap", ctypes.c_double), ("power_steps", ctypes.c_longlong),
+                ("f_history", ctypes.POINTER(ctypes.c_double)), ("alpha_history", ctypes.POINTER(ctypes.c_double)),
+                ("beta_history", ctypes.POINTER(ctypes.c_double)), ("sigma_history", ctypes.POINTER(ctypes.c_double)),
+                ("history_len", ctypes.c_int)]
 
 
 class KernelTime(ctypes.Structure):
@@ -110,12 +120,17 @@ def lib() -> ctypes.CDLL:
     L.mlpcp_ialm_step_vjp.argtypes = [i, i, i, vp, i, vp, vp, f, d, vp, vp, vp, vp, vp, vp,
                                       ctypes.POINTER(d), vp, sz, vp]
     L.mlpcp_ialm_step_vjp.restype = i
+    L.mlpcp_fwt_workspace_bytes.argtypes = [i, i, i, i]
+    L.mlpcp_fwt_workspace_bytes.restype = sz
+    L.mlpcp_cpcp_fwt.argtypes = [i, i, vp, i, vp, f, f, i, d, i, vp, vp, vp, sz, ctypes.POINTER(FwtInfo), vp]
+    L.mlpcp_cpcp_fwt.restype = i
     _lib = L
     return L
 
 
 KERNEL_CLASSES = ("init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply", "jacobi_misc",
-                  "svt_prep", "epilogue", "reduce", "finalize", "coarse_svt_small", "other")
+                  "svt_prep", "epilogue", "reduce", "finalize", "coarse_svt_small", "fw_pass", "fw_power",
+                  "fw_small", "other")
 
 
 def profile_enable(on=True) -> None:
@@ -390,3 +405,69 @@ def penalty_schedule(mu0: float, iters: int, rho: float = 1.5, mu_max_factor: fl
     for _ in range(iters - 1):
         mus.append(min(rho * mus[-1], mu_max_factor * mu0))
     return mus
+
+
+# ---- unconstrained CPCP by (multilevel) Frank-Wolfe Thresholding ----------------------
+
+@dataclasses.dataclass
+class FwtResult:
+    L: object
+    S: object
+    status: int
+    iters: int
+    converged: bool
+    f: float
+    t_L: float
+    t_S: float
+    rel_change: float
+    gap: float
+    power_steps: int
+    f_history: list
+    alpha_history: list
+    beta_history: list
+    sigma_history: list
+
+
+def fwt_workspace_bytes(m: int, n: int, levels: int, masked: bool) -> int:
+    return int(lib().mlpcp_fwt_workspace_bytes(int(m), int(n), int(levels), 1 if masked else 0))
+
+
+def cpcp_fwt(D, Q, lam_L: float, lam_S: float, *, levels: int = 0, tol: float = 1e-3, max_iter: int = 1000,
+             workspace=None, history: int = 0) -> FwtResult:
+    """min 1/2 ||P_Q[L + S - D]||^2 + lam_L ||L||_* + lam_S ||S||_1 by FW-T (levels = 0)
+    or ML-FWT (levels > 0); D m x n float32 on the GPU, Q uint8 mask or None."""
+    torch = _torch()
+    _check_dev(D, "D", torch.float32)
+    if D.dim() != 2 or D.stride(1) != 1:
+        raise ValueError("D must be a 2-D row-major tensor")
+    m, n = D.shape
+    dev = D.device
+    if Q is not None:
+        _check_dev(Q, "Q", torch.uint8)
+        if not Q.is_contiguous() or tuple(Q.shape) != (m, n):
+            raise ValueError("Q must be a contiguous m x n uint8 tensor")
+    L = torch.empty((m, n), dtype=torch.float32, device=dev)
+    S = torch.empty((m, n), dtype=torch.float32, device=dev)
+    wsb = fwt_workspace_bytes(m, n, levels, Q is not None)
+    if wsb == 0:
+        raise MLPCPError(MLPCP_E_SHAPE, "cpcp_fwt")
+    if workspace is None:
+        ws = torch.empty(wsb, dtype=torch.uint8, device=dev)
+    else:
+        ws = workspace
+        if ws.numel() < wsb:
+            raise ValueError(f"workspace needs {wsb} bytes")
+    info = FwtInfo()
+    hs = [(ctypes.c_double * history)() for _ in range(4)] if history else None
+    if history:
+        info.f_history, info.alpha_history, info.beta_history, info.sigma_history = hs
+        info.history_len = history
+    st = lib().mlpcp_cpcp_fwt(m, n, _ptr(D), D.stride(0), _ptr(Q), float(lam_L), float(lam_S), int(levels),
+                              float(tol), int(max_iter), _ptr(L), _ptr(S), _ptr(ws), ws.numel(), ctypes.byref(info),
+                              _stream(dev))
+    if st < 0:
+        raise MLPCPError(st, "cpcp_fwt")
+    k = min(info.iters, history) if history else 0
+    hist = [[h[i] for i in range(k)] for h in hs] if history else [[], [], [], []]
+    return FwtResult(L, S, st, info.iters, bool(info.converged), info.f, info.t_L, info.t_S, info.rel_change,
+                     info.gap, int(info.power_steps), *hist)

@@ -17,6 +17,9 @@ enum KernelClass {
   KC_REDUCE,
   KC_FINAL,
   KC_COARSE_SMALL,
+  KC_FW_PASS,
+  KC_FW_POWER,
+  KC_FW_SMALL,
   KC_OTHER,
   KC_COUNT
 };

@@ -124,3 +124,45 @@ def test_stream_ops_validation():
 def test_status_strings():
     for s in (0, 1, -1, -2, -3, -4, -5, -6, -7, -8, 99):
         assert isinstance(mlp.status_string(s), str) and mlp.status_string(s)
+
+
+# ---- unconstrained CPCP by Frank-Wolfe Thresholding --------------------------------
+
+def _fwt(m, n, ldd, lamL, lamS, levels=2, tol=1e-3, max_iter=10, L=ctypes.c_void_p(12288),
+         S=ctypes.c_void_p(8192), ws=None, ws_bytes=0):
+    return mlp.lib().mlpcp_cpcp_fwt(m, n, FAKE, ldd, None, lamL, lamS, levels, tol, max_iter, L, S, ws, ws_bytes,
+                                    None, None)
+
+
+@pytest.mark.parametrize("args,status", [
+    ((100, 20, 20, 0.0, 0.1), mlp.MLPCP_E_INVALID_ARG),
+    ((100, 20, 20, 1.0, -0.1), mlp.MLPCP_E_INVALID_ARG),
+    ((100, 20, 20, float("nan"), 0.1), mlp.MLPCP_E_INVALID_ARG),
+    ((10, 20, 20, 1.0, 0.1), mlp.MLPCP_E_SHAPE),
+    ((100, 20, 10, 1.0, 0.1), mlp.MLPCP_E_SHAPE),
+    ((0, 20, 20, 1.0, 0.1), mlp.MLPCP_E_SHAPE),
+])
+def test_fwt_rejects_bad_arguments(args, status):
+    assert _fwt(*args) == status
+
+
+def test_fwt_rejects_bad_options():
+    assert _fwt(100, 20, 20, 1.0, 0.1, tol=0.0) == mlp.MLPCP_E_INVALID_ARG
+    assert _fwt(100, 20, 20, 1.0, 0.1, max_iter=0) == mlp.MLPCP_E_INVALID_ARG
+    assert _fwt(100, 8, 8, 1.0, 0.1, levels=4) == mlp.MLPCP_E_LEVELS
+    assert _fwt(100, 20, 20, 1.0, 0.1, L=ctypes.c_void_p(8192)) == mlp.MLPCP_E_INVALID_ARG   # L aliases S
+    assert _fwt(1000, 200, 200, 1.0, 0.1, levels=1) == mlp.MLPCP_E_UNSUPPORTED               # n_H = 100 > 64
+    assert _fwt(100000, 30000, 30000, 1.0, 0.1, levels=9) == mlp.MLPCP_E_UNSUPPORTED         # m n >= 2^31
+    assert _fwt(20000, 10000, 10000, 1.0, 0.1, levels=0) == mlp.MLPCP_E_UNSUPPORTED          # power path n > 8192
+    assert _fwt(1000, 200, 200, 1.0, 0.1, levels=3, ws=ctypes.c_void_p(4096), ws_bytes=1024) == \
+        mlp.MLPCP_E_WORKSPACE
+
+
+def test_fwt_workspace_bytes():
+    a = mlp.fwt_workspace_bytes(1000, 500, 3, True)
+    b = mlp.fwt_workspace_bytes(2000, 500, 3, True)
+    assert 0 < a < b
+    assert mlp.fwt_workspace_bytes(1000, 500, 3, False) < a          # no mask bits
+    assert mlp.fwt_workspace_bytes(1000, 500, 0, True) > a           # dense L gradient and power buffers
+    assert mlp.fwt_workspace_bytes(10, 20, 0, True) == 0              # m < n
+    assert mlp.fwt_workspace_bytes(1000, 200, 1, True) == 0           # n_H > 64
