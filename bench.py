@@ -12,7 +12,12 @@ The plain method (levels = 0, the same kernels with R = I) is timed on the same
 input for the speedup.  Inputs are resident in HBM before the timed region.
 
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus N (N must be 1)
---workload {c1,c2,c3,c5} --no-plain --no-cpu --prec {fp32,bf16,bf16x3}.
+--workload {c1,c2,c3,c5,fw1,fw2,fw3,fw4} --no-plain --no-cpu --no-fw --prec {fp32,bf16,bf16x3}.
+
+The fw workloads measure the unconstrained-CPCP solvers of the Frank-Wolfe comparison
+(Table 2 sizes): one step = one ML-FWT solve to the 1e-3 tolerance (relative objective
+change), beside FW-T on the same input.  The default line also carries a short summary
+of the fw2 workload (10000 x 5000) under "fw".
 """
 import argparse
 import hashlib
@@ -43,6 +48,7 @@ def parse():
     ap.add_argument("--plain-steps", type=int, default=1)
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "bf16x3"],
                     help="arithmetic of the coarse SVT's Gram and reconstruction products")
+    ap.add_argument("--no-fw", action="store_true", help="skip the Frank-Wolfe summary of the default line")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="run one elementwise copy of MIB MiB (read MIB, write MIB) before the solves, "
                          "the reference kernel for scaling HBM byte counters")
@@ -94,6 +100,98 @@ def algorithmic_work(cls, w, nH, plain, sweeps):
         # 32 rounds of 32 rotations on a 64x64 block and its 64x64 factor
         return "alu", npairs * 32 * 32 * (64 * 6 + 64 * 6)
     return None, None
+
+
+def fw_pass_bytes(w, nH, plain):
+    """Algorithmic HBM bytes of one Frank-Wolfe pass over the data: read D and the mask
+    bits; ML-FWT reads and writes the coarse state Z and writes the restricted gradient
+    (m x n_H each); FW-T reads and writes the dense L and writes the gradient."""
+    m, n = w.m, w.n
+    bits = m * n / 8.0 if w.Q is not None else 0.0
+    if plain:
+        return 4.0 * m * n * 4 + bits
+    return 4.0 * m * n + bits + 12.0 * m * nH
+
+
+def fw_bench(w, dev, steps, plain=True, cpu=True):
+    """ML-FWT (and FW-T) solves to the 1e-3 tolerance on a resident input: time per solve,
+    iterations, per-kernel breakdown, the roofline of the ML pass, the oracle's time."""
+    import numpy as np
+    import torch
+
+    import paper_2206_13369_amd as mlp
+    D = torch.from_numpy(w.D).to(dev)
+    Q = torch.from_numpy(w.Q.astype(np.uint8)).to(dev)
+    nH = mlp.coarse_dim(w.n, w.levels)
+
+    def run(levels, ws):
+        return mlp.cpcp_fwt(D, Q, w.lam_L, w.lam, levels=levels, tol=w.tol, workspace=ws, history=1000)
+
+    ws = torch.empty(mlp.fwt_workspace_bytes(w.m, w.n, w.levels, True), dtype=torch.uint8, device=dev)
+    run(w.levels, ws)   # warm-up
+    torch.cuda.synchronize()
+    mlp.profile_enable(True)
+    run(w.levels, ws)
+    torch.cuda.synchronize()
+    prof = {k: v for k, v in mlp.profile_read().items() if v[0] > 0}
+    mlp.profile_enable(False)
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        r = run(w.levels, ws)
+    torch.cuda.synchronize()
+    ml_s = (time.perf_counter() - t0) / steps
+    mlp.profile_enable(["fw_pass"])
+    for _ in range(steps):
+        run(w.levels, ws)
+    torch.cuda.synchronize()
+    pl, pms = mlp.profile_read()["fw_pass"]
+    mlp.profile_enable(False)
+    roof = roofline("fw_pass", "hbm", fw_pass_bytes(w, nH, False), pms / 1e3 / max(pl, 1), pl)
+    if roof is not None:
+        roof["traffic"] = measured_traffic(w.name, "fw_pass")
+    out = dict(workload=f"{w.name}: CPCP {w.m}x{w.n}, rank {w.rank}, {w.Q.mean():.0%} observed, "
+                        f"{w.levels} levels (n_H={nH}), to 1e-3 relative objective change; {w.recipe}",
+               ml_time_s=round(ml_s, 6), ml_iters=r.iters, ml_f=r.f,
+               ml_ms_per_iter=round(ml_s * 1e3 / max(r.iters, 1), 4),
+               ml_kernel_ms_per_solve={k: round(v[1], 4) for k, v in prof.items()},
+               ml_launches_per_solve={k: v[0] for k, v in prof.items()},
+               roofline=roof)
+    del ws
+    if plain:
+        wsp = torch.empty(mlp.fwt_workspace_bytes(w.m, w.n, 0, True), dtype=torch.uint8, device=dev)
+        mlp.profile_enable(True)
+        rp = run(0, wsp)
+        torch.cuda.synchronize()
+        pprof = {k: v for k, v in mlp.profile_read().items() if v[0] > 0}
+        mlp.profile_enable(False)
+        t0 = time.perf_counter()
+        rp = run(0, wsp)
+        torch.cuda.synchronize()
+        pl_s = time.perf_counter() - t0
+        pw = pprof.get("fw_power", (0, 0.0))
+        out.update(plain_time_s=round(pl_s, 6), plain_iters=rp.iters, plain_f=rp.f,
+                   plain_ms_per_iter=round(pl_s * 1e3 / max(rp.iters, 1), 4),
+                   plain_power_steps=rp.power_steps,
+                   plain_us_per_power_step=round(pw[1] * 1e3 / max(rp.power_steps, 1), 2),
+                   plain_kernel_ms_per_solve={k: round(v[1], 4) for k, v in pprof.items()},
+                   speedup_vs_plain=round(pl_s / ml_s, 2),
+                   per_iter_speedup=round((pl_s / max(rp.iters, 1)) / (ml_s / max(r.iters, 1)), 2))
+        del wsp
+    if cpu:
+        import oracle.fwt as ofw
+        try:
+            from threadpoolctl import threadpool_info
+            cores = max([int(i.get("num_threads", 1)) for i in threadpool_info()] or [1])
+        except Exception:
+            cores = os.cpu_count()
+        K = 2
+        tc0 = time.perf_counter()
+        ofw.fwt(w.D, w.lam_L, w.lam, Q=w.Q, levels=w.levels, fixed_iters=K)
+        tc = time.perf_counter() - tc0
+        out["cpu_baseline"] = dict(value=round(tc / K * r.iters, 3), unit="s", cores=cores, kind="oracle",
+                                   sample=f"{K} ML-FWT iterations of the FP64 oracle on the same input "
+                                          f"({tc:.2f} s), scaled to the GPU's {r.iters} iterations")
+    return out
 
 
 def sources_sha256():
@@ -151,6 +249,20 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if a.workload.startswith("fw"):
+        w = synth.fw_config(a.workload)
+        fb = fw_bench(w, dev, a.steps, plain=not a.no_plain, cpu=not a.no_cpu)
+        out = {
+            "metric": "time to 1e-3 (s): multilevel FW-T (ML-FWT) vs FW-T, unconstrained CPCP, 1 MI355X",
+            "value": fb["ml_time_s"], "unit": "s", "n_gpus": 1, "steps": a.steps, "warmup": a.warmup,
+            "ms_per_step": round(fb["ml_time_s"] * 1e3, 4), "higher_is_better": False, "scaling": "weak",
+            "vs_baseline": None, "dtype": "f32", "data": "synthetic",
+            "config": {"workload": fb.pop("workload")},
+            "roofline": fb.pop("roofline"), "cpu_baseline": fb.pop("cpu_baseline", None),
+        }
+        out.update(fb)
+        print(json.dumps(out))
+        return
     t_gen = time.time()
     w = synth.config(a.workload)
     t_gen = time.time() - t_gen
@@ -270,6 +382,13 @@ def main():
                    iters=ref.iters)
         print(f"[bench] oracle: {tc1-tc0:.2f}s, {ref.iters} iters", file=sys.stderr, flush=True)
 
+    fw = None
+    if not a.no_fw and a.workload == "c2":
+        wf = synth.fw_config("fw2")
+        fw = fw_bench(wf, dev, 3, plain=not a.no_plain, cpu=False)
+        print(f"[bench] fw2 ML-FWT {fw['ml_time_s']*1e3:.2f} ms ({fw['ml_iters']} iters), FW-T "
+              f"{fw.get('plain_time_s', float('nan'))*1e3:.2f} ms", file=sys.stderr, flush=True)
+
     out = {
         "metric": METRIC,
         "value": round(ml_s, 6),
@@ -301,6 +420,7 @@ def main():
         "kernel_rooflines": others,
         "roofline": roof,
         "cpu_baseline": cpu,
+        "fw": fw,
     }
     print(json.dumps(out))
 

@@ -255,7 +255,8 @@ const char* mlpcp_status_string(int status);
 /* Kernel timing, for diagnostics and benchmarking.  Kernels are grouped into
  * classes (read() reports them in a fixed order: init_restrict, gram,
  * coarse_CGC, jacobi_pairs, jacobi_apply, jacobi_misc, svt_prep, epilogue,
- * reduce, finalize, coarse_svt_small, fw_pass, fw_power, fw_small, other).  enable(mask) resets the counters and brackets every
+ * reduce, finalize, coarse_svt_small, fw_pass, fw_power, fw_small, fw_top,
+ * other).  enable(mask) resets the counters and brackets every
  * launch of class i with HIP events on the caller's stream when bit i of mask is
  * set (mask 0 = off, -1 = all); the elapsed times are accumulated per class.
  * read() copies up to `cap` classes into `out` (static names) and returns the

@@ -130,7 +130,7 @@ def lib() -> ctypes.CDLL:
 
 KERNEL_CLASSES = ("init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply", "jacobi_misc",
                   "svt_prep", "epilogue", "reduce", "finalize", "coarse_svt_small", "fw_pass", "fw_power",
-                  "fw_small", "other")
+                  "fw_small", "fw_top", "other")
 
 
 def profile_enable(on=True) -> None:

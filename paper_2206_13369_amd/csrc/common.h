@@ -102,6 +102,11 @@ int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V
                      double* lam, int* perm, double* sw, double* T, double* Tt, double* K, IterStats* st,
                      hipStream_t stream);
 
+// Top eigenpair of C G C (G: n_H x n_H float64 Gram, ld = kEigInner, n_H <= kEigInner;
+// C: n_H x n_H, ld = n_H, or null for the identity) in one workgroup: writes z = C x
+// (kEigInner entries, zero past n_H) for the unit top eigenvector x, and lam = x^T (C G C) x.
+int coarse_top_small(int nH, const double* G, const double* C, double* z, double* lam, hipStream_t stream);
+
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws,
             hipStream_t stream, int* sweeps_out, bool warm, int sweep_hint = 0);
 

@@ -840,6 +840,154 @@ int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V
   return MLPCP_OK;
 }
 
+// Top eigenpair of H = C G C (n_H <= 64, one workgroup of four waves), for the nuclear
+// linear oracle of multilevel Frank-Wolfe: repeated squaring P <- P P / trace(P P) from
+// P = H / trace(H) until P is rank one to rounding (1 - ||P||_F^2 <= 1e-13; the
+// top-eigenvalue share of P grows as (lambda_2 / lambda_1)^(2^s) shrinks), the column of
+// P with the largest diagonal entry as the start, three power steps with H to polish,
+// then z = C x and lam = x^T H x.  With a repeated top eigenvalue the result is a unit
+// vector of the top eigenspace.  H = 0 gives z = 0, lam = 0.
+constexpr int kTopThreads = 256;
+constexpr int kTopSquarings = 24;
+
+__global__ void __launch_bounds__(kTopThreads) k_coarse_top(int nH, const double* __restrict__ G,
+                                                            const double* __restrict__ C, double* __restrict__ z,
+                                                            double* __restrict__ lam_out) {
+  extern __shared__ double dsm[];
+  LdsRow* sC = reinterpret_cast<LdsRow*>(dsm);
+  LdsRow* sH = sC + IN;
+  LdsRow* sP = sH + IN;
+  LdsRow* sQ = sP + IN;
+  __shared__ double red[kTopThreads];
+  __shared__ double sx[IN], sy[IN];
+  const int tid = threadIdx.x;
+  for (int it = tid; it < IN * IN; it += kTopThreads) {
+    const int i = it / IN, j = it % IN;
+    const bool in = i < nH && j < nH;
+    sP[i][j] = in ? G[(size_t)i * IN + j] : 0.0;
+    sC[i][j] = (C && in) ? C[(size_t)i * nH + j] : (C ? 0.0 : (i == j && i < nH ? 1.0 : 0.0));
+  }
+  __syncthreads();
+  d4_t acc[2][2];
+  mm64<false>(sP, sC, acc);                                  // G C
+  mm64_store(acc, [&](int i, int j, double v) { sQ[i][j] = v; });
+  __syncthreads();
+  mm64<false>(sC, sQ, acc);                                  // C (G C)
+  mm64_store(acc, [&](int i, int j, double v) { sP[i][j] = v; });
+  __syncthreads();
+  // H = sym(C G C), its trace
+  double tr = 0.0;
+  for (int it = tid; it < IN * IN; it += kTopThreads) {
+    const int i = it / IN, j = it % IN;
+    const double v = 0.5 * (sP[i][j] + sP[j][i]);
+    sH[i][j] = v;
+    if (i == j) tr += v;
+  }
+  red[tid] = tr;
+  __syncthreads();
+  for (int w = kTopThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) red[tid] += red[tid + w];
+    __syncthreads();
+  }
+  const double trace = red[0];
+  __syncthreads();
+  if (!(trace > 0.0)) {
+    if (tid < IN) z[tid] = 0.0;
+    if (tid == 0) *lam_out = 0.0;
+    return;
+  }
+  for (int it = tid; it < IN * IN; it += kTopThreads) {
+    const int i = it / IN, j = it % IN;
+    sP[i][j] = sH[i][j] / trace;
+  }
+  __syncthreads();
+  for (int sq = 0; sq < kTopSquarings; ++sq) {
+    mm64<false>(sP, sP, acc);
+    mm64_store(acc, [&](int i, int j, double v) { sQ[i][j] = v; });
+    __syncthreads();
+    double t = 0.0;
+    for (int i = tid; i < IN; i += kTopThreads) t += sQ[i][i];
+    red[tid] = t;
+    __syncthreads();
+    for (int w = kTopThreads / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const double tq = red[0];
+    __syncthreads();
+    double f2 = 0.0;
+    for (int it = tid; it < IN * IN; it += kTopThreads) {
+      const int i = it / IN, j = it % IN;
+      const double v = tq > 0.0 ? 0.5 * (sQ[i][j] + sQ[j][i]) / tq : 0.0;
+      sP[i][j] = v;
+      f2 += v * v;
+    }
+    red[tid] = f2;
+    __syncthreads();
+    for (int w = kTopThreads / 2; w > 0; w >>= 1) {
+      if (tid < w) red[tid] += red[tid + w];
+      __syncthreads();
+    }
+    const bool done = !(tq > 0.0) || 1.0 - red[0] <= 1e-13;
+    __syncthreads();
+    if (done) break;
+  }
+  // start: the column with the largest diagonal entry (ties: smallest index)
+  if (tid == 0) {
+    int jb = 0;
+    for (int j = 1; j < nH; ++j)
+      if (sP[j][j] > sP[jb][jb]) jb = j;
+    double nn = 0.0;
+    for (int i = 0; i < IN; ++i) nn += sP[i][jb] * sP[i][jb];
+    nn = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    for (int i = 0; i < IN; ++i) sx[i] = nn > 0.0 ? sP[i][jb] * nn : (i == jb ? 1.0 : 0.0);
+  }
+  __syncthreads();
+  for (int step = 0; step < 3; ++step) {
+    if (tid < IN) {
+      double y = 0.0;
+      for (int k = 0; k < IN; ++k) y += sH[tid][k] * sx[k];
+      sy[tid] = y;
+    }
+    __syncthreads();
+    if (tid == 0) {
+      double nn = 0.0;
+      for (int i = 0; i < IN; ++i) nn += sy[i] * sy[i];
+      red[0] = nn > 0.0 ? 1.0 / sqrt(nn) : 0.0;
+    }
+    __syncthreads();
+    const double inv = red[0];
+    __syncthreads();
+    if (tid < IN && inv > 0.0) sx[tid] = sy[tid] * inv;
+    __syncthreads();
+  }
+  if (tid < IN) {
+    double y = 0.0, zc = 0.0;
+    for (int k = 0; k < IN; ++k) {
+      y += sH[tid][k] * sx[k];
+      zc += sC[tid][k] * sx[k];
+    }
+    sy[tid] = y * sx[tid];
+    z[tid] = tid < nH ? zc : 0.0;
+  }
+  __syncthreads();
+  if (tid == 0) {
+    double l = 0.0;
+    for (int i = 0; i < IN; ++i) l += sy[i];
+    *lam_out = l;
+  }
+}
+
+int coarse_top_small(int nH, const double* G, const double* C, double* z, double* lam, hipStream_t stream) {
+  if (nH < 1 || nH > IN) return MLPCP_E_INVALID_ARG;
+  const size_t lds = (size_t)4 * IN * LDS_LD * sizeof(double);
+  MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse_top),
+                                hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
+  hipLaunchKernelGGL(k_coarse_top, dim3(1), dim3(kTopThreads), lds, stream, nH, G, C, z, lam);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
 size_t eig_workspace_bytes(int N) {
   const size_t npairs = (size_t)(N / IB) / 2;
   return align256(std::max<size_t>(npairs, 1) * (IN * IN + 1) * sizeof(double)) +

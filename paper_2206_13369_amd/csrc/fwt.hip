@@ -27,6 +27,10 @@
 // iterations G^T G x (4 bytes per entry each) for its top singular pair.
 #include <algorithm>
 #include <cmath>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <utility>
 #include <vector>
 
 #include "common.h"
@@ -155,6 +159,43 @@ struct Sums {
   }
 };
 
+// sums of one short run of entries in float32 (a chunk of at most a few dozen
+// entries), folded into the float64 Sums once per run; the argmax keeps the column
+struct RunSums {
+  float E2 = 0, ES = 0, T5 = 0, T6 = 0, T7 = 0, T8 = 0, T9 = 0;
+  float best = -1.0f;
+  int bj = 0;
+  __device__ __forceinline__ void add(float l, float s, float g, bool q, int j) {
+    if (!q) return;
+    E2 = fmaf(g, g, E2);
+    ES += fabsf(s);
+    T5 = fmaf(l, l, T5);
+    T6 = fmaf(g, l, T6);
+    T7 = fmaf(l, s, T7);
+    T8 = fmaf(s, s, T8);
+    T9 = fmaf(g, s, T9);
+    const float a = fabsf(g);
+    if (a > best) {          // runs are visited in increasing j: the first maximum stays
+      best = a;
+      bj = j;
+    }
+  }
+  __device__ __forceinline__ void fold(Sums& sm, long long row_base) const {
+    sm.E2 += E2;
+    sm.ES += ES;
+    sm.T5 += T5;
+    sm.T6 += T6;
+    sm.T7 += T7;
+    sm.T8 += T8;
+    sm.T9 += T9;
+    const long long idx = row_base + bj;
+    if (best > sm.best || (best == sm.best && best >= 0.0f && idx < sm.bidx)) {
+      sm.best = best;
+      sm.bidx = idx;
+    }
+  }
+};
+
 __device__ void store_sums(Sums& sm, double* red, float* rv, long long* ri, double* partial, float* pmax,
                            long long* pidx) {
   double v[7] = {sm.E2, sm.ES, sm.T5, sm.T6, sm.T7, sm.T8, sm.T9};
@@ -186,21 +227,37 @@ __device__ __forceinline__ float lift(const float* zrow, int c, float w0, int nH
 }
 
 // ---------------------------------------------------------------------------------
-// Multilevel pass over a batch of R rows at a time: Z update (the line-search step of
-// the previous iteration), entries (S, G), the sums and the argmax, and the restriction
-// GP = G P of the new gradient.
+// Multilevel pass.  A block takes R rows at a time.  All threads stage the rows of D
+// and of the mask bits in LDS with coalesced loads (the next batch is fetched into
+// registers while the current one is processed).  Each row's fine columns are cut into
+// K contiguous chunks that lie inside one interval [first_c, first_{c+1}) of fine
+// columns whose first stencil tap is the coarse column c, so a chunk only needs Z_c and
+// Z_{c+1}; one (row, chunk) task per thread computes the entries (S, G) from LDS, the
+// sums and the argmax, and the chunk's two partial restriction sums (sum w0 G for c,
+// sum (1 - w0) G for c + 1), which are added per coarse column in chunk order: GP = G P.
+// The new coarse rows (1 - alpha) Z - alpha U_L u_i z^T are formed at staging time.
+constexpr int kChunkMin = 16;      // shortest chunk (unless its interval is shorter)
+constexpr int kPrefetch = 8;       // float4 slots per thread held for the next batch (n <= 8192)
+
+struct Chunk {
+  int c, j0, j1, pad;
+};
+
 struct PassML {
-  int m, n, nH, R, nw, levels;
+  int m, n, nH, R, K, nw, levels;
   const float* D;
   int ldd;
   const uint32_t* bits;
-  float* Z;
+  const float* Zin;
+  float* Zout;
   int ldz;
   float* GP;
   int ldg;
-  const uint32_t* taps;   // [n]
-  const int* first;       // [nH + 1]: first fine column whose first tap is c
-  const double* T;        // direction z = T[c * ldT] (column 0)
+  const float* w0;        // [n] weight of the first tap of each fine column
+  const Chunk* chunks;    // [K]
+  const int* kfirst;      // [nH + 1]: first chunk of interval c
+  const uint32_t* taps;   // [n] packed (output and step kernels)
+  const double* T;        // direction z = T[c * ldT]
   int ldT;
   const double* gz;       // [m]: G w of the previous iterate (u = gz / sigma)
   const FwState* st;
@@ -210,84 +267,156 @@ struct PassML {
   long long* pidx;
 };
 
+__device__ __forceinline__ float lift2(float z0, float z1, float w0, bool has_next) {
+  const float a = w0 * z0;
+  return (w0 < 1.0f && has_next) ? fmaf(1.0f - w0, z1, a) : a;
+}
+
+// LDS layout of the multilevel kernels (bytes), shared by the host sizing
+struct MlLds {
+  size_t sp, w0, z, ch, kf, d, q, total;
+};
+__host__ __device__ inline MlLds ml_lds(int n, int nH, int R, int K, int nw, int nsums) {
+  MlLds L{};
+  size_t o = 0;
+  L.sp = o;  o += (size_t)nsums * R * K * 8;
+  L.w0 = o;  o += (size_t)n * 4;
+  L.z = o;   o += (size_t)R * nH * 4;
+  L.ch = o;  o += (size_t)K * sizeof(Chunk);
+  L.kf = o;  o += (size_t)(nH + 1) * 4;
+  o = (o + 15) & ~size_t(15);
+  L.d = o;   o += (size_t)R * n * 4;
+  L.q = o;   o += (size_t)R * nw * 4;
+  L.total = o;
+  return L;
+}
+
+// stage rows i0 .. i0+rows-1 of D and of the mask words: each thread holds up to
+// 4 kPrefetch floats (float4 slots when VEC == 4, single floats otherwise)
+constexpr int kStageFloats = 4 * kPrefetch;
+
+template <int VEC, bool MASKED>
+__device__ __forceinline__ void stage_load(const PassML& a, int i0, int rows, float (&rd)[kStageFloats],
+                                           uint32_t& rq) {
+  const int nv = a.n / VEC;
+#pragma unroll
+  for (int k = 0; k < kStageFloats / VEC; ++k) {
+    const int f = threadIdx.x + kFT * k;
+    if (f < rows * nv) {
+      const int r = f / nv, s = f - r * nv;
+      const float* src = a.D + (size_t)(i0 + r) * a.ldd + (size_t)s * VEC;
+      if constexpr (VEC == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(src);
+        rd[4 * k] = v.x;
+        rd[4 * k + 1] = v.y;
+        rd[4 * k + 2] = v.z;
+        rd[4 * k + 3] = v.w;
+      } else {
+        rd[k] = *src;
+      }
+    }
+  }
+  if (MASKED && (int)threadIdx.x < rows * a.nw) {
+    const int r = threadIdx.x / a.nw, w = threadIdx.x - r * a.nw;
+    rq = a.bits[(size_t)(i0 + r) * a.nw + w];
+  }
+}
+
+template <int VEC, bool MASKED>
+__device__ __forceinline__ void stage_store(const PassML& a, int rows, const float (&rd)[kStageFloats], uint32_t rq,
+                                            float* sD, uint32_t* sQ) {
+  const int nv = a.n / VEC;
+#pragma unroll
+  for (int k = 0; k < kStageFloats / VEC; ++k) {
+    const int f = threadIdx.x + kFT * k;
+    if (f < rows * nv) {
+      const int r = f / nv, s = f - r * nv;
+      float* dst = sD + (size_t)r * a.n + (size_t)s * VEC;
+      if constexpr (VEC == 4) *reinterpret_cast<float4*>(dst) = make_float4(rd[4 * k], rd[4 * k + 1], rd[4 * k + 2], rd[4 * k + 3]);
+      else *dst = rd[k];
+    }
+  }
+  if (MASKED && (int)threadIdx.x < rows * a.nw) sQ[threadIdx.x] = rq;
+}
+
 template <bool MASKED, int VEC, bool THR>
 __global__ void __launch_bounds__(kFT) k_fw_pass_ml(PassML a) {
-  extern __shared__ char smem_raw[];
-  uint32_t* sTap = reinterpret_cast<uint32_t*>(smem_raw);                 // [n]
-  int* sFirst = reinterpret_cast<int*>(sTap + a.n);                        // [nH + 1]
-  float* sz = reinterpret_cast<float*>(sFirst + a.nH + 1);                 // [nH]
-  float* sZ = sz + a.nH;                                                   // [R][nH]
-  float* sG = sZ + (size_t)a.R * a.nH;                                     // [R][n]
+  extern __shared__ __align__(16) char smem_raw[];
+  const MlLds lay = ml_lds(a.n, a.nH, a.R, a.K, a.nw, 2);
+  double* sp0 = reinterpret_cast<double*>(smem_raw + lay.sp);             // [R][K]
+  double* sp1 = sp0 + (size_t)a.R * a.K;                                   // [R][K]
+  float* sW0 = reinterpret_cast<float*>(smem_raw + lay.w0);                // [n]
+  float* sZ = reinterpret_cast<float*>(smem_raw + lay.z);                  // [R][nH]
+  Chunk* sCh = reinterpret_cast<Chunk*>(smem_raw + lay.ch);                // [K]
+  int* sKf = reinterpret_cast<int*>(smem_raw + lay.kf);                    // [nH + 1]
+  float* sD = reinterpret_cast<float*>(smem_raw + lay.d);                  // [R][n]
+  uint32_t* sQ = reinterpret_cast<uint32_t*>(smem_raw + lay.q);            // [R][nw]
   __shared__ double red[8 * (kFT / 64)];
   __shared__ float rv[kFT / 64];
   __shared__ long long ri[kFT / 64];
   const int tid = threadIdx.x;
-  const float scale = ldexpf(1.0f, -a.levels);
-  for (int j = tid; j < a.n; j += kFT) sTap[j] = a.taps[j];
-  for (int c = tid; c <= a.nH; c += kFT) sFirst[c] = a.first[c];
-  for (int c = tid; c < a.nH; c += kFT) sz[c] = (float)a.T[(size_t)c * a.ldT];
+  for (int j = tid; j < a.n; j += kFT) sW0[j] = a.w0[j];
+  for (int k = tid; k < a.K; k += kFT) sCh[k] = a.chunks[k];
+  for (int c = tid; c <= a.nH; c += kFT) sKf[c] = a.kfirst[c];
   const double alpha = THR ? a.st->alpha : 0.0;
   const double coefL = THR ? a.st->coefL : 0.0;   // alpha U_L / sigma if the atom is taken
-  __syncthreads();
   Sums sm;
-  const int nv = a.n / VEC;
   const int nbatch = (a.m + a.R - 1) / a.R;
-  for (int b = blockIdx.x; b < nbatch; b += gridDim.x) {
+  float rd[kStageFloats];
+  uint32_t rq = 0xFFFFFFFFu;
+  int b = blockIdx.x;
+  if (b < nbatch) stage_load<VEC, MASKED>(a, b * a.R, min(a.R, a.m - b * a.R), rd, rq);
+  for (; b < nbatch; b += gridDim.x) {
     const int i0 = b * a.R;
     const int rows = min(a.R, a.m - i0);
-    // Z <- (1 - alpha) Z - alpha U_L u z^T  (first iteration: Z = 0)
+    stage_store<VEC, MASKED>(a, rows, rd, rq, sD, sQ);
     for (int t = tid; t < rows * a.nH; t += kFT) {
       const int r = t / a.nH, c = t - r * a.nH;
       const int i = i0 + r;
       float zv = 0.0f;
       if (THR) {
-        zv = (float)((1.0 - alpha) * (double)a.Z[(size_t)i * a.ldz + c] - coefL * a.gz[i] * (double)sz[c]);
-        a.Z[(size_t)i * a.ldz + c] = zv;
+        zv = (float)((1.0 - alpha) * (double)a.Zin[(size_t)i * a.ldz + c] - coefL * a.gz[i] * a.T[(size_t)c * a.ldT]);
+        a.Zout[(size_t)i * a.ldz + c] = zv;
       }
       sZ[r * a.nH + c] = zv;
     }
     __syncthreads();
-    for (int f = tid; f < rows * nv; f += kFT) {
-      const int r = f / nv, s = f - r * nv;
-      const int i = i0 + r, j = s * VEC;
-      const float* drow = a.D + (size_t)i * a.ldd;
-      float d[VEC];
-      if constexpr (VEC == 4) {
-        const float4 v = *reinterpret_cast<const float4*>(drow + j);
-        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
-      } else {
-        d[0] = drow[j];
-      }
-      uint32_t qb = 0xFu;
-      if (MASKED) qb = (a.bits[(size_t)i * a.nw + (j >> 5)] >> (j & 31)) & (VEC == 4 ? 0xFu : 0x1u);
-      const float* zr = sZ + r * a.nH;
-#pragma unroll
-      for (int e = 0; e < VEC; ++e) {
-        int c;
-        float w0;
-        unpack_tap(sTap[j + e], scale, c, w0);
-        const float l = lift(zr, c, w0, a.nH);
-        const bool q = (qb >> e) & 1u;
+    const int bn = b + gridDim.x;
+    if (bn < nbatch) stage_load<VEC, MASKED>(a, bn * a.R, min(a.R, a.m - bn * a.R), rd, rq);
+    if (tid < rows * a.K) {
+      const int r = tid / a.K, k = tid - r * a.K;
+      const int i = i0 + r;
+      const Chunk ch = sCh[k];
+      const bool has_next = ch.c + 1 < a.nH;
+      const float z0 = sZ[r * a.nH + ch.c];
+      const float z1 = has_next ? sZ[r * a.nH + ch.c + 1] : 0.0f;
+      const float* drow = sD + (size_t)r * a.n;
+      const uint32_t* qrow = sQ + (size_t)r * a.nw;
+      float p0 = 0.0f, p1 = 0.0f;
+      RunSums rs;
+      for (int j = ch.j0; j < ch.j1; ++j) {
+        const bool q = MASKED ? ((qrow[j >> 5] >> (j & 31)) & 1u) : true;
+        const float w0 = sW0[j];
+        const float l = lift2(z0, z1, w0, has_next);
         float sv, gv;
-        entry<THR>(d[e], l, q, a.lamS, sv, gv);
-        sm.add(l, sv, gv, q, (long long)i * a.n + j + e);
-        sG[r * a.n + j + e] = gv;
+        entry<THR>(drow[j], l, q, a.lamS, sv, gv);
+        rs.add(l, sv, gv, q, j);
+        p0 = fmaf(w0, gv, p0);
+        p1 = fmaf(1.0f - w0, gv, p1);
       }
+      rs.fold(sm, (long long)i * a.n);
+      sp0[r * a.K + k] = p0;
+      sp1[r * a.K + k] = p1;
     }
     __syncthreads();
-    // GP[i][c] = sum_j G_ij P_jc: fine columns whose first tap is c (weight w0) and
-    // those whose first tap is c - 1 (weight 1 - w0), in a fixed order
     for (int t = tid; t < rows * a.nH; t += kFT) {
       const int r = t / a.nH, c = t - r * a.nH;
-      const float* g = sG + r * a.n;
       double acc = 0.0;
-      for (int j = sFirst[c]; j < sFirst[c + 1]; ++j) acc += (double)((float)(sTap[j] & 0xFFFFu) * scale) * g[j];
+      for (int k = sKf[c]; k < sKf[c + 1]; ++k) acc += sp0[r * a.K + k];
       if (c > 0)
-        for (int j = sFirst[c - 1]; j < sFirst[c]; ++j)
-          acc += (double)(1.0f - (float)(sTap[j] & 0xFFFFu) * scale) * g[j];
+        for (int k = sKf[c - 1]; k < sKf[c]; ++k) acc += sp1[r * a.K + k];
       a.GP[(size_t)(i0 + r) * a.ldg + c] = (float)acc;
     }
-    __syncthreads();
   }
   store_sums(sm, red, rv, ri, a.partial, a.pmax, a.pidx);
 }
@@ -366,32 +495,26 @@ __global__ void __launch_bounds__(kFT) k_fw_pass_plain(PassPlain a) {
 
 // Sums the pass partials in a fixed order; f, t_S and the bounds U = f / lam at the
 // current iterate.
-__global__ void __launch_bounds__(64) k_fw_finalize(const double* __restrict__ partial,
-                                                    const float* __restrict__ pmax,
-                                                    const long long* __restrict__ pidx, int nb, double lamL,
-                                                    double lamS, int thr, FwState* st) {
-  const int lane = threadIdx.x;
+__global__ void __launch_bounds__(kFT) k_fw_finalize(const double* __restrict__ partial,
+                                                     const float* __restrict__ pmax,
+                                                     const long long* __restrict__ pidx, int nb, double lamL,
+                                                     double lamS, int thr, FwState* st) {
+  __shared__ double red[8 * (kFT / 64)];
+  __shared__ float rv[kFT / 64];
+  __shared__ long long ri[kFT / 64];
   double v[7] = {0, 0, 0, 0, 0, 0, 0};
   float best = -1.0f;
   long long bi = 0;
-  for (int b = lane; b < nb; b += 64) {
+  for (int b = threadIdx.x; b < nb; b += kFT) {
     for (int k = 0; k < 7; ++k) v[k] += partial[(size_t)b * kNSums + k];
     if (pmax[b] > best || (pmax[b] == best && pidx[b] < bi)) {
       best = pmax[b];
       bi = pidx[b];
     }
   }
-  for (int k = 0; k < 7; ++k) v[k] = wave_sum(v[k]);
-#pragma unroll
-  for (int o = 32; o > 0; o >>= 1) {
-    const float ov = __shfl_xor(best, o, 64);
-    const long long oi = __shfl_xor(bi, o, 64);
-    if (ov > best || (ov == best && oi < bi)) {
-      best = ov;
-      bi = oi;
-    }
-  }
-  if (lane == 0) {
+  block_sums<7>(v, red);
+  block_argmax(best, bi, rv, ri);
+  if (threadIdx.x == 0) {
     st->E2 = v[0];
     st->t_S = v[1];
     st->T5 = v[2];
@@ -421,7 +544,7 @@ struct TermsML {
   int m, nH;
   const float *Z, *GP, *Aq, *Bq, *QDP;
   int ld;                 // leading dimension of all five
-  const double* T;        // z = column 0
+  const double* T;        // direction z = T[c * ldT]
   int ldT;
   double* gz;
   double* partial;
@@ -568,7 +691,7 @@ struct SolveArgs {
   const float* Z;
   int ldz;
   const uint32_t* taps;
-  const double* T;        // ML direction z (column 0)
+  const double* T;        // ML direction z = T[c * ldT]
   int ldT;
   const double* w;        // plain direction
   const double* gz;
@@ -576,13 +699,13 @@ struct SolveArgs {
   FwState* st;
 };
 
-__global__ void __launch_bounds__(64) k_fw_solve(SolveArgs a) {
-  const int lane = threadIdx.x;
+__global__ void __launch_bounds__(kFT) k_fw_solve(SolveArgs a) {
+  __shared__ double red[4 * (kFT / 64)];
   double v[4] = {0, 0, 0, 0};
-  for (int b = lane; b < a.nb; b += 64)
+  for (int b = threadIdx.x; b < a.nb; b += kFT)
     for (int k = 0; k < 4; ++k) v[k] += a.partial[(size_t)b * kNTerms + k];
-  for (int k = 0; k < 4; ++k) v[k] = wave_sum(v[k]);
-  if (lane != 0) return;
+  block_sums<4>(v, red);
+  if (threadIdx.x != 0) return;
   FwState* st = a.st;
   const double S1 = v[0], S2 = v[1], S3 = v[2], S4 = v[3];
   const double sigma = sqrt(S1);
@@ -645,86 +768,94 @@ __global__ void __launch_bounds__(64) k_fw_solve(SolveArgs a) {
 
 // ---------------------------------------------------------------------------------
 // Plain top singular pair: power iteration x <- G^T G x / ||G^T G x|| on the stored
-// gradient, warm-started from the previous direction.  Each step: per-block partial
-// sums of G^T (G x) over its rows (fixed order), a column reduction over the blocks,
-// then the normalisation and the convergence test.  All kernels return at once when
-// the iteration has converged (device-gated steps, queued in batches by the host).
+// gradient, warm-started from the previous direction.  Each step: t = G x (one wave per
+// row), partial sums of G^T t over kPowRanges row ranges (fixed order), the column
+// reduction over the ranges, then the
+// normalisation and the convergence test.  Every kernel returns at once when the
+// iteration has converged (device-gated steps, queued in batches by the host).
+constexpr int kPowRanges = 32;   // row ranges of the G^T t partial sums
+
 struct PowArgs {
-  int m, n, gs, rpb;      // group size (threads per row), rows per block
+  int m, n, nchunk;       // row ranges of the G^T t partial sums
   const float* G;
   double* x;              // [n] current direction (unit)
-  double* partial;        // [nb][n]
+  double* t;              // [m] G x
+  double* partial;        // [nchunk][n]
   double* y;              // [n]
-  double* ypart;          // [nbc]
+  double* ypart;          // [ncolblocks]
   FwState* st;
 };
 
-template <int VEC, int NS>
-__global__ void __launch_bounds__(kFT) k_fw_power(PowArgs a) {
+template <int VEC>
+__global__ void __launch_bounds__(kFT) k_fw_gx(PowArgs a) {
   if (!a.st->pow_active) return;
-  extern __shared__ double sx[];   // [n] x, then [n] the block's G^T G x
-  __shared__ double wsum[kFT / 64];
-  const int tid = threadIdx.x;
-  const int g = tid / a.gs, l = tid - g * a.gs;
-  const int R = kFT / a.gs;
-  const int nv = a.n / VEC;
-  for (int j = tid; j < a.n; j += kFT) sx[j] = a.x[j];
+  extern __shared__ double sx[];   // [n]
+  const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
+  for (int j = threadIdx.x; j < a.n; j += kFT) sx[j] = a.x[j];
   __syncthreads();
-  double acc[NS * VEC];
+  const int nv = a.n / VEC;
+  for (int i = blockIdx.x * (kFT / 64) + wid; i < a.m; i += gridDim.x * (kFT / 64)) {
+    const float* g = a.G + (size_t)i * a.n;
+    double d = 0.0;
+    for (int s = lane; s < nv; s += 64) {
+      if constexpr (VEC == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(g + s * 4);
+        d += (double)v.x * sx[s * 4] + (double)v.y * sx[s * 4 + 1] + (double)v.z * sx[s * 4 + 2] +
+             (double)v.w * sx[s * 4 + 3];
+      } else {
+        d += (double)g[s] * sx[s];
+      }
+    }
+    d = wave_sum(d);
+    if (lane == 0) a.t[i] = d;
+  }
+}
+
+// partial[rc][j] = sum over the rows of range rc of t_i G_ij: a block covers 64 columns
+// of one row range; 16 row groups of 16 threads walk the rows (each thread 4 columns),
+// then the 16 group sums are added in a fixed order
+constexpr int kGtyCols = 64;
+
+template <int VEC>
+__global__ void __launch_bounds__(kFT) k_fw_gty(PowArgs a) {
+  if (!a.st->pow_active) return;
+  __shared__ double red[16][kGtyCols + 1];
+  const int cq = threadIdx.x & 15, rg = threadIdx.x >> 4;
+  const int c0 = blockIdx.x * kGtyCols;
+  const int rc = blockIdx.y;
+  const int per = (a.m + a.nchunk - 1) / a.nchunk;
+  const int i0 = rc * per, i1 = min(a.m, i0 + per);
+  int col[4];
 #pragma unroll
-  for (int k = 0; k < NS * VEC; ++k) acc[k] = 0.0;
-  const int r0 = blockIdx.x * a.rpb;
-  const int r1 = min(a.m, r0 + a.rpb);
-  const int wpg = a.gs / 64;       // waves per group
-  for (int base = r0; base < r1; base += R) {
-    const int i = base + g;
-    const bool valid = i < r1;
-    float v[NS * VEC];
-    double dot = 0.0;
-#pragma unroll
-    for (int k = 0; k < NS; ++k) {
-      const int s = l + a.gs * k;
-      if (valid && s < nv) {
-        const float* gp = a.G + (size_t)i * a.n + (size_t)s * VEC;
-        if constexpr (VEC == 4) {
-          const float4 t = *reinterpret_cast<const float4*>(gp);
-          v[k * 4] = t.x; v[k * 4 + 1] = t.y; v[k * 4 + 2] = t.z; v[k * 4 + 3] = t.w;
-        } else {
-          v[k * VEC] = gp[0];
-        }
-#pragma unroll
-        for (int e = 0; e < VEC; ++e) dot += (double)v[k * VEC + e] * sx[s * VEC + e];
+  for (int e = 0; e < 4; ++e) col[e] = VEC == 4 ? c0 + cq * 4 + e : c0 + cq + 16 * e;
+  double acc[4] = {0.0, 0.0, 0.0, 0.0};
+  if (VEC == 4 ? col[0] < a.n : true) {
+#pragma unroll 4
+    for (int i = i0 + rg; i < i1; i += 16) {
+      const double ti = a.t[i];
+      const float* g = a.G + (size_t)i * a.n;
+      if constexpr (VEC == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(g + col[0]);
+        acc[0] += ti * v.x;
+        acc[1] += ti * v.y;
+        acc[2] += ti * v.z;
+        acc[3] += ti * v.w;
       } else {
 #pragma unroll
-        for (int e = 0; e < VEC; ++e) v[k * VEC + e] = 0.0f;
+        for (int e = 0; e < 4; ++e)
+          if (col[e] < a.n) acc[e] += ti * g[col[e]];
       }
     }
-    dot = wave_sum(dot);
-    if ((tid & 63) == 0) wsum[tid >> 6] = dot;
-    __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < wpg; ++w) t += wsum[g * wpg + w];
-    __syncthreads();
-#pragma unroll
-    for (int k = 0; k < NS * VEC; ++k) acc[k] += t * (double)v[k];
   }
-  // combine the R groups in the block (fixed order), then store the block's partial
-  double* sy = sx + a.n;
-  for (int j = tid; j < a.n; j += kFT) sy[j] = 0.0;
+#pragma unroll
+  for (int e = 0; e < 4; ++e) red[rg][col[e] - c0] = acc[e];
   __syncthreads();
-  for (int gg = 0; gg < R; ++gg) {
-    if (g == gg) {
-#pragma unroll
-      for (int k = 0; k < NS; ++k) {
-        const int s = l + a.gs * k;
-        if (s < nv)
-#pragma unroll
-          for (int e = 0; e < VEC; ++e) sy[s * VEC + e] += acc[k * VEC + e];
-      }
-    }
-    __syncthreads();
+  if (threadIdx.x < kGtyCols) {
+    const int j = c0 + threadIdx.x;
+    double sum = 0.0;
+    for (int r = 0; r < 16; ++r) sum += red[r][threadIdx.x];
+    if (j < a.n) a.partial[(size_t)rc * a.n + j] = sum;
   }
-  for (int j = tid; j < a.n; j += kFT) a.partial[(size_t)blockIdx.x * a.n + j] = sy[j];
 }
 
 // y_j = sum over blocks of partial[b][j]; per-block sums of y_j^2
@@ -735,7 +866,7 @@ __global__ void __launch_bounds__(kFT) k_fw_power_cols(PowArgs a, int nb) {
   const int j = blockIdx.x * kFT + threadIdx.x;
   if (j < a.n) {
     double s = 0.0;
-    for (int b = 0; b < nb; ++b) s += a.partial[(size_t)b * a.n + j];
+    for (int b = 0; b < nb; ++b) s += a.partial[(size_t)b * a.n + j];   // fixed order
     a.y[j] = s;
     sq = s * s;
   }
@@ -789,67 +920,122 @@ __global__ void k_fw_init_state(FwState* st) {
 
 // ---------------------------------------------------------------------------------
 // Precomputed per-row coarse tables of the mask (multilevel): A_ic = sum_j Q_ij P_jc^2,
-// B_ic = sum_j Q_ij P_jc P_j,c+1, QDP_ic = sum_j Q_ij D_ij P_jc.  One thread per (i, c).
-__global__ void __launch_bounds__(kFT) k_fw_mask_tables(int m, int n, int nH, int levels, const float* __restrict__ D,
-                                                       int ldd, const uint32_t* __restrict__ bits, int nw,
-                                                       const uint32_t* __restrict__ taps, const int* __restrict__ first,
-                                                       float* __restrict__ Aq, float* __restrict__ Bq,
-                                                       float* __restrict__ QDP, int ld) {
-  const float scale = ldexpf(1.0f, -levels);
-  const unsigned total = (unsigned)m * nH;
-  for (unsigned t = blockIdx.x * kFT + threadIdx.x; t < total; t += gridDim.x * kFT) {
-    const int i = (int)(t / (unsigned)nH), c = (int)(t - (unsigned)i * nH);
-    const float* drow = D + (size_t)i * ldd;
-    double A = 0.0, B = 0.0, QD = 0.0;
-    for (int j = first[c]; j < first[c + 1]; ++j) {
-      if (bits && !mask_bit(bits, nw, i, j)) continue;
-      const double w0 = (double)((float)(taps[j] & 0xFFFFu) * scale);
-      A += w0 * w0;
-      B += w0 * (1.0 - w0);
-      QD += w0 * (double)drow[j];
-    }
-    if (c > 0)
-      for (int j = first[c - 1]; j < first[c]; ++j) {
-        if (bits && !mask_bit(bits, nw, i, j)) continue;
-        const double w1 = 1.0 - (double)((float)(taps[j] & 0xFFFFu) * scale);
-        A += w1 * w1;
-        QD += w1 * (double)drow[j];
+// B_ic = sum_j Q_ij P_jc P_j,c+1, QDP_ic = sum_j Q_ij D_ij P_jc; the pass's layout, five
+// partial sums per chunk, added per coarse column in chunk order.
+template <bool MASKED, int VEC>
+__global__ void __launch_bounds__(kFT) k_fw_mask_tables(PassML a, float* __restrict__ Aq, float* __restrict__ Bq,
+                                                       float* __restrict__ QDP) {
+  extern __shared__ __align__(16) char smem_raw[];
+  const MlLds lay = ml_lds(a.n, a.nH, a.R, a.K, a.nw, 5);
+  double* sp = reinterpret_cast<double*>(smem_raw + lay.sp);               // [5][R][K]
+  float* sW0 = reinterpret_cast<float*>(smem_raw + lay.w0);
+  Chunk* sCh = reinterpret_cast<Chunk*>(smem_raw + lay.ch);
+  int* sKf = reinterpret_cast<int*>(smem_raw + lay.kf);
+  float* sD = reinterpret_cast<float*>(smem_raw + lay.d);
+  uint32_t* sQ = reinterpret_cast<uint32_t*>(smem_raw + lay.q);
+  const int tid = threadIdx.x;
+  for (int j = tid; j < a.n; j += kFT) sW0[j] = a.w0[j];
+  for (int k = tid; k < a.K; k += kFT) sCh[k] = a.chunks[k];
+  for (int c = tid; c <= a.nH; c += kFT) sKf[c] = a.kfirst[c];
+  const size_t RK = (size_t)a.R * a.K;
+  const int nbatch = (a.m + a.R - 1) / a.R;
+  float rd[kStageFloats];
+  uint32_t rq = 0xFFFFFFFFu;
+  for (int b = blockIdx.x; b < nbatch; b += gridDim.x) {
+    const int i0 = b * a.R;
+    const int rows = min(a.R, a.m - i0);
+    stage_load<VEC, MASKED>(a, i0, rows, rd, rq);
+    stage_store<VEC, MASKED>(a, rows, rd, rq, sD, sQ);
+    __syncthreads();
+    if (tid < rows * a.K) {
+      const int r = tid / a.K, k = tid - r * a.K;
+      const Chunk ch = sCh[k];
+      const float* drow = sD + (size_t)r * a.n;
+      const uint32_t* qrow = sQ + (size_t)r * a.nw;
+      double A0 = 0, A1 = 0, B = 0, Q0 = 0, Q1 = 0;
+      for (int j = ch.j0; j < ch.j1; ++j) {
+        if (MASKED && !((qrow[j >> 5] >> (j & 31)) & 1u)) continue;
+        const double w0 = sW0[j], w1 = (double)(1.0f - sW0[j]);
+        const double d = drow[j];
+        A0 += w0 * w0;
+        A1 += w1 * w1;
+        B += w0 * w1;
+        Q0 += w0 * d;
+        Q1 += w1 * d;
       }
-    Aq[(size_t)i * ld + c] = (float)A;
-    Bq[(size_t)i * ld + c] = (float)B;
-    QDP[(size_t)i * ld + c] = (float)QD;
+      const size_t o = (size_t)r * a.K + k;
+      sp[o] = A0;
+      sp[RK + o] = A1;
+      sp[2 * RK + o] = B;
+      sp[3 * RK + o] = Q0;
+      sp[4 * RK + o] = Q1;
+    }
+    __syncthreads();
+    for (int t = tid; t < rows * a.nH; t += kFT) {
+      const int r = t / a.nH, c = t - r * a.nH;
+      double A = 0, B = 0, QD = 0;
+      for (int k = sKf[c]; k < sKf[c + 1]; ++k) {
+        const size_t o = (size_t)r * a.K + k;
+        A += sp[o];
+        B += sp[2 * RK + o];
+        QD += sp[3 * RK + o];
+      }
+      if (c > 0)
+        for (int k = sKf[c - 1]; k < sKf[c]; ++k) {
+          const size_t o = (size_t)r * a.K + k;
+          A += sp[RK + o];
+          QD += sp[4 * RK + o];
+        }
+      const size_t o = (size_t)(i0 + r) * a.ldz + c;
+      Aq[o] = (float)A;
+      Bq[o] = (float)B;
+      QDP[o] = (float)QD;
+    }
+    __syncthreads();
   }
 }
 
 // Returned iterate: L (multilevel: Z P^T; plain: already in L) and S = P_Q S_{lam_S}[D - L]
-// (zero before the first threshold step).
+// (zero before the first threshold step).  A block walks rows; multilevel stages the
+// stencil taps once and each row of Z in LDS.
 template <bool ML>
 __global__ void __launch_bounds__(kFT) k_fw_output(int m, int n, int nH, int levels, const float* __restrict__ D,
                                                   int ldd, const uint32_t* __restrict__ bits, int nw,
                                                   const float* __restrict__ Z, int ldz,
                                                   const uint32_t* __restrict__ taps, float lamS, int thr,
                                                   float* __restrict__ L, int ldl, float* __restrict__ S, int lds) {
+  extern __shared__ char smem_raw[];
+  uint32_t* sTap = reinterpret_cast<uint32_t*>(smem_raw);   // [n] (multilevel)
+  float* sZr = reinterpret_cast<float*>(sTap + (ML ? n : 0)); // [nH]
   const float scale = ldexpf(1.0f, -levels);
-  const unsigned total = (unsigned)m * n;
-  for (unsigned t = blockIdx.x * kFT + threadIdx.x; t < total; t += gridDim.x * kFT) {
-    const int i = (int)(t / (unsigned)n), j = (int)(t - (unsigned)i * n);
-    float l;
+  if (ML)
+    for (int j = threadIdx.x; j < n; j += kFT) sTap[j] = taps[j];
+  for (int i = blockIdx.x; i < m; i += gridDim.x) {
     if (ML) {
-      int c;
-      float w0;
-      unpack_tap(taps[j], scale, c, w0);
-      l = lift(Z + (size_t)i * ldz, c, w0, nH);
-      L[(size_t)i * ldl + j] = l;
-    } else {
-      l = L[(size_t)i * ldl + j];
+      __syncthreads();
+      for (int c = threadIdx.x; c < nH; c += kFT) sZr[c] = Z[(size_t)i * ldz + c];
+      __syncthreads();
     }
-    const bool q = bits ? mask_bit(bits, nw, i, j) : true;
-    float sv, gv;
-    if (thr)
-      entry<true>(D[(size_t)i * ldd + j], l, q, lamS, sv, gv);
-    else
-      entry<false>(D[(size_t)i * ldd + j], l, q, lamS, sv, gv);
-    S[(size_t)i * lds + j] = sv;
+    const float* drow = D + (size_t)i * ldd;
+    for (int j = threadIdx.x; j < n; j += kFT) {
+      float l;
+      if (ML) {
+        int c;
+        float w0;
+        unpack_tap(sTap[j], scale, c, w0);
+        l = lift(sZr, c, w0, nH);
+        L[(size_t)i * ldl + j] = l;
+      } else {
+        l = L[(size_t)i * ldl + j];
+      }
+      const bool q = bits ? mask_bit(bits, nw, i, j) : true;
+      float sv, gv;
+      if (thr)
+        entry<true>(drow[j], l, q, lamS, sv, gv);
+      else
+        entry<false>(drow[j], l, q, lamS, sv, gv);
+      S[(size_t)i * lds + j] = sv;
+    }
   }
 }
 
@@ -882,19 +1068,93 @@ unsigned grid_of(size_t work, unsigned cap) {
   return (unsigned)b;
 }
 
+// Host tables of the multilevel pass: each fine column's packed first stencil tap and
+// weight, checked against the structure the kernels rely on (adjacent taps summing to
+// one, first taps non-decreasing in j, dyadic weights), and the chunking of a row
+// (contiguous fine columns inside one interval of equal first tap, at least kChunkMin
+// long unless the interval is shorter, at most kFT chunks) with each interval's first
+// chunk.  Built once per (n, levels) and kept.
+struct FwTables {
+  std::vector<uint32_t> taps;
+  std::vector<float> w0;
+  std::vector<Chunk> chunks;
+  std::vector<int> kfirst;
+};
+
+int fw_tables(int n, int levels, int nH, FwTables& t) {
+  std::vector<int> ri, cp, cr;
+  std::vector<float> rw, cw;
+  build_stencil_host(n, levels, ri, rw, cp, cr, cw, nullptr);
+  t.taps.assign(n, 0);
+  t.w0.assign(n, 0.0f);
+  const double den = std::ldexp(1.0, levels);
+  int prev = -1;
+  for (int j = 0; j < n; ++j) {
+    const int c0 = ri[(size_t)j * kMaxStencil], c1 = ri[(size_t)j * kMaxStencil + 1];
+    const double w0 = rw[(size_t)j * kMaxStencil], w1 = rw[(size_t)j * kMaxStencil + 1];
+    if (w1 != 0.0 && c1 != c0 + 1) return MLPCP_E_UNSUPPORTED;      // taps are adjacent pairs
+    if (std::fabs(w0 + w1 - 1.0) > 1e-12) return MLPCP_E_UNSUPPORTED;
+    if (c0 < prev || c0 >= nH) return MLPCP_E_UNSUPPORTED;         // first taps non-decreasing
+    const double num = w0 * den;
+    if (num != std::floor(num) || num < 0 || num > 65535.0) return MLPCP_E_UNSUPPORTED;
+    t.taps[j] = ((uint32_t)c0 << 16) | (uint32_t)num;
+    t.w0[j] = (float)w0;
+    prev = c0;
+  }
+  std::vector<int> first(nH + 1, n);
+  {
+    int j = 0;
+    for (int c = 0; c <= nH; ++c) {
+      while (j < n && (int)(t.taps[j] >> 16) < c) ++j;
+      first[c] = j;
+    }
+  }
+  int L = kChunkMin;
+  for (;; ++L) {
+    long long cnt = 0;
+    for (int c = 0; c < nH; ++c) cnt += (first[c + 1] - first[c] + L - 1) / L;
+    if (cnt <= kFT) break;
+  }
+  t.chunks.clear();
+  t.kfirst.assign(nH + 1, 0);
+  for (int c = 0; c < nH; ++c) {
+    t.kfirst[c] = (int)t.chunks.size();
+    for (int j = first[c]; j < first[c + 1]; j += L) t.chunks.push_back(Chunk{c, j, std::min(first[c + 1], j + L), 0});
+  }
+  t.kfirst[nH] = (int)t.chunks.size();
+  return MLPCP_OK;
+}
+
+std::mutex g_tab_mutex;
+std::map<std::pair<int, int>, std::shared_ptr<const FwTables>> g_tabs;
+
+int fw_tables_cached(int n, int levels, int nH, std::shared_ptr<const FwTables>& out) {
+  std::lock_guard<std::mutex> lock(g_tab_mutex);
+  auto it = g_tabs.find({n, levels});
+  if (it != g_tabs.end()) {
+    out = it->second;
+    return MLPCP_OK;
+  }
+  auto t = std::make_shared<FwTables>();
+  MLPCP_TRY(fw_tables(n, levels, nH, *t));
+  g_tabs.emplace(std::make_pair(n, levels), t);
+  out = t;
+  return MLPCP_OK;
+}
+
 struct FwPlan {
-  int m, n, nH, levels, nw, VEC, R, ldz;
+  int m, n, nH, levels, nw, VEC, R, K, ldz;
   bool ml, masked;
   unsigned grid_pass, grid_terms;
-  size_t lds_pass;
+  size_t lds_pass, lds_tables;
   // plain power iteration
-  int gs, rpb, NS;
-  unsigned grid_pow, grid_cols;
+  int nchunk;
+  unsigned grid_gx, grid_cols;
   size_t lds_pow;
-  size_t off_bits, off_state, off_part, off_pmax, off_pidx, off_tpart, off_gz, off_taps, off_first;
-  size_t off_Z, off_GP, off_Aq, off_Bq, off_QDP, off_gram, off_gws, off_V, off_lam, off_perm, off_sw, off_T, off_Tt,
-      off_ist;
-  size_t off_G, off_w, off_powp, off_y, off_ypart;
+  size_t off_bits, off_state, off_part, off_pmax, off_pidx, off_tpart, off_gz, off_taps, off_w0, off_chunks,
+      off_kfirst;
+  size_t off_Z, off_Z2, off_GP, off_Aq, off_Bq, off_QDP, off_gram, off_gws, off_lam, off_T;
+  size_t off_G, off_w, off_powp, off_t, off_y, off_ypart;
   size_t total;
 };
 
@@ -912,12 +1172,19 @@ int make_fw_plan(int m, int n, int levels, bool masked, bool vec_ok, FwPlan& p) 
   const int C = cus();
   if (p.ml) {
     if (p.nH > kEigInner || levels > 15 || p.nH >= 65535) return MLPCP_E_UNSUPPORTED;
-    const int nv = n / p.VEC;
-    p.R = std::max(1, std::min(8, (2 * kFT) / std::max(1, nv)));
+    std::shared_ptr<const FwTables> t;
+    MLPCP_TRY(fw_tables_cached(n, levels, p.nH, t));
     p.ldz = kPad;   // Z, GP, tables share the Gram's padded width
-    p.lds_pass = (size_t)n * 4 + (size_t)(p.nH + 1) * 4 + (size_t)p.nH * 4 + (size_t)p.R * p.nH * 4 +
-                 (size_t)p.R * n * 4;
-    if (p.lds_pass > 150 * 1024) return MLPCP_E_UNSUPPORTED;
+    p.K = (int)t->chunks.size();
+    const int nv = n / p.VEC;
+    // rows per batch: fill the tasks (R K <= kFT) within the prefetch registers
+    p.R = std::max(1, std::min(8, kFT / std::max(1, p.K)));
+    const int slots = (kStageFloats / p.VEC) * kFT;   // staged entries (or float4s) per batch
+    while (p.R > 1 && (p.R * nv > slots || p.R * p.nw > kFT)) --p.R;
+    if (nv > slots || p.nw > kFT) return MLPCP_E_UNSUPPORTED;
+    p.lds_pass = ml_lds(n, p.nH, p.R, p.K, p.nw, 2).total;
+    p.lds_tables = ml_lds(n, p.nH, p.R, p.K, p.nw, 5).total;
+    if (p.lds_pass > 150 * 1024 || p.lds_tables > 150 * 1024) return MLPCP_E_UNSUPPORTED;
     const int per_cu = std::max(1, std::min(8, (int)((160 * 1024) / (p.lds_pass + 2048))));
     const int nbatch = (m + p.R - 1) / p.R;
     p.grid_pass = (unsigned)std::max(1, std::min(nbatch, per_cu * C));
@@ -925,17 +1192,10 @@ int make_fw_plan(int m, int n, int levels, bool masked, bool vec_ok, FwPlan& p) 
     const size_t slots = (size_t)m * (n / p.VEC);
     p.grid_pass = grid_of(slots, 4u * C);
     // power iteration layout
-    const int nv = n / p.VEC;
-    p.gs = std::min(kFT, (nv + 63) / 64 * 64);
-    const int per = (nv + p.gs - 1) / p.gs;
-    p.NS = per <= 1 ? 1 : per <= 2 ? 2 : per <= 4 ? 4 : per <= 8 ? 8 : 0;
-    if (p.NS == 0) return MLPCP_E_UNSUPPORTED;
-    p.lds_pow = (size_t)2 * n * 8;
-    if (p.lds_pow > 150 * 1024) return MLPCP_E_UNSUPPORTED;
-    const int Rg = kFT / p.gs;
-    const int blocks = std::max(1, std::min(C, (m + Rg - 1) / Rg));
-    p.rpb = (m + blocks - 1) / blocks;
-    p.grid_pow = (unsigned)((m + p.rpb - 1) / p.rpb);
+    if (n > 8192 || (p.VEC == 1 && n > 2048)) return MLPCP_E_UNSUPPORTED;
+    p.lds_pow = (size_t)n * 8;
+    p.nchunk = std::max(1, std::min(kPowRanges, (m + 15) / 16));
+    p.grid_gx = (unsigned)std::max(1, std::min((m + 3) / 4, 8 * C));
     p.grid_cols = (unsigned)((n + kFT - 1) / kFT);
   }
   p.grid_terms = (unsigned)std::max(1, std::min((m + 3) / 4, 4 * C));
@@ -955,9 +1215,12 @@ int make_fw_plan(int m, int n, int levels, bool masked, bool vec_ok, FwPlan& p) 
   p.off_gz = take((size_t)m * 8);
   if (p.ml) {
     p.off_taps = take((size_t)n * 4);
-    p.off_first = take((size_t)(p.nH + 1) * 4);
+    p.off_w0 = take((size_t)n * 4);
+    p.off_chunks = take((size_t)p.K * sizeof(Chunk));
+    p.off_kfirst = take((size_t)(p.nH + 1) * 4);
     const size_t mat = (size_t)m * p.ldz * 4;
     p.off_Z = take(mat);
+    p.off_Z2 = take(mat);
     p.off_GP = take(mat);
     p.off_Aq = take(mat);
     p.off_Bq = take(mat);
@@ -965,17 +1228,13 @@ int make_fw_plan(int m, int n, int levels, bool masked, bool vec_ok, FwPlan& p) 
     const size_t sq = (size_t)kEigInner * kEigInner * 8;
     p.off_gram = take(sq);
     p.off_gws = take(gram_workspace_bytes(m, kPad));
-    p.off_V = take(sq);
-    p.off_lam = take((size_t)kEigInner * 8);
-    p.off_perm = take((size_t)kEigInner * 4);
-    p.off_sw = take((size_t)kEigInner * 8);
-    p.off_T = take(sq);
-    p.off_Tt = take(sq);
-    p.off_ist = take(sizeof(IterStats));
+    p.off_lam = take(8);
+    p.off_T = take((size_t)kEigInner * 8);   // the coarse direction z
   } else {
     p.off_G = take((size_t)m * n * 4);
     p.off_w = take((size_t)n * 8);
-    p.off_powp = take((size_t)p.grid_pow * n * 8);
+    p.off_powp = take((size_t)p.nchunk * n * 8);
+    p.off_t = take((size_t)m * 8);
     p.off_y = take((size_t)n * 8);
     p.off_ypart = take((size_t)p.grid_cols * 8);
   }
@@ -998,8 +1257,9 @@ struct FwWS {
 template <bool MASKED, int VEC>
 int launch_pass_ml(const FwPlan& p, const PassML& a, bool thr, hipStream_t s) {
   auto k = thr ? k_fw_pass_ml<MASKED, VEC, true> : k_fw_pass_ml<MASKED, VEC, false>;
-  MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)p.lds_pass));
+  if (p.lds_pass > 64 * 1024)
+    MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)p.lds_pass));
   hipLaunchKernelGGL(k, dim3(p.grid_pass), dim3(kFT), p.lds_pass, s, a);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
@@ -1017,17 +1277,13 @@ int launch_pass_plain(const FwPlan& p, const PassPlain& a, bool thr, hipStream_t
 
 template <int VEC>
 int launch_power_step(const FwPlan& p, const PowArgs& a, hipStream_t s) {
-  void (*k)(PowArgs) = nullptr;
-  switch (p.NS) {
-    case 1: k = k_fw_power<VEC, 1>; break;
-    case 2: k = k_fw_power<VEC, 2>; break;
-    case 4: k = k_fw_power<VEC, 4>; break;
-    default: k = k_fw_power<VEC, 8>; break;
-  }
-  MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                (int)p.lds_pow));
-  hipLaunchKernelGGL(k, dim3(p.grid_pow), dim3(kFT), p.lds_pow, s, a);
-  hipLaunchKernelGGL(k_fw_power_cols, dim3(p.grid_cols), dim3(kFT), 0, s, a, (int)p.grid_pow);
+  if (p.lds_pow > 64 * 1024)
+    MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fw_gx<VEC>),
+                                  hipFuncAttributeMaxDynamicSharedMemorySize, (int)p.lds_pow));
+  hipLaunchKernelGGL(k_fw_gx<VEC>, dim3(p.grid_gx), dim3(kFT), p.lds_pow, s, a);
+  const unsigned coltiles = (unsigned)((p.n + kGtyCols - 1) / kGtyCols);
+  hipLaunchKernelGGL(k_fw_gty<VEC>, dim3(coltiles, (unsigned)p.nchunk), dim3(kFT), 0, s, a);
+  hipLaunchKernelGGL(k_fw_power_cols, dim3(p.grid_cols), dim3(kFT), 0, s, a, p.nchunk);
   hipLaunchKernelGGL(k_fw_power_fin, dim3(1), dim3(kFT), 0, s, a, (int)p.grid_cols);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
@@ -1073,72 +1329,65 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
 
   // operator tables (multilevel)
   uint32_t* taps = nullptr;
-  int* first = nullptr;
-  std::vector<uint32_t> htaps;
-  std::vector<int> hfirst;
+  std::shared_ptr<const FwTables> tbp;
+  PassML pm{};
   if (p.ml) {
-    std::vector<int> ri, cp, cr;
-    std::vector<float> rw, cw;
-    build_stencil_host(n, levels, ri, rw, cp, cr, cw, nullptr);
-    htaps.resize(n);
-    hfirst.assign(p.nH + 1, n);
-    const double den = std::ldexp(1.0, levels);
-    int prev = -1;
-    for (int j = 0; j < n; ++j) {
-      int c0 = ri[(size_t)j * kMaxStencil];
-      double w0 = rw[(size_t)j * kMaxStencil];
-      const double w1 = rw[(size_t)j * kMaxStencil + 1];
-      const int c1 = ri[(size_t)j * kMaxStencil + 1];
-      if (w1 != 0.0 && c1 != c0 + 1) return MLPCP_E_UNSUPPORTED;     // taps are adjacent pairs
-      if (std::fabs(w0 + w1 - 1.0) > 1e-12) return MLPCP_E_UNSUPPORTED;
-      if (c0 < prev) return MLPCP_E_UNSUPPORTED;                      // first taps non-decreasing
-      const double num = w0 * den;
-      if (num != std::floor(num) || num < 0 || num > 65535.0) return MLPCP_E_UNSUPPORTED;
-      htaps[j] = ((uint32_t)c0 << 16) | (uint32_t)num;
-      prev = c0;
-    }
-    for (int c = 0; c <= p.nH; ++c) {
-      int j = 0;
-      while (j < n && (int)(htaps[j] >> 16) < c) ++j;
-      hfirst[c] = j;
-    }
+    MLPCP_TRY(fw_tables_cached(n, levels, p.nH, tbp));
+    const FwTables& tb = *tbp;
     taps = w.at<uint32_t>(p.off_taps);
-    first = w.at<int>(p.off_first);
-    MLPCP_HIP(hipMemcpyAsync(taps, htaps.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
-    MLPCP_HIP(hipMemcpyAsync(first, hfirst.data(), (size_t)(p.nH + 1) * 4, hipMemcpyHostToDevice, s));
+    MLPCP_HIP(hipMemcpyAsync(taps, tb.taps.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    if ((int)tb.chunks.size() != p.K) return MLPCP_E_UNSUPPORTED;
+    MLPCP_HIP(hipMemcpyAsync(w.at<void>(p.off_w0), tb.w0.data(), (size_t)n * 4, hipMemcpyHostToDevice, s));
+    MLPCP_HIP(hipMemcpyAsync(w.at<void>(p.off_chunks), tb.chunks.data(), (size_t)p.K * sizeof(Chunk),
+                             hipMemcpyHostToDevice, s));
+    MLPCP_HIP(hipMemcpyAsync(w.at<void>(p.off_kfirst), tb.kfirst.data(), (size_t)(p.nH + 1) * 4,
+                             hipMemcpyHostToDevice, s));
     const size_t mat = (size_t)m * p.ldz * 4;
     MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_Z), 0, mat, s));
+    MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_Z2), 0, mat, s));
     MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GP), 0, mat, s));
-    MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_T), 0, (size_t)kEigInner * kEigInner * 8, s));
-    hipLaunchKernelGGL(k_fw_mask_tables, dim3(grid_of((size_t)m * p.nH, 8192)), dim3(kFT), 0, s, m, n, p.nH, levels,
-                       D, ldd, bits, p.nw, taps, first, w.at<float>(p.off_Aq), w.at<float>(p.off_Bq),
-                       w.at<float>(p.off_QDP), p.ldz);
-    MLPCP_HIP(hipGetLastError());
+    MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_T), 0, (size_t)kEigInner * 8, s));
+    pm.m = m; pm.n = n; pm.nH = p.nH; pm.R = p.R; pm.K = p.K; pm.nw = p.nw; pm.levels = levels;
+    pm.D = D; pm.ldd = ldd; pm.bits = bits;
+    pm.Zin = w.at<float>(p.off_Z); pm.Zout = w.at<float>(p.off_Z2); pm.ldz = p.ldz;
+    pm.GP = w.at<float>(p.off_GP); pm.ldg = p.ldz;
+    pm.taps = taps;
+    pm.w0 = w.at<float>(p.off_w0); pm.chunks = w.at<Chunk>(p.off_chunks); pm.kfirst = w.at<int>(p.off_kfirst);
+    pm.T = w.at<double>(p.off_T); pm.ldT = 1;
+    pm.gz = gz; pm.st = st; pm.lamS = lamS;
+    pm.partial = part; pm.pmax = pmax; pm.pidx = pidx;
+    {
+      auto kt = p.masked ? (p.VEC == 4 ? k_fw_mask_tables<true, 4> : k_fw_mask_tables<true, 1>)
+                         : (p.VEC == 4 ? k_fw_mask_tables<false, 4> : k_fw_mask_tables<false, 1>);
+      if (p.lds_tables > 64 * 1024)
+        MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                      (int)p.lds_tables));
+      hipLaunchKernelGGL(kt, dim3(p.grid_pass), dim3(kFT), p.lds_tables, s, pm, w.at<float>(p.off_Aq),
+                         w.at<float>(p.off_Bq), w.at<float>(p.off_QDP));
+      MLPCP_HIP(hipGetLastError());
+    }
   } else {
     hipLaunchKernelGGL(k_fw_fill, dim3((n + 255) / 256), dim3(256), 0, s, w.at<double>(p.off_w), n,
                        1.0 / std::sqrt((double)n));
     MLPCP_HIP(hipGetLastError());
   }
 
-  PassML pm{};
   PassPlain pp{};
-  if (p.ml) {
-    pm.m = m; pm.n = n; pm.nH = p.nH; pm.R = p.R; pm.nw = p.nw; pm.levels = levels;
-    pm.D = D; pm.ldd = ldd; pm.bits = bits;
-    pm.Z = w.at<float>(p.off_Z); pm.ldz = p.ldz;
-    pm.GP = w.at<float>(p.off_GP); pm.ldg = p.ldz;
-    pm.taps = taps; pm.first = first;
-    pm.T = w.at<double>(p.off_T); pm.ldT = kEigInner;
-    pm.gz = gz; pm.st = st; pm.lamS = lamS;
-    pm.partial = part; pm.pmax = pmax; pm.pidx = pidx;
-  } else {
+  if (!p.ml) {
     pp.m = m; pp.n = n; pp.nw = p.nw; pp.D = D; pp.ldd = ldd; pp.bits = bits;
     pp.L = L; pp.G = w.at<float>(p.off_G); pp.w = w.at<double>(p.off_w); pp.gz = gz; pp.st = st;
     pp.lamS = lamS; pp.partial = part; pp.pmax = pmax; pp.pidx = pidx;
   }
+  // the current coarse state: Z (zeros) until the first step; each multilevel pass
+  // reads it and writes the other buffer
+  float* zbuf[2] = {p.ml ? w.at<float>(p.off_Z) : nullptr, p.ml ? w.at<float>(p.off_Z2) : nullptr};
+  int zcur = 0;
   auto pass = [&](bool thr) -> int {
     ProfScope ps(KC_FW_PASS, s);
     if (p.ml) {
+      pm.Zin = zbuf[zcur];
+      pm.Zout = zbuf[1 - zcur];
+      if (thr) zcur = 1 - zcur;
       if (p.masked)
         return p.VEC == 4 ? launch_pass_ml<true, 4>(p, pm, thr, s) : launch_pass_ml<true, 1>(p, pm, thr, s);
       return p.VEC == 4 ? launch_pass_ml<false, 4>(p, pm, thr, s) : launch_pass_ml<false, 1>(p, pm, thr, s);
@@ -1149,7 +1398,7 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
   };
   auto finalize = [&](bool thr) -> int {
     ProfScope ps(KC_FW_SMALL, s);
-    hipLaunchKernelGGL(k_fw_finalize, dim3(1), dim3(64), 0, s, part, pmax, pidx, (int)p.grid_pass, (double)lamL,
+    hipLaunchKernelGGL(k_fw_finalize, dim3(1), dim3(kFT), 0, s, part, pmax, pidx, (int)p.grid_pass, (double)lamL,
                        (double)lamS, thr ? 1 : 0, st);
     MLPCP_HIP(hipGetLastError());
     return MLPCP_OK;
@@ -1171,7 +1420,6 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
   double rel = 0.0;
   if (!(hs.f > 0.0)) converged = hs.f == 0.0;
   if (!std::isfinite(hs.f)) status = MLPCP_E_NONFINITE;
-  bool warm = false;
   while (!converged && status == MLPCP_OK && k < max_iter) {
     // the nuclear direction
     if (p.ml) {
@@ -1180,24 +1428,24 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
         MLPCP_TRY(gram_f64(m, p.nH, kPad, w.at<float>(p.off_GP), p.ldz, w.at<double>(p.off_gram),
                            w.at<void>(p.off_gws), s, 0));
       }
-      // top eigenpair of C (GP^T GP) C: the one-workgroup Jacobi; with a vanishing
-      // threshold the first column of T = C V_sorted diag(1) is z = C v_top
-      MLPCP_TRY(coarse_svt_small(p.nH, kEigInner, w.at<double>(p.off_gram), op->C, w.at<double>(p.off_V), warm,
-                                 1e-300, w.at<double>(p.off_lam), w.at<int>(p.off_perm), w.at<double>(p.off_sw),
-                                 w.at<double>(p.off_T), w.at<double>(p.off_Tt), nullptr,
-                                 w.at<IterStats>(p.off_ist), s));
-      warm = true;
+      // the top eigenpair of C (GP^T GP) C gives z = C v_top: the coarse direction
+      {
+        ProfScope pt(KC_FW_TOP, s);
+        MLPCP_TRY(coarse_top_small(p.nH, w.at<double>(p.off_gram), op->C, w.at<double>(p.off_T),
+                                   w.at<double>(p.off_lam), s));
+      }
       TermsML ta{};
-      ta.m = m; ta.nH = p.nH; ta.Z = w.at<float>(p.off_Z); ta.GP = w.at<float>(p.off_GP);
+      ta.m = m; ta.nH = p.nH; ta.Z = zbuf[zcur]; ta.GP = w.at<float>(p.off_GP);
       ta.Aq = w.at<float>(p.off_Aq); ta.Bq = w.at<float>(p.off_Bq); ta.QDP = w.at<float>(p.off_QDP);
-      ta.ld = p.ldz; ta.T = w.at<double>(p.off_T); ta.ldT = kEigInner; ta.gz = gz; ta.partial = tpart;
+      ta.ld = p.ldz; ta.T = w.at<double>(p.off_T); ta.ldT = 1; ta.gz = gz; ta.partial = tpart;
       ProfScope ps(KC_FW_SMALL, s);
       hipLaunchKernelGGL(k_fw_terms_ml, dim3(p.grid_terms), dim3(kFT), (size_t)p.nH * 8, s, ta);
       MLPCP_HIP(hipGetLastError());
     } else {
       PowArgs pa{};
-      pa.m = m; pa.n = n; pa.gs = p.gs; pa.rpb = p.rpb; pa.G = w.at<float>(p.off_G); pa.x = w.at<double>(p.off_w);
-      pa.partial = w.at<double>(p.off_powp); pa.y = w.at<double>(p.off_y); pa.ypart = w.at<double>(p.off_ypart);
+      pa.m = m; pa.n = n; pa.nchunk = p.nchunk; pa.G = w.at<float>(p.off_G); pa.x = w.at<double>(p.off_w);
+      pa.t = w.at<double>(p.off_t); pa.partial = w.at<double>(p.off_powp); pa.y = w.at<double>(p.off_y);
+      pa.ypart = w.at<double>(p.off_ypart);
       pa.st = st;
       hipLaunchKernelGGL(k_fw_power_start, dim3(1), dim3(1), 0, s, st);
       int done_steps = 0;
@@ -1242,12 +1490,12 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
     {
       SolveArgs sa{};
       sa.m = m; sa.n = n; sa.nH = p.nH; sa.levels = levels; sa.partial = tpart; sa.nb = (int)p.grid_terms;
-      sa.D = D; sa.ldd = ldd; sa.L = L; sa.Z = p.ml ? w.at<float>(p.off_Z) : nullptr; sa.ldz = p.ldz;
+      sa.D = D; sa.ldd = ldd; sa.L = L; sa.Z = p.ml ? zbuf[zcur] : nullptr; sa.ldz = p.ldz;
       sa.taps = taps;
-      sa.T = p.ml ? w.at<double>(p.off_T) : nullptr; sa.ldT = kEigInner;
+      sa.T = p.ml ? w.at<double>(p.off_T) : nullptr; sa.ldT = 1;
       sa.w = p.ml ? nullptr : w.at<double>(p.off_w); sa.gz = gz; sa.lamL = lamL; sa.lamS = lamS; sa.st = st;
       ProfScope ps(KC_FW_SMALL, s);
-      hipLaunchKernelGGL(k_fw_solve, dim3(1), dim3(64), 0, s, sa);
+      hipLaunchKernelGGL(k_fw_solve, dim3(1), dim3(kFT), 0, s, sa);
       MLPCP_HIP(hipGetLastError());
     }
     MLPCP_TRY(pass(true));
@@ -1274,10 +1522,14 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
   }
   if (status == MLPCP_OK) {
     ProfScope ps(KC_FINAL, s);
-    const unsigned g = grid_of((size_t)m * n, 8192);
+    const unsigned g = (unsigned)std::min(m, 8 * cus());
+    const size_t lds = p.ml ? (size_t)n * 4 + (size_t)p.nH * 4 : 0;
+    if (lds > 64 * 1024)
+      MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fw_output<true>),
+                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
     if (p.ml)
-      hipLaunchKernelGGL(k_fw_output<true>, dim3(g), dim3(kFT), 0, s, m, n, p.nH, levels, D, ldd, bits, p.nw,
-                         w.at<float>(p.off_Z), p.ldz, taps, lamS, thr ? 1 : 0, L, n, S, n);
+      hipLaunchKernelGGL(k_fw_output<true>, dim3(g), dim3(kFT), lds, s, m, n, p.nH, levels, D, ldd, bits, p.nw,
+                         zbuf[zcur], p.ldz, taps, lamS, thr ? 1 : 0, L, n, S, n);
     else
       hipLaunchKernelGGL(k_fw_output<false>, dim3(g), dim3(kFT), 0, s, m, n, p.nH, levels, D, ldd, bits, p.nw,
                          nullptr, 0, nullptr, lamS, thr ? 1 : 0, L, n, S, n);

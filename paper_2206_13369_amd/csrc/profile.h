@@ -20,6 +20,7 @@ enum KernelClass {
   KC_FW_PASS,
   KC_FW_POWER,
   KC_FW_SMALL,
+  KC_FW_TOP,
   KC_OTHER,
   KC_COUNT
 };
