@@ -41,7 +41,7 @@ namespace {
 
 constexpr int kFT = 256;          // threads per block of the streaming kernels
 constexpr int kNSums = 8;         // E2, ES, T5..T9, (pad) per block
-constexpr int kNTerms = 4;        // S1..S4 per block
+constexpr int kNTerms = 7;        // S1..S4, and (multilevel) T5..T7 per block
 constexpr int kPowMax = 500;      // power-iteration steps per FW iteration (cap)
 constexpr double kPowEps = 1e-6;  // ||v_new - v_old|| that ends the power iteration
 
@@ -63,7 +63,7 @@ __device__ __forceinline__ float shrinkf(float x, float t) {
   const float a = fabsf(x) - t;
   return a > 0.0f ? copysignf(a, x) : 0.0f;
 }
-__device__ __forceinline__ float clampf(float x, float t) { return fminf(fmaxf(x, -t), t); }
+__device__ __forceinline__ float clampf(float x, float t) { return __builtin_amdgcn_fmed3f(x, -t, t); }
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -160,38 +160,37 @@ struct Sums {
 };
 
 // sums of one short run of entries in float32 (a chunk of at most a few dozen
-// entries), folded into the float64 Sums once per run; the argmax keeps the column
+// entries), folded into the float64 Sums once per run: sum G^2, sum |S|, sum S^2 and,
+// when ARGMAX, the first entry of largest |G| (by column).  The multilevel path gets
+// the sums involving L from coarse quantities and sum G S = -lam_S sum |S| (G =
+// -lam_S sign(S) wherever S != 0).
+template <bool ARGMAX>
 struct RunSums {
-  float E2 = 0, ES = 0, T5 = 0, T6 = 0, T7 = 0, T8 = 0, T9 = 0;
+  float E2 = 0, ES = 0, T8 = 0;
   float best = -1.0f;
   int bj = 0;
-  __device__ __forceinline__ void add(float l, float s, float g, bool q, int j) {
-    if (!q) return;
+  __device__ __forceinline__ void add(float s, float g, int j) {
     E2 = fmaf(g, g, E2);
     ES += fabsf(s);
-    T5 = fmaf(l, l, T5);
-    T6 = fmaf(g, l, T6);
-    T7 = fmaf(l, s, T7);
     T8 = fmaf(s, s, T8);
-    T9 = fmaf(g, s, T9);
-    const float a = fabsf(g);
-    if (a > best) {          // runs are visited in increasing j: the first maximum stays
-      best = a;
-      bj = j;
+    if (ARGMAX) {
+      const float a = fabsf(g);
+      if (a > best) {          // runs are visited in increasing j: the first maximum stays
+        best = a;
+        bj = j;
+      }
     }
   }
   __device__ __forceinline__ void fold(Sums& sm, long long row_base) const {
     sm.E2 += E2;
     sm.ES += ES;
-    sm.T5 += T5;
-    sm.T6 += T6;
-    sm.T7 += T7;
     sm.T8 += T8;
-    sm.T9 += T9;
-    const long long idx = row_base + bj;
-    if (best > sm.best || (best == sm.best && best >= 0.0f && idx < sm.bidx)) {
-      sm.best = best;
-      sm.bidx = idx;
+    if (ARGMAX) {
+      const long long idx = row_base + bj;
+      if (best > sm.best || (best == sm.best && best >= 0.0f && idx < sm.bidx)) {
+        sm.best = best;
+        sm.bidx = idx;
+      }
     }
   }
 };
@@ -237,14 +236,20 @@ __device__ __forceinline__ float lift(const float* zrow, int c, float w0, int nH
 // sum (1 - w0) G for c + 1), which are added per coarse column in chunk order: GP = G P.
 // The new coarse rows (1 - alpha) Z - alpha U_L u_i z^T are formed at staging time.
 constexpr int kChunkMin = 16;      // shortest chunk (unless its interval is shorter)
-constexpr int kPrefetch = 8;       // float4 slots per thread held for the next batch (n <= 8192)
 
+// a run of fine columns j0 <= j < j1 whose first tap is c; when `affine`, the first-tap
+// weight is w0(j) = fmaf(ws, j - j0, wb) exactly (checked on the host), else the table
 struct Chunk {
-  int c, j0, j1, pad;
+  int c, j0, j1, affine;
+  float wb, ws, pad0, pad1;
 };
 
+__device__ __forceinline__ float chunk_w0(const Chunk& ch, int j, const float* __restrict__ w0tab) {
+  return ch.affine ? fmaf(ch.ws, (float)(j - ch.j0), ch.wb) : w0tab[j];
+}
+
 struct PassML {
-  int m, n, nH, R, K, nw, levels;
+  int m, n, nH, R, K, nw, levels, maxlen;   // maxlen: the longest chunk
   const float* D;
   int ldd;
   const uint32_t* bits;
@@ -272,17 +277,18 @@ __device__ __forceinline__ float lift2(float z0, float z1, float w0, bool has_ne
   return (w0 < 1.0f && has_next) ? fmaf(1.0f - w0, z1, a) : a;
 }
 
-// LDS layout of the multilevel kernels (bytes), shared by the host sizing
+// LDS layout of the multilevel kernels (bytes), shared by the host sizing: partial
+// sums (nsums per task, float or double), the coarse rows, the interval -> first chunk
+// table, the staged rows of D and of the mask words
 struct MlLds {
-  size_t sp, w0, z, ch, kf, d, q, total;
+  size_t tz, sp, z, kf, d, q, total;
 };
-__host__ __device__ inline MlLds ml_lds(int n, int nH, int R, int K, int nw, int nsums) {
+__host__ __device__ inline MlLds ml_lds(int n, int nH, int R, int K, int nw, int nsums, int bytes) {
   MlLds L{};
   size_t o = 0;
-  L.sp = o;  o += (size_t)nsums * R * K * 8;
-  L.w0 = o;  o += (size_t)n * 4;
+  L.tz = o;  o += (size_t)nH * 8;
+  L.sp = o;  o += (size_t)nsums * R * K * bytes;
   L.z = o;   o += (size_t)R * nH * 4;
-  L.ch = o;  o += (size_t)K * sizeof(Chunk);
   L.kf = o;  o += (size_t)(nH + 1) * 4;
   o = (o + 15) & ~size_t(15);
   L.d = o;   o += (size_t)R * n * 4;
@@ -291,16 +297,13 @@ __host__ __device__ inline MlLds ml_lds(int n, int nH, int R, int K, int nw, int
   return L;
 }
 
-// stage rows i0 .. i0+rows-1 of D and of the mask words: each thread holds up to
-// 4 kPrefetch floats (float4 slots when VEC == 4, single floats otherwise)
-constexpr int kStageFloats = 4 * kPrefetch;
-
-template <int VEC, bool MASKED>
-__device__ __forceinline__ void stage_load(const PassML& a, int i0, int rows, float (&rd)[kStageFloats],
-                                           uint32_t& rq) {
+// stage rows i0 .. i0+rows-1 of D and of the mask words: each thread holds 4 PF floats
+// (PF float4 slots when VEC == 4, single floats otherwise)
+template <int VEC, int PF, bool MASKED>
+__device__ __forceinline__ void stage_load(const PassML& a, int i0, int rows, float (&rd)[4 * PF], uint32_t& rq) {
   const int nv = a.n / VEC;
 #pragma unroll
-  for (int k = 0; k < kStageFloats / VEC; ++k) {
+  for (int k = 0; k < 4 * PF / VEC; ++k) {
     const int f = threadIdx.x + kFT * k;
     if (f < rows * nv) {
       const int r = f / nv, s = f - r * nv;
@@ -322,12 +325,12 @@ __device__ __forceinline__ void stage_load(const PassML& a, int i0, int rows, fl
   }
 }
 
-template <int VEC, bool MASKED>
-__device__ __forceinline__ void stage_store(const PassML& a, int rows, const float (&rd)[kStageFloats], uint32_t rq,
+template <int VEC, int PF, bool MASKED>
+__device__ __forceinline__ void stage_store(const PassML& a, int rows, const float (&rd)[4 * PF], uint32_t rq,
                                             float* sD, uint32_t* sQ) {
   const int nv = a.n / VEC;
 #pragma unroll
-  for (int k = 0; k < kStageFloats / VEC; ++k) {
+  for (int k = 0; k < 4 * PF / VEC; ++k) {
     const int f = threadIdx.x + kFT * k;
     if (f < rows * nv) {
       const int r = f / nv, s = f - r * nv;
@@ -339,15 +342,13 @@ __device__ __forceinline__ void stage_store(const PassML& a, int rows, const flo
   if (MASKED && (int)threadIdx.x < rows * a.nw) sQ[threadIdx.x] = rq;
 }
 
-template <bool MASKED, int VEC, bool THR>
+template <bool MASKED, int VEC, int PF, bool THR>
 __global__ void __launch_bounds__(kFT) k_fw_pass_ml(PassML a) {
   extern __shared__ __align__(16) char smem_raw[];
-  const MlLds lay = ml_lds(a.n, a.nH, a.R, a.K, a.nw, 2);
-  double* sp0 = reinterpret_cast<double*>(smem_raw + lay.sp);             // [R][K]
-  double* sp1 = sp0 + (size_t)a.R * a.K;                                   // [R][K]
-  float* sW0 = reinterpret_cast<float*>(smem_raw + lay.w0);                // [n]
+  const MlLds lay = ml_lds(a.n, a.nH, a.R, a.K, a.nw, 2, 4);
+  float* sp0 = reinterpret_cast<float*>(smem_raw + lay.sp);                // [R][K]
+  float* sp1 = sp0 + (size_t)a.R * a.K;                                    // [R][K]
   float* sZ = reinterpret_cast<float*>(smem_raw + lay.z);                  // [R][nH]
-  Chunk* sCh = reinterpret_cast<Chunk*>(smem_raw + lay.ch);                // [K]
   int* sKf = reinterpret_cast<int*>(smem_raw + lay.kf);                    // [nH + 1]
   float* sD = reinterpret_cast<float*>(smem_raw + lay.d);                  // [R][n]
   uint32_t* sQ = reinterpret_cast<uint32_t*>(smem_raw + lay.q);            // [R][nw]
@@ -355,58 +356,95 @@ __global__ void __launch_bounds__(kFT) k_fw_pass_ml(PassML a) {
   __shared__ float rv[kFT / 64];
   __shared__ long long ri[kFT / 64];
   const int tid = threadIdx.x;
-  for (int j = tid; j < a.n; j += kFT) sW0[j] = a.w0[j];
-  for (int k = tid; k < a.K; k += kFT) sCh[k] = a.chunks[k];
   for (int c = tid; c <= a.nH; c += kFT) sKf[c] = a.kfirst[c];
   const double alpha = THR ? a.st->alpha : 0.0;
   const double coefL = THR ? a.st->coefL : 0.0;   // alpha U_L / sigma if the atom is taken
+  // this thread's (row, chunk) task, the same for every batch
+  const int tr = tid / a.K, tk = tid - tr * a.K;
+  Chunk ch{};
+  if (tr < a.R) ch = a.chunks[tk];
+  const bool has_next = ch.c + 1 < a.nH;
+  // the coarse direction z, once per block
+  double* sTz = reinterpret_cast<double*>(smem_raw + lay.tz);             // [nH]
+  for (int c = tid; c < a.nH; c += kFT) sTz[c] = THR ? a.T[(size_t)c * a.ldT] : 0.0;
   Sums sm;
   const int nbatch = (a.m + a.R - 1) / a.R;
-  float rd[kStageFloats];
+  float rd[4 * PF];
   uint32_t rq = 0xFFFFFFFFu;
+  // the coarse rows of the next batch (up to two entries per thread) and their gz
+  float zq[2] = {0.0f, 0.0f};
+  double gq[2] = {0.0, 0.0};
+  auto coarse_load = [&](int i0n, int rows_n) {
+    if (!THR) return;
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = tid + kFT * u;
+      if (t < rows_n * a.nH) {
+        const int r = t / a.nH, c = t - r * a.nH;
+        zq[u] = a.Zin[(size_t)(i0n + r) * a.ldz + c];
+        gq[u] = a.gz[i0n + r];
+      }
+    }
+  };
   int b = blockIdx.x;
-  if (b < nbatch) stage_load<VEC, MASKED>(a, b * a.R, min(a.R, a.m - b * a.R), rd, rq);
+  if (b < nbatch) {
+    stage_load<VEC, PF, MASKED>(a, b * a.R, min(a.R, a.m - b * a.R), rd, rq);
+    coarse_load(b * a.R, min(a.R, a.m - b * a.R));
+  }
+  __syncthreads();
   for (; b < nbatch; b += gridDim.x) {
     const int i0 = b * a.R;
     const int rows = min(a.R, a.m - i0);
-    stage_store<VEC, MASKED>(a, rows, rd, rq, sD, sQ);
-    for (int t = tid; t < rows * a.nH; t += kFT) {
-      const int r = t / a.nH, c = t - r * a.nH;
-      const int i = i0 + r;
-      float zv = 0.0f;
-      if (THR) {
-        zv = (float)((1.0 - alpha) * (double)a.Zin[(size_t)i * a.ldz + c] - coefL * a.gz[i] * a.T[(size_t)c * a.ldT]);
-        a.Zout[(size_t)i * a.ldz + c] = zv;
+    stage_store<VEC, PF, MASKED>(a, rows, rd, rq, sD, sQ);
+#pragma unroll
+    for (int u = 0; u < 2; ++u) {
+      const int t = tid + kFT * u;
+      if (t < rows * a.nH) {
+        const int r = t / a.nH, c = t - r * a.nH;
+        float zv = 0.0f;
+        if (THR) {
+          zv = (float)((1.0 - alpha) * (double)zq[u] - coefL * gq[u] * sTz[c]);
+          a.Zout[(size_t)(i0 + r) * a.ldz + c] = zv;
+        }
+        sZ[r * a.nH + c] = zv;
       }
-      sZ[r * a.nH + c] = zv;
     }
     __syncthreads();
     const int bn = b + gridDim.x;
-    if (bn < nbatch) stage_load<VEC, MASKED>(a, bn * a.R, min(a.R, a.m - bn * a.R), rd, rq);
-    if (tid < rows * a.K) {
-      const int r = tid / a.K, k = tid - r * a.K;
-      const int i = i0 + r;
-      const Chunk ch = sCh[k];
-      const bool has_next = ch.c + 1 < a.nH;
-      const float z0 = sZ[r * a.nH + ch.c];
-      const float z1 = has_next ? sZ[r * a.nH + ch.c + 1] : 0.0f;
-      const float* drow = sD + (size_t)r * a.n;
-      const uint32_t* qrow = sQ + (size_t)r * a.nw;
-      float p0 = 0.0f, p1 = 0.0f;
-      RunSums rs;
-      for (int j = ch.j0; j < ch.j1; ++j) {
-        const bool q = MASKED ? ((qrow[j >> 5] >> (j & 31)) & 1u) : true;
-        const float w0 = sW0[j];
-        const float l = lift2(z0, z1, w0, has_next);
-        float sv, gv;
-        entry<THR>(drow[j], l, q, a.lamS, sv, gv);
-        rs.add(l, sv, gv, q, j);
-        p0 = fmaf(w0, gv, p0);
-        p1 = fmaf(1.0f - w0, gv, p1);
+    if (bn < nbatch) {
+      stage_load<VEC, PF, MASKED>(a, bn * a.R, min(a.R, a.m - bn * a.R), rd, rq);
+      coarse_load(bn * a.R, min(a.R, a.m - bn * a.R));
+    }
+    if (tr < rows) {
+      const int i = i0 + tr;
+      const float z0 = sZ[tr * a.nH + ch.c];
+      const float z1 = has_next ? sZ[tr * a.nH + ch.c + 1] : 0.0f;
+      const float* drow = sD + (size_t)tr * a.n;
+      const uint32_t* qrow = sQ + (size_t)tr * a.nw;
+      const int len = ch.j1 - ch.j0;
+      float p0 = 0.0f, ps = 0.0f;
+      RunSums<!THR> rs;     // after the first step |G| <= lam_S: the l1 gate is closed
+      // a uniform trip count (the longest chunk), predicated in groups of four
+      for (int t0 = 0; t0 < a.maxlen; t0 += 4) {
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+          const int t = t0 + u;
+          const bool valid = t < len;
+          const int j = valid ? ch.j0 + t : ch.j0;
+          const float d = drow[j];
+          const bool q = valid && (MASKED ? ((qrow[j >> 5] >> (j & 31)) & 1u) : true);
+          const float w0 = fmaf(ch.ws, (float)t, ch.wb);      // affine within the chunk
+          const float l = fmaf(1.0f - w0, z1, w0 * z0);       // = lift (z1 = 0 past the last column)
+          float sv, gv;
+          entry<THR>(d, l, q, a.lamS, sv, gv);
+          rs.add(sv, gv, j);
+          p0 = fmaf(w0, gv, p0);
+          ps += gv;
+        }
       }
       rs.fold(sm, (long long)i * a.n);
-      sp0[r * a.K + k] = p0;
-      sp1[r * a.K + k] = p1;
+      sp0[tr * a.K + tk] = p0;
+      sp1[tr * a.K + tk] = ps - p0;
     }
     __syncthreads();
     for (int t = tid; t < rows * a.nH; t += kFT) {
@@ -552,14 +590,14 @@ struct TermsML {
 
 __global__ void __launch_bounds__(kFT) k_fw_terms_ml(TermsML a) {
   extern __shared__ double sz[];   // [nH]
-  __shared__ double red[4 * (kFT / 64)];
+  __shared__ double red[7 * (kFT / 64)];
   const int lane = threadIdx.x & 63, wid = threadIdx.x >> 6;
   for (int c = threadIdx.x; c < a.nH; c += kFT) sz[c] = a.T[(size_t)c * a.ldT];
   __syncthreads();
-  double acc[4] = {0, 0, 0, 0};
+  double acc[7] = {0, 0, 0, 0, 0, 0, 0};
   for (int i = blockIdx.x * (kFT / 64) + wid; i < a.m; i += gridDim.x * (kFT / 64)) {
     const size_t o = (size_t)i * a.ld;
-    double g = 0, l = 0, d = 0, q = 0;
+    double g = 0, l = 0, d = 0, q = 0, t5 = 0, t6 = 0, zd = 0;
     for (int c = lane; c < a.nH; c += 64) {
       const double zc = sz[c];
       const double A = a.Aq[o + c], B = a.Bq[o + c];
@@ -568,26 +606,37 @@ __global__ void __launch_bounds__(kFT) k_fw_terms_ml(TermsML a) {
       const double Zn = c + 1 < a.nH ? (double)a.Z[o + c + 1] : 0.0;
       const double Zp = c > 0 ? (double)a.Z[o + c - 1] : 0.0;
       const double Bp = c > 0 ? (double)a.Bq[o + c - 1] : 0.0;
-      g += zc * a.GP[o + c];
-      d += zc * a.QDP[o + c];
+      const double GPc = a.GP[o + c], QDc = a.QDP[o + c];
+      g += zc * GPc;
+      d += zc * QDc;
       l += zc * (A * Zc + B * Zn + Bp * Zp);
       q += A * zc * zc + 2.0 * B * zc * zn;
+      // the iterate's own sums, L = Z P^T: sum_Q L^2, sum G L, sum Z (Q o D) P
+      t5 += A * Zc * Zc + 2.0 * B * Zc * Zn;
+      t6 += Zc * GPc;
+      zd += Zc * QDc;
     }
     g = wave_sum(g);
     l = wave_sum(l);
     d = wave_sum(d);
     q = wave_sum(q);
+    t5 = wave_sum(t5);
+    t6 = wave_sum(t6);
+    zd = wave_sum(zd);
     if (lane == 0) {
       a.gz[i] = g;
       acc[0] += g * g;
       acc[1] += g * g * q;
       acc[2] += g * l;
       acc[3] += g * d;
+      acc[4] += t5;
+      acc[5] += t6;
+      acc[6] += t6 - t5 + zd;     // sum_Q L S: (Q o S) P = GP - (Q o L) P + (Q o D) P
     }
   }
-  block_sums<4>(acc, red);
+  block_sums<7>(acc, red);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) a.partial[(size_t)blockIdx.x * kNTerms + k] = acc[k];
+    for (int k = 0; k < 7; ++k) a.partial[(size_t)blockIdx.x * kNTerms + k] = acc[k];
 }
 
 // plain: one wave per row over the fine columns (G recomputed from D and L)
@@ -642,7 +691,7 @@ __global__ void __launch_bounds__(kFT) k_fw_terms_plain(TermsPlain a) {
   }
   block_sums<4>(acc, red);
   if (threadIdx.x == 0)
-    for (int k = 0; k < 4; ++k) a.partial[(size_t)blockIdx.x * kNTerms + k] = acc[k];
+    for (int k = 0; k < kNTerms; ++k) a.partial[(size_t)blockIdx.x * kNTerms + k] = k < 4 ? acc[k] : 0.0;
 }
 
 // ---------------------------------------------------------------------------------
@@ -700,13 +749,20 @@ struct SolveArgs {
 };
 
 __global__ void __launch_bounds__(kFT) k_fw_solve(SolveArgs a) {
-  __shared__ double red[4 * (kFT / 64)];
-  double v[4] = {0, 0, 0, 0};
+  __shared__ double red[kNTerms * (kFT / 64)];
+  double v[kNTerms] = {0, 0, 0, 0, 0, 0, 0};
   for (int b = threadIdx.x; b < a.nb; b += kFT)
-    for (int k = 0; k < 4; ++k) v[k] += a.partial[(size_t)b * kNTerms + k];
-  block_sums<4>(v, red);
+    for (int k = 0; k < kNTerms; ++k) v[k] += a.partial[(size_t)b * kNTerms + k];
+  block_sums<kNTerms>(v, red);
   if (threadIdx.x != 0) return;
   FwState* st = a.st;
+  if (a.levels > 0) {
+    // the multilevel pass leaves the sums that involve L to the coarse terms
+    st->T5 = v[4];
+    st->T6 = v[5];
+    st->T7 = v[6];
+    st->T9 = -a.lamS * st->t_S;
+  }
   const double S1 = v[0], S2 = v[1], S3 = v[2], S4 = v[3];
   const double sigma = sqrt(S1);
   const double U_L = st->U_L, U_S = st->U_S;
@@ -922,40 +978,38 @@ __global__ void k_fw_init_state(FwState* st) {
 // Precomputed per-row coarse tables of the mask (multilevel): A_ic = sum_j Q_ij P_jc^2,
 // B_ic = sum_j Q_ij P_jc P_j,c+1, QDP_ic = sum_j Q_ij D_ij P_jc; the pass's layout, five
 // partial sums per chunk, added per coarse column in chunk order.
-template <bool MASKED, int VEC>
+template <bool MASKED, int VEC, int PF>
 __global__ void __launch_bounds__(kFT) k_fw_mask_tables(PassML a, float* __restrict__ Aq, float* __restrict__ Bq,
                                                        float* __restrict__ QDP) {
   extern __shared__ __align__(16) char smem_raw[];
-  const MlLds lay = ml_lds(a.n, a.nH, a.R, a.K, a.nw, 5);
+  const MlLds lay = ml_lds(a.n, a.nH, a.R, a.K, a.nw, 5, 8);
   double* sp = reinterpret_cast<double*>(smem_raw + lay.sp);               // [5][R][K]
-  float* sW0 = reinterpret_cast<float*>(smem_raw + lay.w0);
-  Chunk* sCh = reinterpret_cast<Chunk*>(smem_raw + lay.ch);
   int* sKf = reinterpret_cast<int*>(smem_raw + lay.kf);
   float* sD = reinterpret_cast<float*>(smem_raw + lay.d);
   uint32_t* sQ = reinterpret_cast<uint32_t*>(smem_raw + lay.q);
   const int tid = threadIdx.x;
-  for (int j = tid; j < a.n; j += kFT) sW0[j] = a.w0[j];
-  for (int k = tid; k < a.K; k += kFT) sCh[k] = a.chunks[k];
   for (int c = tid; c <= a.nH; c += kFT) sKf[c] = a.kfirst[c];
+  const int tr = tid / a.K, tk = tid - tr * a.K;
+  Chunk ch{};
+  if (tr < a.R) ch = a.chunks[tk];
   const size_t RK = (size_t)a.R * a.K;
   const int nbatch = (a.m + a.R - 1) / a.R;
-  float rd[kStageFloats];
+  float rd[4 * PF];
   uint32_t rq = 0xFFFFFFFFu;
   for (int b = blockIdx.x; b < nbatch; b += gridDim.x) {
     const int i0 = b * a.R;
     const int rows = min(a.R, a.m - i0);
-    stage_load<VEC, MASKED>(a, i0, rows, rd, rq);
-    stage_store<VEC, MASKED>(a, rows, rd, rq, sD, sQ);
+    stage_load<VEC, PF, MASKED>(a, i0, rows, rd, rq);
+    stage_store<VEC, PF, MASKED>(a, rows, rd, rq, sD, sQ);
     __syncthreads();
-    if (tid < rows * a.K) {
-      const int r = tid / a.K, k = tid - r * a.K;
-      const Chunk ch = sCh[k];
-      const float* drow = sD + (size_t)r * a.n;
-      const uint32_t* qrow = sQ + (size_t)r * a.nw;
+    if (tr < rows) {
+      const float* drow = sD + (size_t)tr * a.n;
+      const uint32_t* qrow = sQ + (size_t)tr * a.nw;
       double A0 = 0, A1 = 0, B = 0, Q0 = 0, Q1 = 0;
       for (int j = ch.j0; j < ch.j1; ++j) {
         if (MASKED && !((qrow[j >> 5] >> (j & 31)) & 1u)) continue;
-        const double w0 = sW0[j], w1 = (double)(1.0f - sW0[j]);
+        const float wf = chunk_w0(ch, j, a.w0);
+        const double w0 = wf, w1 = (double)(1.0f - wf);
         const double d = drow[j];
         A0 += w0 * w0;
         A1 += w1 * w1;
@@ -963,7 +1017,7 @@ __global__ void __launch_bounds__(kFT) k_fw_mask_tables(PassML a, float* __restr
         Q0 += w0 * d;
         Q1 += w1 * d;
       }
-      const size_t o = (size_t)r * a.K + k;
+      const size_t o = (size_t)tr * a.K + tk;
       sp[o] = A0;
       sp[RK + o] = A1;
       sp[2 * RK + o] = B;
@@ -1079,6 +1133,7 @@ struct FwTables {
   std::vector<float> w0;
   std::vector<Chunk> chunks;
   std::vector<int> kfirst;
+  int maxlen = 0;
 };
 
 int fw_tables(int n, int levels, int nH, FwTables& t) {
@@ -1109,17 +1164,45 @@ int fw_tables(int n, int levels, int nH, FwTables& t) {
       first[c] = j;
     }
   }
-  int L = kChunkMin;
-  for (;; ++L) {
+  // the shortest L (>= kChunkMin) whose chunking, with cuts where the weight stops being
+  // affine, gives at most kFT chunks
+  auto count = [&](int L) {
     long long cnt = 0;
-    for (int c = 0; c < nH; ++c) cnt += (first[c + 1] - first[c] + L - 1) / L;
-    if (cnt <= kFT) break;
-  }
+    for (int c = 0; c < nH; ++c)
+      for (int j = first[c]; j < first[c + 1];) {
+        int j1 = std::min(first[c + 1], j + L);
+        const float wb = t.w0[j], ws = j1 - j > 1 ? t.w0[j + 1] - t.w0[j] : 0.0f;
+        for (int jj = j + 1; jj < j1; ++jj)
+          if (std::fmaf(ws, (float)(jj - j), wb) != t.w0[jj]) {
+            j1 = jj;
+            break;
+          }
+        ++cnt;
+        j = j1;
+      }
+    return cnt;
+  };
+  int L = kChunkMin;
+  while (count(L) > kFT && L < n) ++L;
+  if (count(L) > kFT) return MLPCP_E_UNSUPPORTED;
   t.chunks.clear();
+  t.maxlen = 0;
   t.kfirst.assign(nH + 1, 0);
   for (int c = 0; c < nH; ++c) {
     t.kfirst[c] = (int)t.chunks.size();
-    for (int j = first[c]; j < first[c + 1]; j += L) t.chunks.push_back(Chunk{c, j, std::min(first[c + 1], j + L), 0});
+    for (int j = first[c]; j < first[c + 1];) {
+      // at most L columns, cut where w0 stops being affine in j (exactly, in float)
+      Chunk ch{c, j, std::min(first[c + 1], j + L), 1, t.w0[j], 0.0f, 0.0f, 0.0f};
+      ch.ws = ch.j1 - ch.j0 > 1 ? t.w0[j + 1] - t.w0[j] : 0.0f;
+      for (int jj = ch.j0 + 1; jj < ch.j1; ++jj)
+        if (std::fmaf(ch.ws, (float)(jj - ch.j0), ch.wb) != t.w0[jj]) {
+          ch.j1 = jj;
+          break;
+        }
+      t.chunks.push_back(ch);
+      t.maxlen = std::max(t.maxlen, ch.j1 - ch.j0);
+      j = ch.j1;
+    }
   }
   t.kfirst[nH] = (int)t.chunks.size();
   return MLPCP_OK;
@@ -1143,7 +1226,7 @@ int fw_tables_cached(int n, int levels, int nH, std::shared_ptr<const FwTables>&
 }
 
 struct FwPlan {
-  int m, n, nH, levels, nw, VEC, R, K, ldz;
+  int m, n, nH, levels, nw, VEC, R, K, PF, ldz;
   bool ml, masked;
   unsigned grid_pass, grid_terms;
   size_t lds_pass, lds_tables;
@@ -1177,13 +1260,15 @@ int make_fw_plan(int m, int n, int levels, bool masked, bool vec_ok, FwPlan& p) 
     p.ldz = kPad;   // Z, GP, tables share the Gram's padded width
     p.K = (int)t->chunks.size();
     const int nv = n / p.VEC;
-    // rows per batch: fill the tasks (R K <= kFT) within the prefetch registers
+    // rows per batch: fill the tasks (R K <= kFT) within 8 float4 of staging per thread
     p.R = std::max(1, std::min(8, kFT / std::max(1, p.K)));
-    const int slots = (kStageFloats / p.VEC) * kFT;   // staged entries (or float4s) per batch
-    while (p.R > 1 && (p.R * nv > slots || p.R * p.nw > kFT)) --p.R;
-    if (nv > slots || p.nw > kFT) return MLPCP_E_UNSUPPORTED;
-    p.lds_pass = ml_lds(n, p.nH, p.R, p.K, p.nw, 2).total;
-    p.lds_tables = ml_lds(n, p.nH, p.R, p.K, p.nw, 5).total;
+    auto pf_for = [&](int R) { return ((R * nv + kFT - 1) / kFT * p.VEC + 3) / 4; };   // float4s per thread
+    while (p.R > 1 && (pf_for(p.R) > 8 || p.R * p.nw > kFT || p.R * p.nH > 2 * kFT)) --p.R;
+    if (pf_for(p.R) > 8 || p.nw > kFT) return MLPCP_E_UNSUPPORTED;
+    const int pf = pf_for(p.R);
+    p.PF = pf <= 2 ? 2 : pf <= 4 ? 4 : pf <= 6 ? 6 : 8;
+    p.lds_pass = ml_lds(n, p.nH, p.R, p.K, p.nw, 2, 4).total;
+    p.lds_tables = ml_lds(n, p.nH, p.R, p.K, p.nw, 5, 8).total;
     if (p.lds_pass > 150 * 1024 || p.lds_tables > 150 * 1024) return MLPCP_E_UNSUPPORTED;
     const int per_cu = std::max(1, std::min(8, (int)((160 * 1024) / (p.lds_pass + 2048))));
     const int nbatch = (m + p.R - 1) / p.R;
@@ -1254,15 +1339,46 @@ struct FwWS {
   }
 };
 
-template <bool MASKED, int VEC>
-int launch_pass_ml(const FwPlan& p, const PassML& a, bool thr, hipStream_t s) {
-  auto k = thr ? k_fw_pass_ml<MASKED, VEC, true> : k_fw_pass_ml<MASKED, VEC, false>;
+template <bool MASKED, int VEC, int PF>
+int launch_pass_ml_pf(const FwPlan& p, const PassML& a, bool thr, hipStream_t s) {
+  auto k = thr ? k_fw_pass_ml<MASKED, VEC, PF, true> : k_fw_pass_ml<MASKED, VEC, PF, false>;
   if (p.lds_pass > 64 * 1024)
     MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k), hipFuncAttributeMaxDynamicSharedMemorySize,
                                   (int)p.lds_pass));
   hipLaunchKernelGGL(k, dim3(p.grid_pass), dim3(kFT), p.lds_pass, s, a);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
+}
+
+template <bool MASKED, int VEC>
+int launch_pass_ml(const FwPlan& p, const PassML& a, bool thr, hipStream_t s) {
+  switch (p.PF) {
+    case 2: return launch_pass_ml_pf<MASKED, VEC, 2>(p, a, thr, s);
+    case 4: return launch_pass_ml_pf<MASKED, VEC, 4>(p, a, thr, s);
+    case 6: return launch_pass_ml_pf<MASKED, VEC, 6>(p, a, thr, s);
+    default: return launch_pass_ml_pf<MASKED, VEC, 8>(p, a, thr, s);
+  }
+}
+
+template <bool MASKED, int VEC, int PF>
+int launch_tables_pf(const FwPlan& p, const PassML& a, float* Aq, float* Bq, float* QDP, hipStream_t s) {
+  auto kt = k_fw_mask_tables<MASKED, VEC, PF>;
+  if (p.lds_tables > 64 * 1024)
+    MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kt), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                  (int)p.lds_tables));
+  hipLaunchKernelGGL(kt, dim3(p.grid_pass), dim3(kFT), p.lds_tables, s, a, Aq, Bq, QDP);
+  MLPCP_HIP(hipGetLastError());
+  return MLPCP_OK;
+}
+
+template <bool MASKED, int VEC>
+int launch_tables(const FwPlan& p, const PassML& a, float* Aq, float* Bq, float* QDP, hipStream_t s) {
+  switch (p.PF) {
+    case 2: return launch_tables_pf<MASKED, VEC, 2>(p, a, Aq, Bq, QDP, s);
+    case 4: return launch_tables_pf<MASKED, VEC, 4>(p, a, Aq, Bq, QDP, s);
+    case 6: return launch_tables_pf<MASKED, VEC, 6>(p, a, Aq, Bq, QDP, s);
+    default: return launch_tables_pf<MASKED, VEC, 8>(p, a, Aq, Bq, QDP, s);
+  }
 }
 
 template <bool MASKED, int VEC>
@@ -1348,6 +1464,7 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
     MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GP), 0, mat, s));
     MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_T), 0, (size_t)kEigInner * 8, s));
     pm.m = m; pm.n = n; pm.nH = p.nH; pm.R = p.R; pm.K = p.K; pm.nw = p.nw; pm.levels = levels;
+    pm.maxlen = tb.maxlen;
     pm.D = D; pm.ldd = ldd; pm.bits = bits;
     pm.Zin = w.at<float>(p.off_Z); pm.Zout = w.at<float>(p.off_Z2); pm.ldz = p.ldz;
     pm.GP = w.at<float>(p.off_GP); pm.ldg = p.ldz;
@@ -1357,14 +1474,14 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
     pm.gz = gz; pm.st = st; pm.lamS = lamS;
     pm.partial = part; pm.pmax = pmax; pm.pidx = pidx;
     {
-      auto kt = p.masked ? (p.VEC == 4 ? k_fw_mask_tables<true, 4> : k_fw_mask_tables<true, 1>)
-                         : (p.VEC == 4 ? k_fw_mask_tables<false, 4> : k_fw_mask_tables<false, 1>);
-      if (p.lds_tables > 64 * 1024)
-        MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(kt), hipFuncAttributeMaxDynamicSharedMemorySize,
-                                      (int)p.lds_tables));
-      hipLaunchKernelGGL(kt, dim3(p.grid_pass), dim3(kFT), p.lds_tables, s, pm, w.at<float>(p.off_Aq),
-                         w.at<float>(p.off_Bq), w.at<float>(p.off_QDP));
-      MLPCP_HIP(hipGetLastError());
+      float *Aq = w.at<float>(p.off_Aq), *Bq = w.at<float>(p.off_Bq), *QDP = w.at<float>(p.off_QDP);
+      int st_tab;
+      if (p.masked)
+        st_tab = p.VEC == 4 ? launch_tables<true, 4>(p, pm, Aq, Bq, QDP, s) : launch_tables<true, 1>(p, pm, Aq, Bq, QDP, s);
+      else
+        st_tab = p.VEC == 4 ? launch_tables<false, 4>(p, pm, Aq, Bq, QDP, s)
+                            : launch_tables<false, 1>(p, pm, Aq, Bq, QDP, s);
+      MLPCP_TRY(st_tab);
     }
   } else {
     hipLaunchKernelGGL(k_fw_fill, dim3((n + 255) / 256), dim3(256), 0, s, w.at<double>(p.off_w), n,
