@@ -901,20 +901,25 @@ __global__ void __launch_bounds__(kTopThreads) k_coarse_top(int nH, const double
     sP[i][j] = sH[i][j] / trace;
   }
   __syncthreads();
-  for (int sq = 0; sq < kTopSquarings; ++sq) {
-    mm64<false>(sP, sP, acc);
-    mm64_store(acc, [&](int i, int j, double v) { sQ[i][j] = v; });
+  // wave sums folded through LDS: two barriers per reduction
+  auto block_total = [&](double v) {
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+    __syncthreads();
+    if ((tid & 63) == 0) red[tid >> 6] = v;
     __syncthreads();
     double t = 0.0;
-    for (int i = tid; i < IN; i += kTopThreads) t += sQ[i][i];
-    red[tid] = t;
-    __syncthreads();
-    for (int w = kTopThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const double tq = red[0];
-    __syncthreads();
+    for (int w = 0; w < kTopThreads / 64; ++w) t += red[w];
+    return t;
+  };
+  for (int sq = 0; sq < kTopSquarings; ++sq) {
+    mm64<false>(sP, sP, acc);
+    // trace(P P) from the accumulators (diagonal entries held by this lane), and P P
+    double t = 0.0;
+    mm64_store(acc, [&](int i, int j, double v) {
+      sQ[i][j] = v;
+      if (i == j) t += v;
+    });
+    const double tq = block_total(t);
     double f2 = 0.0;
     for (int it = tid; it < IN * IN; it += kTopThreads) {
       const int i = it / IN, j = it % IN;
@@ -922,16 +927,10 @@ __global__ void __launch_bounds__(kTopThreads) k_coarse_top(int nH, const double
       sP[i][j] = v;
       f2 += v * v;
     }
-    red[tid] = f2;
-    __syncthreads();
-    for (int w = kTopThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) red[tid] += red[tid + w];
-      __syncthreads();
-    }
-    const bool done = !(tq > 0.0) || 1.0 - red[0] <= 1e-13;
-    __syncthreads();
-    if (done) break;
+    const double fr = block_total(f2);
+    if (!(tq > 0.0) || 1.0 - fr <= 1e-13) break;
   }
+  __syncthreads();
   // start: the column with the largest diagonal entry (ties: smallest index)
   if (tid == 0) {
     int jb = 0;

@@ -1052,7 +1052,7 @@ __global__ void __launch_bounds__(kFT) k_fw_mask_tables(PassML a, float* __restr
 // Returned iterate: L (multilevel: Z P^T; plain: already in L) and S = P_Q S_{lam_S}[D - L]
 // (zero before the first threshold step).  A block walks rows; multilevel stages the
 // stencil taps once and each row of Z in LDS.
-template <bool ML>
+template <bool ML, int VEC>
 __global__ void __launch_bounds__(kFT) k_fw_output(int m, int n, int nH, int levels, const float* __restrict__ D,
                                                   int ldd, const uint32_t* __restrict__ bits, int nw,
                                                   const float* __restrict__ Z, int ldz,
@@ -1064,6 +1064,7 @@ __global__ void __launch_bounds__(kFT) k_fw_output(int m, int n, int nH, int lev
   const float scale = ldexpf(1.0f, -levels);
   if (ML)
     for (int j = threadIdx.x; j < n; j += kFT) sTap[j] = taps[j];
+  const int nv = n / VEC;
   for (int i = blockIdx.x; i < m; i += gridDim.x) {
     if (ML) {
       __syncthreads();
@@ -1071,38 +1072,64 @@ __global__ void __launch_bounds__(kFT) k_fw_output(int m, int n, int nH, int lev
       __syncthreads();
     }
     const float* drow = D + (size_t)i * ldd;
-    for (int j = threadIdx.x; j < n; j += kFT) {
-      float l;
-      if (ML) {
-        int c;
-        float w0;
-        unpack_tap(sTap[j], scale, c, w0);
-        l = lift(sZr, c, w0, nH);
-        L[(size_t)i * ldl + j] = l;
+    float* lrow = L + (size_t)i * ldl;
+    float* srow = S + (size_t)i * lds;
+    for (int sv4 = threadIdx.x; sv4 < nv; sv4 += kFT) {
+      const int j = sv4 * VEC;
+      float d[VEC], l[VEC], sv[VEC];
+      if constexpr (VEC == 4) {
+        const float4 v = *reinterpret_cast<const float4*>(drow + j);
+        d[0] = v.x; d[1] = v.y; d[2] = v.z; d[3] = v.w;
+        if (!ML) {
+          const float4 x = *reinterpret_cast<const float4*>(lrow + j);
+          l[0] = x.x; l[1] = x.y; l[2] = x.z; l[3] = x.w;
+        }
       } else {
-        l = L[(size_t)i * ldl + j];
+        d[0] = drow[j];
+        if (!ML) l[0] = lrow[j];
       }
-      const bool q = bits ? mask_bit(bits, nw, i, j) : true;
-      float sv, gv;
-      if (thr)
-        entry<true>(drow[j], l, q, lamS, sv, gv);
-      else
-        entry<false>(drow[j], l, q, lamS, sv, gv);
-      S[(size_t)i * lds + j] = sv;
+      const uint32_t word = bits ? bits[(size_t)i * nw + (j >> 5)] : 0xFFFFFFFFu;
+#pragma unroll
+      for (int e = 0; e < VEC; ++e) {
+        if (ML) {
+          int c;
+          float w0;
+          unpack_tap(sTap[j + e], scale, c, w0);
+          l[e] = lift(sZr, c, w0, nH);
+        }
+        const bool q = (word >> ((j + e) & 31)) & 1u;
+        float gv;
+        if (thr)
+          entry<true>(d[e], l[e], q, lamS, sv[e], gv);
+        else
+          entry<false>(d[e], l[e], q, lamS, sv[e], gv);
+      }
+      if constexpr (VEC == 4) {
+        if (ML) *reinterpret_cast<float4*>(lrow + j) = make_float4(l[0], l[1], l[2], l[3]);
+        *reinterpret_cast<float4*>(srow + j) = make_float4(sv[0], sv[1], sv[2], sv[3]);
+      } else {
+        if (ML) lrow[j] = l[0];
+        srow[j] = sv[0];
+      }
     }
   }
 }
 
-__global__ void k_fw_pack_mask(int m, int n, const uint8_t* __restrict__ Q, int nw, uint32_t* __restrict__ bits) {
-  const size_t total = (size_t)m * nw;
-  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
-    const size_t i = idx / nw;
-    const int w = (int)(idx % nw);
-    uint32_t v = 0;
-    const int j0 = w * 32;
-    const int jn = min(32, n - j0);
-    for (int b = 0; b < jn; ++b) v |= (Q[i * n + j0 + b] != 0 ? 1u : 0u) << b;
-    bits[idx] = v;
+// bits[i][w] bit b = (Q[i][32 w + b] != 0): one wave per 64 columns of a row, one byte
+// per lane (coalesced), the words from a wave ballot
+__global__ void __launch_bounds__(kFT) k_fw_pack_mask(int m, int n, const uint8_t* __restrict__ Q, int nw,
+                                                     uint32_t* __restrict__ bits) {
+  const int lane = threadIdx.x & 63;
+  const int segs = (n + 63) / 64;
+  const size_t total = (size_t)m * segs;
+  for (size_t t = (size_t)blockIdx.x * (kFT / 64) + (threadIdx.x >> 6); t < total; t += (size_t)gridDim.x * (kFT / 64)) {
+    const int i = (int)(t / segs), sg = (int)(t - (size_t)i * segs);
+    const int j = sg * 64 + lane;
+    const bool q = j < n && Q[(size_t)i * n + j] != 0;
+    const unsigned long long b = __ballot(q);
+    const int w = sg * 2;
+    if (lane == 0) bits[(size_t)i * nw + w] = (uint32_t)b;
+    if (lane == 1 && w + 1 < nw) bits[(size_t)i * nw + w + 1] = (uint32_t)(b >> 32);
   }
 }
 
@@ -1438,8 +1465,9 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
   double* gz = w.at<double>(p.off_gz);
   hipLaunchKernelGGL(k_fw_init_state, dim3(1), dim3(1), 0, s, st);
   if (p.masked) {
-    const size_t words = (size_t)m * p.nw;
-    hipLaunchKernelGGL(k_fw_pack_mask, dim3(grid_of(words, 65536)), dim3(kFT), 0, s, m, n, Q, p.nw, bits);
+    const size_t segs = (size_t)m * ((n + 63) / 64);
+    hipLaunchKernelGGL(k_fw_pack_mask, dim3((unsigned)std::min<size_t>((segs + 3) / 4, 8u * cus())), dim3(kFT), 0, s,
+                       m, n, Q, p.nw, bits);
   }
   MLPCP_HIP(hipMemsetAsync(gz, 0, (size_t)m * 8, s));
 
@@ -1641,15 +1669,14 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
     ProfScope ps(KC_FINAL, s);
     const unsigned g = (unsigned)std::min(m, 8 * cus());
     const size_t lds = p.ml ? (size_t)n * 4 + (size_t)p.nH * 4 : 0;
+    const bool v4 = p.VEC == 4 && reinterpret_cast<uintptr_t>(S) % 16 == 0;
+    float* zc = p.ml ? zbuf[zcur] : nullptr;
+    auto ko = p.ml ? (v4 ? k_fw_output<true, 4> : k_fw_output<true, 1>) : (v4 ? k_fw_output<false, 4> : k_fw_output<false, 1>);
     if (lds > 64 * 1024)
-      MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_fw_output<true>),
-                                    hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-    if (p.ml)
-      hipLaunchKernelGGL(k_fw_output<true>, dim3(g), dim3(kFT), lds, s, m, n, p.nH, levels, D, ldd, bits, p.nw,
-                         zbuf[zcur], p.ldz, taps, lamS, thr ? 1 : 0, L, n, S, n);
-    else
-      hipLaunchKernelGGL(k_fw_output<false>, dim3(g), dim3(kFT), 0, s, m, n, p.nH, levels, D, ldd, bits, p.nw,
-                         nullptr, 0, nullptr, lamS, thr ? 1 : 0, L, n, S, n);
+      MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(ko), hipFuncAttributeMaxDynamicSharedMemorySize,
+                                    (int)lds));
+    hipLaunchKernelGGL(ko, dim3(g), dim3(kFT), lds, s, m, n, p.nH, levels, D, ldd, bits, p.nw, zc, p.ldz, taps, lamS,
+                       thr ? 1 : 0, L, n, S, n);
     MLPCP_HIP(hipGetLastError());
     MLPCP_HIP(hipStreamSynchronize(s));
     prof_drain();
