@@ -221,7 +221,7 @@ int mlpcp_ialm_step_vjp(int m, int n, int levels, const float* D, int ldd, const
  *  lam_L, lam_S > 0 (the arithmetic uses these float values).
  *  levels  0 = FW-T (power iteration for the top pair, n <= 8192 with
  *          16-byte-aligned D and L and ldd % 4 == 0, else n <= 2048);
- *          > 0 = ML-FWT, n_H <= 64.  Other shapes: MLPCP_E_UNSUPPORTED.
+ *          > 0 = ML-FWT, n_H <= 64, n <= 8192.  Other shapes: MLPCP_E_UNSUPPORTED.
  *  L, S outputs m x n (ld = n): the last iterate; S is zero off Q.
  *  ws   device workspace >= mlpcp_fwt_workspace_bytes(m, n, levels, Q != NULL),
  *       or NULL (allocated and freed inside).

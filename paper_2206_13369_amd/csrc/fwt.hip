@@ -422,26 +422,38 @@ __global__ void __launch_bounds__(kFT) k_fw_pass_ml(PassML a) {
       const float* drow = sD + (size_t)tr * a.n;
       const uint32_t* qrow = sQ + (size_t)tr * a.nw;
       const int len = ch.j1 - ch.j0;
-      float p0 = 0.0f, ps = 0.0f;
+      // within the chunk w0(t) = wb + ws t, so L(t) = l0 + t dl is affine too, and
+      // sum w0 G = wb sum G + ws sum t G
+      const float dz = z0 - z1;
+      const float l0 = fmaf(ch.wb, dz, z1), dl = ch.ws * dz;
+      // the chunk's mask bits (chunks are at most 32 long): bit t = entry j0 + t
+      uint32_t qb = 0xFFFFFFFFu;
+      if (MASKED) {
+        const int w = ch.j0 >> 5;
+        const uint32_t lo = qrow[w], hi = w + 1 < a.nw ? qrow[w + 1] : 0u;
+        qb = (uint32_t)((((uint64_t)hi << 32) | lo) >> (ch.j0 & 31));
+      }
+      if (len < 32) qb &= (1u << len) - 1u;
+      float ps = 0.0f, ptg = 0.0f;
       RunSums<!THR> rs;     // after the first step |G| <= lam_S: the l1 gate is closed
       // a uniform trip count (the longest chunk), predicated in groups of four
       for (int t0 = 0; t0 < a.maxlen; t0 += 4) {
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
           const int t = t0 + u;
-          const bool valid = t < len;
-          const int j = valid ? ch.j0 + t : ch.j0;
+          const float tf = (float)t;
+          const bool q = (qb >> t) & 1u;                       // 0 past the chunk's end
+          const int j = ch.j0 + min(t, len - 1);               // a column of the chunk
           const float d = drow[j];
-          const bool q = valid && (MASKED ? ((qrow[j >> 5] >> (j & 31)) & 1u) : true);
-          const float w0 = fmaf(ch.ws, (float)t, ch.wb);      // affine within the chunk
-          const float l = fmaf(1.0f - w0, z1, w0 * z0);       // = lift (z1 = 0 past the last column)
+          const float l = fmaf(tf, dl, l0);
           float sv, gv;
           entry<THR>(d, l, q, a.lamS, sv, gv);
           rs.add(sv, gv, j);
-          p0 = fmaf(w0, gv, p0);
           ps += gv;
+          ptg = fmaf(tf, gv, ptg);
         }
       }
+      const float p0 = fmaf(ch.wb, ps, ch.ws * ptg);
       rs.fold(sm, (long long)i * a.n);
       sp0[tr * a.K + tk] = p0;
       sp1[tr * a.K + tk] = ps - p0;
@@ -1210,8 +1222,8 @@ int fw_tables(int n, int levels, int nH, FwTables& t) {
     return cnt;
   };
   int L = kChunkMin;
-  while (count(L) > kFT && L < n) ++L;
-  if (count(L) > kFT) return MLPCP_E_UNSUPPORTED;
+  while (count(L) > kFT && L < 32) ++L;
+  if (count(L) > kFT) return MLPCP_E_UNSUPPORTED;   // rows wider than 256 chunks of 32
   t.chunks.clear();
   t.maxlen = 0;
   t.kfirst.assign(nH + 1, 0);
