@@ -251,6 +251,12 @@ def main():
     dev = torch.device("cuda:0")
     if a.workload.startswith("fw"):
         w = synth.fw_config(a.workload)
+        if a.calib_copy:
+            src = torch.ones(a.calib_copy << 18, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.mul(src, 1.0, out=dst)
+            torch.cuda.synchronize()
+            del src, dst
         fb = fw_bench(w, dev, a.steps, plain=not a.no_plain, cpu=not a.no_cpu)
         out = {
             "metric": "time to 1e-3 (s): multilevel FW-T (ML-FWT) vs FW-T, unconstrained CPCP, 1 MI355X",
