@@ -49,6 +49,9 @@ def parse():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "bf16x3"],
                     help="arithmetic of the coarse SVT's Gram and reconstruction products")
     ap.add_argument("--no-fw", action="store_true", help="skip the Frank-Wolfe summary of the default line")
+    ap.add_argument("--rnorm", type=int, default=0, choices=[0, 1, 2],
+                    help="restriction normalisation of the multilevel solve: 0 orthonormal, 1 P/||P||_2, 2 P "
+                         "(ablation; the plain solve is unaffected)")
     ap.add_argument("--calib-copy", type=int, default=0, metavar="MIB",
                     help="run one elementwise copy of MIB MiB (read MIB, write MIB) before the solves, "
                          "the reference kernel for scaling HBM byte counters")
@@ -284,7 +287,8 @@ def main():
     nH = mlp.coarse_dim(w.n, w.levels)
 
     def run(levels, ws):
-        kw = dict(levels=levels, tol=a.tol, max_iter=500, want_y=False, workspace=ws, history=600, prec=a.prec)
+        kw = dict(levels=levels, tol=a.tol, max_iter=500, want_y=False, workspace=ws, history=600, prec=a.prec,
+                  r_norm=a.rnorm if levels > 0 else 0)
         if Q is None:
             return mlp.pcp_solve(D, w.lam, w.mu0, **kw)
         return mlp.cpcp_solve(D, Q, w.lam, w.mu0, **kw)
@@ -408,6 +412,7 @@ def main():
         "vs_baseline": None,
         "dtype": "f32" if a.prec == "fp32" else a.prec + "/f32",
         "precision": {"mode": a.prec, "gram_bf16_iters": r.gram_bf16_iters, "gram_split_iters": r.gram_split_iters},
+        "restriction": ["orthonormal P (P^T P)^-1/2", "P / ||P||_2", "P"][a.rnorm],
         "data": "synthetic",
         "config": {"workload": describe(w)},
         "iters": iters,

@@ -87,7 +87,9 @@ typedef struct {
   double mu_max_factor;    /* mu_max = mu_max_factor * mu_0, >= 1             */
   int prec;                /* mlpcp_precision (other values: E_INVALID_ARG)   */
   int check_every;         /* FG check cadence; 1 is implemented              */
-  int r_norm;              /* restriction normalisation; 0 = orthonormal R    */
+  int r_norm;              /* restriction normalisation: 0 = R = P (P^T P)^{-1/2}  */
+                           /* (orthonormal), 1 = P / ||P||_2, 2 = P (the literal */
+                           /* interpolation operator; ablation of the reading)  */
 } mlpcp_opts;
 
 /* Per-solve report.  history (optional, caller host memory): if fg_history is

@@ -19,7 +19,9 @@ Readings (each also listed in the design notes):
 * Initial S, Y: inputs (Alg. 1 / Alg. 4 requirements); zero by default.
 * Stopping: the feasibility gap FG = ||P_Q(D - L - S)||_F / ||P_Q D||_F of the
   experiments section, tested after every iteration.
-* Restriction: the orthonormalised interpolation operator (see restriction.py).
+* Restriction: the orthonormalised interpolation operator (see restriction.py); any
+  other n x n_H operator can be passed as R (the literal interpolation operator for the
+  ablation of that reading).
 * Compressive (masked) form.  The paper states the constrained problem
   P_Q[L + S] = P_Q[D] but solves it only with Frank-Wolfe.  Reading: inexact
   ALM on  min ||L||_* + lam ||P_Q S||_1  s.t. L + S = P_Q D, where S is free
@@ -68,8 +70,8 @@ def ialm(D, lam: float, mu0: float, *, Q: Optional[np.ndarray] = None, levels: i
     fixed_iters: run exactly that many iterations, ignoring ``tol``.
     R: override the restriction (n x n_H); default is the orthonormalised
        interpolation operator for ``levels``.
-    keep_iterates: store (L, S, Y, Yhat, U_r, V_r, R-coarse data) per iteration in
-       the history, for invariant checks on small inputs.
+    keep_iterates: store (L, S, Y, Yhat, U_r, V_r, the coarse iterate L_H) per iteration
+       in the history, for invariant checks on small inputs.
     """
     D = np.asarray(D, dtype=np.float64)
     m, n = D.shape
@@ -96,6 +98,7 @@ def ialm(D, lam: float, mu0: float, *, Q: Optional[np.ndarray] = None, levels: i
         mu_k = mu
         # coarse data: D - S + Y/mu on Q, previous L off Q
         Mk = np.where(Qb, D - S + Y / mu_k, L)
+        LH = None
         if R is None:
             L_new, rank, sig = svt(Mk, 1.0 / mu_k)
             Ur = Vr = None
@@ -120,7 +123,7 @@ def ialm(D, lam: float, mu0: float, *, Q: Optional[np.ndarray] = None, levels: i
             if keep_iterates:
                 Yhat = Y + mu_k * (D - S - L_new)
                 h.update(L=L_new.copy(), S=S_new.copy(), Y=Y_new.copy(), Yprev=Y.copy(), Sprev=S.copy(),
-                         Yhat=Yhat, Ur=Ur, Vr=Vr)
+                         Yhat=Yhat, Ur=Ur, Vr=Vr, LH=None if LH is None else LH.copy())
             hist.append(h)
         L, S, Y = L_new, S_new, Y_new
         mu = min(rho * mu_k, mu_max)

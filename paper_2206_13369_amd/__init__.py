@@ -234,7 +234,7 @@ def _prec(p) -> int:
 
 
 def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
-           prec="fp32"):
+           prec="fp32", r_norm=0):
     torch = _torch()
     _check_dev(D, "D", torch.float32)
     if D.dim() != 2 or D.stride(1) != 1:
@@ -250,7 +250,7 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
             if not t.is_contiguous() or tuple(t.shape) != (m, n):
                 raise ValueError(f"{name} must be a contiguous m x n tensor")
     o = default_opts(levels=levels, tol=tol, max_iter=max_iter, rho=rho, mu_max_factor=mu_max_factor,
-                     prec=_prec(prec))
+                     prec=_prec(prec), r_norm=int(r_norm))
     wsb = workspace_bytes(m, n, o)
     if workspace is None:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
@@ -290,20 +290,22 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
 
 def pcp_solve(D, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
               rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
-              workspace=None, history: int = 0, prec="fp32") -> SolveResult:
+              workspace=None, history: int = 0, prec="fp32", r_norm: int = 0) -> SolveResult:
     """Robust PCA by (multilevel) inexact ALM; D is an m x n float32 tensor on the GPU.
-    prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products)."""
+    prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products).
+    r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P."""
     return _solve(D, None, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
-                  prec)
+                  prec, r_norm)
 
 
 def cpcp_solve(D, Q, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
                rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
-               workspace=None, history: int = 0, prec="fp32") -> SolveResult:
+               workspace=None, history: int = 0, prec="fp32", r_norm: int = 0) -> SolveResult:
     """Compressive PCP (constrained form) by masked (multilevel) inexact ALM; Q uint8 mask.
-    prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products)."""
+    prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products).
+    r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P."""
     return _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
-                  prec)
+                  prec, r_norm)
 
 
 def svt_prox(M, tau: float, levels: int = 0, workspace=None):

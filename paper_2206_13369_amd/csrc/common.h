@@ -60,9 +60,11 @@ struct Operator {
   double* C = nullptr;        // [nH * nH] (nullptr when levels == 0)
 };
 
-// Returns the cached operator for (n, levels) on the current device, building it on
-// first use (host stencil tables, then C on the GPU with the Jacobi eigensolver).
-int get_operator(int n, int levels, hipStream_t stream, const Operator** out);
+// Returns the cached operator for (n, levels, r_norm) on the current device, building it
+// on first use (host stencil tables, then C on the GPU with the Jacobi eigensolver).
+// r_norm 0: C = (P^T P)^{-1/2} (orthonormal R = P C); 1: C = I / ||P||_2; 2: C = I (the
+// literal interpolation operator).
+int get_operator(int n, int levels, hipStream_t stream, const Operator** out, int r_norm = 0);
 
 // Builds the composite interpolation stencil on the host (also used by host tests
 // through mlpcp_coarse_dim and by get_operator).

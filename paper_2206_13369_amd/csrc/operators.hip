@@ -141,7 +141,7 @@ int upload(const std::vector<T>& h, T** d) {
   return MLPCP_OK;
 }
 
-int build_operator(int n, int levels, hipStream_t stream, Operator* op) {
+int build_operator(int n, int levels, int r_norm, hipStream_t stream, Operator* op) {
   const int nH = coarse_dim_checked(n, levels);
   if (nH < 1) return MLPCP_E_LEVELS;
   op->n = n;
@@ -192,11 +192,26 @@ int build_operator(int n, int levels, hipStream_t stream, Operator* op) {
     st = MLPCP_E_HIP;
   int sweeps = 0;
   if (st == MLPCP_OK) st = eig_sym(nH, N, dA, dV, dlam, dperm, ews, stream, &sweeps, false);
-  if (st == MLPCP_OK) {
+  if (st == MLPCP_OK && r_norm == 0) {
     const size_t cnt = (size_t)nH * nH;
     hipLaunchKernelGGL(k_scale_cols_invsqrt, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, dV, dlam,
                        N, nH, dW);
     st = gemm_f64(false, true, nH, nH, nH, 1.0, dW, N, dV, N, op->C, nH, stream);
+  } else if (st == MLPCP_OK) {
+    // the literal interpolation operator: C = I / ||P||_2 (r_norm 1) or C = I (r_norm 2);
+    // ||P||_2^2 is the largest eigenvalue of P^T P
+    std::vector<double> hl(N, 0.0);
+    if (hipMemcpyAsync(hl.data(), dlam, (size_t)N * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
+        hipStreamSynchronize(stream) != hipSuccess) {
+      st = MLPCP_E_HIP;
+    } else {
+      double lmax = 0.0;
+      for (int i = 0; i < nH; ++i) lmax = std::max(lmax, hl[i]);
+      const double sc = r_norm == 1 ? 1.0 / std::sqrt(lmax) : 1.0;
+      std::vector<double> hc((size_t)nH * nH, 0.0);
+      for (int i = 0; i < nH; ++i) hc[(size_t)i * nH + i] = sc;
+      if (hipMemcpyAsync(op->C, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, stream) != hipSuccess) st = MLPCP_E_HIP;
+    }
   }
   if (st == MLPCP_OK && hipStreamSynchronize(stream) != hipSuccess) st = MLPCP_E_HIP;
   (void)hipFree(dA);
@@ -210,18 +225,19 @@ int build_operator(int n, int levels, hipStream_t stream, Operator* op) {
 
 }  // namespace
 
-int get_operator(int n, int levels, hipStream_t stream, const Operator** out) {
+int get_operator(int n, int levels, hipStream_t stream, const Operator** out, int r_norm) {
+  if (r_norm < 0 || r_norm > 2) return MLPCP_E_UNSUPPORTED;
   int dev = 0;
   MLPCP_HIP(hipGetDevice(&dev));
   std::lock_guard<std::mutex> lock(g_op_mutex);
-  auto key = std::make_tuple(dev, n, levels);
+  auto key = std::make_tuple(dev, n, levels * 4 + r_norm);
   auto it = g_ops.find(key);
   if (it != g_ops.end()) {
     *out = it->second.get();
     return MLPCP_OK;
   }
   std::unique_ptr<Operator, OpDeleter> op(new Operator());
-  const int st = build_operator(n, levels, stream, op.get());
+  const int st = build_operator(n, levels, r_norm, stream, op.get());
   if (st != MLPCP_OK) return st;
   *out = op.get();
   g_ops.emplace(key, std::move(op));

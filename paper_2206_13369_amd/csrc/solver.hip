@@ -860,7 +860,7 @@ int valid_opts(const mlpcp_opts& o) {
       !(o.mu_max_factor >= 1.0) || !std::isfinite(o.mu_max_factor))
     return MLPCP_E_INVALID_ARG;
   if (o.prec != MLPCP_FP32 && o.prec != MLPCP_BF16 && o.prec != MLPCP_BF16X3) return MLPCP_E_INVALID_ARG;
-  if (o.check_every != 1 || o.r_norm != 0) return MLPCP_E_UNSUPPORTED;
+  if (o.check_every != 1 || o.r_norm < 0 || o.r_norm > 2) return MLPCP_E_UNSUPPORTED;
   return MLPCP_OK;
 }
 
@@ -1010,7 +1010,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Operator* op = nullptr;
-  MLPCP_TRY(get_operator(n, o.levels, s, &op));
+  MLPCP_TRY(get_operator(n, o.levels, s, &op, o.r_norm));
   WS w;
   MLPCP_TRY(bind_workspace(p, ws, ws_bytes, w));
   float* mp[2] = {w.at<float>(p.off_mp0), w.at<float>(p.off_mp1)};

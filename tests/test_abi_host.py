@@ -81,7 +81,8 @@ def test_pcp_validation():
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(prec=3)) == mlp.MLPCP_E_INVALID_ARG
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(prec=-1)) == mlp.MLPCP_E_INVALID_ARG
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(check_every=3)) == mlp.MLPCP_E_UNSUPPORTED
-    assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(r_norm=1)) == mlp.MLPCP_E_UNSUPPORTED
+    assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(r_norm=3)) == mlp.MLPCP_E_UNSUPPORTED
+    assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(r_norm=-1)) == mlp.MLPCP_E_UNSUPPORTED
     assert _pcp(20, 10, 10, 0.1, 1.0, ws=FAKE, wsb=16) == mlp.MLPCP_E_WORKSPACE
 
 
