@@ -901,34 +901,45 @@ __global__ void __launch_bounds__(kTopThreads) k_coarse_top(int nH, const double
     sP[i][j] = sH[i][j] / trace;
   }
   __syncthreads();
-  // wave sums folded through LDS: two barriers per reduction
-  auto block_total = [&](double v) {
-    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o, 64);
+  // two wave sums folded through LDS together: two barriers per reduction
+  __shared__ double red2[2][kTopThreads / 64];
+  auto block_total2 = [&](double& v0, double& v1) {
+    for (int o = 32; o > 0; o >>= 1) {
+      v0 += __shfl_xor(v0, o, 64);
+      v1 += __shfl_xor(v1, o, 64);
+    }
     __syncthreads();
-    if ((tid & 63) == 0) red[tid >> 6] = v;
+    if ((tid & 63) == 0) {
+      red2[0][tid >> 6] = v0;
+      red2[1][tid >> 6] = v1;
+    }
     __syncthreads();
-    double t = 0.0;
-    for (int w = 0; w < kTopThreads / 64; ++w) t += red[w];
-    return t;
+    v0 = v1 = 0.0;
+    for (int w = 0; w < kTopThreads / 64; ++w) {
+      v0 += red2[0][w];
+      v1 += red2[1][w];
+    }
   };
+  // P holds H / trace(H) (trace 1).  Each squaring stores P P / t^2, t = trace(P), so the
+  // stored matrix is (P / t)^2 with trace in [1 / n_H, 1]; its trace and squared
+  // Frobenius norm come from the accumulators.  Rank one to rounding when
+  // ||P||_F^2 / trace(P)^2 >= 1 - 1e-13.
+  double t_cur = 1.0;
   for (int sq = 0; sq < kTopSquarings; ++sq) {
     mm64<false>(sP, sP, acc);
-    // trace(P P) from the accumulators (diagonal entries held by this lane), and P P
-    double t = 0.0;
+    __syncthreads();                       // every wave has read P before it is overwritten
+    const double inv = 1.0 / (t_cur * t_cur);
+    double tr = 0.0, f2 = 0.0;
     mm64_store(acc, [&](int i, int j, double v) {
-      sQ[i][j] = v;
-      if (i == j) t += v;
+      const double x = v * inv;
+      sP[i][j] = x;
+      f2 += x * x;
+      if (i == j) tr += x;
     });
-    const double tq = block_total(t);
-    double f2 = 0.0;
-    for (int it = tid; it < IN * IN; it += kTopThreads) {
-      const int i = it / IN, j = it % IN;
-      const double v = tq > 0.0 ? 0.5 * (sQ[i][j] + sQ[j][i]) / tq : 0.0;
-      sP[i][j] = v;
-      f2 += v * v;
-    }
-    const double fr = block_total(f2);
-    if (!(tq > 0.0) || 1.0 - fr <= 1e-13) break;
+    block_total2(tr, f2);
+    if (!(tr > 0.0)) break;
+    t_cur = tr;
+    if (1.0 - f2 / (tr * tr) <= 1e-13) break;
   }
   __syncthreads();
   // start: the column with the largest diagonal entry (ties: smallest index)

@@ -69,6 +69,8 @@ def _compare(r, ref, tol=1e-5, check_alpha=True):
     (530, 70, 2, 3, 0.6, True),      # n % 4 != 0: scalar path; odd coarse widths
     (640, 128, 3, 2, 1.0, False),    # fully observed (Q = NULL)
     (300, 300, 4, 3, 0.7, True),     # square
+    (1030, 128, 3, 1, 0.8, True),    # one level: two-column intervals, n_H = 64
+    (512, 255, 3, 2, 0.8, True),     # odd width on the scalar path, n_H = 64
 ])
 def test_ml_fixed_iterations(m, n, rank, levels, obs, masked):
     w = _small(m, n, rank, levels, obs, seed=m + n)
@@ -84,6 +86,7 @@ def test_ml_fixed_iterations(m, n, rank, levels, obs, masked):
     (600, 96, 3, 0.8, True),
     (410, 70, 2, 0.6, True),         # scalar path
     (500, 128, 3, 1.0, False),
+    (1100, 1002, 3, 0.8, True),      # wide, scalar path
 ])
 def test_plain_fixed_iterations(m, n, rank, obs, masked):
     w = _small(m, n, rank, 0, obs, seed=m + 2 * n)
@@ -114,6 +117,16 @@ def test_full_fw1_multilevel_to_tolerance():
     say("fw1 full", w.D.shape, "levels", w.levels, "to 1e-3")
     r = _gpu(w, w.levels)
     ref = _ora(w, w.levels)
+    _compare(r, ref)
+
+
+def test_wide_rows_longest_chunks():
+    # n = 8000 at 7 levels: 127-column intervals cut into chunks of 32, the most per row
+    w = _small(8000, 8000, 2, 7, 0.8, seed=23)
+    K = 3
+    say("ML-FWT 8000x8000 levels 7, K", K)
+    r = _gpu(w, 7, tol=1e-30, max_iter=K)
+    ref = _ora(w, 7, fixed=K)
     _compare(r, ref)
 
 
