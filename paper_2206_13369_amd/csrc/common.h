@@ -82,6 +82,15 @@ size_t eig_workspace_bytes(int N);
 // warm: V holds an orthogonal starting basis on entry (e.g. the previous eigenvectors,
 // identity on the padding); otherwise V is initialised to the identity.
 // sweeps_out receives the number of sweeps.  Synchronises `stream`.
+// cert_tau2 > 0 (N > kEigInner only): threshold certificate for an SVT at tau^2 =
+// cert_tau2 -- when, at the start of a sweep, every row's Gershgorin bound
+// sum_j |a_ij| lies below tau^2, all eigenvalues do and the iteration stops there (A,
+// V and lam as they stand; the SVT of such a matrix is zero).  For N >= 1024 also the
+// partial form: pairs of two rows certified at the start of a sweep are not rotated,
+// so the certified block (all its eigenvalues below tau^2) is left undiagonalised, its
+// diagonal entries in lam and its columns of V spanning that invariant subspace.
+// On return gb[i] (N doubles, caller's memory) holds the bound of each certified row
+// and -1 for the others (all -1 below N = 1024 unless every row is certified).
 // Per-iteration statistics written on the device, read by the host once per iteration.
 struct IterStats {
   double fg2;      // sum of squared residuals on Q
@@ -100,9 +109,12 @@ constexpr int kSweepsOnDevice = -100;
 // weights sw, T = C V_sorted diag(sw), Tt, and K = T T^T (if K is non-null); writes V,
 // lam (diagonal), perm, sw and the rank / margin / trace / sweeps fields of st.
 // Buffers are kEigInner x kEigInner with leading dimension ld (= kEigInner).
+// certify: the threshold certificate of eig_sym at tau^2 (a matrix whose rows all have
+// Gershgorin bounds below tau^2 is not diagonalised; the margin is then taken from
+// the bounds).
 int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V, bool warm, double tau,
-                     double* lam, int* perm, double* sw, double* T, double* Tt, double* K, IterStats* st,
-                     hipStream_t stream);
+                     bool certify, double* lam, int* perm, double* sw, double* T, double* Tt, double* K,
+                     IterStats* st, hipStream_t stream);
 
 // Top eigenpair of C G C (G: n_H x n_H float64 Gram, ld = kEigInner, n_H <= kEigInner;
 // C: n_H x n_H, ld = n_H, or null for the identity) in one workgroup: writes z = C x
@@ -110,7 +122,8 @@ int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V
 int coarse_top_small(int nH, const double* G, const double* C, double* z, double* lam, hipStream_t stream);
 
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws,
-            hipStream_t stream, int* sweeps_out, bool warm, int sweep_hint = 0);
+            hipStream_t stream, int* sweeps_out, bool warm, int sweep_hint = 0, double cert_tau2 = 0.0,
+            double* gb = nullptr);
 
 // ---- Gram (gram.hip) ---------------------------------------------------------------
 // G = A^T A for A m x k (float32, ld = lda, k <= kp, kp multiple of kPad), accumulated

@@ -19,6 +19,23 @@
 //    skipped, its factor marked as the identity.
 //  * Optional warm start: with V0 given, the iteration starts from A = V0^T A V0,
 //    V = V0 (the previous solver iteration's eigenvectors).
+//  * Optional threshold certificate (for the SVT, where only eigenvalues above a
+//    threshold tau^2 matter): at the start of every sweep the Gershgorin bound
+//    g_i = sum_j |a_ij| of every row is formed, and row i is certified if g_i < tau^2.
+//    - If every row is certified, every eigenvalue lies below tau^2, the SVT of the
+//      matrix is zero whatever its eigenvectors, and the iteration stops there.
+//    - Partial form (N >= kCertPartialMin): pairs of two certified indices are not
+//      rotated in the sweep, and convergence is declared when no other pair passes
+//      the rotation test, the certified set taken from the final matrix.  Then the
+//      certified principal block has all its eigenvalues below tau^2 (Gershgorin on
+//      that block) and its coupling to the rest is below the rotation threshold, so it
+//      maps to zero under the SVT whatever its basis; its diagonal entries (each below
+//      tau^2) are returned as they are.
+//    The partial form leaves work to later solves of a warm-started sequence (whose
+//    threshold falls, so indices leave the certified set); it pays where the outer
+//    rounds are bound by the number of tiles to update, which certified block pairs
+//    skip (wide matrices: more apply tiles than compute units), and not where they are
+//    bound by latency, where only the number of sweeps counts.
 //  Problems of width 64 are solved by one kernel directly.
 //  Rotation threshold (relative, Demmel-Veselic style, with an absolute floor for
 //  singular Grams and for the rounding the tile products leave): rotate (p,q) iff
@@ -48,6 +65,9 @@ constexpr double kRelEps2 = 1.0e-24;  // (1e-12)^2
 // resolution; it stops sweeps that would only refine eigenvectors of clusters of
 // tiny eigenvalues to their own relative precision.
 constexpr double kAbsTol = 1.0e-14;
+// Widths from which the threshold certificate takes its partial form: at N = 1024 an
+// outer round updates 120 + 256 tiles, more than the 256 compute units take at once.
+constexpr int kCertPartialMin = 1024;
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
@@ -142,6 +162,7 @@ __device__ __forceinline__ bool rotates(double app, double aqq, double apq, doub
 
 struct RotShared {
   double c[IB], s[IB], t[IB];
+  unsigned long long cert;   // bit l: local index l certified (partial certificate)
   int any;
 };
 
@@ -163,7 +184,9 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       int p, q;
       inner_pair(phase, s, tid, p, q);
       double c, sn, t;
-      const bool on = rotation_fast(A[p][p], A[q][q], A[p][q], floor_abs, c, sn, t);
+      // two certified indices: not rotated (an infinite floor fails the test)
+      const bool both = ((rs.cert >> p) & (rs.cert >> q) & 1ull) != 0;
+      const bool on = rotation_fast(A[p][p], A[q][q], A[p][q], both ? INFINITY : floor_abs, c, sn, t);
       rs.c[tid] = c;
       rs.s[tid] = sn;
       rs.t[tid] = t;
@@ -253,6 +276,7 @@ __global__ void __launch_bounds__(256) k_jacobi_direct(double* __restrict__ A, d
     sQ[i][j] = warm ? V[(size_t)i * N + j] : (i == j ? 1.0 : 0.0);
   }
   const double fl = floor_p[0];
+  if (threadIdx.x == 0) rs.cert = 0;
   int sweeps = 0;
   bool conv = false;
   for (; sweeps < max_sweeps; ++sweeps) {
@@ -284,7 +308,7 @@ __device__ __forceinline__ int pair_global(int l, int I, int J) { return l < IB 
 constexpr int kPairThreads = 1024;
 __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restrict__ A, int N, int nb, int round,
                                                       double* __restrict__ Qblk, const double* __restrict__ floor_p,
-                                                      const int* __restrict__ active) {
+                                                      const int* __restrict__ active, const double* __restrict__ gb) {
   __shared__ double sA[IN][LDS_LD];
   __shared__ double sQ[IN][LDS_LD];
   __shared__ RotShared rs;
@@ -305,16 +329,24 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
     sA[i][j] = ra[x];
     sQ[i][j] = (i == j) ? 1.0 : 0.0;
   }
-  if (threadIdx.x == 0) rs.any = 0;
+  if (threadIdx.x < 64) {   // wave 0: certified local indices (partial certificate)
+    const bool c = gb != nullptr && gb[pair_global(threadIdx.x, I, J)] >= 0.0;
+    const unsigned long long m = __ballot(c);
+    if (threadIdx.x == 0) {
+      rs.cert = m;
+      rs.any = 0;
+    }
+  }
   __syncthreads();
   const double fl = floor_p[0];
+  const unsigned long long cm = rs.cert;
   // nothing to rotate in this block pair (round 0: any pair; later rounds: the cross
   // pairs): leave A as it is and mark the factor as the identity, which the apply
   // step then neither reads nor applies
   int want = 0;
   for (int it = threadIdx.x; it < IN * IN; it += blockDim.x) {
     const int i = it / IN, j = it % IN;
-    const bool cand = round == 0 ? i < j : (i < IB && j >= IB);
+    const bool cand = (round == 0 ? i < j : (i < IB && j >= IB)) && !((cm >> i) & (cm >> j) & 1ull);
     if (cand && rotates(sA[i][i], sA[j][j], sA[i][j], fl)) want = 1;
   }
   if (!__syncthreads_or(want)) {
@@ -494,15 +526,18 @@ __device__ __forceinline__ void pair_at(int ne, int k, int r, int& p, int& q) {
 }
 
 // Jacobi sweeps on the leading ne x ne block of A (LDS), Q <- Q J, until the rotation
-// test passes for no pair (returns true) or max_sweeps sweeps ran.  ACTIVE threads
+// test passes for no pair (returns true) or max_sweeps sweeps ran.  cert_tau2 > 0: the
+// threshold certificate of the blocked solver (at the start of each sweep; when every
+// row's Gershgorin bound lies below cert_tau2 the sweeps stop with gbs[i] = the bound
+// of row i, otherwise gbs[i] = -1).  ACTIVE threads
 // take part in the rounds, each owning MT 2x2 tiles (pair a rows, pair b columns) and
 // MQ (row, pair) items of Q for the whole iteration; the pairs' indices per round
 // follow from the circle method arithmetically, so all loads of a round are issued
 // at once, without branches.  Slots beyond the item counts point at the padding
 // column IN of the thread's own lane row, which no result ever reads.
 template <int ACTIVE, int MT, int MQ>
-__device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, int max_sweeps, double* pc, double* ps,
-                             double* pt, int& sweeps) {
+__device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double cert_tau2, int max_sweeps, double* pc,
+                             double* ps, double* pt, double* gbs, int& sweeps) {
   constexpr int kPadCol = IN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int np = ne / 2;
@@ -523,6 +558,24 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, int max_
     qb_[x] = qv_[x] ? e % np : 0;
   }
   for (sweeps = 0;; ++sweeps) {
+    if (cert_tau2 > 0.0) {
+      // Gershgorin bound of each row: 16 threads per row (blockDim = 1024 covers 64 rows)
+      const int row = tid >> 4, sub = tid & 15;
+      double g = 0.0;
+      if (row < ne)
+        for (int c = sub; c < ne; c += 16) g += fabs(sA[row][c]);
+      g += __shfl_xor(g, 8);
+      g += __shfl_xor(g, 4);
+      g += __shfl_xor(g, 2);
+      g += __shfl_xor(g, 1);
+      const bool cert = g < cert_tau2 * (1.0 - 1.0e-12);   // padding rows (zero) pass
+      const bool all = __syncthreads_and(cert);
+      if (sub == 0) gbs[row] = (all && row < ne) ? g : -1.0;
+      if (all) {
+        __syncthreads();
+        return true;
+      }
+    }
     int want = 0;
     for (int it = tid; it < ne * ne; it += blockDim.x) {
       const int i = it / ne, j = it % ne;
@@ -594,7 +647,7 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, int max_
 
 __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, const double* __restrict__ G,
                                                       const double* __restrict__ C, double* __restrict__ V,
-                                                      int warm, double tau, int max_sweeps,
+                                                      int warm, double tau, int certify, int max_sweeps,
                                                       double* __restrict__ lam, int* __restrict__ perm,
                                                       double* __restrict__ sw, double* __restrict__ T,
                                                       double* __restrict__ Tt, double* __restrict__ K,
@@ -604,7 +657,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   LdsRow* sQ = sA + IN;
   LdsRow* sC = sQ + IN;
   LdsRow* sW = sC + IN;
-  __shared__ double pc[IB], ps[IB], pt[IB], swv[IN], red[kSmallThreads];
+  __shared__ double pc[IB], ps[IB], pt[IB], swv[IN], gbs[IN], red[kSmallThreads];
   __shared__ int prm[IN], redi[kSmallThreads];
   const int tid = threadIdx.x;
   const bool mm_on = tid < 256;   // the 64^3 products run on the first four waves
@@ -664,6 +717,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   }
   // absolute floor of the rotation test: kAbsTol trace
   red[tid] = tid < nH ? fabs(sA[tid][tid]) : 0.0;
+  if (tid < IN) gbs[tid] = -1.0;   // nothing certified unless the sweeps certify it
   __syncthreads();
   for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
     if (tid < w) red[tid] += red[tid + w];
@@ -673,12 +727,13 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   const int ne = nH + (nH & 1);
   int sweeps = 0;
   bool conv = false;
+  const double ct2 = certify ? tau * tau : 0.0;
   if (ne <= 16)
-    conv = small_sweeps<64, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+    conv = small_sweeps<64, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
   else if (ne <= 32)
-    conv = small_sweeps<256, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+    conv = small_sweeps<256, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
   else
-    conv = small_sweeps<kSmallThreads, 1, 2>(sA, sQ, ne, fl, max_sweeps, pc, ps, pt, sweeps);
+    conv = small_sweeps<kSmallThreads, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
   // eigenvalues, descending order (ties by index), weights, rank, margin, trace
   double li = 0.0;
   if (tid < IN) {
@@ -708,7 +763,9 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
     }
     swv[tid] = wk;
     sw[tid] = wk;
-    mg = fabs(sg - tau) / tau;
+    // a certified index enters through its bound: a lower bound on the distance
+    const double g = gbs[prm[tid]];
+    mg = g >= 0.0 ? (tau - sqrt(g)) / tau : fabs(sg - tau) / tau;
     trc = lk;
   } else if (tid < IN) {
     swv[tid] = 0.0;
@@ -775,15 +832,49 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   }
 }
 
-// flag = 1 if any pair (p < q) of A passes the rotation test
+// Threshold certificate of the sweep: gb[i] = sum_j |a_ij| (an upper bound on the
+// Gershgorin interval of row i, as a_ii <= |a_ii|) if that lies below tau2 (less a
+// relative 1e-12, so that rounding of the bound cannot reach tau2), else -1, and
+// *uncert = 1 if some row is not certified.  One wave per row.
+__global__ void __launch_bounds__(256) k_certify(const double* __restrict__ A, int N, double tau2,
+                                                 double* __restrict__ gb, int* __restrict__ uncert) {
+  const int row = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (row >= N) return;
+  const double* a = A + (size_t)row * N;
+  double s = 0.0;
+  for (int j = lane; j < N; j += 64) s += fabs(a[j]);
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) s += __shfl_xor(s, o);
+  if (lane == 0) {
+    const bool c = s < tau2 * (1.0 - 1.0e-12);
+    gb[row] = c ? s : -1.0;
+    if (!c) atomicOr(uncert, 1);
+  }
+}
+
+// after the sweeps (all-or-nothing form): a certificate that did not cover every row
+// is void
+__global__ void k_cert_finish(int N, const int* __restrict__ uncert, double* __restrict__ gb) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < N && *uncert) gb[i] = -1.0;
+}
+
+// flag = 1 if any pair (p < q) of A passes the rotation test, unless the threshold
+// certificate covers every row (uncert non-null and zero); with gb non-null (partial
+// certificate) pairs of two certified indices are not counted
 __global__ void __launch_bounds__(256) k_any_rotation(const double* __restrict__ A, int N,
-                                                      const double* __restrict__ floor_p, int* __restrict__ flag) {
+                                                      const double* __restrict__ floor_p,
+                                                      const int* __restrict__ uncert, const double* __restrict__ gb,
+                                                      int* __restrict__ flag) {
+  if (uncert != nullptr && *uncert == 0) return;
   const double fl = floor_p[0];
   int want = 0;
   const size_t total = (size_t)N * N;
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(idx / N), j = (int)(idx % N);
-    if (i < j && rotates(A[(size_t)i * N + i], A[(size_t)j * N + j], A[idx], fl)) want = 1;
+    if (i < j && !(gb != nullptr && gb[i] >= 0.0 && gb[j] >= 0.0) &&
+        rotates(A[(size_t)i * N + i], A[(size_t)j * N + j], A[idx], fl))
+      want = 1;
   }
   if (__syncthreads_or(want) && threadIdx.x == 0) atomicOr(flag, 1);
 }
@@ -827,15 +918,15 @@ __global__ void __launch_bounds__(256) k_rank(const double* __restrict__ lam, in
 }  // namespace
 
 int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V, bool warm, double tau,
-                     double* lam, int* perm, double* sw, double* T, double* Tt, double* K, IterStats* st,
-                     hipStream_t stream) {
+                     bool certify, double* lam, int* perm, double* sw, double* T, double* Tt, double* K,
+                     IterStats* st, hipStream_t stream) {
   if (nH < 1 || nH > IN || ld != IN) return MLPCP_E_INVALID_ARG;
   const size_t lds = (size_t)4 * IN * LDS_LD * sizeof(double);
   MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse_small),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
   ProfScope ps(KC_COARSE_SMALL, stream);
   hipLaunchKernelGGL(k_coarse_small, dim3(1), dim3(kSmallThreads), lds, stream, nH, ld, G, C, V, warm ? 1 : 0, tau,
-                     kMaxEigSweeps, lam, perm, sw, T, Tt, K, st);
+                     certify ? 1 : 0, kMaxEigSweeps, lam, perm, sw, T, Tt, K, st);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }
@@ -1005,7 +1096,10 @@ size_t eig_workspace_bytes(int N) {
 }
 
 int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws, hipStream_t stream,
-            int* sweeps_out, bool warm, int sweep_hint) {
+            int* sweeps_out, bool warm, int sweep_hint, double cert_tau2, double* gb) {
+  if (cert_tau2 > 0.0 && gb == nullptr) return MLPCP_E_INVALID_ARG;
+  if (!(cert_tau2 > 0.0)) gb = nullptr;
+  const bool partial = gb != nullptr && N >= kCertPartialMin;
   if (N % IN != 0 || n > N || n < 1) return MLPCP_E_INVALID_ARG;
   char* w = static_cast<char*>(ws);
   const int nb = N / IB;
@@ -1016,6 +1110,7 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
   w += align256((size_t)N * N * sizeof(double));
   double* floor_p = reinterpret_cast<double*>(w);
   int* flag = reinterpret_cast<int*>(w + 128);
+  int* uncert = reinterpret_cast<int*>(w + 132);   // cleared with flag (one 8-byte memset)
   int* dsweeps = reinterpret_cast<int*>(w + 192);
 
   {
@@ -1032,6 +1127,7 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
   }
   int sweeps = 0;
   if (N == IN) {
+    if (gb) return MLPCP_E_UNSUPPORTED;   // the certificate is not part of the direct solver
     {
       ProfScope ps(KC_JACOBI_PAIRS, stream);
       hipLaunchKernelGGL(k_jacobi_direct, dim3(1), dim3(256), 0, stream, A, V, N, floor_p, warm ? 1 : 0,
@@ -1056,17 +1152,20 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
     int hstate[2] = {0, 0};
     for (;;) {
       for (int b = 0; b < batch; ++b) {
-        MLPCP_HIP(hipMemsetAsync(active, 0, sizeof(int), stream));
+        MLPCP_HIP(hipMemsetAsync(active, 0, 2 * sizeof(int), stream));   // active, uncert
         {
           ProfScope ps(KC_JACOBI_MISC, stream);
-          hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, A, N, floor_p, active);
+          if (gb)
+            hipLaunchKernelGGL(k_certify, dim3((N + 3) / 4), dim3(256), 0, stream, A, N, cert_tau2, gb, uncert);
+          hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, A, N, floor_p, gb ? uncert : nullptr,
+                             partial ? gb : nullptr, active);
           hipLaunchKernelGGL(k_count_sweep, dim3(1), dim3(64), 0, stream, active, dsweeps);
         }
         for (int r = 0; r < nb - 1; ++r) {
           {
             ProfScope ps(KC_JACOBI_PAIRS, stream);
             hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, A, N, nb, r, Qblk,
-                               floor_p, active);
+                               floor_p, active, partial ? gb : nullptr);
           }
           {
             ProfScope ps(KC_JACOBI_APPLY, stream);
@@ -1090,6 +1189,10 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
       batch = 1;
     }
     if (!converged) return MLPCP_E_EIG;
+    if (gb && !partial) {
+      ProfScope ps(KC_JACOBI_MISC, stream);
+      hipLaunchKernelGGL(k_cert_finish, dim3((N + 255) / 256), dim3(256), 0, stream, N, uncert, gb);
+    }
   }
   {
     ProfScope ps(KC_JACOBI_MISC, stream);

@@ -124,10 +124,14 @@ __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM,
   if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
 }
 
-// sigma_k = sqrt(max(lam_perm[k], 0)), r = #{sigma > tau}, sw[k] = sqrt((sigma-tau)/sigma)
+// sigma_k = sqrt(max(lam_perm[k], 0)), r = #{sigma > tau}, sw[k] = sqrt((sigma-tau)/sigma).
+// gb (nullable): Gershgorin row bounds of the indices the eigensolver certified below
+// tau^2 (else -1); such an index enters the margin through its bound,
+// (tau - sqrt(gb)) / tau, a lower bound on the distance of the certified block's
+// singular values from tau.
 __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict__ lam, const int* __restrict__ perm,
-                                                       int nH, double tau, double* __restrict__ sw,
-                                                       IterStats* __restrict__ st) {
+                                                       int nH, double tau, const double* __restrict__ gb,
+                                                       double* __restrict__ sw, IterStats* __restrict__ st) {
   __shared__ int cnt[kThreads];
   __shared__ double mg[kThreads];
   __shared__ double tr[kThreads];
@@ -142,7 +146,8 @@ __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict_
     } else {
       sw[k] = 0.0;
     }
-    mgn = fmin(mgn, fabs(sg - tau) / tau);
+    const double g = gb != nullptr ? gb[perm[k]] : -1.0;
+    mgn = fmin(mgn, g >= 0.0 ? (tau - sqrt(g)) / tau : fabs(sg - tau) / tau);
   }
   cnt[threadIdx.x] = c;
   mg[threadIdx.x] = mgn;
@@ -703,7 +708,7 @@ struct Plan {
   // precision of the Gram (0 float64 products, 1 bfloat16, 2 split bfloat16) and of
   // the tall reconstruction N = M_P K (0 float32 MFMA, 2 split bfloat16)
   int gram_prec, recon_prec;
-  size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_perm, off_sw, off_T, off_Tt,
+  size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_gb, off_perm, off_sw, off_T, off_Tt,
       off_K, off_part, off_gram, off_eig, off_stats, total;
 };
 
@@ -819,6 +824,7 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
   p.off_tmp = take(p.plain ? 0 : nn * 8);
   p.off_V = take(nn * 8);
   p.off_lam = take((size_t)p.nHp * 8);
+  p.off_gb = take((size_t)p.nHp * 8);
   p.off_perm = take((size_t)p.nHp * 4);
   p.off_sw = take((size_t)p.nHp * 8);
   p.off_T = take(nn * 8);
@@ -865,8 +871,12 @@ int valid_opts(const mlpcp_opts& o) {
 }
 
 // One coarse SVT on M_P (buffer `mp`): Gram, C G C, eigensolve, weights, T.
+// certify: let the eigensolver leave undiagonalised what Gershgorin bounds put below
+// tau^2 (the whole matrix, whose SVT is then zero, or on wide matrices a block of it);
+// V and lam are then not the eigendecomposition, so callers that need it (the SVT's
+// derivative) pass false.
 int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, double tau, hipStream_t s,
-               int* sweeps, bool warm, int gram_prec = -1) {
+               int* sweeps, bool warm, bool certify, int gram_prec = -1) {
   if (gram_prec < 0) gram_prec = p.gram_prec;
   double* G = w.at<double>(p.off_G);
   double* V = w.at<double>(p.off_V);
@@ -880,7 +890,7 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   if (p.nHp == kEigInner) {
     // one workgroup from the Gram to the reconstruction factors; sweeps come back in st
     *sweeps = kSweepsOnDevice;
-    return coarse_svt_small(p.nH, p.nHp, G, p.plain ? nullptr : op.C, V, warm, tau, lam, perm, sw, T, Tt,
+    return coarse_svt_small(p.nH, p.nHp, G, p.plain ? nullptr : op.C, V, warm, tau, certify, lam, perm, sw, T, Tt,
                             p.tall ? w.at<double>(p.off_K) : nullptr, st, s);
   }
   double* GH = G;
@@ -892,9 +902,11 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
   }
   // the previous eigensolve's sweep count (in *sweeps on entry) sizes the first batch
-  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps, warm, warm ? *sweeps : 0));
+  double* gb = certify ? w.at<double>(p.off_gb) : nullptr;
+  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps, warm, warm ? *sweeps : 0,
+                    certify ? tau * tau : 0.0, gb));
   ProfScope ps(KC_SVT, s);
-  hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, sw, st);
+  hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, gb, sw, st);
   const size_t tot = (size_t)p.nH * p.nH;
   if (p.plain)
     hipLaunchKernelGGL(k_build_T<true>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op.C, V, perm, sw,
@@ -1044,7 +1056,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     const int gp = gram_prec_for(o.prec, 1.0 / mu, trace_prev, m, p.nH);
     bf16_iters += gp == 1;
     split_iters += gp == 2;
-    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0, gp));
+    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0, true, gp));
     EpiArgs a{};
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
@@ -1321,7 +1333,7 @@ int step_forward_core(const StepPlan& sp, const Operator& op, const WS& w, const
   if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
   MLPCP_TRY(launch_init(p, op, D, ldd, nullptr, S, Y, (float)(1.0 / mu), mp, nullptr, s));
   int sweeps = 0;
-  MLPCP_TRY(coarse_svt(p, op, w, mp, 1.0 / mu, s, &sweeps, false));
+  MLPCP_TRY(coarse_svt(p, op, w, mp, 1.0 / mu, s, &sweeps, false, false));
   EpiArgs a{};
   a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
   a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
@@ -1391,7 +1403,7 @@ int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
   if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
   MLPCP_TRY(launch_init(p, *op, M, ldm, nullptr, nullptr, nullptr, 0.0f, mp, nullptr, s));
   int sweeps = 0;
-  MLPCP_TRY(coarse_svt(p, *op, w, mp, (double)tau, s, &sweeps, false));
+  MLPCP_TRY(coarse_svt(p, *op, w, mp, (double)tau, s, &sweeps, false, true));
   EpiArgs a{};
   a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
   a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);

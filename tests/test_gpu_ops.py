@@ -50,7 +50,8 @@ def test_restrict_prolong(m, n, levels):
 
 @pytest.mark.parametrize("m,n,levels,rank", [(50, 20, 0, 3), (120, 64, 0, 5), (300, 300, 2, 10), (500, 100, 0, 8),
                                              (400, 200, 4, 6), (257, 250, 1, 12), (90, 33, 0, 4),
-                                             (700, 520, 0, 12), (2000, 2000, 3, 30)])
+                                             (700, 520, 0, 12), (2000, 2000, 3, 30),
+                                             (1200, 1100, 0, 12)])   # width >= 1024: partial certificate
 def test_svt_prox_matches_oracle(m, n, levels, rank):
     say("svt_prox", m, n, levels, rank)
     rng = np.random.default_rng(m * 7 + n)
@@ -72,3 +73,22 @@ def test_svt_prox_thresholds_everything():
     M = rng.normal(size=(80, 40)).astype(np.float32)
     L, r = mlp.svt_prox(to_dev(M), 1e6, 1)
     assert r == 0 and not to_np(L).any()
+
+
+@pytest.mark.parametrize("m,n,tau,levels", [(600, 520, 1e6, 0), (600, 520, 1e6, 2), (600, 520, 1e-3, 0),
+                                             (600, 520, 1e-3, 2), (1100, 1030, 1e6, 0), (1100, 1030, 1e-3, 0)])
+def test_svt_prox_blocked_extremes(m, n, tau, levels):
+    # widths above 64 take the blocked eigensolver: a threshold above the whole spectrum
+    # certifies every index at once (no sweep, rank 0); one below it certifies none
+    # (width 1030 pads to 1088, where the certificate also takes its partial form)
+    say("svt_prox extremes", m, n, tau, levels)
+    rng = np.random.default_rng(17 + levels + n)
+    M = rng.normal(size=(m, n)).astype(np.float32)
+    L, r = mlp.svt_prox(to_dev(M), tau, levels)
+    Lref, rref = oracle.svt_prox(M.astype(np.float64), tau, levels)
+    assert r == rref
+    if rref == 0:
+        assert not to_np(L).any()
+    else:
+        assert rref == oracle.restrict(M.astype(np.float64), levels).shape[1]   # full coarse rank
+        assert rel(to_np(L), Lref) < 1e-5
