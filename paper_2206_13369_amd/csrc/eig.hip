@@ -161,7 +161,8 @@ __device__ __forceinline__ bool rotates(double app, double aqq, double apq, doub
 }
 
 struct RotShared {
-  double c[IB], s[IB], t[IB];
+  double2 cs[IB];            // (c, s) of each rotation of the round
+  double t[IB];
   unsigned long long cert;   // bit l: local index l certified (partial certificate)
   int any;
 };
@@ -187,8 +188,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       // two certified indices: not rotated (an infinite floor fails the test)
       const bool both = ((rs.cert >> p) & (rs.cert >> q) & 1ull) != 0;
       const bool on = rotation_fast(A[p][p], A[q][q], A[p][q], both ? INFINITY : floor_abs, c, sn, t);
-      rs.c[tid] = c;
-      rs.s[tid] = sn;
+      rs.cs[tid] = make_double2(c, sn);
       rs.t[tid] = t;
       if (on) rs.any = 1;
     }
@@ -198,7 +198,8 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       const int a = tid / (IB / NT);
       int pa, qa;
       inner_pair(phase, s, a, pa, qa);
-      const double ca = rs.c[a], sa = rs.s[a], ta = rs.t[a];
+      const double2 pa_ = rs.cs[a];
+      const double ca = pa_.x, sa = pa_.y, ta = rs.t[a];
       int pb[NT], qb[NT];
       double cb[NT], sb[NT];
       double t00[NT], t01[NT], t10[NT], t11[NT];
@@ -206,7 +207,8 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       for (int x = 0; x < NT; ++x) {
         const int b = (tid % (IB / NT)) * NT + x;
         inner_pair(phase, s, b, pb[x], qb[x]);
-        cb[x] = rs.c[b]; sb[x] = rs.s[b];
+        const double2 pb_ = rs.cs[b];
+        cb[x] = pb_.x; sb[x] = pb_.y;
         t00[x] = A[pa][pb[x]]; t01[x] = A[pa][qb[x]];
         t10[x] = A[qa][pb[x]]; t11[x] = A[qa][qb[x]];
       }
@@ -214,7 +216,8 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       const int bq = tid % IB;
       int qp, qq;
       inner_pair(phase, s, bq, qp, qq);
-      const double qc = rs.c[bq], qs = rs.s[bq];
+      const double2 pq_ = rs.cs[bq];
+      const double qc = pq_.x, qs = pq_.y;
       double qx[NQ], qy[NQ];
 #pragma unroll
       for (int x = 0; x < NQ; ++x) {
@@ -247,6 +250,86 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
     }
     __syncthreads();
   }
+}
+
+// Phase 1 (the cross pairs (i, b + (i+s) mod b), b rounds) with the 2x2 tiles and the
+// factor items in registers, for IB * IB threads.  Thread (d, c) = (tid / IB, tid % IB)
+// holds, in round s, the tile of rows (a, IB + (a+s) mod IB) x columns
+// (c, IB + (c+s) mod IB) of A, a = (d + c) mod IB (a skewed layout: the diagonal
+// tiles a = c, whose threads compute the rotations, are the first 32 lanes of wave 0,
+// and the other waves only apply them), and, for the rows i in {d, IB + d}, the factor
+// entries Q[i][c] and Q[i][IB + (c+s) mod IB].  From one round to the next only the
+// J-side indices move, by one position: the tile's J x J entry comes from tile
+// (a+1, c+1) = thread (d, c+1) and the factor's J column from (d, c+1) (the same
+// wave: lane shuffles); the tile's J column comes from tile (a, c+1) = thread
+// (d-1, c+1) and its J row from tile (a+1, c) = thread (d+1, c) (through LDS).  The
+// arithmetic is that of inner_phase; A and Q enter and leave in LDS (A serves as the
+// exchange buffer in between).
+__device__ __forceinline__ void cross_phase_regs(double (*A)[LDS_LD], double (*Q)[LDS_LD], double floor_abs,
+                                                 RotShared& rs) {
+  static_assert(IB == 32 && IN == 64, "lane arithmetic assumes 32 pairs, two tile rows per wave");
+  const int tid = threadIdx.x, d = tid / IB, c = tid % IB;
+  const int a = (d + c) & (IB - 1);
+  const int lane = tid & 63;
+  const int src = (lane & IB) | ((lane + 1) & (IB - 1));   // thread (d, c+1), same wave
+  const bool diag = d == 0;
+  double t00 = A[a][c], t01 = A[a][IB + c], t10 = A[IB + a][c], t11 = A[IB + a][IB + c];
+  double qx0 = Q[d][c], qy0 = Q[d][IB + c], qx1 = Q[IB + d][c], qy1 = Q[IB + d][IB + c];
+  const unsigned long long cm = rs.cert;
+  __syncthreads();   // A now serves as the exchange buffer
+  double* x01 = &A[0][0];        // IB x IB by thread: the tiles' J-column entries
+  double* x10 = x01 + IB * IB;   // IB x IB by thread: the tiles' J-row entries
+  const int from01 = ((d + IB - 1) & (IB - 1)) * IB + ((c + 1) & (IB - 1));
+  const int from10 = ((d + 1) & (IB - 1)) * IB + c;
+  for (int s = 0;; ++s) {
+    double tt = 0.0;
+    if (diag) {   // wave 0, lanes 0..31: rotation c from the diagonal tile (a = c)
+      double cc, sn;
+      const int q = IB + ((c + s) & (IB - 1));
+      // two certified indices: not rotated (an infinite floor fails the test)
+      const bool both = ((cm >> c) & (cm >> q) & 1ull) != 0;
+      if (rotation_fast(t00, t11, t01, both ? INFINITY : floor_abs, cc, sn, tt)) rs.any = 1;
+      rs.cs[c] = make_double2(cc, sn);
+    }
+    __syncthreads();
+    const double2 pa = rs.cs[a], pb = rs.cs[c];
+    const double ca = pa.x, sa = pa.y, cb = pb.x, sb = pb.y;
+    const double u00 = ca * t00 - sa * t10, u01 = ca * t01 - sa * t11;
+    const double u10 = sa * t00 + ca * t10, u11 = sa * t01 + ca * t11;
+    double n00 = u00 * cb - u01 * sb, n01 = u00 * sb + u01 * cb;
+    double n10 = u10 * cb - u11 * sb, n11 = u10 * sb + u11 * cb;
+    if (diag) {   // diagonal 2x2 tile: exact form of the annihilation
+      n00 = t00 - tt * t01;
+      n11 = t11 + tt * t01;
+      n01 = tt != 0.0 ? 0.0 : t01;
+      n10 = n01;
+    }
+    const double m0 = cb * qx0 - sb * qy0, w0 = sb * qx0 + cb * qy0;
+    const double m1 = cb * qx1 - sb * qy1, w1 = sb * qx1 + cb * qy1;
+    t00 = n00;
+    qx0 = m0;
+    qx1 = m1;
+    if (s == IB - 1) {
+      t01 = n01; t10 = n10; t11 = n11;
+      qy0 = w0; qy1 = w1;
+      break;
+    }
+    x01[tid] = n01;
+    x10[tid] = n10;
+    t11 = __shfl(n11, src);
+    qy0 = __shfl(w0, src);
+    qy1 = __shfl(w1, src);
+    __syncthreads();
+    t01 = x01[from01];
+    t10 = x10[from10];
+  }
+  __syncthreads();   // exchange reads done: A and Q take the result (positions of round IB - 1)
+  const int qa = IB + ((a + IB - 1) & (IB - 1)), qc = IB + ((c + IB - 1) & (IB - 1));
+  A[a][c] = t00; A[a][qc] = t01;
+  A[qa][c] = t10; A[qa][qc] = t11;
+  Q[d][c] = qx0; Q[d][qc] = qy0;
+  Q[IB + d][c] = qx1; Q[IB + d][qc] = qy1;
+  __syncthreads();
 }
 
 // trace(A) -> floor = kAbsTol * |trace| (one block)
@@ -306,6 +389,7 @@ __device__ __forceinline__ int pair_global(int l, int I, int J) { return l < IB 
 // kPairThreads threads: a round is bound by LDS latency, which sixteen waves hide
 // better than four (one 2x2 tile and two factor items per thread).
 constexpr int kPairThreads = 1024;
+static_assert(kPairThreads == IB * IB, "the cross phase keeps one 2x2 tile per thread");
 __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restrict__ A, int N, int nb, int round,
                                                       double* __restrict__ Qblk, const double* __restrict__ floor_p,
                                                       const int* __restrict__ active, const double* __restrict__ gb) {
@@ -354,7 +438,7 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
     return;
   }
   if (round == 0) inner_phase<kPairThreads>(sA, sQ, 0, fl, rs);
-  inner_phase<kPairThreads>(sA, sQ, 1, fl, rs);
+  cross_phase_regs(sA, sQ, fl, rs);
   // the rotated 2b x 2b block goes straight back (annihilated entries stay exactly 0;
   // the apply step skips these diagonal tiles), and Q_pair to the workspace
   double* Qo = Qblk + (size_t)blockIdx.x * (IN * IN + 1);
