@@ -43,6 +43,8 @@
 #include "common.h"
 #include "profile.h"
 
+#include <hip/hip_ext.h>
+
 #include <algorithm>
 #include <cmath>
 
@@ -1008,9 +1010,9 @@ int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V
   const size_t lds = (size_t)4 * IN * LDS_LD * sizeof(double);
   MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(k_coarse_small),
                                 hipFuncAttributeMaxDynamicSharedMemorySize, (int)lds));
-  ProfScope ps(KC_COARSE_SMALL, stream);
-  hipLaunchKernelGGL(k_coarse_small, dim3(1), dim3(kSmallThreads), lds, stream, nH, ld, G, C, V, warm ? 1 : 0, tau,
-                     certify ? 1 : 0, kMaxEigSweeps, lam, perm, sw, T, Tt, K, st);
+  ProfKernel pk(KC_COARSE_SMALL);
+  hipExtLaunchKernelGGL(k_coarse_small, dim3(1), dim3(kSmallThreads), lds, stream, pk.start, pk.stop, 0, nH, ld, G,
+                        C, V, warm ? 1 : 0, tau, certify ? 1 : 0, kMaxEigSweeps, lam, perm, sw, T, Tt, K, st);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }
@@ -1247,14 +1249,14 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
         }
         for (int r = 0; r < nb - 1; ++r) {
           {
-            ProfScope ps(KC_JACOBI_PAIRS, stream);
-            hipLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, A, N, nb, r, Qblk,
-                               floor_p, active, partial ? gb : nullptr);
+            ProfKernel pk(KC_JACOBI_PAIRS);
+            hipExtLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, pk.start, pk.stop, 0,
+                                  A, N, nb, r, Qblk, floor_p, active, partial ? gb : nullptr);
           }
           {
-            ProfScope ps(KC_JACOBI_APPLY, stream);
-            hipLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, A, V, N, nb, r, Qblk,
-                               active);
+            ProfKernel pk(KC_JACOBI_APPLY);
+            hipExtLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, pk.start, pk.stop, 0,
+                                  A, V, N, nb, r, Qblk, active);
           }
         }
       }

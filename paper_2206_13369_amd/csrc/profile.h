@@ -37,4 +37,14 @@ struct ProfScope {
   ~ProfScope() { prof_end(cls, s); }
 };
 
+// Events for one kernel of class cls launched by hipExtLaunchKernelGGL, which records
+// them at the kernel's own start and end (the dispatch gap that events recorded
+// around a launch take in stays out); both null when the class is not being timed.
+struct ProfKernel {
+  int cls;
+  hipEvent_t start = nullptr, stop = nullptr;
+  explicit ProfKernel(int c);
+  ~ProfKernel();   // queues the pair for accumulation
+};
+
 }  // namespace mlpcp

@@ -63,6 +63,24 @@ void prof_end(int cls, hipStream_t s) {
   t_cls = -1;
 }
 
+ProfKernel::ProfKernel(int c) : cls(c) {
+  if (!((g_mask.load(std::memory_order_relaxed) >> cls) & 1)) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  start = get_event();
+  stop = get_event();
+  if (!start || !stop) {
+    if (start) g_pool.push_back(start);
+    if (stop) g_pool.push_back(stop);
+    start = stop = nullptr;
+  }
+}
+
+ProfKernel::~ProfKernel() {
+  if (!start) return;
+  std::lock_guard<std::mutex> lk(g_mu);
+  g_pending.push_back({cls, start, stop});
+}
+
 void prof_drain() {
   if (!g_mask.load(std::memory_order_relaxed)) return;
   std::lock_guard<std::mutex> lk(g_mu);
