@@ -392,13 +392,24 @@ __device__ __forceinline__ int pair_global(int l, int I, int J) { return l < IB 
 // better than four (one 2x2 tile and two factor items per thread).
 constexpr int kPairThreads = 1024;
 static_assert(kPairThreads == IB * IB, "the cross phase keeps one 2x2 tile per thread");
-__global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restrict__ A, int N, int nb, int round,
-                                                      double* __restrict__ Qblk, const double* __restrict__ floor_p,
+// A and Aout: the matrix before and after the round (the same buffer, or, with the
+// split apply step, the two buffers it alternates between; then this kernel writes
+// the pair blocks of Aout, and on a round the pre-test disabled it copies all of A).
+__global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(const double* A, double* Aout, int N, int nb,
+                                                      int round, double* __restrict__ Qblk,
+                                                      const double* __restrict__ floor_p,
                                                       const int* __restrict__ active, const double* __restrict__ gb) {
   __shared__ double sA[IN][LDS_LD];
   __shared__ double sQ[IN][LDS_LD];
   __shared__ RotShared rs;
-  if (!*active) return;   // the sweep's pre-test found nothing to rotate
+  if (!*active) {   // the sweep's pre-test found nothing to rotate
+    if (Aout != A) {
+      const size_t nn = (size_t)N * N;
+      for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < nn; e += (size_t)gridDim.x * blockDim.x)
+        Aout[e] = A[e];
+    }
+    return;
+  }
   int I, J;
   rr_pair(blockIdx.x, round, nb, I, J);
   constexpr int PER = IN * IN / kPairThreads;
@@ -437,6 +448,13 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
   }
   if (!__syncthreads_or(want)) {
     if (threadIdx.x == 0) Qblk[(size_t)blockIdx.x * (IN * IN + 1) + IN * IN] = 0.0;
+    if (Aout != A) {
+#pragma unroll
+      for (int x = 0; x < PER; ++x) {
+        const int it = threadIdx.x + kPairThreads * x;
+        Aout[(size_t)pair_global(it / IN, I, J) * N + pair_global(it % IN, I, J)] = ra[x];
+      }
+    }
     return;
   }
   if (round == 0) inner_phase<kPairThreads>(sA, sQ, 0, fl, rs);
@@ -449,7 +467,7 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(double* __restric
     const int it = threadIdx.x + kPairThreads * x;
     const int i = it / IN, j = it % IN;
     Qo[it] = sQ[i][j];
-    A[(size_t)pair_global(i, I, J) * N + pair_global(j, I, J)] = sA[i][j];
+    Aout[(size_t)pair_global(i, I, J) * N + pair_global(j, I, J)] = sA[i][j];
   }
   if (threadIdx.x == 0) Qo[IN * IN] = rs.any ? 1.0 : 0.0;   // per-pair "rotated" marker
 }
@@ -580,6 +598,152 @@ __global__ void __launch_bounds__(256) k_jacobi_apply(double* __restrict__ A, do
     __syncthreads();
     mm64<false>(sT, sQ, acc);
     mm64_store(acc, [&](int i, int j, double v) { V[(size_t)(rb * IN + i) * N + pair_global(j, Ib, Jb)] = v; });
+  }
+}
+
+// Outer round, step 2, for few tiles (N <= kSplitApplyMax): the same transformation
+// spread over four blocks per tile, A out of place (A -> Aout), V in place.
+//  * Off-diagonal tile pair (a < b), quadrant (hi, hj) of 32 x 32:
+//      T'[hi, hj] = (Qa[:, hi]^T T) Qb[:, hj]   (T the whole 64 x 64 tile of A),
+//    written to Aout at the tile's and at the mirrored position; a tile whose two
+//    factors are the identity is copied.  Reading A and writing Aout keeps the four
+//    blocks of a tile free of races.
+//  * V tile (64-row chunk rb, pair b), quarter of 16 rows: V[rows, Pb] <- V[rows, Pb] Qb
+//    (rows are independent, so in place).
+// Each block does 0.75 (tile) or 0.25 (V) of a 64^3 product instead of 2 or 1: these
+// rounds are few tiles on a 256-CU chip, bound by one CU's MFMA time per tile.
+constexpr int kSplitApplyMax = 512;
+__global__ void __launch_bounds__(256) k_jacobi_apply_split(const double* __restrict__ A, double* __restrict__ Aout,
+                                                            double* __restrict__ V, int N, int nb, int round,
+                                                            const double* __restrict__ Qblk,
+                                                            const int* __restrict__ active) {
+  __shared__ double sT[IN][LDS_LD];        // A tile, or the 16 V rows
+  __shared__ double sQ[IN][LDS_LD];        // V: Qb; A tile: Qa[:, hi] in columns 0..31, Qb[:, hj] in 32..63
+  __shared__ double sU[IB][LDS_LD];        // Qa[:, hi]^T T
+  if (!*active) return;                    // the pair kernel copied A to Aout
+  const int npairs = nb / 2;
+  const int ntri = npairs * (npairs - 1) / 2;
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int li = lane & 15, lk = lane >> 4;
+  int bid = blockIdx.x;
+  if (bid < 4 * ntri) {
+    const int quad = bid & 3, hi = quad >> 1, hj = quad & 1;
+    int a = 0, rem = bid >> 2;   // strictly upper pairs (a < b), row by row
+    while (rem >= npairs - 1 - a) {
+      rem -= npairs - 1 - a;
+      ++a;
+    }
+    const int b = a + 1 + rem;
+    const double* Qa = Qblk + (size_t)a * (IN * IN + 1);
+    const double* Qb = Qblk + (size_t)b * (IN * IN + 1);
+    int Ia, Ja, Ib, Jb;
+    rr_pair(a, round, nb, Ia, Ja);
+    rr_pair(b, round, nb, Ib, Jb);
+    // all global loads up front: the tile, both factor halves and the markers
+    constexpr int PT = IN * IN / 256, PQ = IN * IB / 256;
+    double rt[PT], rqa[PQ], rqb[PQ];
+#pragma unroll
+    for (int x = 0; x < PT; ++x) {
+      const int it = tid + 256 * x;
+      rt[x] = A[(size_t)pair_global(it / IN, Ia, Ja) * N + pair_global(it % IN, Ib, Jb)];
+    }
+#pragma unroll
+    for (int x = 0; x < PQ; ++x) {
+      const int it = tid + 256 * x, k = it / IB, c = it % IB;
+      rqa[x] = Qa[k * IN + hi * IB + c];
+      rqb[x] = Qb[k * IN + hj * IB + c];
+    }
+    const bool rot_a = Qa[IN * IN] != 0.0, rot_b = Qb[IN * IN] != 0.0;
+    if (!rot_a && !rot_b) {   // copy the quadrant
+#pragma unroll
+      for (int x = 0; x < PT; ++x) {
+        const int it = tid + 256 * x, i = it / IN, j = it % IN;
+        if ((i >> 5) == hi && (j >> 5) == hj) {
+          const int gi = pair_global(i, Ia, Ja), gj = pair_global(j, Ib, Jb);
+          Aout[(size_t)gi * N + gj] = rt[x];
+          Aout[(size_t)gj * N + gi] = rt[x];
+        }
+      }
+      return;
+    }
+#pragma unroll
+    for (int x = 0; x < PT; ++x) {
+      const int it = tid + 256 * x;
+      sT[it / IN][it % IN] = rt[x];
+    }
+#pragma unroll
+    for (int x = 0; x < PQ; ++x) {
+      const int it = tid + 256 * x, k = it / IB, c = it % IB;
+      sQ[k][c] = rot_a ? rqa[x] : (k == hi * IB + c ? 1.0 : 0.0);
+      sQ[k][IB + c] = rot_b ? rqb[x] : (k == hj * IB + c ? 1.0 : 0.0);
+    }
+    __syncthreads();
+    // U = Qa[:, hi]^T T (32 x 64): wave w takes columns [16 w, 16 w + 16), both row blocks
+    d4_t u[2] = {{0.0, 0.0, 0.0, 0.0}, {0.0, 0.0, 0.0, 0.0}};
+#pragma unroll 4
+    for (int k0 = 0; k0 < IN; k0 += 4) {
+      const double bv = sT[k0 + lk][16 * wave + li];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+        u[bi] = __builtin_amdgcn_mfma_f64_16x16x4f64(sQ[k0 + lk][bi * 16 + li], bv, u[bi], 0, 0, 0);
+    }
+#pragma unroll
+    for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+      for (int v = 0; v < 4; ++v) sU[bi * 16 + 4 * v + lk][16 * wave + li] = u[bi][v];
+    __syncthreads();
+    // T'[hi, hj] = U Qb[:, hj] (32 x 32): wave w takes the 16 x 16 block (w / 2, w % 2)
+    const int bi = wave >> 1, bj = wave & 1;
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < IN; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sU[bi * 16 + li][k0 + lk], sQ[k0 + lk][IB + bj * 16 + li], acc, 0,
+                                                 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int gi = pair_global(hi * IB + bi * 16 + 4 * v + lk, Ia, Ja);
+      const int gj = pair_global(hj * IB + bj * 16 + li, Ib, Jb);
+      Aout[(size_t)gi * N + gj] = acc[v];
+      Aout[(size_t)gj * N + gi] = acc[v];
+    }
+  } else {
+    bid -= 4 * ntri;
+    const int qr = bid & 3;
+    bid >>= 2;
+    const int rb = bid / npairs, b = bid % npairs;
+    const double* Qb = Qblk + (size_t)b * (IN * IN + 1);
+    if (Qb[IN * IN] == 0.0) return;
+    int Ib, Jb;
+    rr_pair(b, round, nb, Ib, Jb);
+    const int r0 = rb * IN + qr * 16;
+    constexpr int PV = 16 * IN / 256, PQ = IN * IN / 256;
+    double rv[PV], rq[PQ];
+#pragma unroll
+    for (int x = 0; x < PV; ++x) {
+      const int it = tid + 256 * x;
+      rv[x] = V[(size_t)(r0 + it / IN) * N + pair_global(it % IN, Ib, Jb)];
+    }
+#pragma unroll
+    for (int x = 0; x < PQ; ++x) rq[x] = Qb[tid + 256 * x];
+#pragma unroll
+    for (int x = 0; x < PV; ++x) {
+      const int it = tid + 256 * x;
+      sT[it / IN][it % IN] = rv[x];
+    }
+#pragma unroll
+    for (int x = 0; x < PQ; ++x) {
+      const int it = tid + 256 * x;
+      sQ[it / IN][it % IN] = rq[x];
+    }
+    __syncthreads();
+    // V[r0 + 0..15, Pb] Qb: wave w takes output columns [16 w, 16 w + 16)
+    d4_t acc = {0.0, 0.0, 0.0, 0.0};
+#pragma unroll 4
+    for (int k0 = 0; k0 < IN; k0 += 4)
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(sT[li][k0 + lk], sQ[k0 + lk][16 * wave + li], acc, 0, 0, 0);
+#pragma unroll
+    for (int v = 0; v < 4; ++v)
+      V[(size_t)(r0 + 4 * v + lk) * N + pair_global(16 * wave + li, Ib, Jb)] = acc[v];
   }
 }
 
@@ -1225,7 +1389,12 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
     if (sweeps < 0) return MLPCP_E_EIG;
   } else {
     const int ntri = npairs * (npairs - 1) / 2;
-    const int apply_blocks = ntri + (N / IN) * npairs;
+    // few tiles: the split apply step, with A alternating between the caller's buffer
+    // and tmp (free after the warm start) from round to round
+    const bool split = N <= kSplitApplyMax;
+    const int apply_blocks = split ? 4 * (ntri + (N / IN) * npairs) : ntri + (N / IN) * npairs;
+    double* cur = A;
+    double* other = split ? tmp : A;
     bool converged = false;
     // Each sweep starts with a device-side test (any pair passing the rotation test?)
     // whose result gates every kernel of the sweep, so sweeps can be queued without a
@@ -1242,8 +1411,8 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
         {
           ProfScope ps(KC_JACOBI_MISC, stream);
           if (gb)
-            hipLaunchKernelGGL(k_certify, dim3((N + 3) / 4), dim3(256), 0, stream, A, N, cert_tau2, gb, uncert);
-          hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, A, N, floor_p, gb ? uncert : nullptr,
+            hipLaunchKernelGGL(k_certify, dim3((N + 3) / 4), dim3(256), 0, stream, cur, N, cert_tau2, gb, uncert);
+          hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, cur, N, floor_p, gb ? uncert : nullptr,
                              partial ? gb : nullptr, active);
           hipLaunchKernelGGL(k_count_sweep, dim3(1), dim3(64), 0, stream, active, dsweeps);
         }
@@ -1251,13 +1420,18 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
           {
             ProfKernel pk(KC_JACOBI_PAIRS);
             hipExtLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, pk.start, pk.stop, 0,
-                                  A, N, nb, r, Qblk, floor_p, active, partial ? gb : nullptr);
+                                  cur, other, N, nb, r, Qblk, floor_p, active, partial ? gb : nullptr);
           }
           {
             ProfKernel pk(KC_JACOBI_APPLY);
-            hipExtLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, pk.start, pk.stop, 0,
-                                  A, V, N, nb, r, Qblk, active);
+            if (split)
+              hipExtLaunchKernelGGL(k_jacobi_apply_split, dim3(apply_blocks), dim3(256), 0, stream, pk.start,
+                                    pk.stop, 0, cur, other, V, N, nb, r, Qblk, active);
+            else
+              hipExtLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, pk.start, pk.stop, 0,
+                                    A, V, N, nb, r, Qblk, active);
           }
+          std::swap(cur, other);
         }
       }
       MLPCP_HIP(hipGetLastError());
@@ -1274,6 +1448,7 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
       if (sweeps >= kMaxEigSweeps || queued > 2 * kMaxEigSweeps) break;
       batch = 1;
     }
+    if (cur != A) MLPCP_HIP(hipMemcpyAsync(A, cur, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, stream));
     if (!converged) return MLPCP_E_EIG;
     if (gb && !partial) {
       ProfScope ps(KC_JACOBI_MISC, stream);
