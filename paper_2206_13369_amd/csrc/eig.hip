@@ -103,41 +103,19 @@ __device__ __forceinline__ void inner_pair(int phase, int s, int i, int& p, int&
 // Jacobi rotation annihilating a_pq of [[app, apq], [apq, aqq]]:
 //   [c s; -s c]^T A [c s; -s c] diagonal, t = s/c the root of smaller magnitude of
 //   t^2 + 2 theta t - 1 = 0, theta = (aqq - app)/(2 apq), written without theta:
-//   t = sign(d) 2 apq / (|d| + sqrt(d^2 + 4 apq^2)), d = aqq - app.
-__device__ __forceinline__ bool rotation(double app, double aqq, double apq, double floor_abs, double& c,
-                                         double& s, double& t) {
-  const double a2 = apq * apq;
-  if (!(fabs(apq) > floor_abs && a2 > kRelEps2 * fabs(app * aqq))) {
-    c = 1.0;
-    s = 0.0;
-    t = 0.0;
-    return false;
-  }
-  const double d = aqq - app;
-  const double r = sqrt(d * d + 4.0 * a2);
-  t = 2.0 * apq / (fabs(d) + r);
-  if (d < 0.0) t = -t;
-  c = 1.0 / sqrt(1.0 + t * t);
-  s = t * c;
-  return true;
-}
-
-// The rotation of `rotation` with the square roots and quotients taken from the
-// hardware reciprocal (square root) estimates and two Newton steps each, which
-// leaves them within a few units of the last place: c^2 + s^2 = 1 holds to that
-// accuracy, which is what keeps the accumulated factor orthogonal.  Used by the
-// one-workgroup solver, whose rounds are bound by this latency.
-__device__ __forceinline__ double rsq_nr(double x) {
-  double y = __builtin_amdgcn_rsq(x);
-  y = y * fma(-0.5 * x * y, y, 1.5);
-  y = y * fma(-0.5 * x * y, y, 1.5);
-  return y;
-}
-__device__ __forceinline__ double rcp_nr(double x) {
-  double y = __builtin_amdgcn_rcp(x);
-  y = y * fma(-x, y, 2.0);
-  y = y * fma(-x, y, 2.0);
-  return y;
+//   t = sign(d) 2 apq / (|d| + r), r = sqrt(d^2 + 4 apq^2), d = aqq - app.
+// With u = |d| + r, 1 + t^2 = 2 r / u, so c^2 = u / (2 r), and with y = 1/r and
+// w = 1/c:  s = sign(d) apq y w,  t = sign(d) apq y w^2.  That takes two reciprocal
+// square roots (of r^2 and of c^2) and no division.  Each is the hardware estimate
+// (relative error ~2^-24 on gfx950) refined by one third-order step,
+// y (1 + e/2 + 3 e^2 / 8) with e = 1 - x y^2, whose truncation error is O(e^3): the
+// results stay within a few units of the last place, so c^2 + s^2 = 1 holds to that
+// accuracy, which keeps the accumulated factor orthogonal.  The rounds of the Jacobi
+// kernels are a dependent chain through this computation.
+__device__ __forceinline__ double rsq_refined(double x) {
+  const double y = __builtin_amdgcn_rsq(x);
+  const double e = fma(-(x * y), y, 1.0);
+  return fma(y * e, fma(0.375, e, 0.5), y);
 }
 __device__ __forceinline__ bool rotation_fast(double app, double aqq, double apq, double floor_abs, double& c,
                                               double& s, double& t) {
@@ -150,11 +128,14 @@ __device__ __forceinline__ bool rotation_fast(double app, double aqq, double apq
   }
   const double d = aqq - app;
   const double r2 = fma(d, d, 4.0 * a2);
-  const double r = r2 * rsq_nr(r2);
-  t = 2.0 * apq * rcp_nr(fabs(d) + r);
-  if (d < 0.0) t = -t;
-  c = rsq_nr(fma(t, t, 1.0));
-  s = t * c;
+  const double y = rsq_refined(r2);                 // 1 / r
+  const double u = fma(r2, y, fabs(d));             // |d| + r
+  const double z = (0.5 * u) * y;                   // c^2, in [1/2, 1]
+  const double w = rsq_refined(z);                  // 1 / c
+  const double ay = (d < 0.0 ? -apq : apq) * y;
+  c = z * w;
+  s = ay * w;
+  t = s * w;
   return true;
 }
 
