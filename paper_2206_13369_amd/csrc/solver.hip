@@ -224,6 +224,11 @@ struct EpiArgs {
   double* partial;
 };
 
+// ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7))
+__device__ __forceinline__ double sum8(const double (&v)[8]) {
+  return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+}
+
 template <int MODE, bool PLAIN, bool MASKED>
 __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
   extern __shared__ float sm[];
@@ -244,22 +249,36 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
     sMP[i * nHp + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
   }
   __syncthreads();
-  // 2. A = M_P T   (rows x r), float64 sums rounded once
+  // 2. A = M_P T   (rows x r), float64 sums rounded once; eight partial sums per dot
+  //    product (terms c = 8q + u go to partial u, summed in order u = 0..7), so eight
+  //    loads of T are in flight and the FMA chains are an eighth as long
   for (int e = tid; e < rows * r; e += kThreads) {
     const int i = e / r, k = e % r;
     const float* x = sMP + i * nHp;
-    double acc = 0.0;
-    for (int c = 0; c < nH; ++c) acc = fma((double)x[c], a.T[(size_t)c * a.ldT + k], acc);
-    sA[i * nHp + k] = (float)acc;
+    const double* tc = a.T + k;
+    double acc[8] = {};
+    int c = 0;
+    for (; c + 8 <= nH; c += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = fma((double)x[c + u], tc[(size_t)(c + u) * a.ldT], acc[u]);
+    }
+    for (int u = 0; c < nH; ++c, ++u) acc[u] = fma((double)x[c], tc[(size_t)c * a.ldT], acc[u]);
+    sA[i * nHp + k] = (float)sum8(acc);
   }
   __syncthreads();
-  // 3. N = A T^T  (rows x nH), over the M_P panel
+  // 3. N = A T^T  (rows x nH), over the M_P panel, the same way
   for (int e = tid; e < rows * nH; e += kThreads) {
     const int i = e / nH, c = e % nH;
     const float* y = sA + i * nHp;
-    double acc = 0.0;
-    for (int k = 0; k < r; ++k) acc = fma((double)y[k], a.Tt[(size_t)k * a.ldT + c], acc);
-    sMP[i * nHp + c] = (float)acc;
+    const double* tc = a.Tt + c;
+    double acc[8] = {};
+    int k = 0;
+    for (; k + 8 <= r; k += 8) {
+#pragma unroll
+      for (int u = 0; u < 8; ++u) acc[u] = fma((double)y[k + u], tc[(size_t)(k + u) * a.ldT], acc[u]);
+    }
+    for (int u = 0; k < r; ++k, ++u) acc[u] = fma((double)y[k], tc[(size_t)k * a.ldT], acc[u]);
+    sMP[i * nHp + c] = (float)sum8(acc);
   }
   __syncthreads();
   // 4. fine elements
