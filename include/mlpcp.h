@@ -100,8 +100,12 @@ typedef struct {
   double fg;               /* final feasibility gap                           */
   int rank;                /* singular values kept by the last coarse SVT     */
   double mu_final;         /* penalty used by the last iteration              */
-  double tau_margin;       /* min_i |sigma_i - tau| / tau at the last SVT     */
-  int eig_sweeps;          /* Jacobi sweeps of the last eigensolve            */
+  double tau_margin;       /* min_i |sigma_i - tau| / tau at the last SVT; a  */
+                           /* lower bound where the eigensolver certified the */
+                           /* spectrum below tau^2 by Gershgorin bounds       */
+                           /* instead of diagonalising it                     */
+  int eig_sweeps;          /* Jacobi sweeps of the last eigensolve (0 when    */
+                           /* the certificate settled it)                     */
   double* fg_history;      /* in: optional host array                         */
   int* rank_history;       /* in: optional host array                         */
   int history_len;         /* in: length of the two arrays                    */

@@ -338,7 +338,7 @@ void gram_plan(int m, int kp, int& splits, int& rows_per_split, bool cross = fal
   const int nt = kp / GT;
   const int pairs = cross ? nt * nt : nt * (nt + 1) / 2;
   int sp = (768 + pairs - 1) / pairs;
-  const int max_by_rows = (m + 511) / 512;
+  const int max_by_rows = (m + 127) / 128;   // at least 128 rows per split
   if (sp > max_by_rows) sp = max_by_rows;
   const size_t cap = (size_t)64 << 20;
   const size_t per = (size_t)kp * kp * sizeof(double);
