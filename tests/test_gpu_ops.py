@@ -51,7 +51,8 @@ def test_restrict_prolong(m, n, levels):
 @pytest.mark.parametrize("m,n,levels,rank", [(50, 20, 0, 3), (120, 64, 0, 5), (300, 300, 2, 10), (500, 100, 0, 8),
                                              (400, 200, 4, 6), (257, 250, 1, 12), (90, 33, 0, 4),
                                              (700, 520, 0, 12), (2000, 2000, 3, 30),
-                                             (1200, 1100, 0, 12)])   # width >= 1024: partial certificate
+                                             (1200, 1100, 0, 12),    # width >= 1024: partial certificate
+                                             (640, 512, 0, 10)])     # widest split apply step (A alternates)
 def test_svt_prox_matches_oracle(m, n, levels, rank):
     say("svt_prox", m, n, levels, rank)
     rng = np.random.default_rng(m * 7 + n)
