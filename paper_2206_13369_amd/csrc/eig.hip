@@ -144,7 +144,7 @@ __device__ __forceinline__ bool rotates(double app, double aqq, double apq, doub
 }
 
 struct RotShared {
-  double2 cs[IB];            // (c, s) of each rotation of the round
+  double2 cs[2][IB];         // (c, s) of each rotation of the round (two buffers, by round parity)
   double t[IB];
   unsigned long long cert;   // bit l: local index l certified (partial certificate)
   int any;
@@ -171,7 +171,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       // two certified indices: not rotated (an infinite floor fails the test)
       const bool both = ((rs.cert >> p) & (rs.cert >> q) & 1ull) != 0;
       const bool on = rotation_fast(A[p][p], A[q][q], A[p][q], both ? INFINITY : floor_abs, c, sn, t);
-      rs.cs[tid] = make_double2(c, sn);
+      rs.cs[0][tid] = make_double2(c, sn);
       rs.t[tid] = t;
       if (on) rs.any = 1;
     }
@@ -181,7 +181,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       const int a = tid / (IB / NT);
       int pa, qa;
       inner_pair(phase, s, a, pa, qa);
-      const double2 pa_ = rs.cs[a];
+      const double2 pa_ = rs.cs[0][a];
       const double ca = pa_.x, sa = pa_.y, ta = rs.t[a];
       int pb[NT], qb[NT];
       double cb[NT], sb[NT];
@@ -190,7 +190,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       for (int x = 0; x < NT; ++x) {
         const int b = (tid % (IB / NT)) * NT + x;
         inner_pair(phase, s, b, pb[x], qb[x]);
-        const double2 pb_ = rs.cs[b];
+        const double2 pb_ = rs.cs[0][b];
         cb[x] = pb_.x; sb[x] = pb_.y;
         t00[x] = A[pa][pb[x]]; t01[x] = A[pa][qb[x]];
         t10[x] = A[qa][pb[x]]; t11[x] = A[qa][qb[x]];
@@ -199,7 +199,7 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
       const int bq = tid % IB;
       int qp, qq;
       inner_pair(phase, s, bq, qp, qq);
-      const double2 pq_ = rs.cs[bq];
+      const double2 pq_ = rs.cs[0][bq];
       const double qc = pq_.x, qs = pq_.y;
       double qx[NQ], qy[NQ];
 #pragma unroll
@@ -238,44 +238,55 @@ __device__ __forceinline__ void inner_phase(double (*A)[LDS_LD], double (*Q)[LDS
 // Phase 1 (the cross pairs (i, b + (i+s) mod b), b rounds) with the 2x2 tiles and the
 // factor items in registers, for IB * IB threads.  Thread (d, c) = (tid / IB, tid % IB)
 // holds, in round s, the tile of rows (a, IB + (a+s) mod IB) x columns
-// (c, IB + (c+s) mod IB) of A, a = (d + c) mod IB (a skewed layout: the diagonal
-// tiles a = c, whose threads compute the rotations, are the first 32 lanes of wave 0,
-// and the other waves only apply them), and, for the rows i in {d, IB + d}, the factor
-// entries Q[i][c] and Q[i][IB + (c+s) mod IB].  From one round to the next only the
-// J-side indices move, by one position: the tile's J x J entry comes from tile
-// (a+1, c+1) = thread (d, c+1) and the factor's J column from (d, c+1) (the same
-// wave: lane shuffles); the tile's J column comes from tile (a, c+1) = thread
-// (d-1, c+1) and its J row from tile (a+1, c) = thread (d+1, c) (through LDS).  The
-// arithmetic is that of inner_phase; A and Q enter and leave in LDS (A serves as the
-// exchange buffer in between).
+// (c, IB + (c+s) mod IB) of A, a = (d + c) mod IB (a skewed layout: the diagonal tiles
+// a = c are the first 32 lanes of wave 0, the subdiagonal tiles (c+1, c) its other 32
+// lanes), and, for the rows i in {d, IB + d}, the factor entries Q[i][c] and
+// Q[i][IB + (c+s) mod IB].  From one round to the next only the J-side indices move,
+// by one position: the tile's J x J entry comes from tile (a+1, c+1) = thread (d, c+1)
+// and the factor's J column from (d, c+1) (the same wave: lane shuffles); the tile's J
+// column comes from tile (a, c+1) = thread (d-1, c+1) and its J row from tile
+// (a+1, c) = thread (d+1, c) (through LDS).
+// One barrier per round: wave 0 computes the next round's rotations as soon as its own
+// tiles are updated, because everything they need is in wave 0 -- a_pp and a_qq of the
+// diagonal tile (its own n00 and the n11 of thread (0, c+1)) and a_pq = a_{p_c, q_c(s+1)},
+// which by symmetry is the n10 of the subdiagonal tile (c+1, c), thread (1, c).  The
+// other waves meanwhile apply the current round, so the rotation chain overlaps their
+// updates; rotation parameters and exchanged entries alternate between two buffers by
+// round parity.  The arithmetic per tile is that of inner_phase; A and Q enter and leave
+// in LDS (A serves as the exchange buffer in between).
 __device__ __forceinline__ void cross_phase_regs(double (*A)[LDS_LD], double (*Q)[LDS_LD], double floor_abs,
                                                  RotShared& rs) {
   static_assert(IB == 32 && IN == 64, "lane arithmetic assumes 32 pairs, two tile rows per wave");
+  static_assert(4 * IB * IB <= IN * LDS_LD, "two parities of two exchange arrays fit in the A buffer");
   const int tid = threadIdx.x, d = tid / IB, c = tid % IB;
   const int a = (d + c) & (IB - 1);
   const int lane = tid & 63;
   const int src = (lane & IB) | ((lane + 1) & (IB - 1));   // thread (d, c+1), same wave
-  const bool diag = d == 0;
+  const int sub = IB | (lane & (IB - 1));                  // wave 0: thread (1, c)
+  const bool diag = d == 0;                                 // wave 0, lanes 0..31
+  const bool wave0 = tid < 64;                              // wave-uniform
   double t00 = A[a][c], t01 = A[a][IB + c], t10 = A[IB + a][c], t11 = A[IB + a][IB + c];
   double qx0 = Q[d][c], qy0 = Q[d][IB + c], qx1 = Q[IB + d][c], qy1 = Q[IB + d][IB + c];
   const unsigned long long cm = rs.cert;
   __syncthreads();   // A now serves as the exchange buffer
-  double* x01 = &A[0][0];        // IB x IB by thread: the tiles' J-column entries
-  double* x10 = x01 + IB * IB;   // IB x IB by thread: the tiles' J-row entries
+  double* x01 = &A[0][0];            // [parity][IB x IB by thread]: the tiles' J-column entries
+  double* x10 = x01 + 2 * IB * IB;   // [parity][IB x IB by thread]: the tiles' J-row entries
   const int from01 = ((d + IB - 1) & (IB - 1)) * IB + ((c + 1) & (IB - 1));
   const int from10 = ((d + 1) & (IB - 1)) * IB + c;
+  double tt = 0.0;
+  auto rotate = [&](int s, int par) {   // diagonal threads: rotation c of round s
+    double cc, sn;
+    const int q = IB + ((c + s) & (IB - 1));
+    // two certified indices: not rotated (an infinite floor fails the test)
+    const bool both = ((cm >> c) & (cm >> q) & 1ull) != 0;
+    if (rotation_fast(t00, t11, t01, both ? INFINITY : floor_abs, cc, sn, tt)) rs.any = 1;
+    rs.cs[par][c] = make_double2(cc, sn);
+  };
+  if (diag) rotate(0, 0);
+  __syncthreads();
   for (int s = 0;; ++s) {
-    double tt = 0.0;
-    if (diag) {   // wave 0, lanes 0..31: rotation c from the diagonal tile (a = c)
-      double cc, sn;
-      const int q = IB + ((c + s) & (IB - 1));
-      // two certified indices: not rotated (an infinite floor fails the test)
-      const bool both = ((cm >> c) & (cm >> q) & 1ull) != 0;
-      if (rotation_fast(t00, t11, t01, both ? INFINITY : floor_abs, cc, sn, tt)) rs.any = 1;
-      rs.cs[c] = make_double2(cc, sn);
-    }
-    __syncthreads();
-    const double2 pa = rs.cs[a], pb = rs.cs[c];
+    const int par = s & 1;
+    const double2 pa = rs.cs[par][a], pb = rs.cs[par][c];
     const double ca = pa.x, sa = pa.y, cb = pb.x, sb = pb.y;
     const double u00 = ca * t00 - sa * t10, u01 = ca * t01 - sa * t11;
     const double u10 = sa * t00 + ca * t10, u11 = sa * t01 + ca * t11;
@@ -297,14 +308,23 @@ __device__ __forceinline__ void cross_phase_regs(double (*A)[LDS_LD], double (*Q
       qy0 = w0; qy1 = w1;
       break;
     }
-    x01[tid] = n01;
-    x10[tid] = n10;
+    double* xo01 = x01 + par * IB * IB;
+    double* xo10 = x10 + par * IB * IB;
+    xo01[tid] = n01;
+    xo10[tid] = n10;
     t11 = __shfl(n11, src);
     qy0 = __shfl(w0, src);
     qy1 = __shfl(w1, src);
+    if (wave0) {
+      const double sub10 = __shfl(n10, sub);
+      if (diag) {
+        t01 = sub10;
+        rotate(s + 1, par ^ 1);
+      }
+    }
     __syncthreads();
-    t01 = x01[from01];
-    t10 = x10[from10];
+    if (!diag) t01 = xo01[from01];
+    t10 = xo10[from10];
   }
   __syncthreads();   // exchange reads done: A and Q take the result (positions of round IB - 1)
   const int qa = IB + ((a + IB - 1) & (IB - 1)), qc = IB + ((c + IB - 1) & (IB - 1));
