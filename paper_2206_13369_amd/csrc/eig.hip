@@ -1399,44 +1399,53 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
     bool converged = false;
     // Each sweep starts with a device-side test (any pair passing the rotation test?)
     // whose result gates every kernel of the sweep, so sweeps can be queued without a
-    // host round trip: a sweep after convergence costs its empty launches only.  The
-    // first batch is one sweep less than the caller's hint (the previous solve's
-    // count); then one sweep per host check until the test finds nothing.
+    // host round trip: a sweep after convergence costs its empty launches only.
     int* active = flag;
     MLPCP_HIP(hipMemsetAsync(dsweeps, 0, sizeof(int), stream));
-    int queued = 0, batch = std::max(1, std::min(sweep_hint - 1, kMaxEigSweeps));
+    // a sweep is its pre-test (which sets `active` and counts the sweep) and its rounds,
+    // whose kernels do nothing when the pre-test found nothing to rotate
+    auto pretest = [&]() -> int {
+      MLPCP_HIP(hipMemsetAsync(active, 0, 2 * sizeof(int), stream));   // active, uncert
+      ProfScope ps(KC_JACOBI_MISC, stream);
+      if (gb) hipLaunchKernelGGL(k_certify, dim3((N + 3) / 4), dim3(256), 0, stream, cur, N, cert_tau2, gb, uncert);
+      hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, cur, N, floor_p, gb ? uncert : nullptr,
+                         partial ? gb : nullptr, active);
+      hipLaunchKernelGGL(k_count_sweep, dim3(1), dim3(64), 0, stream, active, dsweeps);
+      return MLPCP_OK;
+    };
+    auto rounds = [&]() {
+      for (int r = 0; r < nb - 1; ++r) {
+        {
+          ProfKernel pk(KC_JACOBI_PAIRS);
+          hipExtLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, pk.start, pk.stop, 0,
+                                cur, other, N, nb, r, Qblk, floor_p, active, partial ? gb : nullptr);
+        }
+        {
+          ProfKernel pk(KC_JACOBI_APPLY);
+          if (split)
+            hipExtLaunchKernelGGL(k_jacobi_apply_split, dim3(apply_blocks), dim3(256), 0, stream, pk.start, pk.stop,
+                                  0, cur, other, V, N, nb, r, Qblk, active);
+          else
+            hipExtLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, pk.start, pk.stop, 0, A,
+                                  V, N, nb, r, Qblk, active);
+        }
+        std::swap(cur, other);
+      }
+    };
+    // The first batch is one sweep less than the caller's hint (the previous solve's
+    // count), followed by the pre-test of the next sweep alone; each host check then
+    // queues that sweep's rounds only if its pre-test found something, and the next
+    // pre-test.  So the sweep that confirms convergence costs its pre-test, not rounds.
+    const int batch = std::max(0, std::min(sweep_hint - 1, kMaxEigSweeps));
+    for (int b = 0; b < batch; ++b) {
+      MLPCP_TRY(pretest());
+      rounds();
+    }
+    MLPCP_TRY(pretest());
+    int queued = batch;
     int hstate[2] = {0, 0};
     for (;;) {
-      for (int b = 0; b < batch; ++b) {
-        MLPCP_HIP(hipMemsetAsync(active, 0, 2 * sizeof(int), stream));   // active, uncert
-        {
-          ProfScope ps(KC_JACOBI_MISC, stream);
-          if (gb)
-            hipLaunchKernelGGL(k_certify, dim3((N + 3) / 4), dim3(256), 0, stream, cur, N, cert_tau2, gb, uncert);
-          hipLaunchKernelGGL(k_any_rotation, dim3(64), dim3(256), 0, stream, cur, N, floor_p, gb ? uncert : nullptr,
-                             partial ? gb : nullptr, active);
-          hipLaunchKernelGGL(k_count_sweep, dim3(1), dim3(64), 0, stream, active, dsweeps);
-        }
-        for (int r = 0; r < nb - 1; ++r) {
-          {
-            ProfKernel pk(KC_JACOBI_PAIRS);
-            hipExtLaunchKernelGGL(k_jacobi_pairs, dim3(npairs), dim3(kPairThreads), 0, stream, pk.start, pk.stop, 0,
-                                  cur, other, N, nb, r, Qblk, floor_p, active, partial ? gb : nullptr);
-          }
-          {
-            ProfKernel pk(KC_JACOBI_APPLY);
-            if (split)
-              hipExtLaunchKernelGGL(k_jacobi_apply_split, dim3(apply_blocks), dim3(256), 0, stream, pk.start,
-                                    pk.stop, 0, cur, other, V, N, nb, r, Qblk, active);
-            else
-              hipExtLaunchKernelGGL(k_jacobi_apply, dim3(apply_blocks), dim3(256), 0, stream, pk.start, pk.stop, 0,
-                                    A, V, N, nb, r, Qblk, active);
-          }
-          std::swap(cur, other);
-        }
-      }
       MLPCP_HIP(hipGetLastError());
-      queued += batch;
       // active and the sweep count are adjacent in the workspace
       MLPCP_HIP(hipMemcpyAsync(&hstate[0], active, sizeof(int), hipMemcpyDeviceToHost, stream));
       MLPCP_HIP(hipMemcpyAsync(&hstate[1], dsweeps, sizeof(int), hipMemcpyDeviceToHost, stream));
@@ -1447,7 +1456,9 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
         break;
       }
       if (sweeps >= kMaxEigSweeps || queued > 2 * kMaxEigSweeps) break;
-      batch = 1;
+      rounds();           // the sweep whose pre-test passed
+      MLPCP_TRY(pretest());
+      ++queued;
     }
     if (cur != A) MLPCP_HIP(hipMemcpyAsync(A, cur, (size_t)N * N * sizeof(double), hipMemcpyDeviceToDevice, stream));
     if (!converged) return MLPCP_E_EIG;
