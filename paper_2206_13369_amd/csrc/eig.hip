@@ -1130,6 +1130,59 @@ __global__ void __launch_bounds__(256) k_any_rotation(const double* __restrict__
   if (__syncthreads_or(want) && threadIdx.x == 0) atomicOr(flag, 1);
 }
 
+// The pre-test of a sweep in one launch, for widths below kCertPartialMin (so the
+// certificate is all or nothing): each block forms the Gershgorin bounds of its rows
+// (one wave per row; gb non-null) and the rotation test over its share of the pairs,
+// and ORs both into scratch flags; the last block to finish (an atomic ticket, taken
+// after a fence, so every block's flags are in; nothing waits) sets
+// active = (some pair rotates) and (not every row certified), keeps the certificate's
+// outcome for k_cert_finish, counts the sweep and clears the scratch for the next one.
+// flags: [0] active, [1] some row not certified (kept), [2], [3] scratch ORs, [4] ticket.
+__global__ void __launch_bounds__(256) k_pretest(const double* __restrict__ A, int N,
+                                                 const double* __restrict__ floor_p, double tau2,
+                                                 double* __restrict__ gb, int* __restrict__ flags,
+                                                 int* __restrict__ count) {
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  int unc = 0, want = 0;
+  if (gb != nullptr) {
+    for (int row = blockIdx.x * 4 + wv; row < N; row += gridDim.x * 4) {
+      const double* a = A + (size_t)row * N;
+      double sum = 0.0;
+      for (int j = lane; j < N; j += 64) sum += fabs(a[j]);
+#pragma unroll
+      for (int o = 32; o > 0; o >>= 1) sum += __shfl_xor(sum, o);
+      if (lane == 0) {
+        const bool c = sum < tau2 * (1.0 - 1.0e-12);
+        gb[row] = c ? sum : -1.0;
+        unc |= c ? 0 : 1;
+      }
+    }
+  }
+  const double fl = floor_p[0];
+  const size_t total = (size_t)N * N;
+  for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total; idx += (size_t)gridDim.x * blockDim.x) {
+    const int i = (int)(idx / N), j = (int)(idx % N);
+    if (i < j && rotates(A[(size_t)i * N + i], A[(size_t)j * N + j], A[idx], fl)) want = 1;
+  }
+  unc = __syncthreads_or(unc);
+  want = __syncthreads_or(want);
+  if (threadIdx.x == 0) {
+    if (unc) atomicOr(&flags[2], 1);
+    if (want) atomicOr(&flags[3], 1);
+    __threadfence();
+    if (atomicAdd(&flags[4], 1) == (int)gridDim.x - 1) {   // the last block
+      const int u = atomicOr(&flags[2], 0), w = atomicOr(&flags[3], 0);
+      const int act = (w && (gb == nullptr || u)) ? 1 : 0;
+      flags[0] = act;
+      flags[1] = u;
+      if (act) count[0] += 1;
+      flags[2] = 0;
+      flags[3] = 0;
+      flags[4] = 0;
+    }
+  }
+}
+
 // counts the sweeps whose pre-test found something to rotate
 __global__ void k_count_sweep(const int* __restrict__ active, int* __restrict__ count) {
   if (threadIdx.x == 0 && *active) count[0] += 1;
@@ -1402,9 +1455,17 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
     // host round trip: a sweep after convergence costs its empty launches only.
     int* active = flag;
     MLPCP_HIP(hipMemsetAsync(dsweeps, 0, sizeof(int), stream));
+    // flag[0..4]: active, uncert, two scratch ORs and the ticket of k_pretest (zero
+    // between its launches)
+    MLPCP_HIP(hipMemsetAsync(flag, 0, 5 * sizeof(int), stream));
     // a sweep is its pre-test (which sets `active` and counts the sweep) and its rounds,
     // whose kernels do nothing when the pre-test found nothing to rotate
     auto pretest = [&]() -> int {
+      if (!partial) {   // one launch
+        ProfScope ps(KC_JACOBI_MISC, stream);
+        hipLaunchKernelGGL(k_pretest, dim3(64), dim3(256), 0, stream, cur, N, floor_p, cert_tau2, gb, flag, dsweeps);
+        return MLPCP_OK;
+      }
       MLPCP_HIP(hipMemsetAsync(active, 0, 2 * sizeof(int), stream));   // active, uncert
       ProfScope ps(KC_JACOBI_MISC, stream);
       if (gb) hipLaunchKernelGGL(k_certify, dim3((N + 3) / 4), dim3(256), 0, stream, cur, N, cert_tau2, gb, uncert);
