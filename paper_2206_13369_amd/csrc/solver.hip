@@ -62,6 +62,32 @@ __device__ double block_sum(double v, double* red) {
 __device__ __forceinline__ void restrict_panel(const float* sX, int rows, int n, int nH, float* __restrict__ MP,
                                                int ldp, int i0, const int* __restrict__ col_ptr,
                                                const int* __restrict__ col_row, const float* __restrict__ col_w) {
+  if (nH <= kThreads) {
+    // thread -> coarse column c and rows r0, r0 + rstep, ...: each tap's index and weight
+    // are read once for up to four of the thread's rows (same sum order per output)
+    const int rstep = kThreads / nH;
+    const int r0 = threadIdx.x / nH, c = threadIdx.x % nH;
+    if (r0 >= rstep) return;
+    const int t0 = col_ptr[c], t1 = col_ptr[c + 1];
+    for (int rb = r0; rb < rows; rb += 4 * rstep) {
+      float acc[4] = {0.0f, 0.0f, 0.0f, 0.0f};
+      for (int t = t0; t < t1; ++t) {
+        const int jr = col_row[t];
+        const float w = col_w[t];
+#pragma unroll
+        for (int k = 0; k < 4; ++k) {
+          const int i = rb + k * rstep;
+          if (i < rows) acc[k] = fmaf(w, sX[(size_t)i * n + jr], acc[k]);
+        }
+      }
+#pragma unroll
+      for (int k = 0; k < 4; ++k) {
+        const int i = rb + k * rstep;
+        if (i < rows) MP[(size_t)(i0 + i) * ldp + c] = acc[k];
+      }
+    }
+    return;
+  }
   for (int e = threadIdx.x; e < rows * nH; e += kThreads) {
     const int i = e / nH, c = e % nH;
     const float* x = sX + (size_t)i * n;
@@ -100,8 +126,10 @@ __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM,
   const int i0 = blockIdx.x * TM;
   const int rows = min(TM, m - i0);
   double acc = 0.0;
+  // element e = i n + j, stepped by kThreads without a division per element
+  int i = threadIdx.x / n, j = threadIdx.x % n;
+  const int di = kThreads / n, dj = kThreads % n;
   for (int e = threadIdx.x; e < rows * n; e += kThreads) {
-    const int i = e / n, j = e % n;
     const int gi = i0 + i;
     float x = 0.0f;
     if (!MASKED || qbit(bits, nw, gi, j)) {
@@ -115,6 +143,12 @@ __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM,
       MP[(size_t)gi * ldp + j] = x;
     else
       sm[(size_t)i * n + j] = x;
+    j += dj;
+    i += di;
+    if (j >= n) {
+      j -= n;
+      ++i;
+    }
   }
   if (!PLAIN) {
     __syncthreads();
