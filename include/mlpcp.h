@@ -49,7 +49,8 @@ typedef enum {
   MLPCP_E_INVALID_ARG = -1,   /* NULL pointer, non-positive lambda/tol, ...     */
   MLPCP_E_SHAPE = -2,         /* m < n, ld < columns, non-positive sizes        */
   MLPCP_E_LEVELS = -3,        /* levels < 0 or too deep for n (n_H < 1)         */
-  MLPCP_E_NONFINITE = -4,     /* the feasibility gap became NaN or Inf          */
+  MLPCP_E_NONFINITE = -4,     /* NaN/Inf in an observed entry of D, S0 or Y0,   */
+                              /* or the feasibility gap became NaN or Inf       */
   MLPCP_E_EIG = -5,           /* the Jacobi eigensolver hit its sweep cap       */
   MLPCP_E_WORKSPACE = -6,     /* caller workspace smaller than required         */
   MLPCP_E_HIP = -7,           /* a HIP runtime call failed                       */
@@ -113,6 +114,8 @@ typedef struct {
   int gram_split_iters;    /* iterations whose Gram ran in split bfloat16     */
   int* sweeps_history;     /* in: optional host array (history_len entries):  */
                            /* Jacobi sweeps of each iteration's eigensolve    */
+  double mu0;              /* initial penalty used (the computed default when */
+                           /* the call passed mu0 <= 0)                       */
 } mlpcp_info;
 
 /* Fills defaults: levels 0, tol 1e-6, max_iter 500, rho 1.5, mu_max_factor 1e7,
@@ -124,22 +127,32 @@ void mlpcp_default_opts(mlpcp_opts* opts);
 int mlpcp_coarse_dim(int n, int levels);
 
 /* Device workspace (bytes) a solve of an m x n problem needs with these
- * options; 0 if the arguments are invalid.  The solvers and svt_prox accept
- * ws = NULL, in which case they allocate (and free) it themselves.           */
+ * options (including the default-mu0 phase); 0 if the arguments are invalid.
+ * The solvers and svt_prox accept ws = NULL, in which case they allocate (and
+ * free) it themselves.                                                       */
 size_t mlpcp_workspace_bytes(int m, int n, const mlpcp_opts* opts);
 
 /* Robust PCA, eq. (rpca): min ||L||_* + lambda ||S||_1 s.t. D = L + S, by
  * inexact ALM (Alg. 1, opts->levels = 0) or multilevel inexact ALM (Alg. 4).
  *  D      m x n input, leading dimension ldd.
  *  lambda weight of the l1 term, > 0.
- *  mu0    initial penalty, > 0 (Alg. 1 / Alg. 4 require it).
+ *  mu0    initial penalty (Alg. 1 / Alg. 4 require one).  mu0 <= 0 selects
+ *         the customary default 1.25 / ||P_Q D||_2, computed on the device
+ *         before the iterations (float64 Gram of P_Q D, its top eigenvalue by
+ *         repeated squaring, a Rayleigh quotient; relative error below 1e-7);
+ *         info->mu0 reports the value used.  NaN/Inf: MLPCP_E_INVALID_ARG.
  *  S0, Y0 optional m x n (ld = n) initial sparse part and multiplier; NULL =
  *         zeros.  They may alias the S and Y outputs.
  *  L, S   outputs, m x n, ld = n.  Y: optional output multiplier (NULL = not
  *         returned).  L, S, Y must not alias D or each other.
  *  ws     device workspace of ws_bytes >= mlpcp_workspace_bytes(), or NULL.
  *  info   optional report (may be NULL).
- * Returns MLPCP_OK when FG <= tol, MLPCP_NOT_CONVERGED after max_iter.       */
+ * Returns MLPCP_OK when FG <= tol, MLPCP_NOT_CONVERGED after max_iter (the
+ * outputs then hold the last iterate).  Degenerate and invalid data:
+ *  - P_Q D = 0: L = S = 0 (Y = 0), zero iterations, MLPCP_OK;
+ *  - a NaN or Inf in an observed entry of D, S0 or Y0: MLPCP_E_NONFINITE
+ *    before any iteration (detected by the initial pass over the data).
+ * L must not alias S0 or Y0 (it stages P_Q D for the default mu0).           */
 int mlpcp_pcp_solve(int m, int n, const float* D, int ldd, float lambda, double mu0,
                     const mlpcp_opts* opts, const float* S0, const float* Y0,
                     float* L, float* S, float* Y, void* ws, size_t ws_bytes,

@@ -52,7 +52,8 @@ class Info(ctypes.Structure):
                 ("mu_final", ctypes.c_double), ("tau_margin", ctypes.c_double), ("eig_sweeps", ctypes.c_int),
                 ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
                 ("history_len", ctypes.c_int), ("gram_bf16_iters", ctypes.c_int),
-                ("gram_split_iters", ctypes.c_int), ("sweeps_history", ctypes.POINTER(ctypes.c_int))]
+                ("gram_split_iters", ctypes.c_int), ("sweeps_history", ctypes.POINTER(ctypes.c_int)),
+                ("mu0", ctypes.c_double)]
 
 
 class FwtInfo(ctypes.Structure):
@@ -195,6 +196,15 @@ def _check_dev(t, name, dtype=None):
     return t
 
 
+def _check_mn(t, name, m, n):
+    """Optional (None) or a contiguous m x n float32 device tensor."""
+    if t is None:
+        return
+    _check_dev(t, name, _torch().float32)
+    if tuple(t.shape) != (m, n) or not t.is_contiguous():
+        raise ValueError(f"{name} must be a contiguous m x n tensor")
+
+
 def _ptr(t):
     return None if t is None else ctypes.c_void_p(t.data_ptr())
 
@@ -220,6 +230,7 @@ class SolveResult:
     gram_bf16_iters: int = 0
     gram_split_iters: int = 0
     sweeps_history: list = dataclasses.field(default_factory=list)
+    mu0: float = 0.0
 
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
@@ -268,6 +279,7 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
         info.sweeps_history = sh
         info.history_len = history
     ld = D.stride(0)
+    mu0 = 0.0 if mu0 is None else float(mu0)
     if Q is None:
         st = lib().mlpcp_pcp_solve(m, n, _ptr(D), ld, float(lam), float(mu0), ctypes.byref(o), _ptr(S0), _ptr(Y0),
                                    _ptr(L), _ptr(S), _ptr(Y), _ptr(ws), ws.numel(), ctypes.byref(info),
@@ -285,23 +297,25 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
     return SolveResult(L, S, Y, st, info.iters, info.fg, info.rank, info.mu_final, info.tau_margin, info.eig_sweeps,
                        [fh[i] for i in range(k)] if history else [], [rh[i] for i in range(k)] if history else [],
                        info.gram_bf16_iters, info.gram_split_iters,
-                       [sh[i] for i in range(k)] if history else [])
+                       [sh[i] for i in range(k)] if history else [], info.mu0)
 
 
-def pcp_solve(D, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
+def pcp_solve(D, lam: float, mu0: Optional[float] = None, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
               rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
               workspace=None, history: int = 0, prec="fp32", r_norm: int = 0) -> SolveResult:
     """Robust PCA by (multilevel) inexact ALM; D is an m x n float32 tensor on the GPU.
+    mu0: initial penalty; None or <= 0 selects 1.25 / ||D||_2, computed on the device.
     prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products).
     r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P."""
     return _solve(D, None, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
                   prec, r_norm)
 
 
-def cpcp_solve(D, Q, lam: float, mu0: float, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
+def cpcp_solve(D, Q, lam: float, mu0: Optional[float] = None, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
                rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
                workspace=None, history: int = 0, prec="fp32", r_norm: int = 0) -> SolveResult:
     """Compressive PCP (constrained form) by masked (multilevel) inexact ALM; Q uint8 mask.
+    mu0: initial penalty; None or <= 0 selects 1.25 / ||P_Q D||_2, computed on the device.
     prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products).
     r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P."""
     return _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
@@ -373,7 +387,11 @@ def ialm_step(D, S, Y, lam: float, mu: float, levels: int, workspace=None):
     Returns (L, S_next, Y_next, rank)."""
     torch = _torch()
     _check_dev(D, "D", torch.float32)
+    if D.dim() != 2 or D.stride(1) != 1:
+        raise ValueError("D must be a 2-D row-major tensor")
     m, n = D.shape
+    _check_mn(S, "S", m, n)
+    _check_mn(Y, "Y", m, n)
     L = torch.empty((m, n), dtype=torch.float32, device=D.device)
     Sn = torch.empty_like(L)
     Yn = torch.empty_like(L)
@@ -387,9 +405,19 @@ def ialm_step(D, S, Y, lam: float, mu: float, levels: int, workspace=None):
 
 
 def ialm_step_vjp(D, S, Y, lam: float, mu: float, levels: int, L_bar, S_bar, Y_bar, D_bar, workspace=None):
-    """Adjoint of ialm_step: accumulates into D_bar, returns (S_bar_prev, Y_bar_prev, lambda_bar)."""
+    """Adjoint of ialm_step: accumulates into D_bar, returns (S_bar_prev, Y_bar_prev, lambda_bar).
+    D_bar must have D's shape and row stride (the C ABI addresses both with D's leading
+    dimension)."""
     torch = _torch()
+    _check_dev(D, "D", torch.float32)
+    if D.dim() != 2 or D.stride(1) != 1:
+        raise ValueError("D must be a 2-D row-major tensor")
     m, n = D.shape
+    _check_dev(D_bar, "D_bar", torch.float32)
+    if tuple(D_bar.shape) != (m, n) or D_bar.stride(1) != 1 or D_bar.stride(0) != D.stride(0):
+        raise ValueError("D_bar must be m x n with D's row stride")
+    for name, t in (("S", S), ("Y", Y), ("L_bar", L_bar), ("S_bar", S_bar), ("Y_bar", Y_bar)):
+        _check_mn(t, name, m, n)
     Sbp = torch.empty((m, n), dtype=torch.float32, device=D.device)
     Ybp = torch.empty_like(Sbp)
     ws = workspace if workspace is not None else step_workspace(m, n, levels, D.device)
@@ -400,13 +428,6 @@ def ialm_step_vjp(D, S, Y, lam: float, mu: float, levels: int, L_bar, S_bar, Y_b
     if st < 0:
         raise MLPCPError(st, "ialm_step_vjp")
     return Sbp, Ybp, lb.value
-
-
-def penalty_schedule(mu0: float, iters: int, rho: float = 1.5, mu_max_factor: float = 1e7):
-    mus = [float(mu0)]
-    for _ in range(iters - 1):
-        mus.append(min(rho * mus[-1], mu_max_factor * mu0))
-    return mus
 
 
 # ---- unconstrained CPCP by (multilevel) Frank-Wolfe Thresholding ----------------------

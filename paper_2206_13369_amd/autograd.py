@@ -40,6 +40,9 @@ class UnrolledMLPCP(torch.autograd.Function):
     @staticmethod
     def backward(ctx, gL, gS):
         (D,) = ctx.saved_tensors
+        # the adjoint of D shares D's leading dimension in the C ABI: work on a
+        # contiguous D so that both are m x n with ld = n
+        D = D.contiguous()
         Db = torch.zeros_like(D)
         Lb = gL.contiguous() if gL is not None else None
         Sb = gS.contiguous() if gS is not None else None

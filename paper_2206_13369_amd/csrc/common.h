@@ -145,6 +145,15 @@ int gemm_f64(bool transA, bool transB, int M, int N, int K, double alpha, const 
 int rmul_f32_by_f64(int m, int k1, int k2, const float* In, int ldi, const double* W, int ldw,
                     float* Out, int ldo, hipStream_t stream);
 
+// ---- spectral norm of the observed data (spectral.hip) --------------------------------
+// Workspace of spectral_norm_sq for an m x n matrix.
+size_t spectral_workspace_bytes(int m, int n);
+// *out (host) = ||A||_2^2 for A m x n float32 (ld = lda): float64 Gram, its top eigenvalue
+// by repeated squaring and a Rayleigh quotient.  Synchronises `stream`.
+int spectral_norm_sq(int m, int n, const float* A, int lda, void* ws, hipStream_t stream, double* out);
+// out (m x n, ld = n) = Q ? D : 0.
+int stage_masked(int m, int n, const float* D, int ldd, const uint8_t* Q, float* out, hipStream_t stream);
+
 // ---- stencil kernels (operators.hip) ---------------------------------------------------
 // XP = X P  (m x n -> m x nH, float32; the interpolation stencil, no C factor).
 int apply_P(const Operator& op, int m, const float* X, int ldx, float* XP, int ldp, hipStream_t s);

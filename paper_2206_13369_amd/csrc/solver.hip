@@ -113,7 +113,8 @@ __global__ void k_pack_mask(int m, int n, const uint8_t* __restrict__ Q, int nw,
 }
 
 // Initial coarse data: X_0 = P_Q(D - S0 + Y0/mu0) (or X_0 = M for the standalone SVT),
-// M_P = X_0 P (PLAIN: M_P = X_0), and partial sums of ||P_Q D||^2.
+// M_P = X_0 P (PLAIN: M_P = X_0), and partial sums of ||P_Q D||^2 (NaN if an observed
+// entry of D, S0 or Y0 is not finite).
 template <bool PLAIN, bool MASKED>
 __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM, const float* __restrict__ D,
                                                    int ldd, const uint32_t* __restrict__ bits, int nw,
@@ -138,6 +139,7 @@ __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM,
       x = d;
       if (S0) x -= S0[(size_t)gi * n + j];
       if (Y0) x += Y0[(size_t)gi * n + j] * inv_mu0;
+      acc += (double)(x - x);   // 0, or NaN when D, S0 or Y0 is not finite here
     }
     if (PLAIN)
       MP[(size_t)gi * ldp + j] = x;
@@ -1065,19 +1067,37 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     mlpcp_default_opts(&o);
   if (m < 1 || n < 1 || m < n || ldd < n) return MLPCP_E_SHAPE;
   if (!D || !L || !S || (masked && !Q)) return MLPCP_E_INVALID_ARG;
-  if (!(lambda > 0.0f) || !std::isfinite(lambda) || !(mu0 > 0.0) || !std::isfinite(mu0)) return MLPCP_E_INVALID_ARG;
+  if (!(lambda > 0.0f) || !std::isfinite(lambda) || !std::isfinite(mu0)) return MLPCP_E_INVALID_ARG;
   MLPCP_TRY(valid_opts(o));
   if (coarse_dim_checked(n, o.levels) < 1) return MLPCP_E_LEVELS;
   if (L == S || L == Y || (Y && S == Y) || (const float*)L == D || (const float*)S == D) return MLPCP_E_INVALID_ARG;
+  if ((S0 && (const float*)L == S0) || (Y0 && (const float*)L == Y0)) return MLPCP_E_INVALID_ARG;
   Plan p;
   MLPCP_TRY(make_plan(m, n, o.levels, masked, p, o.prec));
-  if (ws && ws_bytes < p.total) return MLPCP_E_WORKSPACE;
+  const size_t need = std::max(p.total, spectral_workspace_bytes(m, n) + 256);
+  if (ws && ws_bytes < need) return MLPCP_E_WORKSPACE;
 
   hipStream_t s = static_cast<hipStream_t>(stream);
   const Operator* op = nullptr;
   MLPCP_TRY(get_operator(n, o.levels, s, &op, o.r_norm));
+  Plan pw = p;
+  pw.total = need;
   WS w;
-  MLPCP_TRY(bind_workspace(p, ws, ws_bytes, w));
+  MLPCP_TRY(bind_workspace(pw, ws, ws_bytes, w));
+  // default initial penalty mu_0 = 1.25 / ||P_Q D||_2 (the workspace serves this phase
+  // first; P_Q D is staged in the L output, which aliases no input)
+  double sigma2 = 0.0;
+  if (mu0 <= 0.0) {
+    const float* A = D;
+    int lda = ldd;
+    if (masked) {
+      MLPCP_TRY(stage_masked(m, n, D, ldd, Q, L, s));
+      A = L;
+      lda = n;
+    }
+    MLPCP_TRY(spectral_norm_sq(m, n, A, lda, w.base, s, &sigma2));
+    mu0 = (sigma2 > 0.0 && std::isfinite(sigma2)) ? 1.25 / std::sqrt(sigma2) : 1.0;
+  }
   float* mp[2] = {w.at<float>(p.off_mp0), w.at<float>(p.off_mp1)};
   uint32_t* bits = masked ? w.at<uint32_t>(p.off_bits) : nullptr;
   double* part = w.at<double>(p.off_part);
@@ -1093,6 +1113,34 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   IterStats hs;
   MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
   MLPCP_HIP(hipStreamSynchronize(s));
+  if (info) info->mu0 = mu0;
+  // an observed entry of D, S0 or Y0 that is NaN or infinite: nothing is iterated
+  if (!std::isfinite(hs.nrm2)) {
+    if (info) {
+      info->iters = 0;
+      info->fg = NAN;
+    }
+    return MLPCP_E_NONFINITE;
+  }
+  // P_Q D = 0: the solution is L = S = 0 (and Y = 0), with no iteration
+  if (hs.nrm2 == 0.0) {
+    MLPCP_HIP(hipMemsetAsync(L, 0, (size_t)m * n * sizeof(float), s));
+    MLPCP_HIP(hipMemsetAsync(S, 0, (size_t)m * n * sizeof(float), s));
+    if (Y) MLPCP_HIP(hipMemsetAsync(Y, 0, (size_t)m * n * sizeof(float), s));
+    MLPCP_HIP(hipStreamSynchronize(s));
+    if (info) {
+      info->iters = 0;
+      info->fg = 0.0;
+      info->rank = 0;
+      info->mu_final = mu0;
+      info->tau_margin = 0.0;
+      info->eig_sweeps = 0;
+      info->gram_bf16_iters = 0;
+      info->gram_split_iters = 0;
+    }
+    return MLPCP_OK;
+  }
+  if (!(mu0 > 0.0)) return MLPCP_E_NONFINITE;
   const double nrmD = std::sqrt(hs.nrm2);
 
   const double mu_max = o.mu_max_factor * mu0;
@@ -1423,7 +1471,8 @@ size_t mlpcp_workspace_bytes(int m, int n, const mlpcp_opts* optp) {
   if (m < 1 || n < 1 || m < n) return 0;
   Plan p;
   if (make_plan(m, n, o.levels, true, p) != MLPCP_OK) return 0;
-  return p.total;
+  // the default-mu_0 phase (mu0 <= 0) runs in the same workspace before the iterations
+  return std::max(p.total, spectral_workspace_bytes(m, n) + 256);
 }
 
 int mlpcp_pcp_solve(int m, int n, const float* D, int ldd, float lambda, double mu0, const mlpcp_opts* opts,

@@ -52,7 +52,11 @@ def test_workspace_bytes():
     o = mlp.default_opts(levels=3)
     a = mlp.workspace_bytes(2000, 2000, o)
     b = mlp.workspace_bytes(4000, 2000, o)
-    assert 0 < a < b
+    assert 0 < a <= b
+    # the default-mu0 phase (Gram of P_Q D and two squaring buffers, 2048^2 doubles each)
+    # shares the workspace, so it bounds the size from below
+    assert a >= 3 * 2048 * 2048 * 8
+    assert mlp.workspace_bytes(262144, 200, mlp.default_opts(levels=4)) >= 262144 * 64 * 4 * 2
     assert mlp.workspace_bytes(10, 20, o) == 0          # m < n
     assert mlp.workspace_bytes(100, 8, mlp.default_opts(levels=4)) == 0
 
@@ -68,7 +72,9 @@ def test_pcp_validation():
     assert _pcp(20, 10, 5, 0.1, 1.0) == mlp.MLPCP_E_SHAPE            # ld < n
     assert _pcp(0, 0, 0, 0.1, 1.0) == mlp.MLPCP_E_SHAPE
     assert _pcp(20, 10, 10, 0.0, 1.0) == mlp.MLPCP_E_INVALID_ARG     # lambda
-    assert _pcp(20, 10, 10, 0.1, -1.0) == mlp.MLPCP_E_INVALID_ARG    # mu0
+    assert _pcp(20, 10, 10, 0.1, float("nan")) == mlp.MLPCP_E_INVALID_ARG    # mu0 (<= 0 selects the default)
+    assert _pcp(20, 10, 10, 0.1, float("inf")) == mlp.MLPCP_E_INVALID_ARG
+    assert _pcp(20, 10, 10, 0.1, float("-inf")) == mlp.MLPCP_E_INVALID_ARG
     assert _pcp(20, 10, 10, float("nan"), 1.0) == mlp.MLPCP_E_INVALID_ARG
     assert _pcp(20, 10, 10, 0.1, 1.0, D=None) == mlp.MLPCP_E_INVALID_ARG
     assert _pcp(20, 10, 10, 0.1, 1.0, L=None) == mlp.MLPCP_E_INVALID_ARG
@@ -84,6 +90,14 @@ def test_pcp_validation():
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(r_norm=3)) == mlp.MLPCP_E_UNSUPPORTED
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(r_norm=-1)) == mlp.MLPCP_E_UNSUPPORTED
     assert _pcp(20, 10, 10, 0.1, 1.0, ws=FAKE, wsb=16) == mlp.MLPCP_E_WORKSPACE
+    # L stages P_Q D for the default mu0, so it may not alias the initial S0 / Y0
+    L_ = ctypes.c_void_p(12288)
+    st = mlp.lib().mlpcp_pcp_solve(20, 10, FAKE, 10, 0.1, 0.0, None, L_, None, L_, ctypes.c_void_p(8192), None,
+                                   None, 0, None, None)
+    assert st == mlp.MLPCP_E_INVALID_ARG
+    st = mlp.lib().mlpcp_pcp_solve(20, 10, FAKE, 10, 0.1, 0.0, None, None, L_, L_, ctypes.c_void_p(8192), None,
+                                   None, 0, None, None)
+    assert st == mlp.MLPCP_E_INVALID_ARG
 
 
 def test_cpcp_validation():

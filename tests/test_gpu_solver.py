@@ -119,3 +119,93 @@ def test_determinism():
     a = _run_gpu(w, 2, fixed=15)
     b = _run_gpu(w, 2, fixed=15)
     assert np.array_equal(to_np(a.L), to_np(b.L)) and np.array_equal(to_np(a.S), to_np(b.S))
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_default_mu0_on_device(masked):
+    """mu0 <= 0 selects 1.25 / ||P_Q D||_2, computed by the library on the device; it
+    matches the oracle's LAPACK spectral norm to 1e-6 and the solve then matches the
+    oracle run with that penalty."""
+    w = synth.gaussian_lowrank_plus_sparse(400, 300, 8, seed=23, sparse_frac=0.08, levels=2,
+                                           observed_frac=0.7 if masked else None)
+    torch, dev = torch_dev()
+    mu_ref = 1.25 / oracle.spectral_norm(w.D, w.Q)
+    say("default mu0", masked)
+    kw = dict(levels=2, tol=1e-6, history=600)
+    D = to_dev(w.D)
+    if masked:
+        res = mlp.cpcp_solve(D, to_dev(w.Q.astype(np.uint8)), w.lam, 0.0, **kw)
+    else:
+        res = mlp.pcp_solve(D, w.lam, None, **kw)
+    torch.cuda.synchronize()
+    say(f"   mu0 {res.mu0:.12e} oracle {mu_ref:.12e}")
+    assert abs(res.mu0 - mu_ref) <= 1e-6 * mu_ref
+    ref = oracle.ialm(w.D, w.lam, res.mu0, Q=w.Q, levels=2, tol=1e-6)
+    assert res.status == mlp.MLPCP_OK and res.iters == ref.iters
+    _check(res, ref)
+
+
+@pytest.mark.parametrize("where", ["D", "S0", "Y0"])
+@pytest.mark.parametrize("value", [float("nan"), float("inf")])
+def test_nonfinite_input_is_reported(where, value):
+    """A NaN or Inf in an observed entry of D, S0 or Y0 gives MLPCP_E_NONFINITE before
+    any iteration (the initial pass over the data detects it)."""
+    w = synth.config("c1")
+    torch, dev = torch_dev()
+    D = w.D.copy()
+    S0 = np.zeros_like(D)
+    Y0 = np.zeros_like(D)
+    {"D": D, "S0": S0, "Y0": Y0}[where][17, 5] = value
+    say("nonfinite", where, value)
+    with pytest.raises(mlp.MLPCPError) as e:
+        mlp.pcp_solve(to_dev(D), w.lam, w.mu0, levels=2, S0=to_dev(S0), Y0=to_dev(Y0))
+    torch.cuda.synchronize()
+    assert e.value.status == mlp.MLPCP_E_NONFINITE
+
+
+def test_nonfinite_off_mask_is_ignored():
+    """D off Q never reaches the result: NaN there gives the same bits as zeros there."""
+    w = synth.gaussian_lowrank_plus_sparse(240, 200, 5, seed=29, sparse_frac=0.05, levels=2, observed_frac=0.6)
+    torch, dev = torch_dev()
+    Dz = np.where(w.Q, w.D, 0.0).astype(np.float32)
+    Dn = np.where(w.Q, w.D, np.nan).astype(np.float32)
+    Q = to_dev(w.Q.astype(np.uint8))
+    say("nan off mask")
+    a = mlp.cpcp_solve(to_dev(Dz), Q, w.lam, w.mu0, levels=2, tol=1e-6)
+    b = mlp.cpcp_solve(to_dev(Dn), Q, w.lam, w.mu0, levels=2, tol=1e-6)
+    torch.cuda.synchronize()
+    assert a.status == b.status == mlp.MLPCP_OK and a.iters == b.iters
+    assert np.array_equal(to_np(a.L), to_np(b.L)) and np.array_equal(to_np(a.S), to_np(b.S))
+
+
+@pytest.mark.parametrize("levels", [0, 2])
+@pytest.mark.parametrize("masked", [False, True])
+def test_max_iter_exhaustion(levels, masked):
+    """max_iter reached before the tolerance: MLPCP_NOT_CONVERGED with valid outputs,
+    equal to the oracle's iterate after max_iter iterations."""
+    w = synth.gaussian_lowrank_plus_sparse(300, 240, 6, seed=37, sparse_frac=0.05, levels=levels,
+                                           observed_frac=0.7 if masked else None)
+    K = 5
+    ref = oracle.ialm(w.D, w.lam, w.mu0, Q=w.Q, levels=levels, fixed_iters=K)
+    say("max_iter", levels, masked)
+    res = _run_gpu(w, levels, tol=1e-6, fixed=K)
+    assert res.status == mlp.MLPCP_NOT_CONVERGED and res.iters == K and res.fg > 1e-6
+    _check(res, ref)
+
+
+@pytest.mark.parametrize("masked", [False, True])
+def test_zero_data(masked):
+    """P_Q D = 0: L = S = Y = 0 with no iteration, status OK (also with the default mu0)."""
+    torch, dev = torch_dev()
+    m, n = 256, 200
+    D = torch.zeros((m, n), dtype=torch.float32, device=dev)
+    say("zero data", masked)
+    for mu0 in (1.0, None):
+        if masked:
+            Q = torch.ones((m, n), dtype=torch.uint8, device=dev)
+            r = mlp.cpcp_solve(D, Q, 0.05, mu0, levels=2)
+        else:
+            r = mlp.pcp_solve(D, 0.05, mu0, levels=2)
+        torch.cuda.synchronize()
+        assert r.status == mlp.MLPCP_OK and r.iters == 0 and r.rank == 0
+        assert not to_np(r.L).any() and not to_np(r.S).any() and not to_np(r.Y).any()

@@ -258,3 +258,41 @@ def test_tolerance_stop():
     res = fw.fwt(D, lam_L, lam_S, Q=Q, tol=1e-3)
     assert res.converged and res.history[-1]["rel_change"] <= 1e-3
     assert all(h["rel_change"] > 1e-3 for h in res.history[:-1])
+
+
+@pytest.mark.parametrize("lam_L,lam_S", [(0.3, 0.7), (0.7, 0.3)])
+def test_first_iteration_closed_form(lam_L, lam_S):
+    """Alg. 3 from its initial point on D = d e_1 e_1^T (Q = all), worked by hand.
+    Start: L = S = 0, t_L = t_S = 0, f_0 = d^2 / 2, U_L = f_0 / lam_L, U_S = f_0 / lam_S.
+    G = -D, so both linear oracles return the atom e_1 e_1^T with <G, M> = -d; both
+    gates open (lam < d).  Along V_L = U_L e_1 e_1^T and V_S = U_S e_1 e_1^T the
+    objective is 1/2 (alpha U_L + beta U_S - d)^2 + lam_L alpha U_L + lam_S beta U_S, a
+    function of x = alpha U_L + beta U_S plus a cost that makes the cheaper weight win:
+    with lam_L < lam_S, x = d - lam_L on the alpha edge, alpha = (d - lam_L) / U_L, beta = 0;
+    otherwise alpha = 0, beta = (d - lam_S) / U_S.  The Frank-Wolfe gap at the start is
+    U_L (d - lam_L) + U_S (d - lam_S).  Step sizes and gap therefore fix both initial
+    bounds (a swap of U_L and U_S changes them)."""
+    d = 2.0
+    D = np.zeros((5, 4))
+    D[0, 0] = d
+    res = fw.fwt(D, lam_L, lam_S, fixed_iters=1)
+    h = res.history[0]
+    f0 = 0.5 * d * d
+    UL, US = f0 / lam_L, f0 / lam_S
+    assert h["takeL"] and h["takeS"]
+    assert h["sigma"] == pytest.approx(d, rel=1e-14) and h["gmax"] == pytest.approx(d, rel=1e-14)
+    assert h["gap"] == pytest.approx(UL * (d - lam_L) + US * (d - lam_S), rel=1e-13)
+    E11 = np.zeros_like(D)
+    E11[0, 0] = 1.0
+    if lam_L < lam_S:
+        assert h["alpha"] == pytest.approx((d - lam_L) / UL, rel=1e-13) and h["beta"] == 0.0
+        # L = (d - lam_L) e_1 e_1^T; the threshold of D - L = lam_L at lam_S leaves S = 0
+        assert np.allclose(res.L, (d - lam_L) * E11, atol=1e-14) and not res.S.any()
+        assert res.t_L == pytest.approx(d - lam_L, rel=1e-14) and res.t_S == 0.0
+        assert res.f == pytest.approx(0.5 * lam_L ** 2 + lam_L * (d - lam_L), rel=1e-14)
+    else:
+        assert h["alpha"] == 0.0 and h["beta"] == pytest.approx((d - lam_S) / US, rel=1e-13)
+        # S_half = (d - lam_S) e_1 e_1^T; the threshold step gives S = S_{lam_S}[D] = (d - lam_S) e_1 e_1^T
+        assert not res.L.any() and np.allclose(res.S, (d - lam_S) * E11, atol=1e-14)
+        assert res.t_L == 0.0 and res.t_S == pytest.approx(d - lam_S, rel=1e-14)
+        assert res.f == pytest.approx(0.5 * lam_S ** 2 + lam_S * (d - lam_S), rel=1e-14)
