@@ -1,8 +1,8 @@
 #!/usr/bin/env python3
 """Benchmark: time to feasibility gap <= 1e-6, multilevel vs plain, on one MI355X.
 
-Workload (default): compressive PCP, 2000 x 2000, rank-50 Gaussian low-rank part,
-10% corruptions U[-10, 10], 60% of entries observed, 3 levels (n_H = 250),
+Headline workload (default): compressive PCP, 2000 x 2000, rank-50 Gaussian low-rank
+part, 10% corruptions U[-10, 10], 60% of entries observed, 3 levels (n_H = 250),
 float32 data (Gram accumulated and eigensolved in float64).
 
 One step = one complete multilevel solve from the initial point to FG <= 1e-6
@@ -10,14 +10,24 @@ One step = one complete multilevel solve from the initial point to FG <= 1e-6
 prolongation, fused soft threshold / mask / dual step / feasibility gap).
 The plain method (levels = 0, the same kernels with R = I) is timed on the same
 input for the speedup.  Inputs are resident in HBM before the timed region.
+The speedup is a time to the same feasibility gap, not to the same recovery: the
+relative errors of L and S against the generating L0 and S0 at the stop are
+reported beside it for both methods (on Q for S in the compressive workloads).
+
+The default line also carries, under "configs", the two tall workloads at their own
+precision and at float32: the 76800 x 400 video stand-in (bf16 tiers, as its
+workload states: bfloat16 GEMMs) and the 262144 x 200 hyperspectral stand-in
+(bf16x3: split-bfloat16 compensated products), each multilevel vs plain with
+iterations, ranks, recovery errors and the roofline of its dominant kernel; and a
+short summary of the Frank-Wolfe comparison (ML-FWT vs FW-T) under "fw".
 
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus N (N must be 1)
---workload {c1,c2,c3,c5,fw1,fw2,fw3,fw4} --no-plain --no-cpu --no-fw --prec {fp32,bf16,bf16x3}.
+--workload {c1,c2,c3,c5,fw1,fw2,fw3,fw4} --no-plain --no-cpu --no-fw --no-configs
+--prec {fp32,bf16,bf16x3}.
 
 The fw workloads measure the unconstrained-CPCP solvers of the Frank-Wolfe comparison
 (Table 2 sizes): one step = one ML-FWT solve to the 1e-3 tolerance (relative objective
-change), beside FW-T on the same input.  The default line also carries a short summary
-of the fw2 workload (10000 x 5000) under "fw".
+change), beside FW-T on the same input.
 """
 import argparse
 import hashlib
@@ -49,6 +59,9 @@ def parse():
     ap.add_argument("--prec", default="fp32", choices=["fp32", "bf16", "bf16x3"],
                     help="arithmetic of the coarse SVT's Gram and reconstruction products")
     ap.add_argument("--no-fw", action="store_true", help="skip the Frank-Wolfe summary of the default line")
+    ap.add_argument("--no-configs", action="store_true",
+                    help="skip the tall workloads (c3, c5) of the default line")
+    ap.add_argument("--config-steps", type=int, default=3, help="timed multilevel solves per tall-workload entry")
     ap.add_argument("--rnorm", type=int, default=0, choices=[0, 1, 2],
                     help="restriction normalisation of the multilevel solve: 0 orthonormal, 1 P/||P||_2, 2 P "
                          "(ablation; the plain solve is unaffected)")
@@ -59,11 +72,30 @@ def parse():
 
 
 def describe(w):
+    import paper_2206_13369_amd as mlp
     masked = w.Q is not None
     kind = "CPCP" if masked else "PCP"
     obs = f", {w.Q.mean():.0%} observed" if masked else ""
     return (f"{w.name}: {kind} {w.m}x{w.n}, rank {w.rank}{obs}, {w.levels} levels "
-            f"(n_H={int(__import__('oracle').coarse_dim(w.n, w.levels))}), FG<=1e-6; {w.recipe}")
+            f"(n_H={mlp.coarse_dim(w.n, w.levels)}), FG<=1e-6; {w.recipe}")
+
+
+def recovery_errors(w, r, dev):
+    """Relative Frobenius errors of the returned L and S against the generating L0 and
+    S0 (S on the observed entries for the compressive problem: off Q it is not
+    identifiable), computed on the device outside the timed region."""
+    import torch
+    L0 = torch.from_numpy(w.L0).to(dev)
+    S0 = torch.from_numpy(w.S0).to(dev)
+    L = r.L.double()
+    S = r.S.double()
+    if w.Q is not None:
+        Q = torch.from_numpy(w.Q).to(dev)
+        S0 = torch.where(Q, S0, torch.zeros_like(S0))
+    eL = float(torch.linalg.norm(L - L0) / torch.linalg.norm(L0))
+    eS = float(torch.linalg.norm(S - S0) / torch.linalg.norm(S0))
+    del L0, S0, L, S
+    return round(eL, 6), round(eS, 6)
 
 
 def algorithmic_work(cls, w, nH, plain, sweeps):
@@ -276,104 +308,15 @@ def main():
     w = synth.config(a.workload)
     t_gen = time.time() - t_gen
     print(f"[bench] workload {w.name} {w.m}x{w.n} generated in {t_gen:.1f}s", file=sys.stderr, flush=True)
-    D = torch.from_numpy(w.D).to(dev)
-    Q = torch.from_numpy(w.Q.astype(np.uint8)).to(dev) if w.Q is not None else None
     if a.calib_copy:
         src = torch.ones(a.calib_copy << 18, dtype=torch.float32, device=dev)
         dst = torch.empty_like(src)
         torch.mul(src, 1.0, out=dst)
         torch.cuda.synchronize()
         del src, dst
-    nH = mlp.coarse_dim(w.n, w.levels)
-
-    def run(levels, ws):
-        kw = dict(levels=levels, tol=a.tol, max_iter=500, want_y=False, workspace=ws, history=600, prec=a.prec,
-                  r_norm=a.rnorm if levels > 0 else 0)
-        if Q is None:
-            return mlp.pcp_solve(D, w.lam, w.mu0, **kw)
-        return mlp.cpcp_solve(D, Q, w.lam, w.mu0, **kw)
-
-    ws_ml = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=w.levels)), dtype=torch.uint8,
-                        device=dev)
-    for i in range(a.warmup):
-        r = run(w.levels, ws_ml)
-        print(f"[bench] warmup {i}: iters {r.iters} fg {r.fg:.2e}", file=sys.stderr, flush=True)
-    # per-kernel breakdown of one solve (every launch bracketed by events)
-    torch.cuda.synchronize()
-    mlp.profile_enable(True)
-    run(w.levels, ws_ml)
-    torch.cuda.synchronize()
-    prof = mlp.profile_read()
-    mlp.profile_enable(False)
-    kernel_ms = {k: round(v[1], 4) for k, v in prof.items() if v[0] > 0}
-    launches = {k: v[0] for k, v in prof.items() if v[0] > 0}
-    dom = max(kernel_ms.items(), key=lambda kv: kv[1])[0]
-
-    # timed region: K solves, no instrumentation
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    results = []
-    for i in range(a.steps):
-        results.append(run(w.levels, ws_ml))
-    torch.cuda.synchronize()
-    t1 = time.perf_counter()
-    ml_s = (t1 - t0) / a.steps
-    r = results[-1]
-    iters = r.iters
-    print(f"[bench] multilevel: {ml_s*1e3:.2f} ms/solve, {iters} iters, fg {r.fg:.2e}, rank {r.rank}; "
-          f"dominant kernel {dom}; Gram bf16/split iters {r.gram_bf16_iters}/{r.gram_split_iters}; "
-          f"last eigensolve sweeps {r.eig_sweeps}",
-          file=sys.stderr, flush=True)
-
-    # the same K solves with HIP events around the dominant kernel class only
-    torch.cuda.synchronize()
-    mlp.profile_enable([dom])
-    ti0 = time.perf_counter()
-    for i in range(a.steps):
-        run(w.levels, ws_ml)
-    torch.cuda.synchronize()
-    ti1 = time.perf_counter()
-    dprof = mlp.profile_read()[dom]
-    mlp.profile_enable(False)
-    dom_launches, dom_ms = dprof
-    inst_s = (ti1 - ti0) / a.steps
-
-    plain = None
-    if not a.no_plain:
-        ws_pl = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=0)), dtype=torch.uint8,
-                            device=dev)
-        torch.cuda.synchronize()
-        mlp.profile_enable(True)       # warm-up solve, also the plain kernel breakdown
-        rp = run(0, ws_pl)
-        torch.cuda.synchronize()
-        pprof = mlp.profile_read()
-        mlp.profile_enable(False)
-        tp0 = time.perf_counter()
-        for _ in range(a.plain_steps):
-            rp = run(0, ws_pl)
-        torch.cuda.synchronize()
-        tp1 = time.perf_counter()
-        plain_s = (tp1 - tp0) / a.plain_steps
-        plain = dict(time_s=plain_s, iters=rp.iters, fg=rp.fg, rank=rp.rank,
-                     kernel_ms={k: round(v[1], 3) for k, v in pprof.items() if v[0] > 0})
-        print(f"[bench] plain: {plain_s*1e3:.1f} ms/solve, {rp.iters} iters, fg {rp.fg:.2e}, rank {rp.rank}",
-              file=sys.stderr, flush=True)
-        del ws_pl
-
-    # roofline of the dominant kernel, from its event-timed launches; the other kernel
-    # classes from the all-class breakdown solve
-    sweeps = r.sweeps_history
-    bound, amount = algorithmic_work(dom, w, nH, False, sweeps)
-    roof = roofline(dom, bound, amount, dom_ms / 1e3 / max(dom_launches, 1), dom_launches)
-    if roof is not None:
-        roof["traffic"] = measured_traffic(w.name, dom)
-    others = {}
-    for cls in kernel_ms:
-        bd, am = algorithmic_work(cls, w, nH, False, sweeps)
-        rf = roofline(cls, bd, am, kernel_ms[cls] / 1e3 / launches[cls], launches[cls])
-        if rf is not None:
-            others[cls] = {k: rf[k] for k in ("bound", "achieved", "unit", "frac", "avg_launch_us")}
-            others[cls]["traffic"] = measured_traffic(w.name, cls)
+    hb = ialm_bench(w, dev, a.steps, a.warmup, a.prec, plain=not a.no_plain, plain_steps=a.plain_steps,
+                    rnorm=a.rnorm, tol=a.tol)
+    ml_s = hb["time_s"]
 
     cpu = None
     if not a.no_cpu:
@@ -391,6 +334,24 @@ def main():
                           f"({ref.iters} iterations, {ref.iters/(tc1-tc0):.2f} iters/s)",
                    iters=ref.iters)
         print(f"[bench] oracle: {tc1-tc0:.2f}s, {ref.iters} iters", file=sys.stderr, flush=True)
+
+    configs = None
+    if not a.no_configs and a.workload == "c2":
+        configs = {}
+        for name, prec in (("c3", "bf16"), ("c5", "bf16x3")):
+            wc = synth.config(name)
+            entry = {"workload": describe(wc)}
+            for pr in (prec, "fp32"):
+                r = ialm_bench(wc, dev, a.config_steps, 1, pr, plain=not a.no_plain, plain_steps=1, tol=a.tol,
+                               breakdown=False)
+                r.pop("kernel_ms_per_solve", None)
+                r.pop("launches_per_solve", None)
+                r.pop("plain_kernel_ms_per_solve", None)
+                r.pop("kernel_rooflines", None)
+                entry[pr] = r
+            configs[name] = entry
+            del wc
+            torch.cuda.empty_cache()
 
     fw = None
     if not a.no_fw and a.workload == "c2":
@@ -411,29 +372,124 @@ def main():
         "scaling": "weak",
         "vs_baseline": None,
         "dtype": "f32" if a.prec == "fp32" else a.prec + "/f32",
-        "precision": {"mode": a.prec, "gram_bf16_iters": r.gram_bf16_iters, "gram_split_iters": r.gram_split_iters},
         "restriction": ["orthonormal P (P^T P)^-1/2", "P / ||P||_2", "P"][a.rnorm],
         "data": "synthetic",
         "config": {"workload": describe(w)},
-        "iters": iters,
-        "iters_per_s": round(iters / ml_s, 2),
-        "fg": r.fg,
-        "rank": r.rank,
-        "plain_time_s": None if plain is None else round(plain["time_s"], 5),
-        "plain_iters": None if plain is None else plain["iters"],
-        "plain_iters_per_s": None if plain is None else round(plain["iters"] / plain["time_s"], 3),
-        "speedup_vs_plain": None if plain is None else round(plain["time_s"] / ml_s, 2),
-        "instrumented_ms_per_step": round(inst_s * 1e3, 4),
-        "kernel_ms_per_solve": kernel_ms,
-        "launches_per_solve": launches,
-        "plain_kernel_ms_per_solve": None if plain is None else plain["kernel_ms"],
-        "sweeps_per_iteration": sweeps,
-        "kernel_rooflines": others,
-        "roofline": roof,
-        "cpu_baseline": cpu,
-        "fw": fw,
+        "speedup_basis": "time to the same feasibility gap FG <= 1e-6 (Sec. 4 stopping measure), not to the same "
+                         "recovery; err_L0 / err_S0 give each method's relative error to the generating L0, S0",
     }
+    out.update({k: v for k, v in hb.items() if k not in ("time_s",)})
+    out["roofline"] = out.pop("roofline")
+    out["cpu_baseline"] = cpu
+    out["configs"] = configs
+    out["fw"] = fw
     print(json.dumps(out))
+
+
+def ialm_bench(w, dev, steps, warmup, prec, *, plain=True, plain_steps=1, rnorm=0, tol=1e-6, breakdown=True):
+    """Multilevel (and plain) solves of one workload to FG <= tol on a resident input:
+    mean time per solve over `steps` timed solves, iterations, ranks, recovery errors,
+    the per-kernel breakdown of one solve and the roofline of its dominant kernel."""
+    import numpy as np
+    import torch
+
+    import paper_2206_13369_amd as mlp
+    D = torch.from_numpy(w.D).to(dev)
+    Q = torch.from_numpy(w.Q.astype(np.uint8)).to(dev) if w.Q is not None else None
+    nH = mlp.coarse_dim(w.n, w.levels)
+
+    def run(levels, ws, pr=prec):
+        kw = dict(levels=levels, tol=tol, max_iter=500, want_y=False, workspace=ws, history=600, prec=pr,
+                  r_norm=rnorm if levels > 0 else 0)
+        if Q is None:
+            return mlp.pcp_solve(D, w.lam, w.mu0, **kw)
+        return mlp.cpcp_solve(D, Q, w.lam, w.mu0, **kw)
+
+    ws_ml = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=w.levels)), dtype=torch.uint8,
+                        device=dev)
+    for i in range(max(warmup, 1)):
+        r = run(w.levels, ws_ml)
+        print(f"[bench] {w.name} {prec} warmup {i}: iters {r.iters} fg {r.fg:.2e}", file=sys.stderr, flush=True)
+    # per-kernel breakdown of one solve (every launch bracketed by events)
+    torch.cuda.synchronize()
+    mlp.profile_enable(True)
+    run(w.levels, ws_ml)
+    torch.cuda.synchronize()
+    prof = mlp.profile_read()
+    mlp.profile_enable(False)
+    kernel_ms = {k: round(v[1], 4) for k, v in prof.items() if v[0] > 0}
+    launches = {k: v[0] for k, v in prof.items() if v[0] > 0}
+    dom = max(kernel_ms.items(), key=lambda kv: kv[1])[0]
+
+    # timed region: `steps` solves, no instrumentation
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    results = []
+    for _ in range(steps):
+        results.append(run(w.levels, ws_ml))
+    torch.cuda.synchronize()
+    ml_s = (time.perf_counter() - t0) / steps
+    r = results[-1]
+    del results
+    eL, eS = recovery_errors(w, r, dev)
+    print(f"[bench] {w.name} {prec} multilevel: {ml_s*1e3:.2f} ms/solve, {r.iters} iters, fg {r.fg:.2e}, "
+          f"rank {r.rank}, errL0 {eL:.3g}, errS0 {eS:.3g}; dominant kernel {dom}; Gram bf16/split iters "
+          f"{r.gram_bf16_iters}/{r.gram_split_iters}", file=sys.stderr, flush=True)
+
+    # the same solves with HIP events around the dominant kernel class only
+    torch.cuda.synchronize()
+    mlp.profile_enable([dom])
+    ti0 = time.perf_counter()
+    for _ in range(steps):
+        run(w.levels, ws_ml)
+    torch.cuda.synchronize()
+    inst_s = (time.perf_counter() - ti0) / steps
+    dom_launches, dom_ms = mlp.profile_read()[dom]
+    mlp.profile_enable(False)
+    del ws_ml
+
+    out = dict(time_s=ml_s, prec=prec, iters=r.iters, iters_per_s=round(r.iters / ml_s, 2), fg=r.fg, rank=r.rank,
+               err_L0=eL, err_S0=eS, tau_margin=r.tau_margin,
+               gram_tiers={"bf16": r.gram_bf16_iters, "split": r.gram_split_iters})
+    if plain:
+        ws_pl = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=0)), dtype=torch.uint8,
+                            device=dev)
+        torch.cuda.synchronize()
+        mlp.profile_enable(True)       # warm-up solve, also the plain kernel breakdown
+        rp = run(0, ws_pl)
+        torch.cuda.synchronize()
+        pprof = mlp.profile_read()
+        mlp.profile_enable(False)
+        tp0 = time.perf_counter()
+        for _ in range(plain_steps):
+            rp = run(0, ws_pl)
+        torch.cuda.synchronize()
+        plain_s = (time.perf_counter() - tp0) / plain_steps
+        peL, peS = recovery_errors(w, rp, dev)
+        print(f"[bench] {w.name} {prec} plain: {plain_s*1e3:.1f} ms/solve, {rp.iters} iters, fg {rp.fg:.2e}, "
+              f"rank {rp.rank}, errL0 {peL:.3g}, errS0 {peS:.3g}", file=sys.stderr, flush=True)
+        out.update(plain_time_s=round(plain_s, 5), plain_iters=rp.iters,
+                   plain_iters_per_s=round(rp.iters / plain_s, 3), plain_rank=rp.rank, plain_fg=rp.fg,
+                   plain_err_L0=peL, plain_err_S0=peS, speedup_vs_plain=round(plain_s / ml_s, 2),
+                   plain_kernel_ms_per_solve={k: round(v[1], 3) for k, v in pprof.items() if v[0] > 0})
+        del ws_pl, rp
+
+    sweeps = r.sweeps_history
+    bound, amount = algorithmic_work(dom, w, nH, False, sweeps)
+    roof = roofline(dom, bound, amount, dom_ms / 1e3 / max(dom_launches, 1), dom_launches)
+    if roof is not None:
+        roof["traffic"] = measured_traffic(w.name, dom)
+    others = {}
+    for cls in kernel_ms:
+        bd, am = algorithmic_work(cls, w, nH, False, sweeps)
+        rf = roofline(cls, bd, am, kernel_ms[cls] / 1e3 / launches[cls], launches[cls])
+        if rf is not None:
+            others[cls] = {k: rf[k] for k in ("bound", "achieved", "unit", "frac", "avg_launch_us")}
+            others[cls]["traffic"] = measured_traffic(w.name, cls)
+    out.update(instrumented_ms_per_step=round(inst_s * 1e3, 4), kernel_ms_per_solve=kernel_ms,
+               launches_per_solve=launches, sweeps_per_iteration=sweeps, kernel_rooflines=others, roofline=roof)
+    del r, D, Q
+    return out
 
 
 if __name__ == "__main__":
