@@ -180,6 +180,20 @@ int mlpcp_cpcp_solve(int m, int n, const float* D, int ldd, const uint8_t* Q,
 int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
                    float* L, int* rank, void* ws, size_t ws_bytes, void* stream);
 
+/* mlpcp_svt_prox without any device allocation, for callers that cannot allocate
+ * (code under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc): the same kernels and result as mlpcp_svt_prox, with the workspace, and
+ * the restriction operator of the last (n, levels) served, in a static device array
+ * of 64 MiB that the library holds on each GPU it runs on until the process ends.
+ * Sizes whose operator plus workspace exceed it return MLPCP_E_WORKSPACE before
+ * anything is launched.  The first call on a device looks up the array's device
+ * address once; a call with a new (n, levels) rebuilds the operator in the array.
+ * Every call on one GPU shares its array: calls that overlap on one GPU (other
+ * threads, other streams) race and must be serialised by the caller.  Kernel timing
+ * (mlpcp_profile_enable) must be off.  Synchronises the stream.               */
+int mlpcp_svt_prox_static(int m, int n, const float* M, int ldm, int levels, float tau,
+                          float* L, int* rank, void* stream);
+
 /* Elementwise soft threshold S_tau[x] = sign(x) max(|x| - tau, 0) (the sparse
  * step of Alg. 1), on `count` contiguous floats.  Y may alias X.  tau >= 0.
  * NaN inputs propagate.                                                      */

@@ -38,6 +38,7 @@ EXPORTED = (
     "mlpcp_cpcp_solve", "mlpcp_svt_prox", "mlpcp_shrink", "mlpcp_restrict", "mlpcp_prolong",
     "mlpcp_status_string", "mlpcp_profile_enable", "mlpcp_profile_read", "mlpcp_step_workspace_bytes",
     "mlpcp_ialm_step", "mlpcp_ialm_step_vjp", "mlpcp_fwt_workspace_bytes", "mlpcp_cpcp_fwt",
+    "mlpcp_svt_prox_static",
 )
 
 
@@ -102,6 +103,8 @@ def lib() -> ctypes.CDLL:
     L.mlpcp_cpcp_solve.restype = i
     L.mlpcp_svt_prox.argtypes = [i, i, vp, i, i, f, vp, ctypes.POINTER(i), vp, sz, vp]
     L.mlpcp_svt_prox.restype = i
+    L.mlpcp_svt_prox_static.argtypes = [i, i, vp, i, i, f, vp, ctypes.POINTER(i), vp]
+    L.mlpcp_svt_prox_static.restype = i
     L.mlpcp_shrink.argtypes = [sz, vp, f, vp, vp]
     L.mlpcp_shrink.restype = i
     L.mlpcp_restrict.argtypes = [i, i, vp, i, i, vp, i, vp]

@@ -58,6 +58,7 @@ struct Operator {
   int* col_row = nullptr;     // [nnz]
   float* col_w = nullptr;     // [nnz]
   double* C = nullptr;        // [nH * nH] (nullptr when levels == 0)
+  void* mem = nullptr;        // device block holding the tables and C (owned by the cache)
 };
 
 // Returns the cached operator for (n, levels, r_norm) on the current device, building it
@@ -65,6 +66,12 @@ struct Operator {
 // r_norm 0: C = (P^T P)^{-1/2} (orthonormal R = P C); 1: C = I / ||P||_2; 2: C = I (the
 // literal interpolation operator).
 int get_operator(int n, int levels, hipStream_t stream, const Operator** out, int r_norm = 0);
+// The same operator built into caller memory: `mem` (operator_bytes: the tables and C,
+// kept) and `tmp` (operator_tmp_bytes: the eigensolve that forms C, free again on
+// return).  Synchronises `stream`.
+size_t operator_bytes(int n, int levels);
+size_t operator_tmp_bytes(int n, int levels);
+int build_operator_at(int n, int levels, int r_norm, hipStream_t stream, Operator* op, void* mem, void* tmp);
 
 // Builds the composite interpolation stencil on the host (also used by host tests
 // through mlpcp_coarse_dim and by get_operator).

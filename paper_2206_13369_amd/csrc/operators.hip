@@ -13,6 +13,7 @@
 // range(P) (the normalisation for which the nuclear-norm gap of Thm. LH-eps vanishes).
 #include "common.h"
 
+#include <algorithm>
 #include <cmath>
 #include <cstring>
 #include <map>
@@ -120,12 +121,7 @@ __global__ void k_scale_cols_invsqrt(const double* __restrict__ V, const double*
 struct OpDeleter {
   void operator()(Operator* op) const {
     if (!op) return;
-    (void)hipFree(op->row_idx);
-    (void)hipFree(op->row_w);
-    (void)hipFree(op->col_ptr);
-    (void)hipFree(op->col_row);
-    (void)hipFree(op->col_w);
-    (void)hipFree(op->C);
+    (void)hipFree(op->mem);
     delete op;
   }
 };
@@ -133,17 +129,64 @@ struct OpDeleter {
 std::mutex g_op_mutex;
 std::map<std::tuple<int, int, int>, std::unique_ptr<Operator, OpDeleter>> g_ops;
 
+// Device memory of one operator, carved from two blocks: `kept` (stencil tables and C,
+// alive as long as the operator) and `tmp` (the eigensolve that forms C).
+struct OpLayout {
+  size_t off_row_idx, off_row_w, off_col_ptr, off_col_row, off_col_w, off_C, kept;
+  size_t off_A, off_V, off_W, off_lam, off_perm, off_ews, tmp;
+};
+
+OpLayout op_layout(int n, int levels) {
+  OpLayout l{};
+  const int nH = coarse_dim_checked(n, levels);
+  const size_t nnz = (size_t)kMaxStencil * n;   // upper bound on the nonzeros of P
+  size_t off = 0;
+  auto take = [&](size_t b) {
+    const size_t o = off;
+    off += align256(std::max<size_t>(b, 1));
+    return o;
+  };
+  l.off_row_idx = take((size_t)n * kMaxStencil * sizeof(int));
+  l.off_row_w = take((size_t)n * kMaxStencil * sizeof(float));
+  l.off_col_ptr = take((size_t)(nH + 1) * sizeof(int));
+  l.off_col_row = take(nnz * sizeof(int));
+  l.off_col_w = take(nnz * sizeof(float));
+  l.off_C = take(levels > 0 ? (size_t)nH * nH * sizeof(double) : 0);
+  l.kept = off;
+  off = 0;
+  if (levels > 0) {
+    const int N = round_up(nH, kPad);
+    const size_t nn = (size_t)N * N * sizeof(double);
+    l.off_A = take(nn);
+    l.off_V = take(nn);
+    l.off_W = take(nn);
+    l.off_lam = take((size_t)N * sizeof(double));
+    l.off_perm = take((size_t)N * sizeof(int));
+    l.off_ews = take(eig_workspace_bytes(N));
+  }
+  l.tmp = off;
+  return l;
+}
+
 template <typename T>
-int upload(const std::vector<T>& h, T** d) {
-  const size_t bytes = std::max<size_t>(h.size(), 1) * sizeof(T);
-  MLPCP_HIP(hipMalloc(reinterpret_cast<void**>(d), bytes));
-  if (!h.empty()) MLPCP_HIP(hipMemcpy(*d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice));
+int upload(const std::vector<T>& h, T* d, hipStream_t s) {
+  if (!h.empty()) MLPCP_HIP(hipMemcpyAsync(d, h.data(), h.size() * sizeof(T), hipMemcpyHostToDevice, s));
   return MLPCP_OK;
 }
 
-int build_operator(int n, int levels, int r_norm, hipStream_t stream, Operator* op) {
+}  // namespace
+
+size_t operator_bytes(int n, int levels) { return coarse_dim_checked(n, levels) < 1 ? 0 : op_layout(n, levels).kept; }
+size_t operator_tmp_bytes(int n, int levels) {
+  return coarse_dim_checked(n, levels) < 1 ? 0 : op_layout(n, levels).tmp;
+}
+
+int build_operator_at(int n, int levels, int r_norm, hipStream_t stream, Operator* op, void* mem, void* tmpmem) {
   const int nH = coarse_dim_checked(n, levels);
   if (nH < 1) return MLPCP_E_LEVELS;
+  const OpLayout l = op_layout(n, levels);
+  char* base = static_cast<char*>(mem);
+  char* tb = static_cast<char*>(tmpmem);
   op->n = n;
   op->levels = levels;
   op->nH = nH;
@@ -160,12 +203,21 @@ int build_operator(int n, int levels, int r_norm, hipStream_t stream, Operator* 
     for (int j = 0; j < n; ++j)
       if (row_cnt[j] > kMaxStencil) return MLPCP_E_UNSUPPORTED;
   }
-  MLPCP_TRY(upload(ri, &op->row_idx));
-  MLPCP_TRY(upload(rw, &op->row_w));
-  MLPCP_TRY(upload(cp, &op->col_ptr));
-  MLPCP_TRY(upload(cr, &op->col_row));
-  MLPCP_TRY(upload(cw, &op->col_w));
-  if (levels == 0) return MLPCP_OK;
+  op->row_idx = reinterpret_cast<int*>(base + l.off_row_idx);
+  op->row_w = reinterpret_cast<float*>(base + l.off_row_w);
+  op->col_ptr = reinterpret_cast<int*>(base + l.off_col_ptr);
+  op->col_row = reinterpret_cast<int*>(base + l.off_col_row);
+  op->col_w = reinterpret_cast<float*>(base + l.off_col_w);
+  op->C = levels > 0 ? reinterpret_cast<double*>(base + l.off_C) : nullptr;
+  MLPCP_TRY(upload(ri, op->row_idx, stream));
+  MLPCP_TRY(upload(rw, op->row_w, stream));
+  MLPCP_TRY(upload(cp, op->col_ptr, stream));
+  MLPCP_TRY(upload(cr, op->col_row, stream));
+  MLPCP_TRY(upload(cw, op->col_w, stream));
+  if (levels == 0) {
+    MLPCP_HIP(hipStreamSynchronize(stream));   // the host tables go out of scope
+    return MLPCP_OK;
+  }
   // P^T P from the column lists (exact: dyadic weights), then C = (P^T P)^{-1/2}
   const int N = round_up(nH, kPad);
   std::vector<double> PtP((size_t)N * N, 0.0);
@@ -177,49 +229,47 @@ int build_operator(int n, int levels, int r_norm, hipStream_t stream, Operator* 
       for (const auto& a : rowsP[j])
         for (const auto& b : rowsP[j]) PtP[(size_t)a.first * N + b.first] += a.second * b.second;
   }
-  double *dA = nullptr, *dV = nullptr, *dW = nullptr, *dlam = nullptr;
-  int* dperm = nullptr;
-  void* ews = nullptr;
-  int st = MLPCP_OK;
+  double* dA = reinterpret_cast<double*>(tb + l.off_A);
+  double* dV = reinterpret_cast<double*>(tb + l.off_V);
+  double* dW = reinterpret_cast<double*>(tb + l.off_W);
+  double* dlam = reinterpret_cast<double*>(tb + l.off_lam);
+  int* dperm = reinterpret_cast<int*>(tb + l.off_perm);
+  void* ews = tb + l.off_ews;
   const size_t nn = (size_t)N * N;
-  if (hipMalloc(&dA, nn * 8) != hipSuccess || hipMalloc(&dV, nn * 8) != hipSuccess ||
-      hipMalloc(&dW, nn * 8) != hipSuccess || hipMalloc(&dlam, (size_t)N * 8) != hipSuccess ||
-      hipMalloc(&dperm, (size_t)N * 4) != hipSuccess || hipMalloc(&ews, eig_workspace_bytes(N)) != hipSuccess ||
-      hipMalloc(&op->C, (size_t)nH * nH * 8) != hipSuccess) {
-    st = MLPCP_E_HIP;
-  }
-  if (st == MLPCP_OK && hipMemcpyAsync(dA, PtP.data(), nn * 8, hipMemcpyHostToDevice, stream) != hipSuccess)
-    st = MLPCP_E_HIP;
+  MLPCP_HIP(hipMemcpyAsync(dA, PtP.data(), nn * 8, hipMemcpyHostToDevice, stream));
   int sweeps = 0;
-  if (st == MLPCP_OK) st = eig_sym(nH, N, dA, dV, dlam, dperm, ews, stream, &sweeps, false);
-  if (st == MLPCP_OK && r_norm == 0) {
+  MLPCP_TRY(eig_sym(nH, N, dA, dV, dlam, dperm, ews, stream, &sweeps, false));
+  if (r_norm == 0) {
     const size_t cnt = (size_t)nH * nH;
     hipLaunchKernelGGL(k_scale_cols_invsqrt, dim3((unsigned)((cnt + 255) / 256)), dim3(256), 0, stream, dV, dlam,
                        N, nH, dW);
-    st = gemm_f64(false, true, nH, nH, nH, 1.0, dW, N, dV, N, op->C, nH, stream);
-  } else if (st == MLPCP_OK) {
+    MLPCP_TRY(gemm_f64(false, true, nH, nH, nH, 1.0, dW, N, dV, N, op->C, nH, stream));
+  } else {
     // the literal interpolation operator: C = I / ||P||_2 (r_norm 1) or C = I (r_norm 2);
     // ||P||_2^2 is the largest eigenvalue of P^T P
     std::vector<double> hl(N, 0.0);
-    if (hipMemcpyAsync(hl.data(), dlam, (size_t)N * 8, hipMemcpyDeviceToHost, stream) != hipSuccess ||
-        hipStreamSynchronize(stream) != hipSuccess) {
-      st = MLPCP_E_HIP;
-    } else {
-      double lmax = 0.0;
-      for (int i = 0; i < nH; ++i) lmax = std::max(lmax, hl[i]);
-      const double sc = r_norm == 1 ? 1.0 / std::sqrt(lmax) : 1.0;
-      std::vector<double> hc((size_t)nH * nH, 0.0);
-      for (int i = 0; i < nH; ++i) hc[(size_t)i * nH + i] = sc;
-      if (hipMemcpyAsync(op->C, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, stream) != hipSuccess) st = MLPCP_E_HIP;
-    }
+    MLPCP_HIP(hipMemcpyAsync(hl.data(), dlam, (size_t)N * 8, hipMemcpyDeviceToHost, stream));
+    MLPCP_HIP(hipStreamSynchronize(stream));
+    double lmax = 0.0;
+    for (int i = 0; i < nH; ++i) lmax = std::max(lmax, hl[i]);
+    const double sc = r_norm == 1 ? 1.0 / std::sqrt(lmax) : 1.0;
+    std::vector<double> hc((size_t)nH * nH, 0.0);
+    for (int i = 0; i < nH; ++i) hc[(size_t)i * nH + i] = sc;
+    MLPCP_HIP(hipMemcpyAsync(op->C, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, stream));
   }
-  if (st == MLPCP_OK && hipStreamSynchronize(stream) != hipSuccess) st = MLPCP_E_HIP;
-  (void)hipFree(dA);
-  (void)hipFree(dV);
-  (void)hipFree(dW);
-  (void)hipFree(dlam);
-  (void)hipFree(dperm);
-  (void)hipFree(ews);
+  MLPCP_HIP(hipStreamSynchronize(stream));
+  return MLPCP_OK;
+}
+
+namespace {
+
+int build_operator(int n, int levels, int r_norm, hipStream_t stream, Operator* op) {
+  const OpLayout l = op_layout(n, levels);
+  MLPCP_HIP(hipMalloc(&op->mem, l.kept));
+  void* tmp = nullptr;
+  if (l.tmp) MLPCP_HIP(hipMalloc(&tmp, l.tmp));
+  const int st = build_operator_at(n, levels, r_norm, stream, op, op->mem, tmp);
+  if (tmp) (void)hipFree(tmp);
   return st;
 }
 
@@ -283,7 +333,7 @@ unsigned stream_grid(size_t total) {
   return (unsigned)b;
 }
 
-// XH rows = (X rows P) C for ROWS rows per block, accumulated in float64.
+// XH rows = (X rows P) C for RROWS rows per block, accumulated in float64.
 constexpr int RROWS = 8;
 __global__ void __launch_bounds__(256) k_restrict_full(int m, int n, int nH, const float* __restrict__ X, int ldx,
                                                        float* __restrict__ XH, int ldh,

@@ -20,6 +20,8 @@
 // large corruptions, so the updates are written in terms of W and clip(D + W) and never
 // subtract two large float32 numbers.  A final pass recomputes L from the last coarse
 // factors and writes L, S = S[D + W] and Y.
+#include <mutex>
+
 #include "common.h"
 #include "profile.h"
 
@@ -1454,6 +1456,76 @@ int step_args_ok(int m, int n, int levels, const float* D, int ldd, float lambda
   return MLPCP_OK;
 }
 
+int svt_prox_args(int m, int n, const float* M, int ldm, int levels, float tau, const float* L) {
+  if (m < 1 || n < 1 || m < n || ldm < n) return MLPCP_E_SHAPE;
+  if (!M || !L) return MLPCP_E_INVALID_ARG;
+  if (!(tau > 0.0f) || !std::isfinite(tau)) return MLPCP_E_INVALID_ARG;
+  if (coarse_dim_checked(n, levels) < 1) return MLPCP_E_LEVELS;
+  return MLPCP_OK;
+}
+
+// L = SVT_tau(M R) R^T with the workspace bound to `w` (plan `p`).  Synchronises.
+int svt_prox_core(const Plan& p, const Operator& op, const WS& w, const float* M, int ldm, float tau, float* L,
+                  int* rank, hipStream_t s) {
+  float* mp = w.at<float>(p.off_mp0);
+  if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
+  MLPCP_TRY(launch_init(p, op, M, ldm, nullptr, nullptr, nullptr, 0.0f, mp, nullptr, s));
+  int sweeps = 0;
+  MLPCP_TRY(coarse_svt(p, op, w, mp, (double)tau, s, &sweeps, false, true));
+  EpiArgs a{};
+  a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+  a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
+  a.st = w.at<IterStats>(p.off_stats);
+  a.Lout = L;
+  a.row_idx = op.row_idx; a.row_w = op.row_w;
+  int nparts = 0;
+  MLPCP_TRY(launch_epilogue<MODE_RECON>(p, a, w.at<double>(p.off_K), op.nnz, s, &nparts));
+  IterStats hs;
+  MLPCP_HIP(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
+  MLPCP_HIP(hipStreamSynchronize(s));
+  MLPCP_TRY(resolve_sweeps(sweeps, hs));
+  if (rank) *rank = hs.rank;
+  return MLPCP_OK;
+}
+
+// ---- the allocation-free entry point ------------------------------------------------
+// Its workspace (and the operator of the last (n, levels) it served) lives in one
+// file-scope device array per GPU.  In host code `scratch` is only a symbol: its device
+// address on the current GPU comes from hipGetSymbolAddress, taken once per device on
+// the first call there and kept; kernels and copies get that address, never the name.
+constexpr size_t kScratchBytes = (size_t)64 << 20;
+
+struct StaticScratch {
+  void* ptr = nullptr;
+  int op_n = -1, op_levels = -1;   // operator currently built at the start of the array
+  Operator op;
+};
+
+std::mutex g_scratch_mutex;
+StaticScratch g_scratch[64];
+
+}  // namespace
+
+static __device__ __align__(256) unsigned char scratch[kScratchBytes];
+
+namespace {
+
+int static_scratch(StaticScratch** out) {
+  int dev = 0;
+  MLPCP_HIP(hipGetDevice(&dev));
+  if (dev < 0 || dev >= 64) return MLPCP_E_UNSUPPORTED;
+  std::lock_guard<std::mutex> lock(g_scratch_mutex);
+  StaticScratch& sc = g_scratch[dev];
+  if (!sc.ptr) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || p == nullptr) return MLPCP_E_HIP;
+    sc.ptr = p;
+  }
+  *out = &sc;
+  return MLPCP_OK;
+}
+
 }  // namespace
 
 }  // namespace mlpcp
@@ -1489,10 +1561,7 @@ int mlpcp_cpcp_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, fl
 
 int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau, float* L, int* rank, void* ws,
                    size_t ws_bytes, void* stream) {
-  if (m < 1 || n < 1 || m < n || ldm < n) return MLPCP_E_SHAPE;
-  if (!M || !L) return MLPCP_E_INVALID_ARG;
-  if (!(tau > 0.0f) || !std::isfinite(tau)) return MLPCP_E_INVALID_ARG;
-  if (coarse_dim_checked(n, levels) < 1) return MLPCP_E_LEVELS;
+  MLPCP_TRY(svt_prox_args(m, n, M, ldm, levels, tau, L));
   Plan p;
   MLPCP_TRY(make_plan(m, n, levels, false, p));
   if (ws && ws_bytes < p.total) return MLPCP_E_WORKSPACE;
@@ -1501,25 +1570,30 @@ int mlpcp_svt_prox(int m, int n, const float* M, int ldm, int levels, float tau,
   MLPCP_TRY(get_operator(n, levels, s, &op));
   WS w;
   MLPCP_TRY(bind_workspace(p, ws, ws_bytes, w));
-  float* mp = w.at<float>(p.off_mp0);
-  if (!p.plain) MLPCP_HIP(hipMemsetAsync(w.at<void>(p.off_GH), 0, (size_t)p.nHp * p.nHp * 8, s));
-  MLPCP_TRY(launch_init(p, *op, M, ldm, nullptr, nullptr, nullptr, 0.0f, mp, nullptr, s));
-  int sweeps = 0;
-  MLPCP_TRY(coarse_svt(p, *op, w, mp, (double)tau, s, &sweeps, false, true));
-  EpiArgs a{};
-  a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
-  a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
-  a.st = w.at<IterStats>(p.off_stats);
-  a.Lout = L;
-  a.row_idx = op->row_idx; a.row_w = op->row_w;
-  int nparts = 0;
-  MLPCP_TRY(launch_epilogue<MODE_RECON>(p, a, w.at<double>(p.off_K), op->nnz, s, &nparts));
-  IterStats hs;
-  MLPCP_HIP(hipMemcpyAsync(&hs, a.st, sizeof(hs), hipMemcpyDeviceToHost, s));
-  MLPCP_HIP(hipStreamSynchronize(s));
-  MLPCP_TRY(resolve_sweeps(sweeps, hs));
-  if (rank) *rank = hs.rank;
-  return MLPCP_OK;
+  return svt_prox_core(p, *op, w, M, ldm, tau, L, rank, s);
+}
+
+int mlpcp_svt_prox_static(int m, int n, const float* M, int ldm, int levels, float tau, float* L, int* rank,
+                          void* stream) {
+  MLPCP_TRY(svt_prox_args(m, n, M, ldm, levels, tau, L));
+  Plan p;
+  MLPCP_TRY(make_plan(m, n, levels, false, p));
+  const size_t op_bytes = align256(operator_bytes(n, levels));
+  if (op_bytes + std::max(p.total, operator_tmp_bytes(n, levels)) > kScratchBytes) return MLPCP_E_WORKSPACE;
+  hipStream_t s = static_cast<hipStream_t>(stream);
+  StaticScratch* sc = nullptr;
+  MLPCP_TRY(static_scratch(&sc));
+  char* base = static_cast<char*>(sc->ptr);
+  // the operator sits at the start of the array, the solver's workspace after it
+  if (sc->op_n != n || sc->op_levels != levels) {
+    sc->op_n = -1;
+    MLPCP_TRY(build_operator_at(n, levels, 0, s, &sc->op, base, base + op_bytes));
+    sc->op_n = n;
+    sc->op_levels = levels;
+  }
+  WS w;
+  w.base = base + op_bytes;
+  return svt_prox_core(p, sc->op, w, M, ldm, tau, L, rank, s);
 }
 
 }  // extern "C"
