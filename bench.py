@@ -18,11 +18,13 @@ The default line also carries, under "configs", the two tall workloads at their 
 precision and at float32: the 76800 x 400 video stand-in (bf16 tiers, as its
 workload states: bfloat16 GEMMs) and the 262144 x 200 hyperspectral stand-in
 (bf16x3: split-bfloat16 compensated products), each multilevel vs plain with
-iterations, ranks, recovery errors and the roofline of its dominant kernel; and a
-short summary of the Frank-Wolfe comparison (ML-FWT vs FW-T) under "fw".
+iterations, ranks, recovery errors and the roofline of its dominant kernel; the
+achieved HBM bandwidth of the standalone restrict, prolong and shrink at the
+hyperspectral shape under "streaming"; and a short summary of the Frank-Wolfe
+comparison (ML-FWT vs FW-T) under "fw".
 
 Prints ONE JSON line.  Options: --steps K --warmup W --gpus N (N must be 1)
---workload {c1,c2,c3,c5,fw1,fw2,fw3,fw4} --no-plain --no-cpu --no-fw --no-configs
+--workload {c1,c2,c3,c5,fw1,fw2,fw3,fw4} --no-plain --no-cpu --no-fw --no-configs --no-stream
 --prec {fp32,bf16,bf16x3}.
 
 The fw workloads measure the unconstrained-CPCP solvers of the Frank-Wolfe comparison
@@ -62,6 +64,7 @@ def parse():
     ap.add_argument("--no-configs", action="store_true",
                     help="skip the tall workloads (c3, c5) of the default line")
     ap.add_argument("--config-steps", type=int, default=3, help="timed multilevel solves per tall-workload entry")
+    ap.add_argument("--no-stream", action="store_true", help="skip the streaming-kernel bandwidth summary")
     ap.add_argument("--rnorm", type=int, default=0, choices=[0, 1, 2],
                     help="restriction normalisation of the multilevel solve: 0 orthonormal, 1 P/||P||_2, 2 P "
                          "(ablation; the plain solve is unaffected)")
@@ -229,6 +232,63 @@ def fw_bench(w, dev, steps, plain=True, cpu=True):
     return out
 
 
+def stream_bench(dev, m=262144, n=200, levels=4, reps=10):
+    """Achieved HBM bandwidth of the standalone streaming entry points (restrict, prolong,
+    shrink) at the hyperspectral workload's shape.  The 210 MB operand fits the 256 MB
+    Infinity Cache, so back-to-back launches read it partly from there; the HBM figure is
+    the median of `reps` single launches each preceded by a read of a 768 MiB buffer
+    (clean lines only, so the timed launch evicts without write-backs), timed by events
+    on the stream the library launches on (torch's current stream).  Algorithmic bytes =
+    what each call must read and write once.  The back-to-back (cache-warm) rate is
+    reported beside it."""
+    import torch
+
+    import paper_2206_13369_amd as mlp
+    g = torch.Generator(device=dev)
+    g.manual_seed(5)
+    X = torch.randn((m, n), generator=g, device=dev, dtype=torch.float32)
+    nH = mlp.coarse_dim(n, levels)
+    XH = mlp.restrict(X, levels)
+    Y = torch.empty_like(X)
+    flush = torch.ones(768 * 1024 * 1024 // 4, device=dev, dtype=torch.float32)
+    sink = torch.empty(1, device=dev, dtype=torch.float32)
+    cases = {
+        "restrict": (lambda: mlp.restrict(X, levels), 4.0 * m * n + 4.0 * m * nH),
+        "prolong": (lambda: mlp.prolong(XH, n, levels), 4.0 * m * nH + 4.0 * m * n),
+        "shrink": (lambda: mlp.shrink(X, 0.5, out=Y), 8.0 * m * n),
+        "copy (torch, reference)": (lambda: Y.copy_(X), 8.0 * m * n),
+    }
+    out = {"shape": f"{m}x{n}, {levels} levels (n_H={nH})", "timing": "cold: one launch after a 768 MiB read; "
+           "warm: mean of back-to-back launches"}
+    for name, (fn, byts) in cases.items():
+        for _ in range(3):
+            fn()
+        ts = []
+        for _ in range(reps):
+            torch.sum(flush, 0, out=sink[0])
+            torch.cuda.synchronize()
+            e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            e0.record()
+            fn()
+            e1.record()
+            torch.cuda.synchronize()
+            ts.append(e0.elapsed_time(e1) / 1e3)
+        t = sorted(ts)[len(ts) // 2]
+        e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        e0.record()
+        for _ in range(2 * reps):
+            fn()
+        e1.record()
+        torch.cuda.synchronize()
+        tw = e0.elapsed_time(e1) / 1e3 / (2 * reps)
+        out[name] = dict(avg_launch_us=round(t * 1e6, 2), algorithmic_bytes=byts,
+                         achieved_GBps=round(byts / t / 1e9, 1), frac=round(byts / t / HBM_PEAK, 4),
+                         warm_launch_us=round(tw * 1e6, 2), warm_GBps=round(byts / tw / 1e9, 1))
+    del X, XH, Y, flush
+    torch.cuda.empty_cache()
+    return out
+
+
 def sources_sha256():
     """Hash of the kernel sources: HBM traffic measured for other sources is not reused."""
     h = hashlib.sha256()
@@ -353,6 +413,13 @@ def main():
             del wc
             torch.cuda.empty_cache()
 
+    streaming = None
+    if not a.no_stream and a.workload == "c2":
+        streaming = stream_bench(dev)
+        print(f"[bench] streaming kernels (cold / cache-warm): " + ", ".join(
+            f"{k} {v['achieved_GBps']} / {v['warm_GBps']} GB/s" for k, v in streaming.items() if isinstance(v, dict)),
+            file=sys.stderr, flush=True)
+
     fw = None
     if not a.no_fw and a.workload == "c2":
         wf = synth.fw_config("fw2")
@@ -382,6 +449,7 @@ def main():
     out["roofline"] = out.pop("roofline")
     out["cpu_baseline"] = cpu
     out["configs"] = configs
+    out["streaming"] = streaming
     out["fw"] = fw
     print(json.dumps(out))
 

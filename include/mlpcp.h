@@ -200,12 +200,14 @@ int mlpcp_svt_prox_static(int m, int n, const float* M, int ldm, int levels, flo
 int mlpcp_shrink(size_t count, const float* X, float tau, float* Y, void* stream);
 
 /* Restriction XH = X R (m x n -> m x n_H; Alg. 4, coarse data), asynchronous.
- *  X m x n (ldx >= n), XH m x n_H (ldh >= n_H).                              */
+ *  X m x n (ldx >= n), XH m x n_H (ldh >= n_H).  Coarse widths up to 1024
+ *  (MLPCP_E_UNSUPPORTED beyond).                                             */
 int mlpcp_restrict(int m, int n, const float* X, int ldx, int levels, float* XH, int ldh,
                    void* stream);
 
 /* Prolongation X = XH R^T (m x n_H -> m x n; Alg. 4, lift), asynchronous.
- *  XH m x n_H (ldh >= n_H), X m x n (ldx >= n).                              */
+ *  XH m x n_H (ldh >= n_H), X m x n (ldx >= n).  Coarse widths up to 512
+ *  (MLPCP_E_UNSUPPORTED beyond).                                             */
 int mlpcp_prolong(int m, int n, const float* XH, int ldh, int levels, float* X, int ldx,
                   void* stream);
 

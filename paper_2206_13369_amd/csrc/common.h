@@ -52,6 +52,7 @@ struct Operator {
   int n = 0, levels = 0, nH = 0;
   int max_col_nnz = 0;
   int nnz = 0;                // nonzeros of P
+  bool contig = false;        // every column's fine rows are consecutive (ascending)
   int* row_idx = nullptr;     // [n * kMaxStencil]
   float* row_w = nullptr;     // [n * kMaxStencil]
   int* col_ptr = nullptr;     // [nH + 1]

@@ -197,6 +197,9 @@ int build_operator_at(int n, int levels, int r_norm, hipStream_t stream, Operato
   for (int c = 0; c < nH; ++c) mx = std::max(mx, cp[c + 1] - cp[c]);
   op->max_col_nnz = mx;
   op->nnz = cp[nH];
+  op->contig = true;
+  for (int c = 0; c < nH; ++c)
+    for (int t = cp[c] + 1; t < cp[c + 1]; ++t) op->contig = op->contig && cr[t] == cr[t - 1] + 1;
   {  // the kernels read exactly kMaxStencil weights per fine row
     std::vector<int> row_cnt(n, 0);
     for (int t = 0; t < op->nnz; ++t) ++row_cnt[cr[t]];
@@ -333,6 +336,9 @@ unsigned stream_grid(size_t total) {
   return (unsigned)b;
 }
 
+static_assert(kMaxStencil == 2, "the streaming prolongation reads two weights per fine row");
+
+// Fallback for coarse widths whose float64 tiles do not fit the streaming kernels' LDS:
 // XH rows = (X rows P) C for RROWS rows per block, accumulated in float64.
 constexpr int RROWS = 8;
 __global__ void __launch_bounds__(256) k_restrict_full(int m, int n, int nH, const float* __restrict__ X, int ldx,
@@ -404,11 +410,382 @@ __global__ void __launch_bounds__(256) k_prolong_full(int m, int n, int nH, cons
 }
 
 // S_tau[x] = sign(x) max(|x| - tau, 0); NaN propagates.
+__device__ __forceinline__ float shrink1(float x, float tau) {
+  const float a = fabsf(x) - tau;
+  return (a > 0.0f) ? copysignf(a, x) : ((a == a) ? 0.0f : a);
+}
+
 __global__ void k_shrink(size_t count, const float* __restrict__ X, float tau, float* __restrict__ Y) {
-  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x) {
-    const float x = X[i];
-    const float a = fabsf(x) - tau;
-    Y[i] = (a > 0.0f) ? copysignf(a, x) : ((a == a) ? 0.0f : a);
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += (size_t)gridDim.x * blockDim.x)
+    Y[i] = shrink1(X[i], tau);
+}
+
+// the same on 16-byte groups (X and Y 16-byte aligned): one float4 load and store per
+// thread and step, the grid sized to a few blocks per compute unit
+__global__ void __launch_bounds__(256) k_shrink4(size_t n4, const float4* __restrict__ X, float tau,
+                                                 float4* __restrict__ Y) {
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < n4; i += (size_t)gridDim.x * blockDim.x) {
+    const float4 x = X[i];
+    Y[i] = make_float4(shrink1(x.x, tau), shrink1(x.y, tau), shrink1(x.z, tau), shrink1(x.w, tau));
+  }
+}
+
+// ---- streaming restriction and prolongation (the standalone entry points) ----------
+// A block takes a tile of R rows.  Restriction: the R rows of X are staged in LDS with
+// coalesced (float4 where aligned) loads, Y = X_tile P is formed in float64 from the
+// column stencil, and XH_tile = Y C on float64 MFMA (v_mfma_f64_16x16x4f64, 16 x 16 output
+// tiles over the four waves; Y padded to 16-row multiples and 16-column multiples with
+// zeros, C read from global memory, where it stays cached).  Prolongation: the XH tile is
+// staged (as float64), W = XH_tile C on MFMA, and X_tile = W P^T through the two-tap row
+// stencil, written with coalesced (float4 where aligned) stores.
+typedef double sd4_t __attribute__((ext_vector_type(4)));
+
+// Z = Y C for Y (R16 x nHp, LDS, ld ldy, zero beyond the valid rows and columns) and C
+// (nH x nH, global, ld nH); out(row, col, value) for every row < R16 and col < nHp.
+template <typename F>
+__device__ __forceinline__ void tile_times_C(const double* sY, int ldy, int R16, int nH, int nHp,
+                                             const double* __restrict__ C, F out) {
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  const int rt = R16 / 16, ct = nHp / 16;
+  const int K4 = (nH + 3) & ~3;
+  for (int t = wave; t < rt * ct; t += 4) {
+    const int ti = t / ct, tj = t % ct;
+    const int col = tj * 16 + (lane & 15);
+    sd4_t acc = {0.0, 0.0, 0.0, 0.0};
+    for (int k0 = 0; k0 < K4; k0 += 4) {
+      const int k = k0 + (lane >> 4);
+      const double a = sY[(ti * 16 + (lane & 15)) * ldy + k];
+      const double b = (k < nH && col < nH) ? C[(size_t)k * nH + col] : 0.0;
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, acc, 0, 0, 0);
+    }
+    // output register v of lane l: row 4v + l/16, column l%16 of the tile
+#pragma unroll
+    for (int v = 0; v < 4; ++v) out(ti * 16 + 4 * v + (lane >> 4), col, acc[v]);
+  }
+}
+
+struct StreamPlan {
+  int R, R16, nHp, ldy;   // rows per tile, rows padded to 16, n_H padded to 16, LDS ld of the float64 tiles
+  size_t off_tab;         // byte offset of the stencil tables in the dynamic LDS
+  size_t lds;             // dynamic LDS bytes
+};
+
+// Rows per tile for the streaming kernels: as many (up to 64) as the LDS budget allows,
+// with the stencil tables staged too.  Restriction: the float64 Y tile, the float32 row
+// tile and the column stencil (col_ptr, col_row, col_w); prolongation: the float64 XH
+// and W tiles and the row stencil (row_idx, row_w).
+bool stream_plan(int n, int nH, bool prolong, StreamPlan& sp) {
+  constexpr size_t kBudget = 64 * 1024;
+  sp.nHp = (nH + 15) / 16 * 16;
+  sp.ldy = sp.nHp + 1;   // odd stride in doubles: MFMA operand reads across rows hit distinct banks
+  const size_t tab = prolong ? (size_t)kMaxStencil * n * (sizeof(int) + sizeof(float))
+                             : (size_t)(nH + 1) * sizeof(int) + (size_t)kMaxStencil * n * (sizeof(int) + sizeof(float));
+  // restriction: at most 32 rows (about 34 KB at n = 200, so four blocks share a compute
+  // unit and their loads overlap the others' arithmetic); prolongation: up to 64
+  for (int R = prolong ? 64 : 32; R >= 1; R /= 2) {
+    const int R16 = (R + 15) / 16 * 16;
+    const size_t tiles = (size_t)(prolong ? 2 : 1) * R16 * sp.ldy * sizeof(double);
+    const size_t rows = prolong ? 0 : (size_t)R * (n | 1) * sizeof(float);
+    const size_t off_tab = (tiles + rows + 15) & ~size_t(15);
+    if (off_tab + tab <= kBudget) {
+      sp.R = R;
+      sp.R16 = R16;
+      sp.off_tab = off_tab;
+      sp.lds = off_tab + tab;
+      return true;
+    }
+  }
+  return false;
+}
+
+// XH (m x nH) = X (m x n) P C
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_restrict_stream(int m, int n, int nH, int R, int R16, int nHp, int ldy,
+                                                         int off_tab, int nnz, const float* __restrict__ X, int ldx,
+                                                         float* __restrict__ XH, int ldh,
+                                                         const int* __restrict__ col_ptr,
+                                                         const int* __restrict__ col_row,
+                                                         const float* __restrict__ col_w,
+                                                         const double* __restrict__ C) {
+  extern __shared__ double dsm[];
+  double* sY = dsm;                                              // R16 x ldy
+  float* sX = reinterpret_cast<float*>(dsm + (size_t)R16 * ldy);   // R x n
+  char* tb = reinterpret_cast<char*>(dsm) + off_tab;
+  int* sptr = reinterpret_cast<int*>(tb);                        // nH + 1
+  int* srow = sptr + (nH + 1);                                   // nnz
+  float* sw = reinterpret_cast<float*>(srow + nnz);              // nnz
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * R;
+  const int rows = min(R, m - i0);
+  // 1. stage the rows (all loads issued before the first use) and the column stencil;
+  //    the LDS row stride ls = n | 1 is odd, so the lanes of step 2, one row each, read
+  //    the same fine column of different rows from different banks
+  const int ls = n | 1;
+  if (VEC) {
+    const int n4 = n / 4;
+    for (int e = tid; e < rows * n4; e += 256) {
+      const int r = e / n4, q = e % n4;
+      const float4 v = *reinterpret_cast<const float4*>(X + (size_t)(i0 + r) * ldx + 4 * q);
+      float* d = sX + (size_t)r * ls + 4 * q;
+      d[0] = v.x;
+      d[1] = v.y;
+      d[2] = v.z;
+      d[3] = v.w;
+    }
+  } else {
+    for (int e = tid; e < rows * n; e += 256) {
+      const int r = e / n, j = e % n;
+      sX[(size_t)r * ls + j] = X[(size_t)(i0 + r) * ldx + j];
+    }
+  }
+  for (int e = tid; e <= nH; e += 256) sptr[e] = col_ptr[e];
+  for (int e = tid; e < nnz; e += 256) {
+    srow[e] = col_row[e];
+    sw[e] = col_w[e];
+  }
+  __syncthreads();
+  // 2. Y = X_tile P (float64), zero in the padding.  Lane l of a wave takes row l % 32;
+  //    the wave's two halves and the four waves split the coarse columns (c = h + 2 w + 8 k),
+  //    so the 32 lanes of a half read the same stencil entry (broadcast) and one fine
+  //    column of 32 rows (distinct banks).  Rows r >= R16 (a 16-row tile) are skipped.
+  {
+    const int lane = tid & 63, w = tid >> 6;
+    const int half = lane >> 5, rl = lane & 31;
+    for (int rb = 0; rb < R16; rb += 32) {
+      const int r = rb + rl;
+      const bool live = r < rows;
+      const float* x = sX + (size_t)(live ? r : 0) * ls;
+      for (int c = half + 2 * w; r < R16 && c < nHp; c += 8) {
+        double acc = 0.0;
+        if (c < nH && live) {
+          const int t1 = sptr[c + 1];
+          for (int t = sptr[c]; t < t1; ++t) acc = fma((double)sw[t], (double)x[srow[t]], acc);
+        }
+        sY[(size_t)r * ldy + c] = acc;
+      }
+    }
+  }
+  __syncthreads();
+  // 3. XH_tile = Y C on MFMA
+  tile_times_C(sY, ldy, R16, nH, nHp, C, [&](int r, int c, double v) {
+    if (r < rows && c < nH) XH[(size_t)(i0 + r) * ldh + c] = (float)v;
+  });
+}
+
+// Persistent restriction for float4-aligned rows whose tile and C fit the LDS together,
+// for stencils whose columns have contiguous supports (true of the composite linear
+// interpolation: column c of P touches the fine rows lo_c .. lo_c + cnt_c - 1).
+// Each block walks the tiles blockIdx.x, blockIdx.x + gridDim.x, ...; the rows of the
+// next tile are loaded into registers (kPipeChunks float4 per thread) before the current
+// tile's stencil and MFMA work, so every wave keeps several HBM reads in flight through
+// the arithmetic.  C is staged once per block in LDS (K4 x ldc, zero padded), which keeps
+// the MFMA operand reads off the in-order vector-memory counter that the prefetch holds.
+// The column weights are staged as float64, zero padded to W8 (a multiple of 8) per
+// column, so a lane reads eight row entries at constant offsets from one base address
+// and eight broadcast weights per step.
+constexpr int kPipeChunks = 8;
+
+__global__ void __launch_bounds__(256) k_restrict_pipe(int m, int n, int nH, int R, int R16, int nHp, int ldy,
+                                                       int ldc, int W8, int off_c, int off_tab,
+                                                       const float* __restrict__ X, int ldx, float* __restrict__ XH,
+                                                       int ldh, const int* __restrict__ col_ptr,
+                                                       const int* __restrict__ col_row,
+                                                       const float* __restrict__ col_w,
+                                                       const double* __restrict__ C) {
+  extern __shared__ double dsm[];
+  double* sY = dsm;                                              // R16 x ldy
+  float* sX = reinterpret_cast<float*>(dsm + (size_t)R16 * ldy);   // R x (n | 1), then W8 spare
+  double* sC = reinterpret_cast<double*>(reinterpret_cast<char*>(dsm) + off_c);   // K4 x ldc
+  double* sw = reinterpret_cast<double*>(reinterpret_cast<char*>(dsm) + off_tab);   // nH x W8
+  int* slo = reinterpret_cast<int*>(sw + (size_t)nH * W8);                          // nH
+  int* scnt = slo + nH;                                                             // nH
+  const int tid = threadIdx.x;
+  const int n4 = n >> 2, ls = n | 1;
+  const int K4 = (nH + 3) & ~3;
+  const int ntiles = (m + R - 1) / R;
+  for (int c = tid; c < nH; c += 256) {
+    const int t0 = col_ptr[c];
+    slo[c] = col_row[t0];
+    scnt[c] = col_ptr[c + 1] - t0;
+  }
+  for (int e = tid; e < nH * W8; e += 256) {
+    const int c = e / W8, k = e % W8;
+    const int t0 = col_ptr[c];
+    sw[e] = k < col_ptr[c + 1] - t0 ? (double)col_w[t0 + k] : 0.0;
+  }
+  for (int e = tid; e < K4 * nHp; e += 256) {
+    const int k = e / nHp, c = e % nHp;
+    sC[(size_t)k * ldc + c] = (k < nH && c < nH) ? C[(size_t)k * nH + c] : 0.0;
+  }
+  float4 buf[kPipeChunks];
+  auto load = [&](int tile) {
+    const int i0 = tile * R, cnt = min(R, m - i0) * n4;
+#pragma unroll
+    for (int k = 0; k < kPipeChunks; ++k) {
+      const int e = tid + 256 * k;
+      if (e < cnt) buf[k] = *reinterpret_cast<const float4*>(X + (size_t)(i0 + e / n4) * ldx + 4 * (e % n4));
+    }
+  };
+  int tile = blockIdx.x;
+  if (tile < ntiles) load(tile);
+  const int lane = tid & 63, w = tid >> 6;
+  for (; tile < ntiles; tile += gridDim.x) {
+    const int i0 = tile * R, rows = min(R, m - i0), cnt = rows * n4;
+#pragma unroll
+    for (int k = 0; k < kPipeChunks; ++k) {
+      const int e = tid + 256 * k;
+      if (e < cnt) {
+        float* d = sX + (size_t)(e / n4) * ls + 4 * (e % n4);
+        d[0] = buf[k].x;
+        d[1] = buf[k].y;
+        d[2] = buf[k].z;
+        d[3] = buf[k].w;
+      }
+    }
+    __syncthreads();
+    if (tile + (int)gridDim.x < ntiles) load(tile + gridDim.x);
+    // Y = X_tile P in float64 (lane layout as in k_restrict_stream): eight entries per
+    // step; beyond cnt_c the weight is zero and the row value is replaced by zero, so
+    // the spare reads past the support (inside the tile buffer) never reach the sum
+    {
+      const int half = lane >> 5, rl = lane & 31;
+      for (int rb = 0; rb < R16; rb += 32) {
+        const int r = rb + rl;
+        const bool live = r < rows;
+        for (int c = half + 2 * w; r < R16 && c < nHp; c += 8) {
+          double acc = 0.0;
+          if (c < nH && live) {
+            const int cnt = scnt[c];
+            const float* x = sX + (size_t)r * ls + slo[c];
+            const double* wc = sw + (size_t)c * W8;
+            for (int k = 0; k < cnt; k += 8) {
+              float xv[8];
+              double wv[8];
+#pragma unroll
+              for (int i = 0; i < 8; ++i) {
+                xv[i] = x[k + i];
+                wv[i] = wc[k + i];
+              }
+#pragma unroll
+              for (int i = 0; i < 8; ++i) acc = fma(wv[i], k + i < cnt ? (double)xv[i] : 0.0, acc);
+            }
+          }
+          sY[(size_t)r * ldy + c] = acc;
+        }
+      }
+    }
+    __syncthreads();
+    // XH_tile = Y C on float64 MFMA, both operands from LDS
+    {
+      const int rt = R16 / 16, ct = nHp / 16;
+      for (int t = w; t < rt * ct; t += 4) {
+        const int ti = t / ct, tj = t % ct;
+        const int col = tj * 16 + (lane & 15);
+        const double* a = sY + (size_t)(ti * 16 + (lane & 15)) * ldy + (lane >> 4);
+        const double* b = sC + (size_t)(lane >> 4) * ldc + col;
+        sd4_t acc = {0.0, 0.0, 0.0, 0.0};
+        for (int k0 = 0; k0 < K4; k0 += 4)
+          acc = __builtin_amdgcn_mfma_f64_16x16x4f64(a[k0], b[(size_t)k0 * ldc], acc, 0, 0, 0);
+#pragma unroll
+        for (int v = 0; v < 4; ++v) {
+          const int r = ti * 16 + 4 * v + (lane >> 4);
+          if (r < rows && col < nH) XH[(size_t)(i0 + r) * ldh + col] = (float)acc[v];
+        }
+      }
+    }
+    __syncthreads();
+  }
+}
+
+// LDS plan of k_restrict_pipe: R rows with R * n / 4 <= 256 * kPipeChunks (the tile
+// plus W8 spare floats), C (K4 x (nHp + 1) doubles) and the tables (nH x W8 float64
+// weights, lo_c and cnt_c).  False if nothing fits.
+struct PipePlan {
+  int R, R16, nHp, ldy, ldc, W8;
+  size_t off_c, off_tab, lds;
+};
+
+bool pipe_plan(int n, int nH, int max_col_nnz, PipePlan& pp) {
+  constexpr size_t kBudget = 64 * 1024;
+  if (n % 4) return false;
+  pp.nHp = (nH + 15) / 16 * 16;
+  pp.ldy = pp.nHp + 1;
+  pp.ldc = pp.nHp + 1;
+  pp.W8 = (max_col_nnz + 7) / 8 * 8;
+  const int K4 = (nH + 3) & ~3;
+  const size_t tab = (size_t)nH * pp.W8 * sizeof(double) + (size_t)2 * nH * sizeof(int);
+  const size_t cbytes = (size_t)K4 * pp.ldc * sizeof(double);
+  int R = (256 * kPipeChunks) / (n / 4);
+  if (R > 32) R = 32;
+  for (; R >= 16; R /= 2) {
+    const int R16 = (R + 15) / 16 * 16;
+    const size_t xs = ((size_t)R * (n | 1) + pp.W8) * sizeof(float);
+    const size_t off_c = (size_t)R16 * pp.ldy * sizeof(double) + ((xs + 15) & ~size_t(15));
+    const size_t off_tab = off_c + cbytes;
+    if (off_tab + tab <= kBudget) {
+      pp.R = R;
+      pp.R16 = R16;
+      pp.off_c = off_c;
+      pp.off_tab = off_tab;
+      pp.lds = off_tab + tab;
+      return true;
+    }
+  }
+  return false;
+}
+
+// X (m x n) = XH (m x nH) C P^T
+template <bool VEC>
+__global__ void __launch_bounds__(256) k_prolong_stream(int m, int n, int nH, int R, int R16, int nHp, int ldy,
+                                                        int off_tab, const float* __restrict__ XH, int ldh,
+                                                        float* __restrict__ X, int ldx,
+                                                        const int* __restrict__ row_idx,
+                                                        const float* __restrict__ row_w,
+                                                        const double* __restrict__ C) {
+  extern __shared__ double dsm[];
+  double* sW = dsm;                        // R16 x ldy: the XH tile
+  double* sN = dsm + (size_t)R16 * ldy;    // R16 x ldy: W = XH_tile C
+  char* tb = reinterpret_cast<char*>(dsm) + off_tab;
+  int* sri = reinterpret_cast<int*>(tb);                  // 2 n
+  float* srw = reinterpret_cast<float*>(sri + 2 * n);     // 2 n
+  const int tid = threadIdx.x;
+  const int i0 = blockIdx.x * R;
+  const int rows = min(R, m - i0);
+  for (int e = tid; e < R16 * nHp; e += 256) {
+    const int r = e / nHp, c = e % nHp;
+    sW[(size_t)r * ldy + c] = (r < rows && c < nH) ? (double)XH[(size_t)(i0 + r) * ldh + c] : 0.0;
+  }
+  for (int e = tid; e < 2 * n; e += 256) {
+    sri[e] = row_idx[e];
+    srw[e] = row_w[e];
+  }
+  __syncthreads();
+  tile_times_C(sW, ldy, R16, nH, nHp, C, [&](int r, int c, double v) { sN[(size_t)r * ldy + c] = v; });
+  __syncthreads();
+  if (VEC) {
+    const int n4 = n / 4;
+    for (int e = tid; e < rows * n4; e += 256) {
+      const int r = e / n4, j0 = 4 * (e % n4);
+      const double* w = sN + (size_t)r * ldy;
+      // the eight stencil entries of the four columns with two 16-byte LDS reads each
+      // (consecutive lanes read consecutive 32-byte runs)
+      const int4 ia = *reinterpret_cast<const int4*>(sri + 2 * j0), ib = *reinterpret_cast<const int4*>(sri + 2 * j0 + 4);
+      const float4 wa = *reinterpret_cast<const float4*>(srw + 2 * j0),
+                   wb = *reinterpret_cast<const float4*>(srw + 2 * j0 + 4);
+      float o[4];
+      o[0] = (float)fma((double)wa.y, w[ia.y], (double)wa.x * w[ia.x]);
+      o[1] = (float)fma((double)wa.w, w[ia.w], (double)wa.z * w[ia.z]);
+      o[2] = (float)fma((double)wb.y, w[ib.y], (double)wb.x * w[ib.x]);
+      o[3] = (float)fma((double)wb.w, w[ib.w], (double)wb.z * w[ib.z]);
+      *reinterpret_cast<float4*>(X + (size_t)(i0 + r) * ldx + j0) = make_float4(o[0], o[1], o[2], o[3]);
+    }
+  } else {
+    for (int e = tid; e < rows * n; e += 256) {
+      const int r = e / n, j = e % n;
+      const double* w = sN + (size_t)r * ldy;
+      X[(size_t)(i0 + r) * ldx + j] =
+          (float)fma((double)srw[2 * j + 1], w[sri[2 * j + 1]], (double)srw[2 * j] * w[sri[2 * j]]);
+    }
   }
 }
 
@@ -482,7 +859,16 @@ int mlpcp_shrink(size_t count, const float* X, float tau, float* Y, void* stream
   if ((count > 0 && (!X || !Y)) || !(tau >= 0.0f) || std::isinf(tau)) return MLPCP_E_INVALID_ARG;
   if (count == 0) return MLPCP_OK;
   hipStream_t s = static_cast<hipStream_t>(stream);
-  hipLaunchKernelGGL(k_shrink, dim3(stream_grid(count)), dim3(256), 0, s, count, X, tau, Y);
+  const bool vec = ((reinterpret_cast<uintptr_t>(X) | reinterpret_cast<uintptr_t>(Y)) & 15u) == 0;
+  const size_t n4 = vec ? count / 4 : 0;
+  if (n4) {
+    const unsigned grid = (unsigned)std::min<size_t>((n4 + 255) / 256, 8192);
+    hipLaunchKernelGGL(k_shrink4, dim3(grid), dim3(256), 0, s, n4, reinterpret_cast<const float4*>(X), tau,
+                       reinterpret_cast<float4*>(Y));
+  }
+  if (count > 4 * n4)
+    hipLaunchKernelGGL(k_shrink, dim3(stream_grid(count - 4 * n4)), dim3(256), 0, s, count - 4 * n4, X + 4 * n4, tau,
+                       Y + 4 * n4);
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }
@@ -502,6 +888,29 @@ int mlpcp_restrict(int m, int n, const float* X, int ldx, int levels, float* XH,
   }
   const Operator* op = nullptr;
   MLPCP_TRY(get_operator(n, levels, s, &op));
+  const bool vec = n % 4 == 0 && ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  PipePlan pp;
+  if (vec && op->contig && pipe_plan(n, nH, op->max_col_nnz, pp)) {
+    const int ntiles = (m + pp.R - 1) / pp.R;
+    int per_cu = 0, cus = 0, dev = 0;
+    MLPCP_HIP(hipGetDevice(&dev));
+    MLPCP_HIP(hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev));
+    MLPCP_HIP(hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, k_restrict_pipe, 256, pp.lds));
+    const int grid = std::max(1, std::min(ntiles, std::max(per_cu, 1) * std::max(cus, 1)));
+    hipLaunchKernelGGL(k_restrict_pipe, dim3(grid), dim3(256), pp.lds, s, m, n, nH, pp.R, pp.R16, pp.nHp, pp.ldy,
+                       pp.ldc, pp.W8, (int)pp.off_c, (int)pp.off_tab, X, ldx, XH, ldh, op->col_ptr, op->col_row,
+                       op->col_w, op->C);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
+  StreamPlan sp;
+  if (stream_plan(n, nH, false, sp)) {
+    auto fn = vec ? k_restrict_stream<true> : k_restrict_stream<false>;
+    hipLaunchKernelGGL(fn, dim3((m + sp.R - 1) / sp.R), dim3(256), sp.lds, s, m, n, nH, sp.R, sp.R16, sp.nHp, sp.ldy,
+                       (int)sp.off_tab, op->nnz, X, ldx, XH, ldh, op->col_ptr, op->col_row, op->col_w, op->C);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
   const size_t sm = (size_t)RROWS * nH * sizeof(double);
   if (sm > 64 * 1024) return MLPCP_E_UNSUPPORTED;
   hipLaunchKernelGGL(k_restrict_full, dim3((m + RROWS - 1) / RROWS), dim3(256), sm, s, m, n, nH, X, ldx, XH, ldh,
@@ -525,6 +934,15 @@ int mlpcp_prolong(int m, int n, const float* XH, int ldh, int levels, float* X, 
   }
   const Operator* op = nullptr;
   MLPCP_TRY(get_operator(n, levels, s, &op));
+  StreamPlan sp;
+  if (stream_plan(n, nH, true, sp)) {
+    const bool vec = n % 4 == 0 && ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+    auto fn = vec ? k_prolong_stream<true> : k_prolong_stream<false>;
+    hipLaunchKernelGGL(fn, dim3((m + sp.R - 1) / sp.R), dim3(256), sp.lds, s, m, n, nH, sp.R, sp.R16, sp.nHp, sp.ldy,
+                       (int)sp.off_tab, XH, ldh, X, ldx, op->row_idx, op->row_w, op->C);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
   const size_t sm = (size_t)2 * RROWS * nH * sizeof(double);
   if (sm > 64 * 1024) return MLPCP_E_UNSUPPORTED;
   hipLaunchKernelGGL(k_prolong_full, dim3((m + RROWS - 1) / RROWS), dim3(256), sm, s, m, n, nH, XH, ldh, X, ldx,

@@ -181,3 +181,22 @@ def test_fwt_workspace_bytes():
     assert mlp.fwt_workspace_bytes(1000, 500, 0, True) > a           # dense L gradient and power buffers
     assert mlp.fwt_workspace_bytes(10, 20, 0, True) == 0              # m < n
     assert mlp.fwt_workspace_bytes(1000, 200, 1, True) == 0           # n_H > 64
+
+
+@pytest.mark.slow
+def test_validation_under_host_sanitizers(tmp_path):
+    """Every host-side rejection path of the C ABI (tests/abi_host_check.c), run against a
+    build whose host code carries AddressSanitizer and UndefinedBehaviorSanitizer: the
+    statuses match and neither sanitizer reports anything."""
+    import shutil
+    import subprocess
+    from paper_2206_13369_amd.build import build_host_sanitized
+    if not (shutil.which("hipcc") or os.path.exists("/opt/rocm/bin/hipcc")):
+        pytest.skip("hipcc not available")
+    exe = build_host_sanitized(str(tmp_path / "san"))
+    env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:halt_on_error=1",
+               UBSAN_OPTIONS="halt_on_error=1:print_stacktrace=1")
+    res = subprocess.run([exe], capture_output=True, text=True, env=env, timeout=300)
+    assert res.returncode == 0, res.stdout + res.stderr
+    assert "abi host checks passed" in res.stdout
+    assert "runtime error" not in res.stderr and "AddressSanitizer" not in res.stderr

@@ -93,3 +93,53 @@ def test_svt_prox_blocked_extremes(m, n, tau, levels):
     else:
         assert rref == oracle.restrict(M.astype(np.float64), levels).shape[1]   # full coarse rank
         assert rel(to_np(L), Lref) < 1e-5
+
+
+def test_shrink_unaligned_and_tails():
+    """The vector path (16-byte groups) and the scalar path (misaligned views, tails)
+    give the float32 formula's bits."""
+    torch, dev = torch_dev()
+    rng = np.random.default_rng(3)
+    x = (rng.normal(size=4 * 65536 + 7) * 2).astype(np.float32)
+    t = to_dev(x)
+    for off, cnt in ((0, x.size), (1, x.size - 1), (2, 4 * 65536), (3, 10)):
+        say("shrink offset", off, cnt)
+        y = to_np(mlp.shrink(t[off:off + cnt], 0.7))
+        ref = np.sign(x[off:off + cnt]) * np.maximum(np.abs(x[off:off + cnt]) - np.float32(0.7), np.float32(0))
+        assert np.array_equal(y, ref.astype(np.float32))
+
+
+@pytest.mark.parametrize("m,n,levels,pad", [(1000, 200, 4, 0), (513, 203, 3, 5), (77, 1000, 2, 3), (40, 1024, 1, 0)])
+def test_restrict_prolong_padded_rows(m, n, levels, pad):
+    """Row-padded inputs (ld > n, also not a multiple of 4) and widths whose coarse
+    tiles take the fallback kernels (n_H = 512 at 1024 / 1 level)."""
+    torch, dev = torch_dev()
+    say("restrict/prolong padded", m, n, levels, pad)
+    rng = np.random.default_rng(m + 3 * n)
+    X = rng.normal(size=(m, n + pad)).astype(np.float32)
+    Xd = to_dev(X)[:, :n]
+    XH = to_np(mlp.restrict(Xd, levels))
+    ref = oracle.restrict(X[:, :n].astype(np.float64), levels)
+    assert rel(XH, ref) < 2e-6
+    nH = ref.shape[1]
+    Z = rng.normal(size=(m, nH + pad)).astype(np.float32)
+    Xf = to_np(mlp.prolong(to_dev(Z)[:, :nH], n, levels))
+    assert rel(Xf, oracle.prolong(Z[:, :nH].astype(np.float64), n, levels)) < 2e-6
+
+
+def test_restrict_prolong_full_hyperspectral_size():
+    """262144 x 200, 4 levels (n_H = 13), the size the streaming kernels are measured at:
+    every row on the GPU, the FP64 oracle on a seeded sample of rows (the maps act row
+    by row)."""
+    torch, dev = torch_dev()
+    m, n, levels = 262144, 200, 4
+    rng = np.random.default_rng(11)
+    X = rng.normal(size=(m, n)).astype(np.float32)
+    say("restrict/prolong full size")
+    XH = to_np(mlp.restrict(to_dev(X), levels))
+    rows = np.sort(rng.choice(m, 4096, replace=False))
+    rows = np.concatenate([rows, [0, m - 1]])
+    assert rel(XH[rows], oracle.restrict(X[rows].astype(np.float64), levels)) < 2e-6
+    Z = rng.normal(size=(m, XH.shape[1])).astype(np.float32)
+    Xf = to_np(mlp.prolong(to_dev(Z), n, levels))
+    assert rel(Xf[rows], oracle.prolong(Z[rows].astype(np.float64), n, levels)) < 2e-6
