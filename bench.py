@@ -502,7 +502,8 @@ def ialm_bench(w, dev, steps, warmup, prec, *, plain=True, plain_steps=1, rnorm=
     eL, eS = recovery_errors(w, r, dev)
     print(f"[bench] {w.name} {prec} multilevel: {ml_s*1e3:.2f} ms/solve, {r.iters} iters, fg {r.fg:.2e}, "
           f"rank {r.rank}, errL0 {eL:.3g}, errS0 {eS:.3g}; dominant kernel {dom}; Gram bf16/split iters "
-          f"{r.gram_bf16_iters}/{r.gram_split_iters}", file=sys.stderr, flush=True)
+          f"{r.gram_bf16_iters}/{r.gram_split_iters}; partial-eigensolve iters {r.partial_eig_iters}",
+          file=sys.stderr, flush=True)
 
     # the same solves with HIP events around the dominant kernel class only
     torch.cuda.synchronize()
@@ -517,7 +518,7 @@ def ialm_bench(w, dev, steps, warmup, prec, *, plain=True, plain_steps=1, rnorm=
     del ws_ml
 
     out = dict(time_s=ml_s, prec=prec, iters=r.iters, iters_per_s=round(r.iters / ml_s, 2), fg=r.fg, rank=r.rank,
-               err_L0=eL, err_S0=eS, tau_margin=r.tau_margin,
+               err_L0=eL, err_S0=eS, tau_margin=r.tau_margin, partial_eig_iters=r.partial_eig_iters,
                gram_tiers={"bf16": r.gram_bf16_iters, "split": r.gram_split_iters})
     if plain:
         ws_pl = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=0)), dtype=torch.uint8,
@@ -535,10 +536,12 @@ def ialm_bench(w, dev, steps, warmup, prec, *, plain=True, plain_steps=1, rnorm=
         plain_s = (time.perf_counter() - tp0) / plain_steps
         peL, peS = recovery_errors(w, rp, dev)
         print(f"[bench] {w.name} {prec} plain: {plain_s*1e3:.1f} ms/solve, {rp.iters} iters, fg {rp.fg:.2e}, "
-              f"rank {rp.rank}, errL0 {peL:.3g}, errS0 {peS:.3g}", file=sys.stderr, flush=True)
+              f"rank {rp.rank}, errL0 {peL:.3g}, errS0 {peS:.3g}; partial-eigensolve iters {rp.partial_eig_iters}",
+              file=sys.stderr, flush=True)
         out.update(plain_time_s=round(plain_s, 5), plain_iters=rp.iters,
                    plain_iters_per_s=round(rp.iters / plain_s, 3), plain_rank=rp.rank, plain_fg=rp.fg,
                    plain_err_L0=peL, plain_err_S0=peS, speedup_vs_plain=round(plain_s / ml_s, 2),
+                   plain_partial_eig_iters=rp.partial_eig_iters,
                    plain_kernel_ms_per_solve={k: round(v[1], 3) for k, v in pprof.items() if v[0] > 0})
         del ws_pl, rp
 

@@ -116,6 +116,13 @@ typedef struct {
                            /* Jacobi sweeps of each iteration's eigensolve    */
   double mu0;              /* initial penalty used (the computed default when */
                            /* the call passed mu0 <= 0)                       */
+  int partial_eig_iters;   /* iterations whose SVT came from the rank-        */
+                           /* predicted partial eigensolve (the previous rank */
+                           /* at most 56 on a model at least 1024 wide):      */
+                           /* subspace iteration on a 64-column block,        */
+                           /* Rayleigh-Ritz, and a Cholesky certificate that  */
+                           /* no other eigenvalue of the Gram reaches tau^2;  */
+                           /* the full Jacobi eigensolve otherwise            */
 } mlpcp_info;
 
 /* Fills defaults: levels 0, tol 1e-6, max_iter 500, rho 1.5, mu_max_factor 1e7,

@@ -54,7 +54,7 @@ class Info(ctypes.Structure):
                 ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
                 ("history_len", ctypes.c_int), ("gram_bf16_iters", ctypes.c_int),
                 ("gram_split_iters", ctypes.c_int), ("sweeps_history", ctypes.POINTER(ctypes.c_int)),
-                ("mu0", ctypes.c_double)]
+                ("mu0", ctypes.c_double), ("partial_eig_iters", ctypes.c_int)]
 
 
 class FwtInfo(ctypes.Structure):
@@ -234,6 +234,7 @@ class SolveResult:
     gram_split_iters: int = 0
     sweeps_history: list = dataclasses.field(default_factory=list)
     mu0: float = 0.0
+    partial_eig_iters: int = 0
 
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
@@ -300,7 +301,7 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
     return SolveResult(L, S, Y, st, info.iters, info.fg, info.rank, info.mu_final, info.tau_margin, info.eig_sweeps,
                        [fh[i] for i in range(k)] if history else [], [rh[i] for i in range(k)] if history else [],
                        info.gram_bf16_iters, info.gram_split_iters,
-                       [sh[i] for i in range(k)] if history else [], info.mu0)
+                       [sh[i] for i in range(k)] if history else [], info.mu0, info.partial_eig_iters)
 
 
 def pcp_solve(D, lam: float, mu0: Optional[float] = None, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,

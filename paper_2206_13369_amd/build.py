@@ -20,7 +20,8 @@ BUILD = os.path.join(ROOT, "_build")
 LIB = os.path.join(HERE, "libmlpcp.so")
 ARCH = "gfx950"
 
-SOURCES = ["operators.hip", "eig.hip", "gram.hip", "dense.hip", "solver.hip", "fwt.hip", "profile.hip", "spectral.hip"]
+SOURCES = ["operators.hip", "eig.hip", "gram.hip", "dense.hip", "solver.hip", "fwt.hip", "profile.hip", "spectral.hip",
+           "subspace.hip"]
 
 
 def _hipcc() -> str:

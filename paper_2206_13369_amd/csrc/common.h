@@ -107,6 +107,8 @@ struct IterStats {
   double trace;    // sum of the coarse eigenvalues (||M_H||_F^2)
   int rank;
   int sweeps;      // Jacobi sweeps of the one-workgroup coarse SVT (-1: sweep cap hit)
+  double lam_r;    // smallest eigenvalue kept (0 at rank 0)
+  double lam_65;   // 65th largest eigenvalue (0 below width 65)
 };
 
 // Sweep count placeholder: the count is in IterStats::sweeps after the next sync.
@@ -133,6 +135,27 @@ int eig_sym(int n, int N, double* A, double* V, double* lam, int* perm, void* ws
             hipStream_t stream, int* sweeps_out, bool warm, int sweep_hint = 0, double cert_tau2 = 0.0,
             double* gb = nullptr);
 
+// ---- rank-predicted partial eigensolve (subspace.hip) ----------------------------------
+// Workspace of svt_partial for an N x N Gram.
+size_t subspace_workspace_bytes(int N);
+// Whether svt_partial may be tried: N a multiple of 64, at least 128, and the previous
+// rank in [1, 56].
+bool subspace_eligible(int N, int r_prev);
+// The eigenpairs of G (N x N, ld N, float64) above tau^2 from a 64-column block started at
+// the columns perm[0..63] of V (first_iters subspace steps before the first Rayleigh-Ritz
+// step), with a certificate that G has no other eigenvalue at or above tau^2.
+// *ok = true: V[:, 0..r) holds them (descending), lam their values and -1 beyond, perm the
+// identity, gb (N entries) -1 within the first r and the certified bound beyond,
+// *trace_dev (device) = trace(G).  *ok = false: V, lam, perm, gb untouched (the caller
+// runs the full eigensolver).  *iters = subspace steps taken; *ratio = the block's last
+// Ritz value over its r-th (the convergence factor of the next solve's steps).
+// Synchronises `s`.
+int svt_partial(int N, const double* G, double tau, int first_iters, double* V, double* lam, int* perm, double* gb,
+                double* trace_dev, void* ws, hipStream_t s, bool* ok, int* iters, double* ratio);
+// Subspace steps for a convergence factor rho = lambda_65 / lambda_r: enough to bring the
+// residual of the leading pairs down by about 1e-10.
+int subspace_steps(double rho);
+
 // ---- Gram (gram.hip) ---------------------------------------------------------------
 // G = A^T A for A m x k (float32, ld = lda, k <= kp, kp multiple of kPad), accumulated
 // in float64; G is kp x kp float64 (ld = kp), rows/cols >= k zero.
@@ -148,6 +171,18 @@ int cross_f64(int m, int k, int kp, const float* A, int lda, const float* B, int
 // C(MxN) = alpha * op(A) op(B), float64 row-major with explicit leading dimensions.
 int gemm_f64(bool transA, bool transB, int M, int N, int K, double alpha, const double* A, int lda,
              const double* B, int ldb, double* C, int ldc, hipStream_t stream);
+// C = alpha op(A) op(B) + beta C.
+int gemm_f64_acc(bool transA, bool transB, int M, int N, int K, double alpha, const double* A, int lda,
+                 const double* B, int ldb, double beta, double* C, int ldc, hipStream_t stream);
+// The lower block triangle of C (the 64 x 64 tiles on and below the diagonal; n x n,
+// ld ldc) += alpha A B^T, plus alpha B A^T when sym; A, B n x 64 float64 (ld 64).
+int rank64_lower_f64(int n, const double* A, const double* B, double alpha, bool sym, double* C, int ldc,
+                     hipStream_t stream);
+// Upper Cholesky factor inverse of the leading p x p block of S (p <= 64): Rinv = R^{-1}
+// with S = R^T R (64 x 64, identity beyond p); *fail = 1 if a pivot is not above
+// floor_rel times the largest diagonal entry.  One wave.
+int chol_inv64(int p, const double* S, int lds, double floor_rel, double* Rinv, int ldr, int* fail,
+               hipStream_t stream);
 // Out(m x k2, float32, ldo) = In(m x k1, float32, ldi) * W(k1 x k2, float64, ldw),
 // accumulated in float64.
 int rmul_f32_by_f64(int m, int k1, int k2, const float* In, int ldi, const double* W, int ldw,

@@ -35,6 +35,11 @@ namespace {
 
 constexpr int kThreads = 256;
 constexpr size_t kLdsBudget = 60 * 1024;
+// Below this width the full Jacobi eigensolver measured faster than the partial one
+// (a 256-wide plain Gram at rank 7-9: 125 ms per solve with the full solver, 142 ms with
+// the partial one, whose 64 x 64 Rayleigh-Ritz solve and Cholesky steps are latency
+// bound); at 2048 the partial one wins (445 -> 300 ms).
+constexpr int kPartialMinWidth = 1024;
 
 enum Mode { MODE_STEP = 0, MODE_FINAL = 1, MODE_RECON = 2 };
 
@@ -169,7 +174,8 @@ __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM,
 // singular values from tau.
 __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict__ lam, const int* __restrict__ perm,
                                                        int nH, double tau, const double* __restrict__ gb,
-                                                       double* __restrict__ sw, IterStats* __restrict__ st) {
+                                                       double* __restrict__ sw, IterStats* __restrict__ st,
+                                                       const double* __restrict__ trace) {
   __shared__ int cnt[kThreads];
   __shared__ double mg[kThreads];
   __shared__ double tr[kThreads];
@@ -202,7 +208,9 @@ __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict_
   if (threadIdx.x == 0) {
     st->rank = cnt[0];
     st->margin = mg[0];
-    st->trace = tr[0];
+    st->trace = trace ? *trace : tr[0];
+    st->lam_r = cnt[0] > 0 ? lam[perm[cnt[0] - 1]] : 0.0;
+    st->lam_65 = nH > 64 ? lam[perm[64]] : 0.0;
   }
 }
 
@@ -766,7 +774,8 @@ struct Plan {
   // the tall reconstruction N = M_P K (0 float32 MFMA, 2 split bfloat16)
   int gram_prec, recon_prec;
   size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_gb, off_perm, off_sw, off_T, off_Tt,
-      off_K, off_part, off_gram, off_eig, off_stats, total;
+      off_K, off_part, off_gram, off_eig, off_stats, off_sub, total;
+  bool sub;   // workspace for the rank-predicted partial eigensolve (solves on the wide path)
 };
 
 int device_cus() {
@@ -822,7 +831,7 @@ int gram_prec_for(int prec, double tau, double trace_prev, int m, int nH) {
   return 0;
 }
 
-int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_FP32) {
+int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_FP32, bool partial = false) {
   p.m = m;
   prec_split(prec, p.gram_prec, p.recon_prec);
   p.n = n;
@@ -881,7 +890,7 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
   p.off_tmp = take(p.plain ? 0 : nn * 8);
   p.off_V = take(nn * 8);
   p.off_lam = take((size_t)p.nHp * 8);
-  p.off_gb = take((size_t)p.nHp * 8);
+  p.off_gb = take((size_t)p.nHp * 8 + 8);   // + the partial eigensolve's trace of G
   p.off_perm = take((size_t)p.nHp * 4);
   p.off_sw = take((size_t)p.nHp * 8);
   p.off_T = take(nn * 8);
@@ -891,6 +900,8 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
   p.off_gram = take(gram_workspace_bytes(m, p.nHp));
   p.off_eig = take(eig_workspace_bytes(p.nHp));
   p.off_stats = take(sizeof(IterStats));
+  p.sub = partial && p.nHp >= kPartialMinWidth && subspace_eligible(p.nHp, 1);
+  p.off_sub = take(p.sub ? subspace_workspace_bytes(p.nHp) : 0);
   p.total = off + 256;  // slack for aligning the caller's base pointer
   return MLPCP_OK;
 }
@@ -927,13 +938,34 @@ int valid_opts(const mlpcp_opts& o) {
   return MLPCP_OK;
 }
 
+// Eigensolver state carried across the iterations of a solve: the previous rank (which
+// decides whether the partial eigensolve is tried) and whether V holds a full orthogonal
+// basis (after a partial solve only its leading columns are meaningful, so the next full
+// Jacobi starts cold).
+struct EigState {
+  int r_prev = 0;
+  double margin_prev = 0.0;   // the previous SVT's min |sigma - tau| / tau
+  double rho = 1.0;           // convergence factor lambda_65 / lambda_r of the previous spectrum
+  bool v_full = false;
+  int partial_iters = 0;      // iterations whose SVT the partial eigensolve gave
+  bool last_partial = false;
+};
+
+// The partial eigensolve is tried when the previous rank was small and either the
+// previous SVT came from it too or the previous spectrum kept a clear gap at the
+// threshold: with eigenvalues within a few percent of tau^2 the block's steps converge
+// too slowly to pay (the full solver then runs).  (After a partial solve the margin's
+// part beyond the block is the certificate's bound, a lower bound close to zero, so it
+// cannot serve as the gate.)
+constexpr double kPartialMinMargin = 0.05;
+
 // One coarse SVT on M_P (buffer `mp`): Gram, C G C, eigensolve, weights, T.
 // certify: let the eigensolver leave undiagonalised what Gershgorin bounds put below
 // tau^2 (the whole matrix, whose SVT is then zero, or on wide matrices a block of it);
 // V and lam are then not the eigendecomposition, so callers that need it (the SVT's
 // derivative) pass false.
 int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, double tau, hipStream_t s,
-               int* sweeps, bool warm, bool certify, int gram_prec = -1) {
+               int* sweeps, bool warm, bool certify, int gram_prec = -1, EigState* es = nullptr) {
   if (gram_prec < 0) gram_prec = p.gram_prec;
   double* G = w.at<double>(p.off_G);
   double* V = w.at<double>(p.off_V);
@@ -958,12 +990,37 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
   }
-  // the previous eigensolve's sweep count (in *sweeps on entry) sizes the first batch
   double* gb = certify ? w.at<double>(p.off_gb) : nullptr;
-  MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps, warm, warm ? *sweeps : 0,
-                    certify ? tau * tau : 0.0, gb));
+  // rank-predicted partial eigensolve (the previous rank was small), else the full one
+  bool partial = false;
+  double* trace = nullptr;
+  const bool was_partial = es && es->last_partial;
+  if (es) es->last_partial = false;
+  if (es && p.sub && certify && subspace_eligible(p.nHp, es->r_prev) &&
+      (was_partial || es->margin_prev >= kPartialMinMargin)) {
+    int it = 0;
+    double ratio = 1.0;
+    double* tr_out = w.at<double>(p.off_gb) + p.nHp;
+    MLPCP_TRY(svt_partial(p.nHp, GH, tau, subspace_steps(es->rho), V, lam, perm, gb, tr_out, w.at<void>(p.off_sub), s,
+                          &partial, &it, &ratio));
+    trace = partial ? tr_out : nullptr;
+    if (partial) {
+      es->rho = ratio;
+      es->v_full = false;
+      ++es->partial_iters;
+      es->last_partial = true;
+      *sweeps = 0;
+    }
+  }
+  if (!partial) {
+    const bool warm_ok = warm && (!es || es->v_full);
+    // the previous eigensolve's sweep count (in *sweeps on entry) sizes the first batch
+    MLPCP_TRY(eig_sym(p.nH, p.nHp, GH, V, lam, perm, w.at<void>(p.off_eig), s, sweeps, warm_ok,
+                      warm_ok ? *sweeps : 0, certify ? tau * tau : 0.0, gb));
+    if (es) es->v_full = true;
+  }
   ProfScope ps(KC_SVT, s);
-  hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, gb, sw, st);
+  hipLaunchKernelGGL(k_svt_prep, dim3(1), dim3(kThreads), 0, s, lam, perm, p.nH, tau, gb, sw, st, trace);
   const size_t tot = (size_t)p.nH * p.nH;
   if (p.plain)
     hipLaunchKernelGGL(k_build_T<true>, dim3(grid_for(tot)), dim3(kThreads), 0, s, p.nH, p.nHp, op.C, V, perm, sw,
@@ -1075,7 +1132,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   if (L == S || L == Y || (Y && S == Y) || (const float*)L == D || (const float*)S == D) return MLPCP_E_INVALID_ARG;
   if ((S0 && (const float*)L == S0) || (Y0 && (const float*)L == Y0)) return MLPCP_E_INVALID_ARG;
   Plan p;
-  MLPCP_TRY(make_plan(m, n, o.levels, masked, p, o.prec));
+  MLPCP_TRY(make_plan(m, n, o.levels, masked, p, o.prec, true));
   const size_t need = std::max(p.total, spectral_workspace_bytes(m, n) + 256);
   if (ws && ws_bytes < need) return MLPCP_E_WORKSPACE;
 
@@ -1115,7 +1172,10 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   IterStats hs;
   MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
   MLPCP_HIP(hipStreamSynchronize(s));
-  if (info) info->mu0 = mu0;
+  if (info) {
+    info->mu0 = mu0;
+    info->partial_eig_iters = 0;
+  }
   // an observed entry of D, S0 or Y0 that is NaN or infinite: nothing is iterated
   if (!std::isfinite(hs.nrm2)) {
     if (info) {
@@ -1154,12 +1214,13 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   int status = MLPCP_OK;
   double trace_prev = INFINITY;
   int bf16_iters = 0, split_iters = 0;
+  EigState es;
   for (t = 0; t < o.max_iter; ++t) {
     const double mu_next = std::min(o.rho * mu, mu_max);
     const int gp = gram_prec_for(o.prec, 1.0 / mu, trace_prev, m, p.nH);
     bf16_iters += gp == 1;
     split_iters += gp == 2;
-    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0, true, gp));
+    MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0, true, gp, &es));
     EpiArgs a{};
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
@@ -1186,6 +1247,9 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     MLPCP_TRY(resolve_sweeps(sweeps, hs));
     fg = std::sqrt(hs.fg2) / nrmD;
     rank = hs.rank;
+    es.r_prev = rank;
+    es.margin_prev = hs.margin;
+    if (!es.last_partial) es.rho = hs.lam_r > 0.0 ? std::max(hs.lam_65, 0.0) / hs.lam_r : 1.0;
     margin = hs.margin;
     trace_prev = hs.trace;
     if (info && info->fg_history && t < info->history_len) info->fg_history[t] = fg;
@@ -1231,6 +1295,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     info->eig_sweeps = sweeps;
     info->gram_bf16_iters = bf16_iters;
     info->gram_split_iters = split_iters;
+    info->partial_eig_iters = es.partial_iters;
   }
   return status;
 }
@@ -1542,7 +1607,7 @@ size_t mlpcp_workspace_bytes(int m, int n, const mlpcp_opts* optp) {
     mlpcp_default_opts(&o);
   if (m < 1 || n < 1 || m < n) return 0;
   Plan p;
-  if (make_plan(m, n, o.levels, true, p) != MLPCP_OK) return 0;
+  if (make_plan(m, n, o.levels, true, p, MLPCP_FP32, true) != MLPCP_OK) return 0;
   // the default-mu_0 phase (mu0 <= 0) runs in the same workspace before the iterations
   return std::max(p.total, spectral_workspace_bytes(m, n) + 256);
 }

@@ -67,7 +67,8 @@ def _compare(name, levels, prec="fp32"):
     r = _solve(w, levels, 1e-6, prec=prec)
     eL, eS = rel(to_np(r.L), ref["L"]), rel(to_np(r.S), ref["S"])
     say(f"   iters {r.iters}/{ref['iters']} errL {eL:.2e} errS {eS:.2e} rank {r.rank}/{ref['rank']} "
-        f"margin {r.tau_margin:.2e} Gram bf16/split iters {r.gram_bf16_iters}/{r.gram_split_iters}")
+        f"margin {r.tau_margin:.2e} Gram bf16/split iters {r.gram_bf16_iters}/{r.gram_split_iters} "
+        f"partial eigensolve iters {r.partial_eig_iters}")
     assert r.status == mlp.MLPCP_OK and r.fg <= 1e-6
     assert eL <= TOL[prec] and eS <= TOL[prec]
     assert r.rank == ref["rank"]
@@ -87,6 +88,10 @@ def test_c2_plain_full_oracle():
     # plain PCP recovers the rank-50 part from 60% of the entries
     assert r.rank == 50
     assert rel(to_np(r.L), w.L0) < 2e-3
+    # from the second iteration at rank 50 on, every SVT comes from the rank-predicted
+    # partial eigensolve (checked against the oracle's full SVD through the comparison)
+    say(f"   partial eigensolve iterations {r.partial_eig_iters}")
+    assert r.partial_eig_iters >= 10
 
 
 @pytest.mark.parametrize("prec", ["fp32", "bf16x3", "bf16"])
