@@ -25,6 +25,26 @@ constexpr int KC = 16;   // rows per LDS chunk
 
 typedef double d4_t __attribute__((ext_vector_type(4)));
 
+// Blocks are dealt to the eight XCDs in turn (block L to XCD L mod 8), and each XCD has
+// its own L2.  With at least 8 splits a 1-D grid of 8 pairs ceil(splits / 8) blocks is
+// decoded so that every block of split s runs on XCD s mod 8: the rows of a split are
+// then fetched from HBM into one L2 only, however many output tiles read them (blocks
+// with s >= splits exit).  With fewer splits the grid is pairs x splits, split-major.
+__device__ __forceinline__ void xcd_decode(int L, int pairs, int splits, int& pair, int& s) {
+  if (splits < 8) {
+    pair = L % pairs;
+    s = L / pairs;
+    return;
+  }
+  const int xcd = L & 7, j = L >> 3;
+  pair = j % pairs;
+  s = (j / pairs) * 8 + xcd;
+}
+
+unsigned xcd_grid(int pairs, int splits) {
+  return splits < 8 ? (unsigned)(pairs * splits) : (unsigned)(8 * pairs * ((splits + 7) / 8));
+}
+
 __device__ __forceinline__ void tri_decode(int p, int nt, int& ti, int& tj) {
   // p enumerates pairs (ti <= tj) row by row
   ti = 0;
@@ -39,18 +59,20 @@ __device__ __forceinline__ void tri_decode(int p, int nt, int& ti, int& tj) {
 // CROSS = false: G = A^T A, tiles on/above the diagonal; CROSS = true: G = A^T B, all tiles
 template <bool CROSS>
 __global__ void __launch_bounds__(256) k_gram_partial(const float* __restrict__ A, int m, int k, int lda, int kp,
-                                                      int rows_per_split, int ntile, double* __restrict__ part,
-                                                      const float* __restrict__ B, int ldb) {
+                                                      int rows_per_split, int ntile, int splits,
+                                                      double* __restrict__ part, const float* __restrict__ B,
+                                                      int ldb) {
   __shared__ double sI[KC][GT + 1];
   __shared__ double sJ[KC][GT + 1];
-  int ti, tj;
+  int ti, tj, pair, s;
+  xcd_decode(blockIdx.x, CROSS ? ntile * ntile : ntile * (ntile + 1) / 2, splits, pair, s);
+  if (s >= splits) return;
   if (CROSS) {
-    ti = blockIdx.x / ntile;
-    tj = blockIdx.x % ntile;
+    ti = pair / ntile;
+    tj = pair % ntile;
   } else {
-    tri_decode(blockIdx.x, ntile, ti, tj);
+    tri_decode(pair, ntile, ti, tj);
   }
-  const int s = blockIdx.y;
   const int r0 = s * rows_per_split;
   const int r1 = min(m, r0 + rows_per_split);
   const int tid = threadIdx.x;
@@ -102,12 +124,14 @@ constexpr int KB = 32;  // rows per LDS chunk (one MFMA k-step)
 
 template <int PREC>
 __global__ void __launch_bounds__(256) k_gram_partial_bf16(const float* __restrict__ A, int m, int k, int lda, int kp,
-                                                           int rows_per_split, int ntile, double* __restrict__ part) {
+                                                           int rows_per_split, int ntile, int splits,
+                                                           double* __restrict__ part) {
   __shared__ float sI[KB][GT + 1];
   __shared__ float sJ[KB][GT + 1];
-  int ti, tj;
-  tri_decode(blockIdx.x, ntile, ti, tj);
-  const int s = blockIdx.y;
+  int ti, tj, pair, s;
+  xcd_decode(blockIdx.x, ntile * (ntile + 1) / 2, splits, pair, s);
+  if (s >= splits) return;
+  tri_decode(pair, ntile, ti, tj);
   const int r0 = s * rows_per_split;
   const int r1 = min(m, r0 + rows_per_split);
   const int tid = threadIdx.x;
@@ -296,6 +320,76 @@ __global__ void __launch_bounds__(256) k_gram_tall(const float* __restrict__ A, 
   }
 }
 
+// Gram of coarse data at most 16 wide (the finest restrictions of the tall workloads),
+// k <= 16: wave w of block b takes 64-row chunks of rows [r0 + w R, r0 + (w + 1) R),
+// the next chunk's loads in flight while the current one is multiplied.  For
+// v_mfma_f64_16x16x4f64 lane l reads A[row + l/16][l%16], which is both operands at once
+// (A^T[l%16][l/16] and A[l/16][l%16]); with a leading dimension of 16 the four rows of a
+// step are 256 contiguous bytes.  Precision forms (PREC 1 / 2) take 32 rows per
+// v_mfma_f32_16x16x32_bf16 (lane l holds rows 8(l/16) + q, q < 8, of column l%16, again
+// both operands), float32 sums over each 64-row chunk added in float64 as in
+// k_gram_tall.  The four waves' 16 x 16 sums are added in a fixed order into the
+// block's partial (split b, tile 0 of the tall partial layout).
+template <int PREC>
+__global__ void __launch_bounds__(256) k_gram16(const float* __restrict__ A, int m, int k, int lda,
+                                                int rows_per_split, double* __restrict__ part) {
+  __shared__ double red[4][256];
+  const int tid = threadIdx.x, wave = tid >> 6, lane = tid & 63;
+  const int rw = rows_per_split / 4;   // rows per wave (a multiple of 64)
+  const int r0 = blockIdx.x * rows_per_split + wave * rw;
+  const int r1 = min(m, r0 + rw);
+  const int c = lane & 15, g = lane >> 4;
+  const bool cok = c < k;
+  d4_t acc = {0.0, 0.0, 0.0, 0.0};
+  float cur[16], nxt[16];
+  // element u of a chunk: PREC 0 row 4u + g; PREC 1/2 row 32(u / 8) + 8g + u % 8
+  auto fetch = [&](int c0, float (&x)[16]) {
+#pragma unroll
+    for (int u = 0; u < 16; ++u) {
+      const int row = PREC == 0 ? c0 + 4 * u + g : c0 + 32 * (u >> 3) + 8 * g + (u & 7);
+      x[u] = (cok && row < r1) ? A[(size_t)row * lda + c] : 0.0f;
+    }
+  };
+  if (r0 < r1) fetch(r0, cur);
+  for (int c0 = r0; c0 < r1; c0 += 64) {
+    if (c0 + 64 < r1) fetch(c0 + 64, nxt);
+    if (PREC == 0) {
+#pragma unroll
+      for (int u = 0; u < 16; ++u) acc = __builtin_amdgcn_mfma_f64_16x16x4f64((double)cur[u], (double)cur[u], acc, 0, 0, 0);
+    } else {
+      f32x4_t cs = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+      for (int s2 = 0; s2 < 2; ++s2) {
+        bf16x8_t h, lo;
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const float x = cur[8 * s2 + q];
+          const unsigned short hb = f2bf(x);
+          h[q] = __builtin_bit_cast(__bf16, hb);
+          lo[q] = __builtin_bit_cast(__bf16, f2bf(x - bf2f(hb)));
+        }
+        if (PREC == 2) {
+          cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(lo, h, cs, 0, 0, 0);
+          cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, lo, cs, 0, 0, 0);
+        }
+        cs = __builtin_amdgcn_mfma_f32_16x16x32_bf16(h, h, cs, 0, 0, 0);
+      }
+#pragma unroll
+      for (int v = 0; v < 4; ++v) acc[v] += (double)cs[v];
+    }
+#pragma unroll
+    for (int u = 0; u < 16; ++u) cur[u] = nxt[u];
+  }
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    // f64 output: register v of lane l is row 4v + l/16; bf16: row 4(l/16) + v
+    const int row = PREC == 0 ? 4 * v + g : 4 * g + v;
+    red[wave][row * 16 + c] = acc[v];
+  }
+  __syncthreads();
+  part[(size_t)blockIdx.x * 256 + tid] = ((red[0][tid] + red[1][tid]) + red[2][tid]) + red[3][tid];
+}
+
 // G from the tall partials: 16 tile entries per block, 16 thread groups each summing
 // every 16th split, then the group sums in order; each entry written to both halves.
 // In a diagonal tile only the upper triangle is used: the split product sums (i, j)
@@ -374,6 +468,20 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
   const int pairs = nt * (nt + 1) / 2;
   double* part = static_cast<double*>(ws);
   ProfScope ps(KC_GRAM, stream);
+  if (kp == 64 && k <= 16) {
+    // 256 rows per wave at most, at most 256 splits (blocks)
+    rps = round_up((m + 255) / 256, 256);
+    sp = (m + rps - 1) / rps;
+    if (prec == MLPCP_BF16)
+      hipLaunchKernelGGL(k_gram16<1>, dim3(sp), dim3(256), 0, stream, A, m, k, lda, rps, part);
+    else if (prec == MLPCP_BF16X3)
+      hipLaunchKernelGGL(k_gram16<2>, dim3(sp), dim3(256), 0, stream, A, m, k, lda, rps, part);
+    else
+      hipLaunchKernelGGL(k_gram16<0>, dim3(sp), dim3(256), 0, stream, A, m, k, lda, rps, part);
+    hipLaunchKernelGGL(k_gram_tall_reduce, dim3(256 / 16), dim3(256), 0, stream, part, sp, 1, G, kp);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
   if (kp == 64) {
     const int nt = (k + 15) / 16;
     gram_tall_plan(m, nt, sp, rps);
@@ -388,12 +496,13 @@ int gram_f64(int m, int k, int kp, const float* A, int lda, double* G, void* ws,
     MLPCP_HIP(hipGetLastError());
     return MLPCP_OK;
   }
+  const dim3 grid(xcd_grid(pairs, sp));
   if (prec == MLPCP_BF16)
-    hipLaunchKernelGGL(k_gram_partial_bf16<1>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
+    hipLaunchKernelGGL(k_gram_partial_bf16<1>, grid, dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, sp, part);
   else if (prec == MLPCP_BF16X3)
-    hipLaunchKernelGGL(k_gram_partial_bf16<2>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part);
+    hipLaunchKernelGGL(k_gram_partial_bf16<2>, grid, dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, sp, part);
   else
-    hipLaunchKernelGGL(k_gram_partial<false>, dim3(pairs, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part,
+    hipLaunchKernelGGL(k_gram_partial<false>, grid, dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, sp, part,
                        nullptr, 0);
   const size_t nn = (size_t)kp * kp;
   hipLaunchKernelGGL(k_gram_reduce<false>, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, stream, part, sp, kp, G);
@@ -409,8 +518,8 @@ int cross_f64(int m, int k, int kp, const float* A, int lda, const float* B, int
   const int nt = kp / GT;
   double* part = static_cast<double*>(ws);
   ProfScope ps(KC_OTHER, stream);
-  hipLaunchKernelGGL(k_gram_partial<true>, dim3(nt * nt, sp), dim3(256), 0, stream, A, m, k, lda, kp, rps, nt, part,
-                     B, ldb);
+  hipLaunchKernelGGL(k_gram_partial<true>, dim3(xcd_grid(nt * nt, sp)), dim3(256), 0, stream, A, m, k, lda, kp,
+                     rps, nt, sp, part, B, ldb);
   const size_t nn = (size_t)kp * kp;
   hipLaunchKernelGGL(k_gram_reduce<true>, dim3((unsigned)((nn + 63) / 64)), dim3(256), 0, stream, part, sp, kp, G);
   MLPCP_HIP(hipGetLastError());

@@ -769,6 +769,10 @@ struct Plan {
   // tall path (n_H <= kTallNH, not plain): persistent grid over TM_tall-row tiles
   bool tall;
   int TM_tall, ntiles_tall, grid_tall, nnz;
+  // leading dimension of the coarse data M_P (m x n_H float32): n_H rounded up to 16 on
+  // the tall path (the rows are then 64-byte aligned and nothing beyond is stored),
+  // nHp on the wide path (whose epilogue stages M_P rows at that width)
+  int ldmp;
   size_t lds_tall;
   // precision of the Gram (0 float64 products, 1 bfloat16, 2 split bfloat16) and of
   // the tall reconstruction N = M_P K (0 float32 MFMA, 2 split bfloat16)
@@ -882,8 +886,9 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
     return o;
   };
   const size_t nn = (size_t)p.nHp * p.nHp;
-  p.off_mp0 = take((size_t)m * p.nHp * 4);
-  p.off_mp1 = take((size_t)m * p.nHp * 4);
+  p.ldmp = p.tall ? round_up(p.nH, 16) : p.nHp;
+  p.off_mp0 = take((size_t)m * p.ldmp * 4);
+  p.off_mp1 = take((size_t)m * p.ldmp * 4);
   p.off_bits = take(masked ? (size_t)m * p.nw * 4 : 0);
   p.off_G = take(nn * 8);
   p.off_GH = take(p.plain ? 0 : nn * 8);
@@ -975,7 +980,7 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   double* T = w.at<double>(p.off_T);
   double* Tt = w.at<double>(p.off_Tt);
   IterStats* st = w.at<IterStats>(p.off_stats);
-  MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.nHp, G, w.at<void>(p.off_gram), s, gram_prec));
+  MLPCP_TRY(gram_f64(p.m, p.nH, p.nHp, mp, p.ldmp, G, w.at<void>(p.off_gram), s, gram_prec));
   if (p.nHp == kEigInner) {
     // one workgroup from the Gram to the reconstruction factors; sweeps come back in st
     *sweeps = kSweepsOnDevice;
@@ -1100,17 +1105,17 @@ int launch_init(const Plan& p, const Operator& op, const float* D, int ldd, cons
   if (p.plain) {
     if (p.masked)
       hipLaunchKernelGGL((k_init<true, true>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
     else
       hipLaunchKernelGGL((k_init<true, false>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
   } else {
     if (p.masked)
       hipLaunchKernelGGL((k_init<false, true>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
     else
       hipLaunchKernelGGL((k_init<false, false>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.nHp, op.col_ptr, op.col_row, op.col_w, partial);
+                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
   }
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
@@ -1222,7 +1227,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     split_iters += gp == 2;
     MLPCP_TRY(coarse_svt(p, *op, w, mp[t & 1], 1.0 / mu, s, &sweeps, t > 0, true, gp, &es));
     EpiArgs a{};
-    a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+    a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
     a.MPcur = mp[t & 1]; a.MPnext = mp[(t + 1) & 1];
     a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt); a.st = st;
@@ -1273,7 +1278,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     const int last = t - 1;
     const double mu_last = converged ? mu : mu_prev;
     EpiArgs a{};
-    a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+    a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
     a.MPcur = mp[last & 1]; a.MPnext = nullptr;
     a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt); a.st = st;
@@ -1503,7 +1508,7 @@ int step_forward_core(const StepPlan& sp, const Operator& op, const WS& w, const
   int sweeps = 0;
   MLPCP_TRY(coarse_svt(p, op, w, mp, 1.0 / mu, s, &sweeps, false, false));
   EpiArgs a{};
-  a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+  a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
   a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
   a.st = w.at<IterStats>(p.off_stats);
   a.Lout = Lout;
@@ -1538,7 +1543,7 @@ int svt_prox_core(const Plan& p, const Operator& op, const WS& w, const float* M
   int sweeps = 0;
   MLPCP_TRY(coarse_svt(p, op, w, mp, (double)tau, s, &sweeps, false, true));
   EpiArgs a{};
-  a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.nHp; a.nw = p.nw; a.ldT = p.nHp;
+  a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
   a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
   a.st = w.at<IterStats>(p.off_stats);
   a.Lout = L;
@@ -1737,7 +1742,7 @@ int mlpcp_ialm_step_vjp(int m, int n, int levels, const float* D, int ldd, const
   const float* MP = w.at<float>(p.off_mp0);
   double* Z = w.at<double>(sp.off_Z);
   MLPCP_HIP(hipMemsetAsync(Z, 0, (size_t)p.nHp * p.nHp * 8, s));
-  MLPCP_TRY(cross_f64(m, p.nH, p.nHp, MP, p.nHp, FbP, ldF, Z, w.at<void>(p.off_gram), s));
+  MLPCP_TRY(cross_f64(m, p.nH, p.nHp, MP, p.ldmp, FbP, ldF, Z, w.at<void>(p.off_gram), s));
   double* V = w.at<double>(p.off_V);
   double* lam = w.at<double>(p.off_lam);
   int* perm = w.at<int>(p.off_perm);
@@ -1765,10 +1770,10 @@ int mlpcp_ialm_step_vjp(int m, int n, int levels, const float* D, int ldd, const
   MLPCP_TRY(gemm_f64(false, true, h, h, h, 1.0, Tw, N, Tf, N, WF, N, s));    // Tf diag(w) Tf^T
   float* Xb = w.at<float>(sp.off_Xb);
   if (p.plain) {
-    hipLaunchKernelGGL(k_rmul2, dim3(m), dim3(kThreads), 0, s, m, h, h, MP, p.nHp, WA, FbP, ldF, WF, N, Xb, n);
+    hipLaunchKernelGGL(k_rmul2, dim3(m), dim3(kThreads), 0, s, m, h, h, MP, p.ldmp, WA, FbP, ldF, WF, N, Xb, n);
   } else {
     float* Xbp = w.at<float>(sp.off_Xbp);
-    hipLaunchKernelGGL(k_rmul2, dim3(m), dim3(kThreads), 0, s, m, h, h, MP, p.nHp, WA, FbP, ldF, WF, N, Xbp, p.nHp);
+    hipLaunchKernelGGL(k_rmul2, dim3(m), dim3(kThreads), 0, s, m, h, h, MP, p.ldmp, WA, FbP, ldF, WF, N, Xbp, p.nHp);
     MLPCP_TRY(apply_Pt(*op, m, Xbp, p.nHp, Xb, n, s));
   }
   hipLaunchKernelGGL(k_vjp_elem2, dim3(grid_for((size_t)m * n)), dim3(kThreads), 0, s, m, n, Xb, inv_mu, D_bar, ldd,
