@@ -65,6 +65,9 @@ def parse():
                     help="skip the tall workloads (c3, c5) of the default line")
     ap.add_argument("--config-steps", type=int, default=3, help="timed multilevel solves per tall-workload entry")
     ap.add_argument("--no-stream", action="store_true", help="skip the streaming-kernel bandwidth summary")
+    ap.add_argument("--stream-only", action="store_true",
+                    help="measure only the standalone streaming entry points (restrict, prolong, shrink) and print "
+                         "their bandwidth summary as one JSON line")
     ap.add_argument("--rnorm", type=int, default=0, choices=[0, 1, 2],
                     help="restriction normalisation of the multilevel solve: 0 orthonormal, 1 P/||P||_2, 2 P "
                          "(ablation; the plain solve is unaffected)")
@@ -344,6 +347,15 @@ def main():
         print("bench.py needs a GPU", file=sys.stderr)
         sys.exit(1)
     dev = torch.device("cuda:0")
+    if a.stream_only:
+        if a.calib_copy:
+            src = torch.ones(a.calib_copy << 18, dtype=torch.float32, device=dev)
+            dst = torch.empty_like(src)
+            torch.mul(src, 1.0, out=dst)
+            torch.cuda.synchronize()
+            del src, dst
+        print(json.dumps({"streaming": stream_bench(dev)}))
+        return
     if a.workload.startswith("fw"):
         w = synth.fw_config(a.workload)
         if a.calib_copy:
