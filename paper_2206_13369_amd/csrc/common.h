@@ -28,6 +28,7 @@ constexpr int kEigBlock = 32;          // Jacobi block width b; inner problems a
 constexpr int kEigInner = 2 * kEigBlock;
 constexpr int kPad = 64;               // padding of n_H for the Gram / eigensolver tiles
 constexpr int kMaxStencil = 2;         // nonzeros per fine row of the composite interpolation
+constexpr int kQfWidth = 16;           // coarse widths up to this also get the dense float32 operator P C
 constexpr int kMaxEigSweeps = 40;
 
 inline int round_up(int x, int m) { return (x + m - 1) / m * m; }
@@ -59,6 +60,7 @@ struct Operator {
   int* col_row = nullptr;     // [nnz]
   float* col_w = nullptr;     // [nnz]
   double* C = nullptr;        // [nH * nH] (nullptr when levels == 0)
+  float* Qf = nullptr;        // [kQfWidth * n]: (P C)^T in float32, zero rows beyond nH (nH <= kQfWidth only)
   void* mem = nullptr;        // device block holding the tables and C (owned by the cache)
 };
 

@@ -129,10 +129,25 @@ struct OpDeleter {
 std::mutex g_op_mutex;
 std::map<std::tuple<int, int, int>, std::unique_ptr<Operator, OpDeleter>> g_ops;
 
+// QfT = (P C)^T in float32 (kQfWidth x n, zero rows beyond n_H): row j of P has at most
+// two taps, so column j of QfT is w0 C[c0, :] + w1 C[c1, :], formed in float64 and
+// rounded once.
+__global__ void k_build_Qf(int n, int nH, const int* __restrict__ row_idx, const float* __restrict__ row_w,
+                           const double* __restrict__ C, float* __restrict__ Qf) {
+  for (int e = blockIdx.x * blockDim.x + threadIdx.x; e < n * kQfWidth; e += gridDim.x * blockDim.x) {
+    const int j = e / kQfWidth, c = e % kQfWidth;
+    double v = 0.0;
+    if (c < nH)
+      for (int t = 0; t < kMaxStencil; ++t)
+        v = fma((double)row_w[j * kMaxStencil + t], C[(size_t)row_idx[j * kMaxStencil + t] * nH + c], v);
+    Qf[(size_t)c * n + j] = (float)v;
+  }
+}
+
 // Device memory of one operator, carved from two blocks: `kept` (stencil tables and C,
 // alive as long as the operator) and `tmp` (the eigensolve that forms C).
 struct OpLayout {
-  size_t off_row_idx, off_row_w, off_col_ptr, off_col_row, off_col_w, off_C, kept;
+  size_t off_row_idx, off_row_w, off_col_ptr, off_col_row, off_col_w, off_C, off_Qf, kept;
   size_t off_A, off_V, off_W, off_lam, off_perm, off_ews, tmp;
 };
 
@@ -152,6 +167,7 @@ OpLayout op_layout(int n, int levels) {
   l.off_col_row = take(nnz * sizeof(int));
   l.off_col_w = take(nnz * sizeof(float));
   l.off_C = take(levels > 0 ? (size_t)nH * nH * sizeof(double) : 0);
+  l.off_Qf = take(levels > 0 && nH <= kQfWidth ? (size_t)n * kQfWidth * sizeof(float) : 0);
   l.kept = off;
   off = 0;
   if (levels > 0) {
@@ -259,6 +275,13 @@ int build_operator_at(int n, int levels, int r_norm, hipStream_t stream, Operato
     std::vector<double> hc((size_t)nH * nH, 0.0);
     for (int i = 0; i < nH; ++i) hc[(size_t)i * nH + i] = sc;
     MLPCP_HIP(hipMemcpyAsync(op->C, hc.data(), hc.size() * 8, hipMemcpyHostToDevice, stream));
+  }
+  if (nH <= kQfWidth) {
+    op->Qf = reinterpret_cast<float*>(base + l.off_Qf);
+    const int cnt = n * kQfWidth;
+    hipLaunchKernelGGL(k_build_Qf, dim3((cnt + 255) / 256), dim3(256), 0, stream, n, nH, op->row_idx, op->row_w,
+                       op->C, op->Qf);
+    MLPCP_HIP(hipGetLastError());
   }
   MLPCP_HIP(hipStreamSynchronize(stream));
   return MLPCP_OK;
@@ -734,6 +757,66 @@ bool pipe_plan(int n, int nH, int max_col_nnz, PipePlan& pp) {
   return false;
 }
 
+// ---- restriction at coarse widths up to 16: the dense operator P C on float32 MFMA ----
+// The restriction is then a product with an n x 16 matrix, which each wave keeps in
+// registers as MFMA operand fragments for the whole launch; the data rows go from HBM
+// straight to registers, with no LDS and no barrier, so a wave's whole tile is in flight
+// at once, and the waves loop over 16-row tiles.  v_mfma_f32_16x16x4f32: lane l supplies
+// A[l%16][k] and B[k][l%16] for its k of the step, and receives D[4(l/16) + v][l%16],
+// v < 4.  Float32 accumulation (the output is float32): relative error about 1e-7
+// against the float64 products at n = 200.  (The prolongation keeps the LDS-staged
+// kernel: from registers its stores cover 64 bytes of each of 16 rows per instruction,
+// which measured slower, 4.9 against 5.6 TB/s with the operand cache-resident, than
+// whole staged rows.)
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+// XH (m x nH) = X (m x n) Qf: D = XH^T tile (coarse c x 16 rows) = Qf^T X^T.  Step (s, t)
+// of lane group g = l/16 contracts the fine index k = 16 s + 4 g + t, so one float4 load
+// per s gives a lane its four B operands; the A fragments qa[s][t] = Qf[k][l%16] follow
+// the same order.
+__global__ void __launch_bounds__(256) k_restrict_mfma(int m, int n, int nH, const float* __restrict__ X, int ldx,
+                                                       float* __restrict__ XH, int ldh, const float* __restrict__ Qf) {
+  const int lane = threadIdx.x & 63, g = lane >> 4, c = lane & 15;
+  const int S = (n + 15) >> 4;   // at most 16 (n <= 256)
+  // qa[s][t] = (P C)[16 s + 4 g + t][c] = QfT[c][16 s + 4 g + t]: one float4
+  const float* QfT = Qf;
+  float4 qa[16];
+#pragma unroll
+  for (int s = 0; s < 16; ++s) {
+    const int k0 = 16 * s + 4 * g;
+    qa[s] = (s < S && k0 < n) ? *reinterpret_cast<const float4*>(QfT + (size_t)c * n + k0)
+                              : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+  }
+  const int tiles = (m + 15) >> 4;
+  const int nw = gridDim.x * 4;
+  for (int tile = blockIdx.x * 4 + (threadIdx.x >> 6); tile < tiles; tile += nw) {
+    const int row = tile * 16 + c;
+    float4 xv[16];
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      const int k0 = 16 * s + 4 * g;
+      xv[s] = (s < S && k0 < n && row < m) ? *reinterpret_cast<const float4*>(X + (size_t)row * ldx + k0)
+                                           : make_float4(0.0f, 0.0f, 0.0f, 0.0f);
+    }
+    f4_t acc = {0.0f, 0.0f, 0.0f, 0.0f};
+#pragma unroll
+    for (int s = 0; s < 16; ++s) {
+      if (s < S) {
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[s].x, xv[s].x, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[s].y, xv[s].y, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[s].z, xv[s].z, acc, 0, 0, 0);
+        acc = __builtin_amdgcn_mfma_f32_16x16x4f32(qa[s].w, xv[s].w, acc, 0, 0, 0);
+      }
+    }
+    // lane l holds XH[row][4g + v]
+    if (row < m) {
+#pragma unroll
+      for (int v = 0; v < 4; ++v)
+        if (4 * g + v < nH) XH[(size_t)row * ldh + 4 * g + v] = acc[v];
+    }
+  }
+}
+
 // X (m x n) = XH (m x nH) C P^T
 template <bool VEC>
 __global__ void __launch_bounds__(256) k_prolong_stream(int m, int n, int nH, int R, int R16, int nHp, int ldy,
@@ -787,6 +870,18 @@ __global__ void __launch_bounds__(256) k_prolong_stream(int m, int n, int nH, in
           (float)fma((double)srw[2 * j + 1], w[sri[2 * j + 1]], (double)srw[2 * j] * w[sri[2 * j]]);
     }
   }
+}
+
+// blocks of four waves for the register-operator kernels: one wave per 16-row tile up to
+// a few waves per SIMD on every compute unit, the waves then looping over the tiles (the
+// operator fragments are loaded once per wave)
+unsigned mfma_grid(int tiles) {
+  int dev = 0, cus = 0;
+  if (hipGetDevice(&dev) != hipSuccess || hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) !=
+                                              hipSuccess || cus < 1)
+    cus = 256;
+  const int blocks = (tiles + 3) / 4;
+  return (unsigned)std::max(1, std::min(blocks, 8 * cus));
 }
 
 __global__ void k_copy_rows(int m, int n, const float* __restrict__ X, int ldx, float* __restrict__ Y, int ldy) {
@@ -889,6 +984,12 @@ int mlpcp_restrict(int m, int n, const float* X, int ldx, int levels, float* XH,
   const Operator* op = nullptr;
   MLPCP_TRY(get_operator(n, levels, s, &op));
   const bool vec = n % 4 == 0 && ldx % 4 == 0 && (reinterpret_cast<uintptr_t>(X) & 15u) == 0;
+  if (vec && op->Qf && n <= 256) {
+    const int tiles = (m + 15) / 16;
+    hipLaunchKernelGGL(k_restrict_mfma, dim3(mfma_grid(tiles)), dim3(256), 0, s, m, n, nH, X, ldx, XH, ldh, op->Qf);
+    MLPCP_HIP(hipGetLastError());
+    return MLPCP_OK;
+  }
   PipePlan pp;
   if (vec && op->contig && pipe_plan(n, nH, op->max_col_nnz, pp)) {
     const int ntiles = (m + pp.R - 1) / pp.R;

@@ -31,7 +31,7 @@ def test_shrink_matches_float32_formula_exactly():
 
 
 @pytest.mark.parametrize("m,n,levels", [(37, 50, 2), (130, 200, 4), (65, 25, 1), (9, 300, 2), (300, 2000, 3),
-                                        (64, 64, 0)])
+                                        (64, 64, 0), (77, 64, 2), (33, 128, 3), (50, 252, 4), (17, 256, 5)])
 def test_restrict_prolong(m, n, levels):
     say("restrict/prolong", m, n, levels)
     rng = np.random.default_rng(m + n)
@@ -109,7 +109,8 @@ def test_shrink_unaligned_and_tails():
         assert np.array_equal(y, ref.astype(np.float32))
 
 
-@pytest.mark.parametrize("m,n,levels,pad", [(1000, 200, 4, 0), (513, 203, 3, 5), (77, 1000, 2, 3), (40, 1024, 1, 0)])
+@pytest.mark.parametrize("m,n,levels,pad", [(1000, 200, 4, 0), (513, 203, 3, 5), (77, 1000, 2, 3), (40, 1024, 1, 0),
+                                             (300, 96, 3, 4), (61, 200, 4, 8)])
 def test_restrict_prolong_padded_rows(m, n, levels, pad):
     """Row-padded inputs (ld > n, also not a multiple of 4) and widths whose coarse
     tiles take the fallback kernels (n_H = 512 at 1024 / 1 level)."""
