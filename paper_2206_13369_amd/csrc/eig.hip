@@ -786,9 +786,25 @@ __device__ __forceinline__ void pair_at(int ne, int k, int r, int& p, int& q) {
 // follow from the circle method arithmetically, so all loads of a round are issued
 // at once, without branches.  Slots beyond the item counts point at the padding
 // column IN of the thread's own lane row, which no result ever reads.
-template <int ACTIVE, int MT, int MQ>
+// WAVE: problems of width ne <= 16 run on wave 0 alone (ACTIVE = 64), synchronised at
+// wavefront scope instead of by workgroup barriers (a wave's LDS accesses complete in
+// issue order, so the fences only keep the compiler from reordering them); the caller
+// synchronises the workgroup afterwards.
+template <bool WAVE>
+__device__ __forceinline__ void sweep_sync() {
+  if (WAVE) {
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+  } else {
+    __syncthreads();
+  }
+}
+
+template <int ACTIVE, int MT, int MQ, bool WAVE = false>
 __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double cert_tau2, int max_sweeps, double* pc,
                              double* ps, double* pt, double* gbs, int& sweeps) {
+  static_assert(!WAVE || ACTIVE == 64, "the wave form runs on one wave");
   constexpr int kPadCol = IN;
   const int tid = threadIdx.x, lane = tid & 63;
   const int np = ne / 2;
@@ -810,29 +826,33 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double c
   }
   for (sweeps = 0;; ++sweeps) {
     if (cert_tau2 > 0.0) {
-      // Gershgorin bound of each row: 16 threads per row (blockDim = 1024 covers 64 rows)
-      const int row = tid >> 4, sub = tid & 15;
+      // Gershgorin bound of each row: 16 threads per row (blockDim = 1024 covers 64 rows);
+      // the wave form: 4 lanes per row (16 rows)
+      constexpr int SUB = WAVE ? 4 : 16;
+      const int row = tid / SUB, sub = tid % SUB;
       double g = 0.0;
       if (row < ne)
-        for (int c = sub; c < ne; c += 16) g += fabs(sA[row][c]);
-      g += __shfl_xor(g, 8);
-      g += __shfl_xor(g, 4);
+        for (int c = sub; c < ne; c += SUB) g += fabs(sA[row][c]);
+      if (!WAVE) {
+        g += __shfl_xor(g, 8);
+        g += __shfl_xor(g, 4);
+      }
       g += __shfl_xor(g, 2);
       g += __shfl_xor(g, 1);
       const bool cert = g < cert_tau2 * (1.0 - 1.0e-12);   // padding rows (zero) pass
-      const bool all = __syncthreads_and(cert);
+      const bool all = WAVE ? (__all(cert) != 0) : __syncthreads_and(cert);
       if (sub == 0) gbs[row] = (all && row < ne) ? g : -1.0;
       if (all) {
-        __syncthreads();
+        sweep_sync<WAVE>();
         return true;
       }
     }
     int want = 0;
-    for (int it = tid; it < ne * ne; it += blockDim.x) {
+    for (int it = tid; it < ne * ne; it += (WAVE ? 64 : (int)blockDim.x)) {
       const int i = it / ne, j = it % ne;
       if (i < j && rotates(sA[i][i], sA[j][j], sA[i][j], fl)) want = 1;
     }
-    if (!__syncthreads_or(want)) return true;
+    if (!(WAVE ? (__any(want) != 0) : __syncthreads_or(want))) return true;
     if (sweeps == max_sweeps) return false;
     for (int r = 0; r < ne - 1; ++r) {
       if (tid < np) {
@@ -842,7 +862,7 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double c
         rotation_fast(sA[p][p], sA[q][q], sA[p][q], fl, c, sn, t);
         pc[tid] = c; ps[tid] = sn; pt[tid] = t;
       }
-      __syncthreads();
+      sweep_sync<WAVE>();
       if (tid < ACTIVE) {
         double t00[MT], t01[MT], t10[MT], t11[MT], qx[MQ], qy[MQ];
         int rp[MT], rq[MT], cp[MT], cq[MT], qp[MQ], qq[MQ];
@@ -891,7 +911,7 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double c
           sQ[qi_[x]][qq[x]] = sn * qx[x] + c * qy[x];
         }
       }
-      __syncthreads();
+      sweep_sync<WAVE>();
     }
   }
 }
@@ -979,9 +999,19 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   int sweeps = 0;
   bool conv = false;
   const double ct2 = certify ? tau * tau : 0.0;
-  if (ne <= 16)
-    conv = small_sweeps<64, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
-  else if (ne <= 32)
+  if (ne <= 16) {
+    __shared__ int wave_res[2];
+    if (tid < 64) {
+      const bool c = small_sweeps<64, 1, 2, true>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
+      if (tid == 0) {
+        wave_res[0] = c ? 1 : 0;
+        wave_res[1] = sweeps;
+      }
+    }
+    __syncthreads();
+    conv = wave_res[0] != 0;
+    sweeps = wave_res[1];
+  } else if (ne <= 32)
     conv = small_sweeps<256, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
   else
     conv = small_sweeps<kSmallThreads, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);

@@ -52,7 +52,8 @@ def test_restrict_prolong(m, n, levels):
                                              (400, 200, 4, 6), (257, 250, 1, 12), (90, 33, 0, 4),
                                              (700, 520, 0, 12), (2000, 2000, 3, 30),
                                              (1200, 1100, 0, 12),    # width >= 1024: partial certificate
-                                             (640, 512, 0, 10)])     # widest split apply step (A alternates)
+                                             (640, 512, 0, 10),      # widest split apply step (A alternates)
+                                             (100, 16, 0, 3), (300, 60, 2, 4), (130, 7, 0, 2)])   # one-wave sweeps
 def test_svt_prox_matches_oracle(m, n, levels, rank):
     say("svt_prox", m, n, levels, rank)
     rng = np.random.default_rng(m * 7 + n)
