@@ -462,8 +462,11 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
   const int n = a.n, nH = a.nH, TM = a.TM;
   float* sMP = reinterpret_cast<float*>(smd);                // 16 x kLdA
   float* sN = sMP + kTallRows * kLdA;                        // 16 x kLdN
-  float* sX = sN + kTallRows * kLdN;                         // TM x n
-  int* sRi = reinterpret_cast<int*>(sX + (size_t)TM * n);   // n x 2
+  // TM x ls, ls = n | 1 odd: the restriction's lanes (one row each) read the same
+  // stencil column of sixteen rows from distinct banks
+  const int ls = n | 1;
+  float* sX = sN + kTallRows * kLdN;
+  int* sRi = reinterpret_cast<int*>(sX + (size_t)TM * ls);   // n x 2
   float* sRw = reinterpret_cast<float*>(sRi + 2 * n);       // n x 2
   int* sCp = reinterpret_cast<int*>(sRw + 2 * n);           // nH + 1
   int* sCr = sCp + (nH + 1);                                // nnz
@@ -518,11 +521,9 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     st_w0[v] = a.row_w[2 * j];
     st_w1[v] = a.row_w[2 * j + 1];
   }
-  // restriction: thread -> coarse column rc_c, rows rc_r0 + k rc_rstep (n_H <= 64, so
-  // at least 4 rows per pass and at most kTallRows / 4 rows per thread)
-  const int rc_rstep = kThreads / nH;
-  const int rc_r0 = tid / nH, rc_c = tid % nH;
-  const bool rc_on = rc_r0 < rc_rstep;
+  // restriction: thread -> row rc_r (of the 16-row tile), coarse columns rc_g + 16 q,
+  // q < 4 (n_H <= 64)
+  const int rc_r = tid & (kTallRows - 1), rc_g = tid / kTallRows;
   double racc = 0.0;
   // the M_P rows of the block's next tile are fetched into registers one tile ahead
   constexpr int MPR = kTallRows * kTallNH / kThreads;
@@ -659,7 +660,7 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
         else
           a.Zout[gij] = o1[0];
 #pragma unroll
-        for (int v = 0; v < V; ++v) sX[(size_t)i * n + j0 + v] = o2[v];
+        for (int v = 0; v < V; ++v) sX[(size_t)i * ls + j0 + v] = o2[v];
       }
     };
     if (fixed_cols) {
@@ -705,36 +706,31 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     }
     if (MODE == MODE_STEP) {
       __syncthreads();
-      // restrict X_{t+1}: thread -> coarse column rc_c, rows rc_r0 + k rc_rstep; each
-      // tap's index and weight are read once for all of the thread's rows
-      if (rc_on) {
-        float acc[kTallRows / 4] = {};
-        const int t0 = sCp[rc_c], t1 = sCp[rc_c + 1];
-        // taps in chunks of 8: their indices and weights are read together, then the
-        // data (same accumulation order as one tap at a time)
-        for (int t = t0; t < t1; t += 8) {
-          int cols[8];
-          float ws[8];
+      // restrict X_{t+1}: thread -> row rc_r, coarse columns rc_g + 16 q; a wave's lanes
+      // read one tap of four columns in sixteen rows (odd row stride: distinct banks)
+      if (rc_r < rows) {
+        const float* x = sX + (size_t)rc_r * ls;
 #pragma unroll
-          for (int u = 0; u < 8; ++u) {
-            cols[u] = t + u < t1 ? sCr[t + u] : 0;
-            ws[u] = t + u < t1 ? sCw[t + u] : 0.0f;
-          }
+        for (int q = 0; q < kTallNH / kTallRows; ++q) {
+          const int c = rc_g + kTallRows * q;
+          if (c >= nH) break;
+          float acc = 0.0f;
+          const int t0 = sCp[c], t1 = sCp[c + 1];
+          // taps in chunks of 8: their indices and weights are read together, then the
+          // data (same accumulation order as one tap at a time)
+          for (int t = t0; t < t1; t += 8) {
+            int cols[8];
+            float ws[8];
 #pragma unroll
-          for (int k = 0; k < kTallRows / 4; ++k) {
-            const int i = rc_r0 + k * rc_rstep;
-            if (i < rows) {
-              const float* x = sX + (size_t)i * n;
-#pragma unroll
-              for (int u = 0; u < 8; ++u)
-                if (t + u < t1) acc[k] = fmaf(ws[u], x[cols[u]], acc[k]);
+            for (int u = 0; u < 8; ++u) {
+              cols[u] = t + u < t1 ? sCr[t + u] : 0;
+              ws[u] = t + u < t1 ? sCw[t + u] : 0.0f;
             }
-          }
-        }
 #pragma unroll
-        for (int k = 0; k < kTallRows / 4; ++k) {
-          const int i = rc_r0 + k * rc_rstep;
-          if (i < rows) a.MPnext[(size_t)(i0 + i) * a.ldp + rc_c] = acc[k];
+            for (int u = 0; u < 8; ++u)
+              if (t + u < t1) acc = fmaf(ws[u], x[cols[u]], acc);
+          }
+          a.MPnext[(size_t)(i0 + rc_r) * a.ldp + c] = acc;
         }
       }
     }
@@ -864,7 +860,7 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
     p.nnz = 2 * n;   // upper bound: at most two weights per fine row
     const size_t fixed = (size_t)4 * kTallRows * (kLdA + kLdN) + (size_t)16 * n + (size_t)4 * (p.nH + 1) +
                          (size_t)8 * p.nnz;
-    const size_t per = (size_t)4 * n;
+    const size_t per = (size_t)4 * (n | 1);
     const size_t budget = 76 * 1024;   // at least two blocks per 160 KB CU
     int tm = budget > fixed ? (int)((budget - fixed) / per) : 0;
     if (tm > kTallRows) tm = kTallRows;
