@@ -453,7 +453,7 @@ constexpr int kRowBatch = 2;           // rows whose loads a thread issues toget
 constexpr int kLdA = kTallNH + 8;      // padded LDS row of the M_P tile
 constexpr int kLdN = kTallNH + 4;      // padded LDS row of the N tile
 
-template <int MODE, bool MASKED, bool VEC, int PREC>
+template <int MODE, bool MASKED, bool VEC, int PREC, bool NARROW>
 __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const double* __restrict__ K, int ntiles,
                                                            int nnz) {
   extern __shared__ double smd[];
@@ -521,9 +521,15 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     st_w0[v] = a.row_w[2 * j];
     st_w1[v] = a.row_w[2 * j + 1];
   }
-  // restriction: thread -> row rc_r (of the 16-row tile), coarse columns rc_g + 16 q,
-  // q < 4 (n_H <= 64)
+  // restriction.  n_H <= 16: thread -> row rc_r of the 16-row tile and coarse column
+  // rc_g (a wave's lanes read one tap of four columns in sixteen rows: with the odd row
+  // stride, distinct banks).  Wider: thread -> coarse column rc_c, rows rc_r0 + k rc_rstep
+  // (at least 4 rows per pass, each tap's index and weight read once for all of them;
+  // measured faster there, 89 against 100 us per launch at n_H = 50)
   const int rc_r = tid & (kTallRows - 1), rc_g = tid / kTallRows;
+  const int rc_rstep = kThreads / nH;
+  const int rc_r0 = tid / nH, rc_c = tid % nH;
+  const bool rc_on = rc_r0 < rc_rstep;
   double racc = 0.0;
   // the M_P rows of the block's next tile are fetched into registers one tile ahead
   constexpr int MPR = kTallRows * kTallNH / kThreads;
@@ -706,18 +712,13 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
     }
     if (MODE == MODE_STEP) {
       __syncthreads();
-      // restrict X_{t+1}: thread -> row rc_r, coarse columns rc_g + 16 q; a wave's lanes
-      // read one tap of four columns in sixteen rows (odd row stride: distinct banks)
-      if (rc_r < rows) {
-        const float* x = sX + (size_t)rc_r * ls;
-#pragma unroll
-        for (int q = 0; q < kTallNH / kTallRows; ++q) {
-          const int c = rc_g + kTallRows * q;
-          if (c >= nH) break;
+      // restrict X_{t+1} (same accumulation order in both forms: taps in order)
+      if (NARROW) {   // n_H <= kTallRows
+        if (rc_r < rows && rc_g < nH) {
+          const float* x = sX + (size_t)rc_r * ls;
           float acc = 0.0f;
-          const int t0 = sCp[c], t1 = sCp[c + 1];
-          // taps in chunks of 8: their indices and weights are read together, then the
-          // data (same accumulation order as one tap at a time)
+          const int t0 = sCp[rc_g], t1 = sCp[rc_g + 1];
+          // taps in chunks of 8: their indices and weights are read together, then the data
           for (int t = t0; t < t1; t += 8) {
             int cols[8];
             float ws[8];
@@ -730,7 +731,34 @@ __global__ void __launch_bounds__(kThreads) k_epilogue_tall(EpiArgs a, const dou
             for (int u = 0; u < 8; ++u)
               if (t + u < t1) acc = fmaf(ws[u], x[cols[u]], acc);
           }
-          a.MPnext[(size_t)(i0 + rc_r) * a.ldp + c] = acc;
+          a.MPnext[(size_t)(i0 + rc_r) * a.ldp + rc_g] = acc;
+        }
+      } else if (rc_on) {
+        float acc[kTallRows / 4] = {};
+        const int t0 = sCp[rc_c], t1 = sCp[rc_c + 1];
+        for (int t = t0; t < t1; t += 8) {
+          int cols[8];
+          float ws[8];
+#pragma unroll
+          for (int u = 0; u < 8; ++u) {
+            cols[u] = t + u < t1 ? sCr[t + u] : 0;
+            ws[u] = t + u < t1 ? sCw[t + u] : 0.0f;
+          }
+#pragma unroll
+          for (int k = 0; k < kTallRows / 4; ++k) {
+            const int i = rc_r0 + k * rc_rstep;
+            if (i < rows) {
+              const float* x = sX + (size_t)i * ls;
+#pragma unroll
+              for (int u = 0; u < 8; ++u)
+                if (t + u < t1) acc[k] = fmaf(ws[u], x[cols[u]], acc[k]);
+            }
+          }
+        }
+#pragma unroll
+        for (int k = 0; k < kTallRows / 4; ++k) {
+          const int i = rc_r0 + k * rc_rstep;
+          if (i < rows) a.MPnext[(size_t)(i0 + i) * a.ldp + rc_c] = acc[k];
         }
       }
     }
@@ -1051,7 +1079,9 @@ bool aligned16(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 15u) ==
 
 template <int MODE, bool MASKED, bool VEC>
 int launch_tall_one(const Plan& p, const EpiArgs& a, const double* K, int nnz, int grid, hipStream_t s) {
-  auto fn = p.recon_prec == 2 ? k_epilogue_tall<MODE, MASKED, VEC, 2> : k_epilogue_tall<MODE, MASKED, VEC, 0>;
+  const bool narrow = p.nH <= kTallRows;
+  auto fn = p.recon_prec == 2 ? (narrow ? k_epilogue_tall<MODE, MASKED, VEC, 2, true> : k_epilogue_tall<MODE, MASKED, VEC, 2, false>)
+                              : (narrow ? k_epilogue_tall<MODE, MASKED, VEC, 0, true> : k_epilogue_tall<MODE, MASKED, VEC, 0, false>);
   MLPCP_HIP(hipFuncSetAttribute(reinterpret_cast<const void*>(fn), hipFuncAttributeMaxDynamicSharedMemorySize,
                                 (int)p.lds_tall));
   hipLaunchKernelGGL(fn, dim3(grid), dim3(kThreads), p.lds_tall, s, a, K, p.ntiles_tall, nnz);
