@@ -65,10 +65,25 @@ __device__ double block_sum(double v, double* red) {
   return s;
 }
 
-// restrict the TM x n panel sX (LDS, ld n) into MP rows i0.. (ld ldp), c < nH
-__device__ __forceinline__ void restrict_panel(const float* sX, int rows, int n, int nH, float* __restrict__ MP,
-                                               int ldp, int i0, const int* __restrict__ col_ptr,
-                                               const int* __restrict__ col_row, const float* __restrict__ col_w) {
+// restrict the TM x n panel sX (LDS, ld ls) into MP rows i0.. (ld ldp), c < nH
+__device__ __forceinline__ void restrict_panel(const float* sX, int ls, int rows, int n, int nH,
+                                               float* __restrict__ MP, int ldp, int i0,
+                                               const int* __restrict__ col_ptr, const int* __restrict__ col_row,
+                                               const float* __restrict__ col_w) {
+  if (nH <= 16 && (ls & 1)) {
+    // thread -> coarse column c = t / 16 and rows t % 16, + 16, ...: a wave's lanes read
+    // one tap of four columns in sixteen rows, from distinct banks (odd row stride)
+    const int c = threadIdx.x >> 4, r0 = threadIdx.x & 15;
+    if (c >= nH) return;
+    const int t0 = col_ptr[c], t1 = col_ptr[c + 1];
+    for (int i = r0; i < rows; i += 16) {
+      const float* x = sX + (size_t)i * ls;
+      float acc = 0.0f;
+      for (int t = t0; t < t1; ++t) acc = fmaf(col_w[t], x[col_row[t]], acc);
+      MP[(size_t)(i0 + i) * ldp + c] = acc;
+    }
+    return;
+  }
   if (nH <= kThreads) {
     // thread -> coarse column c and rows r0, r0 + rstep, ...: each tap's index and weight
     // are read once for up to four of the thread's rows (same sum order per output)
@@ -84,7 +99,7 @@ __device__ __forceinline__ void restrict_panel(const float* sX, int rows, int n,
 #pragma unroll
         for (int k = 0; k < 4; ++k) {
           const int i = rb + k * rstep;
-          if (i < rows) acc[k] = fmaf(w, sX[(size_t)i * n + jr], acc[k]);
+          if (i < rows) acc[k] = fmaf(w, sX[(size_t)i * ls + jr], acc[k]);
         }
       }
 #pragma unroll
@@ -97,7 +112,7 @@ __device__ __forceinline__ void restrict_panel(const float* sX, int rows, int n,
   }
   for (int e = threadIdx.x; e < rows * nH; e += kThreads) {
     const int i = e / nH, c = e % nH;
-    const float* x = sX + (size_t)i * n;
+    const float* x = sX + (size_t)i * ls;
     float acc = 0.0f;
     const int t1 = col_ptr[c + 1];
     for (int t = col_ptr[c]; t < t1; ++t) acc = fmaf(col_w[t], x[col_row[t]], acc);
@@ -122,7 +137,7 @@ __global__ void k_pack_mask(int m, int n, const uint8_t* __restrict__ Q, int nw,
 // Initial coarse data: X_0 = P_Q(D - S0 + Y0/mu0) (or X_0 = M for the standalone SVT),
 // M_P = X_0 P (PLAIN: M_P = X_0), and partial sums of ||P_Q D||^2 (NaN if an observed
 // entry of D, S0 or Y0 is not finite).
-template <bool PLAIN, bool MASKED>
+template <bool PLAIN, bool MASKED, bool VEC>
 __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM, const float* __restrict__ D,
                                                    int ldd, const uint32_t* __restrict__ bits, int nw,
                                                    const float* __restrict__ S0, const float* __restrict__ Y0,
@@ -133,35 +148,80 @@ __global__ void __launch_bounds__(kThreads) k_init(int m, int n, int nH, int TM,
   __shared__ double red[kThreads];
   const int i0 = blockIdx.x * TM;
   const int rows = min(TM, m - i0);
+  const int ls = PLAIN ? n : (n | 1);   // odd LDS row stride of the staged panel
   double acc = 0.0;
-  // element e = i n + j, stepped by kThreads without a division per element
-  int i = threadIdx.x / n, j = threadIdx.x % n;
-  const int di = kThreads / n, dj = kThreads % n;
-  for (int e = threadIdx.x; e < rows * n; e += kThreads) {
-    const int gi = i0 + i;
-    float x = 0.0f;
-    if (!MASKED || qbit(bits, nw, gi, j)) {
-      const float d = D[(size_t)gi * ldd + j];
-      acc += (double)d * (double)d;
-      x = d;
-      if (S0) x -= S0[(size_t)gi * n + j];
-      if (Y0) x += Y0[(size_t)gi * n + j] * inv_mu0;
-      acc += (double)(x - x);   // 0, or NaN when D, S0 or Y0 is not finite here
+  if (VEC && !PLAIN) {
+    // groups of four columns (D, S0, Y0 16-byte aligned rows): one mask word, one float4
+    // of each operand per group, four groups per thread in flight
+    const int n4 = n >> 2;
+    const int total = rows * n4;
+    for (int e0 = threadIdx.x; e0 < total; e0 += 4 * kThreads) {
+      float4 d4[4], s4[4], y4[4];
+      uint32_t qb[4];
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < total) {
+          const int gi = i0 + e / n4, j0 = 4 * (e % n4);
+          qb[u] = MASKED ? (bits[(size_t)gi * nw + (j0 >> 5)] >> (j0 & 31)) & 0xFu : 0xFu;
+          d4[u] = *reinterpret_cast<const float4*>(D + (size_t)gi * ldd + j0);
+          s4[u] = S0 ? *reinterpret_cast<const float4*>(S0 + (size_t)gi * n + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+          y4[u] = Y0 ? *reinterpret_cast<const float4*>(Y0 + (size_t)gi * n + j0) : make_float4(0.f, 0.f, 0.f, 0.f);
+        }
+      }
+#pragma unroll
+      for (int u = 0; u < 4; ++u) {
+        const int e = e0 + u * kThreads;
+        if (e < total) {
+          const int i = e / n4, j0 = 4 * (e % n4);
+          const float dv[4] = {d4[u].x, d4[u].y, d4[u].z, d4[u].w};
+          const float sv[4] = {s4[u].x, s4[u].y, s4[u].z, s4[u].w};
+          const float yv[4] = {y4[u].x, y4[u].y, y4[u].z, y4[u].w};
+#pragma unroll
+          for (int v = 0; v < 4; ++v) {
+            float x = 0.0f;
+            if ((qb[u] >> v) & 1u) {
+              acc += (double)dv[v] * (double)dv[v];
+              x = dv[v];
+              if (S0) x -= sv[v];
+              if (Y0) x += yv[v] * inv_mu0;
+              acc += (double)(x - x);   // 0, or NaN when D, S0 or Y0 is not finite here
+            }
+            sm[(size_t)i * ls + j0 + v] = x;
+          }
+        }
+      }
     }
-    if (PLAIN)
-      MP[(size_t)gi * ldp + j] = x;
-    else
-      sm[(size_t)i * n + j] = x;
-    j += dj;
-    i += di;
-    if (j >= n) {
-      j -= n;
-      ++i;
+  } else {
+    // element e = i n + j, stepped by kThreads without a division per element
+    int i = threadIdx.x / n, j = threadIdx.x % n;
+    const int di = kThreads / n, dj = kThreads % n;
+    for (int e = threadIdx.x; e < rows * n; e += kThreads) {
+      const int gi = i0 + i;
+      float x = 0.0f;
+      if (!MASKED || qbit(bits, nw, gi, j)) {
+        const float d = D[(size_t)gi * ldd + j];
+        acc += (double)d * (double)d;
+        x = d;
+        if (S0) x -= S0[(size_t)gi * n + j];
+        if (Y0) x += Y0[(size_t)gi * n + j] * inv_mu0;
+        acc += (double)(x - x);   // 0, or NaN when D, S0 or Y0 is not finite here
+      }
+      if (PLAIN)
+        MP[(size_t)gi * ldp + j] = x;
+      else
+        sm[(size_t)i * ls + j] = x;
+      j += dj;
+      i += di;
+      if (j >= n) {
+        j -= n;
+        ++i;
+      }
     }
   }
   if (!PLAIN) {
     __syncthreads();
-    restrict_panel(sm, rows, n, nH, MP, ldp, i0, col_ptr, col_row, col_w);
+    restrict_panel(sm, ls, rows, n, nH, MP, ldp, i0, col_ptr, col_row, col_w);
   }
   const double s = block_sum(acc, red);
   if (threadIdx.x == 0 && partial) partial[blockIdx.x] = s;
@@ -389,7 +449,7 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
   if (MODE != MODE_STEP) return;
   if (!PLAIN) {
     __syncthreads();
-    restrict_panel(sX, rows, n, nH, a.MPnext, a.ldp, i0, a.col_ptr, a.col_row, a.col_w);
+    restrict_panel(sX, n, rows, n, nH, a.MPnext, a.ldp, i0, a.col_ptr, a.col_row, a.col_w);
   }
   const double s = block_sum(racc, red);
   if (tid == 0) a.partial[blockIdx.x] = s;
@@ -877,7 +937,7 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
   p.TM = TM;
   p.nblk = (m + TM - 1) / TM;
   p.lds_epi = (size_t)TM * per_row;
-  p.lds_init = p.plain ? 0 : (size_t)TM * n * 4;
+  p.lds_init = p.plain ? 0 : (size_t)TM * (n | 1) * 4;
   p.tall = !p.plain && p.nHp <= kTallNH;
   p.nnz = 0;
   p.TM_tall = 0;
@@ -1128,21 +1188,28 @@ int launch_init(const Plan& p, const Operator& op, const float* D, int ldd, cons
                 const float* S0, const float* Y0, float inv_mu0, float* mp, double* partial, hipStream_t s) {
   const dim3 g(p.nblk), b(kThreads);
   ProfScope ps(KC_INIT, s);
+  auto a16 = [](const void* q) { return (reinterpret_cast<uintptr_t>(q) & 15u) == 0; };
+  const bool vec = !p.plain && p.n % 4 == 0 && ldd % 4 == 0 && a16(D) && (!S0 || a16(S0)) && (!Y0 || a16(Y0));
+#define MLPCP_INIT(PL, MK, VC)                                                                                     \
+  hipLaunchKernelGGL((k_init<PL, MK, VC>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0, Y0, \
+                     inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial)
   if (p.plain) {
     if (p.masked)
-      hipLaunchKernelGGL((k_init<true, true>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
+      MLPCP_INIT(true, true, false);
     else
-      hipLaunchKernelGGL((k_init<true, false>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
+      MLPCP_INIT(true, false, false);
+  } else if (vec) {
+    if (p.masked)
+      MLPCP_INIT(false, true, true);
+    else
+      MLPCP_INIT(false, false, true);
   } else {
     if (p.masked)
-      hipLaunchKernelGGL((k_init<false, true>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
+      MLPCP_INIT(false, true, false);
     else
-      hipLaunchKernelGGL((k_init<false, false>), g, b, p.lds_init, s, p.m, p.n, p.nH, p.TM, D, ldd, bits, p.nw, S0,
-                         Y0, inv_mu0, mp, p.ldmp, op.col_ptr, op.col_row, op.col_w, partial);
+      MLPCP_INIT(false, false, false);
   }
+#undef MLPCP_INIT
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }
