@@ -475,8 +475,12 @@ __global__ void __launch_bounds__(kPairThreads) k_jacobi_pairs(const double* A, 
 
 // 64x64x64 product on MFMA f64 by 4 waves (each a 32x32 quadrant of 2x2 16x16 blocks):
 //   out = opA(X) * Y   with opA(X)[i][k] = TRANS ? X[k][i] : X[i][k]   (X, Y in LDS)
+// kmax (a multiple of 16, at most IN): rows and columns of X and Y from kmax on are zero
+// (or, for the identity-padded basis, contribute nothing to the products formed here),
+// so the contraction stops at kmax and output tiles from kmax on stay zero without MFMAs.
 template <bool TRANS>
-__device__ __forceinline__ void mm64(const double (*X)[LDS_LD], const double (*Y)[LDS_LD], d4_t acc[2][2]) {
+__device__ __forceinline__ void mm64(const double (*X)[LDS_LD], const double (*Y)[LDS_LD], d4_t acc[2][2],
+                                     int kmax = IN) {
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   const int wi = (wave >> 1) * 32, wj = (wave & 1) * 32;
   const int li = lane & 15, lk = lane >> 4;
@@ -484,8 +488,27 @@ __device__ __forceinline__ void mm64(const double (*X)[LDS_LD], const double (*Y
   for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
     for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = (d4_t){0.0, 0.0, 0.0, 0.0};
+  if (kmax >= IN) {
 #pragma unroll 4
-  for (int k0 = 0; k0 < IN; k0 += 4) {
+    for (int k0 = 0; k0 < IN; k0 += 4) {
+      double a[2], b[2];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi) {
+        const int i = wi + bi * 16 + li;
+        a[bi] = TRANS ? X[k0 + lk][i] : X[i][k0 + lk];
+      }
+#pragma unroll
+      for (int bj = 0; bj < 2; ++bj) b[bj] = Y[k0 + lk][wj + bj * 16 + li];
+#pragma unroll
+      for (int bi = 0; bi < 2; ++bi)
+#pragma unroll
+        for (int bj = 0; bj < 2; ++bj)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+    }
+    return;
+  }
+  if (wi >= kmax || wj >= kmax) return;
+  for (int k0 = 0; k0 < kmax; k0 += 4) {
     double a[2], b[2];
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi) {
@@ -497,7 +520,9 @@ __device__ __forceinline__ void mm64(const double (*X)[LDS_LD], const double (*Y
 #pragma unroll
     for (int bi = 0; bi < 2; ++bi)
 #pragma unroll
-      for (int bj = 0; bj < 2; ++bj) acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
+      for (int bj = 0; bj < 2; ++bj)
+        if (wi + bi * 16 < kmax && wj + bj * 16 < kmax)
+          acc[bi][bj] = __builtin_amdgcn_mfma_f64_16x16x4f64(a[bi], b[bj], acc[bi][bj], 0, 0, 0);
   }
 }
 
@@ -932,6 +957,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   __shared__ int prm[IN], redi[kSmallThreads];
   const int tid = threadIdx.x;
   const bool mm_on = tid < 256;   // the 64^3 products run on the first four waves
+  const int km = min(IN, (nH + 15) / 16 * 16);   // beyond it the operands are zero (identity in V)
   d4_t acc[2][2];
   {
     constexpr int PER = IN * IN / kSmallThreads;
@@ -957,22 +983,22 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   __syncthreads();
   if (C) {                                   // G_H = C G C
     if (mm_on) {
-      mm64<false>(sA, sC, acc);
+      mm64<false>(sA, sC, acc, km);
       mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
     }
     __syncthreads();
-    if (mm_on) mm64<false>(sC, sW, acc);
+    if (mm_on) mm64<false>(sC, sW, acc, km);
     __syncthreads();
     if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
     __syncthreads();
   }
   if (warm) {                                // A <- V0^T A V0, Q = V0
     if (mm_on) {
-      mm64<true>(sQ, sA, acc);
+      mm64<true>(sQ, sA, acc, km);
       mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
     }
     __syncthreads();
-    if (mm_on) mm64<false>(sW, sQ, acc);
+    if (mm_on) mm64<false>(sW, sQ, acc, km);
     __syncthreads();
     if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
     __syncthreads();
@@ -1086,7 +1112,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   LdsRow* sT = sW;
   if (C) {
     if (mm_on) {
-      mm64<false>(sC, sW, acc);
+      mm64<false>(sC, sW, acc, km);
       mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
     }
     __syncthreads();
@@ -1107,7 +1133,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
     }
     __syncthreads();
     if (mm_on) {
-      mm64<true>(sQ, sQ, acc);
+      mm64<true>(sQ, sQ, acc, km);
       mm64_store(acc, [&](int i, int j, double v) { K[(size_t)i * IN + j] = v; });
     }
   }
