@@ -104,11 +104,12 @@ def recovery_errors(w, r, dev):
     return round(eL, 6), round(eS, 6)
 
 
-def algorithmic_work(cls, w, nH, plain, sweeps):
+def algorithmic_work(cls, w, nH, plain, sweeps, msvt=None):
     """(bound, amount per launch) of the method's own work for one launch of a kernel
     class: HBM bytes the kernel must move ("hbm"), or float64 flops ("mfma" for the
     matrix-core products, "alu" for the latency-bound Jacobi rounds).  `sweeps` is the
-    per-iteration Jacobi sweep count of the solve."""
+    per-iteration Jacobi sweep count of the solve; `msvt` = (products, launches) of the
+    matrix-function SVT's product kernel in one solve."""
     m, n = w.m, w.n
     masked = w.Q is not None
     k = n if plain else nH
@@ -124,6 +125,12 @@ def algorithmic_work(cls, w, nH, plain, sweeps):
         # whichever side of the float64 ridge (9.8 flop/B) the intensity k/2 falls on
         flops, byts = 2.0 * m * k * k, 4.0 * m * k
         return ("mfma", flops) if flops / byts > FP64_PEAK / HBM_PEAK else ("hbm", byts)
+    if cls == "msvt_mm":
+        # N x N x N float64 products (N = n_H padded to 64), one or two per launch
+        if not msvt or not msvt[1]:
+            return None, None
+        N = int(math.ceil(k / 64.0)) * 64
+        return "mfma", 2.0 * N ** 3 * msvt[0] / msvt[1]
     sw = (sum(sweeps) / len(sweeps)) if sweeps else 0.0
     if cls == "coarse_svt_small":
         # rounds of the circle method: ne/2 rotations; each 2x2 tile of A (ne/2)^2 tiles,
@@ -514,7 +521,8 @@ def ialm_bench(w, dev, steps, warmup, prec, *, plain=True, plain_steps=1, rnorm=
     eL, eS = recovery_errors(w, r, dev)
     print(f"[bench] {w.name} {prec} multilevel: {ml_s*1e3:.2f} ms/solve, {r.iters} iters, fg {r.fg:.2e}, "
           f"rank {r.rank}, errL0 {eL:.3g}, errS0 {eS:.3g}; dominant kernel {dom}; Gram bf16/split iters "
-          f"{r.gram_bf16_iters}/{r.gram_split_iters}; partial-eigensolve iters {r.partial_eig_iters}",
+          f"{r.gram_bf16_iters}/{r.gram_split_iters}; partial-eigensolve iters {r.partial_eig_iters}; "
+          f"matrix-function SVT iters {r.msvt_iters} ({r.msvt_products} products, flags {r.msvt_flags})",
           file=sys.stderr, flush=True)
 
     # the same solves with HIP events around the dominant kernel class only
@@ -531,6 +539,7 @@ def ialm_bench(w, dev, steps, warmup, prec, *, plain=True, plain_steps=1, rnorm=
 
     out = dict(time_s=ml_s, prec=prec, iters=r.iters, iters_per_s=round(r.iters / ml_s, 2), fg=r.fg, rank=r.rank,
                err_L0=eL, err_S0=eS, tau_margin=r.tau_margin, partial_eig_iters=r.partial_eig_iters,
+               msvt_iters=r.msvt_iters, msvt_products=r.msvt_products,
                gram_tiers={"bf16": r.gram_bf16_iters, "split": r.gram_split_iters})
     if plain:
         ws_pl = torch.empty(mlp.workspace_bytes(w.m, w.n, mlp.default_opts(levels=0)), dtype=torch.uint8,
@@ -548,23 +557,25 @@ def ialm_bench(w, dev, steps, warmup, prec, *, plain=True, plain_steps=1, rnorm=
         plain_s = (time.perf_counter() - tp0) / plain_steps
         peL, peS = recovery_errors(w, rp, dev)
         print(f"[bench] {w.name} {prec} plain: {plain_s*1e3:.1f} ms/solve, {rp.iters} iters, fg {rp.fg:.2e}, "
-              f"rank {rp.rank}, errL0 {peL:.3g}, errS0 {peS:.3g}; partial-eigensolve iters {rp.partial_eig_iters}",
+              f"rank {rp.rank}, errL0 {peL:.3g}, errS0 {peS:.3g}; partial-eigensolve iters {rp.partial_eig_iters}; "
+              f"matrix-function SVT iters {rp.msvt_iters}",
               file=sys.stderr, flush=True)
         out.update(plain_time_s=round(plain_s, 5), plain_iters=rp.iters,
                    plain_iters_per_s=round(rp.iters / plain_s, 3), plain_rank=rp.rank, plain_fg=rp.fg,
                    plain_err_L0=peL, plain_err_S0=peS, speedup_vs_plain=round(plain_s / ml_s, 2),
-                   plain_partial_eig_iters=rp.partial_eig_iters,
+                   plain_partial_eig_iters=rp.partial_eig_iters, plain_msvt_iters=rp.msvt_iters,
                    plain_kernel_ms_per_solve={k: round(v[1], 3) for k, v in pprof.items() if v[0] > 0})
         del ws_pl, rp
 
     sweeps = r.sweeps_history
-    bound, amount = algorithmic_work(dom, w, nH, False, sweeps)
+    msvt = (r.msvt_products, launches.get("msvt_mm", 0))
+    bound, amount = algorithmic_work(dom, w, nH, False, sweeps, msvt)
     roof = roofline(dom, bound, amount, dom_ms / 1e3 / max(dom_launches, 1), dom_launches)
     if roof is not None:
         roof["traffic"] = measured_traffic(w.name, dom)
     others = {}
     for cls in kernel_ms:
-        bd, am = algorithmic_work(cls, w, nH, False, sweeps)
+        bd, am = algorithmic_work(cls, w, nH, False, sweeps, msvt)
         rf = roofline(cls, bd, am, kernel_ms[cls] / 1e3 / launches[cls], launches[cls])
         if rf is not None:
             others[cls] = {k: rf[k] for k in ("bound", "achieved", "unit", "frac", "avg_launch_us")}

@@ -91,6 +91,13 @@ typedef struct {
   int r_norm;              /* restriction normalisation: 0 = R = P (P^T P)^{-1/2}  */
                            /* (orthonormal), 1 = P / ||P||_2, 2 = P (the literal */
                            /* interpolation operator; ablation of the reading)  */
+  int svt_method;          /* coarse SVT on models 128..512 wide (padded):     */
+                           /* 0 = the matrix-function form (f(G) = (I - tau    */
+                           /* G^{-1/2})_+ by scaled Newton-Schulz products, no  */
+                           /* eigenvectors) in every iteration that Gershgorin */
+                           /* discs do not settle at rank 0 (tested after a    */
+                           /* zero rank); 1 = always the Jacobi eigensolver.   */
+                           /* Other values: E_INVALID_ARG                      */
 } mlpcp_opts;
 
 /* Per-solve report.  history (optional, caller host memory): if fg_history is
@@ -104,7 +111,9 @@ typedef struct {
   double tau_margin;       /* min_i |sigma_i - tau| / tau at the last SVT; a  */
                            /* lower bound where the eigensolver certified the */
                            /* spectrum below tau^2 by Gershgorin bounds       */
-                           /* instead of diagonalising it                     */
+                           /* instead of diagonalising it; -1 when the last   */
+                           /* SVT took the matrix-function form, which does   */
+                           /* not resolve the singular values one by one      */
   int eig_sweeps;          /* Jacobi sweeps of the last eigensolve (0 when    */
                            /* the certificate settled it)                     */
   double* fg_history;      /* in: optional host array                         */
@@ -123,10 +132,16 @@ typedef struct {
                            /* Rayleigh-Ritz, and a Cholesky certificate that  */
                            /* no other eigenvalue of the Gram reaches tau^2;  */
                            /* the full Jacobi eigensolve otherwise            */
+  int msvt_iters;          /* iterations whose SVT took the matrix-function   */
+                           /* form (see mlpcp_opts.svt_method)                */
+  int msvt_flags;          /* of those, iterations whose Gram norm bounds      */
+                           /* exceeded the growth their step counts assumed;  */
+                           /* the rest of the solve then took the eigensolver */
+  int msvt_products;       /* n_H x n_H x n_H float64 products those SVTs ran  */
 } mlpcp_info;
 
 /* Fills defaults: levels 0, tol 1e-6, max_iter 500, rho 1.5, mu_max_factor 1e7,
- * FP32, check_every 1, orthonormal restriction.                              */
+ * FP32, check_every 1, orthonormal restriction, svt_method 0.                */
 void mlpcp_default_opts(mlpcp_opts* opts);
 
 /* Coarse width n_H after `levels` halvings of n (Sec. 3.1: composite of

@@ -45,7 +45,7 @@ EXPORTED = (
 class Opts(ctypes.Structure):
     _fields_ = [("levels", ctypes.c_int), ("tol", ctypes.c_double), ("max_iter", ctypes.c_int),
                 ("rho", ctypes.c_double), ("mu_max_factor", ctypes.c_double), ("prec", ctypes.c_int),
-                ("check_every", ctypes.c_int), ("r_norm", ctypes.c_int)]
+                ("check_every", ctypes.c_int), ("r_norm", ctypes.c_int), ("svt_method", ctypes.c_int)]
 
 
 class Info(ctypes.Structure):
@@ -54,7 +54,8 @@ class Info(ctypes.Structure):
                 ("fg_history", ctypes.POINTER(ctypes.c_double)), ("rank_history", ctypes.POINTER(ctypes.c_int)),
                 ("history_len", ctypes.c_int), ("gram_bf16_iters", ctypes.c_int),
                 ("gram_split_iters", ctypes.c_int), ("sweeps_history", ctypes.POINTER(ctypes.c_int)),
-                ("mu0", ctypes.c_double), ("partial_eig_iters", ctypes.c_int)]
+                ("mu0", ctypes.c_double), ("partial_eig_iters", ctypes.c_int), ("msvt_iters", ctypes.c_int),
+                ("msvt_flags", ctypes.c_int), ("msvt_products", ctypes.c_int)]
 
 
 class FwtInfo(ctypes.Structure):
@@ -134,7 +135,7 @@ def lib() -> ctypes.CDLL:
 
 KERNEL_CLASSES = ("init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply", "jacobi_misc",
                   "svt_prep", "epilogue", "reduce", "finalize", "coarse_svt_small", "fw_pass", "fw_power",
-                  "fw_small", "fw_top", "other")
+                  "fw_small", "fw_top", "msvt_mm", "recon_gemm", "other")
 
 
 def profile_enable(on=True) -> None:
@@ -235,6 +236,9 @@ class SolveResult:
     sweeps_history: list = dataclasses.field(default_factory=list)
     mu0: float = 0.0
     partial_eig_iters: int = 0
+    msvt_iters: int = 0
+    msvt_flags: int = 0
+    msvt_products: int = 0
 
 
 PRECISIONS = {"fp32": 0, "bf16": 1, "bf16x3": 2}
@@ -249,7 +253,7 @@ def _prec(p) -> int:
 
 
 def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
-           prec="fp32", r_norm=0):
+           prec="fp32", r_norm=0, svt_method=0):
     torch = _torch()
     _check_dev(D, "D", torch.float32)
     if D.dim() != 2 or D.stride(1) != 1:
@@ -265,7 +269,7 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
             if not t.is_contiguous() or tuple(t.shape) != (m, n):
                 raise ValueError(f"{name} must be a contiguous m x n tensor")
     o = default_opts(levels=levels, tol=tol, max_iter=max_iter, rho=rho, mu_max_factor=mu_max_factor,
-                     prec=_prec(prec), r_norm=int(r_norm))
+                     prec=_prec(prec), r_norm=int(r_norm), svt_method=int(svt_method))
     wsb = workspace_bytes(m, n, o)
     if workspace is None:
         ws = torch.empty(max(wsb, 1), dtype=torch.uint8, device=dev)
@@ -301,29 +305,33 @@ def _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, wa
     return SolveResult(L, S, Y, st, info.iters, info.fg, info.rank, info.mu_final, info.tau_margin, info.eig_sweeps,
                        [fh[i] for i in range(k)] if history else [], [rh[i] for i in range(k)] if history else [],
                        info.gram_bf16_iters, info.gram_split_iters,
-                       [sh[i] for i in range(k)] if history else [], info.mu0, info.partial_eig_iters)
+                       [sh[i] for i in range(k)] if history else [], info.mu0, info.partial_eig_iters,
+                       info.msvt_iters, info.msvt_flags, info.msvt_products)
 
 
 def pcp_solve(D, lam: float, mu0: Optional[float] = None, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
               rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
-              workspace=None, history: int = 0, prec="fp32", r_norm: int = 0) -> SolveResult:
+              workspace=None, history: int = 0, prec="fp32", r_norm: int = 0, svt_method: int = 0) -> SolveResult:
     """Robust PCA by (multilevel) inexact ALM; D is an m x n float32 tensor on the GPU.
     mu0: initial penalty; None or <= 0 selects 1.25 / ||D||_2, computed on the device.
     prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products).
-    r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P."""
+    r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P.
+    svt_method: 0 matrix-function coarse SVT where eligible, 1 eigensolver only."""
     return _solve(D, None, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
-                  prec, r_norm)
+                  prec, r_norm, svt_method)
 
 
 def cpcp_solve(D, Q, lam: float, mu0: Optional[float] = None, *, levels: int = 0, tol: float = 1e-6, max_iter: int = 500,
                rho: float = 1.5, mu_max_factor: float = 1e7, S0=None, Y0=None, want_y: bool = True,
-               workspace=None, history: int = 0, prec="fp32", r_norm: int = 0) -> SolveResult:
+               workspace=None, history: int = 0, prec="fp32", r_norm: int = 0,
+               svt_method: int = 0) -> SolveResult:
     """Compressive PCP (constrained form) by masked (multilevel) inexact ALM; Q uint8 mask.
     mu0: initial penalty; None or <= 0 selects 1.25 / ||P_Q D||_2, computed on the device.
     prec: "fp32", "bf16" or "bf16x3" (the arithmetic of the coarse SVT's products).
-    r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P."""
+    r_norm: restriction normalisation, 0 orthonormal (default), 1 P / ||P||_2, 2 P.
+    svt_method: 0 matrix-function coarse SVT where eligible, 1 eigensolver only."""
     return _solve(D, Q, lam, mu0, levels, tol, max_iter, rho, mu_max_factor, S0, Y0, want_y, workspace, history,
-                  prec, r_norm)
+                  prec, r_norm, svt_method)
 
 
 def svt_prox(M, tau: float, levels: int = 0, workspace=None):

@@ -21,7 +21,7 @@ LIB = os.path.join(HERE, "libmlpcp.so")
 ARCH = "gfx950"
 
 SOURCES = ["operators.hip", "eig.hip", "gram.hip", "dense.hip", "solver.hip", "fwt.hip", "profile.hip", "spectral.hip",
-           "subspace.hip"]
+           "subspace.hip", "msvt.hip"]
 
 
 def _hipcc() -> str:

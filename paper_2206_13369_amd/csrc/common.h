@@ -111,6 +111,11 @@ struct IterStats {
   int sweeps;      // Jacobi sweeps of the one-workgroup coarse SVT (-1: sweep cap hit)
   double lam_r;    // smallest eigenvalue kept (0 at rank 0)
   double lam_65;   // 65th largest eigenvalue (0 below width 65)
+  int kform;       // 1: the wide reconstruction factor T holds K itself (n_H columns,
+                   // the matrix-function SVT); 0: T T^T = K with `rank` columns
+  int msvt_flag;   // matrix-function SVT: bit 0 / bit 1 set when its norm bound alpha /
+                   // beta exceeded the cap its step counts assumed
+  double msvt_alpha, msvt_beta;   // those norm bounds
 };
 
 // Sweep count placeholder: the count is in IterStats::sweeps after the next sync.
@@ -157,6 +162,33 @@ int svt_partial(int N, const double* G, double tau, int first_iters, double* V, 
 // Subspace steps for a convergence factor rho = lambda_65 / lambda_r: enough to bring the
 // residual of the leading pairs down by about 1e-10.
 int subspace_steps(double rho);
+
+// ---- matrix-function SVT (msvt.hip) -----------------------------------------------------
+constexpr int kMsvtMaxWidth = 512;
+// Step counts and coefficients of one matrix-function SVT, fixed on the host.
+struct MsvtPlan {
+  double alpha_cap, beta_cap;   // norm bounds the step counts assume
+  int n_sign, n_inv;            // scaled Newton-Schulz steps of the two phases
+  double a_sign[64], a_inv[64];
+};
+// Whether an N x N Gram may take the matrix-function SVT: N a multiple of 64 in
+// [128, kMsvtMaxWidth].
+bool msvt_eligible(int N);
+size_t msvt_workspace_bytes(int N);
+// Plan for threshold tau given estimates (upper bounds) of the two norm bounds.
+int msvt_plan(double tau, double alpha_est, double beta_est, MsvtPlan* mp);
+// Gershgorin certificate that every eigenvalue of G (n_H x n_H block, ld ldg) is below
+// tau^2 (then st takes rank 0 in factor form and a margin bound), and the largest
+// absolute row sum and the trace of G.  Synchronises `s`.
+int msvt_probe(int nH, int N, const double* G, int ldg, double tau, IterStats* st, void* ws, hipStream_t s,
+               bool* certified, double* gmax, double* trace);
+// K (N x N, ld ldk == N) = C f(G) C with f(l) = (1 - tau / sqrt(l))_+ on the eigenvalues
+// of G (n_H x n_H block of an N x N buffer, ld ldg; C n_H x n_H, ld n_H, or null for the
+// identity), zero beyond n_H; st: rank, trace, kform = 1, the flags and bounds.  prep:
+// (re)build the padded C and C^2 kept in the workspace (once per operator).  *products
+// (nullable) += the N x N x N products launched.  No sync.
+int svt_msvt(int nH, int N, const double* G, int ldg, double tau, const double* C, bool prep, const MsvtPlan& mp,
+             double* K, int ldk, IterStats* st, void* ws, hipStream_t s, int* products);
 
 // ---- Gram (gram.hip) ---------------------------------------------------------------
 // G = A^T A for A m x k (float32, ld = lda, k <= kp, kp multiple of kPad), accumulated

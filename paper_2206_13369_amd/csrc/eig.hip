@@ -1099,6 +1099,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   }
   if (tid == 0) {
     st->rank = rank;
+    st->kform = 0;
     st->margin = red[0];
     st->trace = trace;
     st->sweeps = conv ? sweeps : -1;

@@ -930,6 +930,7 @@ void mlpcp_default_opts(mlpcp_opts* o) {
   o->prec = MLPCP_FP32;
   o->check_every = 1;
   o->r_norm = 0;
+  o->svt_method = 0;
 }
 
 int mlpcp_coarse_dim(int n, int levels) { return coarse_dim_checked(n, levels); }

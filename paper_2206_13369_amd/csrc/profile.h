@@ -21,6 +21,8 @@ enum KernelClass {
   KC_FW_POWER,
   KC_FW_SMALL,
   KC_FW_TOP,
+  KC_MSVT,
+  KC_RECON,
   KC_OTHER,
   KC_COUNT
 };

@@ -13,7 +13,7 @@ namespace {
 
 const char* kNames[KC_COUNT] = {"init_restrict", "gram", "coarse_CGC", "jacobi_pairs", "jacobi_apply",
                                 "jacobi_misc", "svt_prep", "epilogue", "reduce", "finalize", "coarse_svt_small",
-                                "fw_pass", "fw_power", "fw_small", "fw_top", "other"};
+                                "fw_pass", "fw_power", "fw_small", "fw_top", "msvt_mm", "recon_gemm", "other"};
 
 struct Pending {
   int cls;

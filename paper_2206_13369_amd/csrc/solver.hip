@@ -267,6 +267,7 @@ __global__ void __launch_bounds__(kThreads) k_svt_prep(const double* __restrict_
   }
   if (threadIdx.x == 0) {
     st->rank = cnt[0];
+    st->kform = 0;
     st->margin = mg[0];
     st->trace = trace ? *trace : tr[0];
     st->lam_r = cnt[0] > 0 ? lam[perm[cnt[0] - 1]] : 0.0;
@@ -283,19 +284,22 @@ __global__ void k_build_T(int nH, int N, const double* __restrict__ C, const dou
                           const IterStats* __restrict__ st, double* __restrict__ T, double* __restrict__ Tt,
                           int ldT) {
   const int r = st->rank;
-  const size_t total = (size_t)nH * r;
+  const size_t total = (size_t)nH * nH;   // columns past the rank are written as zero
   for (size_t idx = (size_t)blockIdx.x * blockDim.x + threadIdx.x; idx < total;
        idx += (size_t)gridDim.x * blockDim.x) {
-    const int c = (int)(idx / r), k = (int)(idx % r);
-    const int col = perm[k];
-    double v;
-    if (PLAIN) {
-      v = V[(size_t)c * N + col];
-    } else {
-      v = 0.0;
-      for (int j = 0; j < nH; ++j) v += C[(size_t)c * nH + j] * V[(size_t)j * N + col];
+    const int c = (int)(idx / nH), k = (int)(idx % nH);
+    double tv = 0.0;
+    if (k < r) {
+      const int col = perm[k];
+      double v;
+      if (PLAIN) {
+        v = V[(size_t)c * N + col];
+      } else {
+        v = 0.0;
+        for (int j = 0; j < nH; ++j) v += C[(size_t)c * nH + j] * V[(size_t)j * N + col];
+      }
+      tv = v * sw[k];
     }
-    const double tv = v * sw[k];
     T[(size_t)c * ldT + k] = tv;
     Tt[(size_t)k * ldT + c] = tv;
   }
@@ -310,6 +314,9 @@ struct EpiArgs {
   float* MPnext;
   const double* T;
   const double* Tt;
+  const double* Kw;   // K form: the n_H x n_H product operator (wide path, n_H padded <= 512)
+  float* Abuf;        // factor form: A = M_P T (m x rank, ld ldp)
+  float* Nbuf;        // N = M_P K (m x n_H, ld ldp), formed before the wide epilogue
   const IterStats* st;
   const float* Zin;   // state (E on Q, L off Q)
   float* Zout;        // may equal Zin
@@ -330,9 +337,64 @@ struct EpiArgs {
   double* partial;
 };
 
-// ((a0 + a1) + (a2 + a3)) + ((a4 + a5) + (a6 + a7))
-__device__ __forceinline__ double sum8(const double (&v)[8]) {
-  return ((v[0] + v[1]) + (v[2] + v[3])) + ((v[4] + v[5]) + (v[6] + v[7]));
+// C (M x N, float32, ldc) = A (M x K, float32, lda) B (K x N, float64, ldb) on float64
+// MFMA, the sums rounded to float32 once: the reconstruction products of the wide path
+// (N = M_P K, or A = M_P T and N = A T^T in the factor form).  K and N are capped on the
+// device by *kcap / *ncap when non-null (the rank of the factor form; output columns at
+// or past *ncap are left untouched).  One 32 x 32 output tile per block, four waves of
+// one 16 x 16 tile each (v_mfma_f64_16x16x4f64); K in steps of 32 staged in LDS, the next
+// step's operands loaded into registers while the current one is multiplied.
+__global__ void __launch_bounds__(256) k_recon_gemm(int M, int N, int K, const float* __restrict__ A, int lda,
+                                                    const double* __restrict__ B, int ldb, float* __restrict__ C,
+                                                    int ldc, const int* __restrict__ kcap,
+                                                    const int* __restrict__ ncap) {
+  __shared__ double sA[32][33];
+  __shared__ double sB[32][33];
+  const int Ke = kcap ? min(K, *kcap) : K;
+  const int Ne = ncap ? min(N, *ncap) : N;
+  const int i0 = blockIdx.x * 32, j0 = blockIdx.y * 32;   // row tiles on x (m can be large)
+  if (j0 >= Ne) return;   // whole block
+  const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
+  const int wi = wave >> 1, wj = wave & 1;
+  typedef double d4 __attribute__((ext_vector_type(4)));
+  d4 acc = {0.0, 0.0, 0.0, 0.0};
+  // thread's four staging elements: rows tid / 32 + 8 q, column tid % 32
+  const int sr = tid >> 5, scol = tid & 31;
+  double ra[4], rb[4];
+  auto load = [&](int k0) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int r = sr + 8 * q;
+      const int gi = i0 + r, gk = k0 + scol;
+      ra[q] = (gi < M && gk < Ke) ? (double)A[(size_t)gi * lda + gk] : 0.0;
+      const int gk2 = k0 + r, gj = j0 + scol;
+      rb[q] = (gk2 < Ke && gj < N) ? B[(size_t)gk2 * ldb + gj] : 0.0;
+    }
+  };
+  if (Ke > 0) load(0);
+  for (int k0 = 0; k0 < Ke; k0 += 32) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      sA[sr + 8 * q][scol] = ra[q];
+      sB[sr + 8 * q][scol] = rb[q];
+    }
+    __syncthreads();
+    if (k0 + 32 < Ke) load(k0 + 32);
+#pragma unroll
+    for (int ks = 0; ks < 8; ++ks) {
+      const double av = sA[wi * 16 + (lane & 15)][ks * 4 + (lane >> 4)];
+      const double bv = sB[ks * 4 + (lane >> 4)][wj * 16 + (lane & 15)];
+      acc = __builtin_amdgcn_mfma_f64_16x16x4f64(av, bv, acc, 0, 0, 0);
+    }
+    __syncthreads();
+  }
+  // output register v of lane l: row 4 v + l / 16, column l % 16
+  const int gj = j0 + wj * 16 + (lane & 15);
+#pragma unroll
+  for (int v = 0; v < 4; ++v) {
+    const int gi = i0 + wi * 16 + 4 * v + (lane >> 4);
+    if (gi < M && gj < N) C[(size_t)gi * ldc + gj] = (float)acc[v];
+  }
 }
 
 template <int MODE, bool PLAIN, bool MASKED>
@@ -340,67 +402,33 @@ __global__ void __launch_bounds__(kThreads) k_epilogue(EpiArgs a) {
   extern __shared__ float sm[];
   __shared__ double red[kThreads];
   const int nHp = a.ldp;
-  float* sMP = sm;                              // TM x nHp: M_P panel, then N panel
-  float* sA = sm + (size_t)a.TM * nHp;          // TM x nHp: A = M_P T (r <= nH columns)
-  float* sX = sA + (size_t)a.TM * nHp;          // TM x n  : next coarse data (not PLAIN)
+  float* sN = sm;                               // TM x nHp: N panel
+  float* sX = sN + (size_t)a.TM * nHp;          // TM x n  : next coarse data (not PLAIN)
   const int tid = threadIdx.x;
   const int i0 = blockIdx.x * a.TM;
   const int rows = min(a.TM, a.m - i0);
   const int nH = a.nH, n = a.n;
-  const int r = a.st->rank;
 
-  // 1. M_P panel
+  // 1. N panel (N = M_P K, formed on MFMA by k_recon_gemm before this launch)
   for (int e = tid; e < rows * nH; e += kThreads) {
     const int i = e / nH, c = e % nH;
-    sMP[i * nHp + c] = a.MPcur[(size_t)(i0 + i) * a.ldp + c];
+    sN[i * nHp + c] = a.Nbuf[(size_t)(i0 + i) * a.ldp + c];
   }
   __syncthreads();
-  // 2. A = M_P T   (rows x r), float64 sums rounded once; eight partial sums per dot
-  //    product (terms c = 8q + u go to partial u, summed in order u = 0..7), so eight
-  //    loads of T are in flight and the FMA chains are an eighth as long
-  for (int e = tid; e < rows * r; e += kThreads) {
-    const int i = e / r, k = e % r;
-    const float* x = sMP + i * nHp;
-    const double* tc = a.T + k;
-    double acc[8] = {};
-    int c = 0;
-    for (; c + 8 <= nH; c += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = fma((double)x[c + u], tc[(size_t)(c + u) * a.ldT], acc[u]);
-    }
-    for (int u = 0; c < nH; ++c, ++u) acc[u] = fma((double)x[c], tc[(size_t)c * a.ldT], acc[u]);
-    sA[i * nHp + k] = (float)sum8(acc);
-  }
-  __syncthreads();
-  // 3. N = A T^T  (rows x nH), over the M_P panel, the same way
-  for (int e = tid; e < rows * nH; e += kThreads) {
-    const int i = e / nH, c = e % nH;
-    const float* y = sA + i * nHp;
-    const double* tc = a.Tt + c;
-    double acc[8] = {};
-    int k = 0;
-    for (; k + 8 <= r; k += 8) {
-#pragma unroll
-      for (int u = 0; u < 8; ++u) acc[u] = fma((double)y[k + u], tc[(size_t)(k + u) * a.ldT], acc[u]);
-    }
-    for (int u = 0; k < r; ++k, ++u) acc[u] = fma((double)y[k], tc[(size_t)k * a.ldT], acc[u]);
-    sMP[i * nHp + c] = (float)sum8(acc);
-  }
-  __syncthreads();
-  // 4. fine elements
+  // 2. fine elements
   double racc = 0.0;
   for (int e = tid; e < rows * n; e += kThreads) {
     const int i = e / n, j = e % n;
     const int gi = i0 + i;
     float L;
     if (PLAIN) {
-      L = sMP[i * nHp + j];
+      L = sN[i * nHp + j];
     } else {
       const int* ri = a.row_idx + j * kMaxStencil;
       const float* rw = a.row_w + j * kMaxStencil;
       L = 0.0f;
 #pragma unroll
-      for (int s = 0; s < kMaxStencil; ++s) L = fmaf(rw[s], sMP[i * nHp + ri[s]], L);
+      for (int s = 0; s < kMaxStencil; ++s) L = fmaf(rw[s], sN[i * nHp + ri[s]], L);
     }
     const size_t gij = (size_t)gi * n + j;
     if (MODE == MODE_RECON) {
@@ -862,8 +890,11 @@ struct Plan {
   // the tall reconstruction N = M_P K (0 float32 MFMA, 2 split bfloat16)
   int gram_prec, recon_prec;
   size_t off_mp0, off_mp1, off_bits, off_G, off_GH, off_tmp, off_V, off_lam, off_gb, off_perm, off_sw, off_T, off_Tt,
-      off_K, off_part, off_gram, off_eig, off_stats, off_sub, total;
+      off_K, off_part, off_gram, off_eig, off_stats, off_sub, off_ms, off_Kw, off_N, off_A, total;
   bool sub;   // workspace for the rank-predicted partial eigensolve (solves on the wide path)
+  bool ms;    // workspace for the matrix-function SVT (solves on the wide path, n_H <= 512)
+  bool kw;    // wide path with the K form of the reconstruction (n_H padded <= 512):
+              // N = M_P K, K = C f(G) C; wider models keep the factor form N = (M_P T) T^T
 };
 
 int device_cus() {
@@ -930,7 +961,7 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
   p.plain = (levels == 0);
   p.masked = masked;
   p.nw = (n + 31) / 32;
-  const size_t per_row = (size_t)4 * (2 * p.nHp + (p.plain ? 0 : n));
+  const size_t per_row = (size_t)4 * (p.nHp + (p.plain ? 0 : n));
   int TM = (int)(kLdsBudget / per_row);
   if (TM < 1) return MLPCP_E_UNSUPPORTED;
   if (TM > 64) TM = 64;
@@ -991,6 +1022,12 @@ int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_F
   p.off_stats = take(sizeof(IterStats));
   p.sub = partial && p.nHp >= kPartialMinWidth && subspace_eligible(p.nHp, 1);
   p.off_sub = take(p.sub ? subspace_workspace_bytes(p.nHp) : 0);
+  p.ms = partial && !p.tall && msvt_eligible(p.nHp);
+  p.off_ms = take(p.ms ? msvt_workspace_bytes(p.nHp) : 0);
+  p.kw = !p.tall && p.nHp <= kMsvtMaxWidth;
+  p.off_Kw = take(p.kw ? nn * 8 : 0);
+  p.off_N = take(p.tall ? 0 : (size_t)m * p.ldmp * 4);
+  p.off_A = take(p.tall || p.kw ? 0 : (size_t)m * p.ldmp * 4);
   p.total = off + 256;  // slack for aligning the caller's base pointer
   return MLPCP_OK;
 }
@@ -1024,6 +1061,7 @@ int valid_opts(const mlpcp_opts& o) {
     return MLPCP_E_INVALID_ARG;
   if (o.prec != MLPCP_FP32 && o.prec != MLPCP_BF16 && o.prec != MLPCP_BF16X3) return MLPCP_E_INVALID_ARG;
   if (o.check_every != 1 || o.r_norm < 0 || o.r_norm > 2) return MLPCP_E_UNSUPPORTED;
+  if (o.svt_method != 0 && o.svt_method != 1) return MLPCP_E_INVALID_ARG;
   return MLPCP_OK;
 }
 
@@ -1038,7 +1076,19 @@ struct EigState {
   bool v_full = false;
   int partial_iters = 0;      // iterations whose SVT the partial eigensolve gave
   bool last_partial = false;
+  bool ms_on = false;         // the matrix-function SVT may be used (opts and workspace)
+  bool ms_prep = false;       // its padded C and C^2 are built
+  int ms_iters = 0;           // iterations whose SVT it gave
+  int ms_flags = 0;           // iterations whose norm bounds exceeded the assumed caps
+  int ms_products = 0;        // N x N x N products those iterations launched
+  double trace_prev = 0.0;    // trace of the previous coarse Gram
+  double ms_alpha = 0.0, ms_beta = 0.0;   // its norm bounds at the previous iteration (0: none)
 };
+
+// Growth allowed for the norm bounds of the matrix-function SVT from one iteration to the
+// next (they follow ||G||_2, which moves slowly along a solve); a larger step flags the
+// iteration and the rest of the solve takes the eigensolver.
+constexpr double kMsvtGrowth = 4.0;
 
 // The partial eigensolve is tried when the previous rank was small and either the
 // previous SVT came from it too or the previous spectrum kept a clear gap at the
@@ -1069,7 +1119,7 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     // one workgroup from the Gram to the reconstruction factors; sweeps come back in st
     *sweeps = kSweepsOnDevice;
     return coarse_svt_small(p.nH, p.nHp, G, p.plain ? nullptr : op.C, V, warm, tau, certify, lam, perm, sw, T, Tt,
-                            p.tall ? w.at<double>(p.off_K) : nullptr, st, s);
+                            p.tall ? w.at<double>(p.off_K) : (p.kw ? w.at<double>(p.off_Kw) : nullptr), st, s);
   }
   double* GH = G;
   if (!p.plain) {
@@ -1078,6 +1128,42 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     double* tmp = w.at<double>(p.off_tmp);
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
     MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
+  }
+  // Matrix-function SVT (no eigenvectors).  After an iteration of rank 0 the Gershgorin
+  // discs are tested first (one sync): when they put every eigenvalue below tau^2 the SVT
+  // is zero; otherwise their bounds cap the norm bounds of the iteration's first phase.
+  // After a nonzero rank the caps are the previous iteration's bounds times the allowed
+  // growth, with no sync.
+  if (es && es->ms_on && p.ms && certify) {
+    const double t = tau * tau;
+    double a_est, b_est;
+    if (es->r_prev == 0 || !(es->ms_alpha > 0.0)) {
+      bool cert = false;
+      double gmax = 0.0, trace = 0.0;
+      MLPCP_TRY(msvt_probe(p.nH, p.nHp, GH, p.nHp, tau, st, w.at<void>(p.off_ms), s, &cert, &gmax, &trace));
+      if (cert) {
+        es->v_full = false;
+        *sweeps = 0;
+        return MLPCP_OK;
+      }
+      // ||G - t I||_2 <= (max row sum of |G|) + t; ||Gt||_2 = max(||G||_2, t)
+      a_est = gmax + t;
+      b_est = kMsvtGrowth * std::max(gmax, t);
+      (void)trace;
+    } else {
+      a_est = kMsvtGrowth * es->ms_alpha;
+      b_est = kMsvtGrowth * es->ms_beta;
+    }
+    MsvtPlan mp;
+    MLPCP_TRY(msvt_plan(tau, a_est, b_est, &mp));
+    MLPCP_TRY(svt_msvt(p.nH, p.nHp, GH, p.nHp, tau, p.plain ? nullptr : op.C, !es->ms_prep, mp,
+                       w.at<double>(p.off_Kw), p.nHp, st, w.at<void>(p.off_ms), s, &es->ms_products));
+    es->ms_prep = true;
+    es->v_full = false;
+    es->last_partial = false;
+    ++es->ms_iters;
+    *sweeps = 0;
+    return MLPCP_OK;
   }
   double* gb = certify ? w.at<double>(p.off_gb) : nullptr;
   // rank-predicted partial eigensolve (the previous rank was small), else the full one
@@ -1124,6 +1210,8 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
   if (p.tall)
     hipLaunchKernelGGL(k_build_K, dim3((kTallNH * kTallNH + kThreads - 1) / kThreads), dim3(kThreads), 0, s, p.nH,
                        kTallNH, T, p.nHp, st, w.at<double>(p.off_K));
+  else if (p.kw)   // K = T T^T for the K form of the reconstruction (T is zero past the rank)
+    MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, T, p.nHp, Tt, p.nHp, w.at<double>(p.off_Kw), p.nHp, s));
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
 }
@@ -1168,6 +1256,23 @@ int launch_epilogue(const Plan& p, const EpiArgs& a, const double* K, int nnz, h
     return launch_tall_one<MODE, false, false>(p, b, K, nnz, grid, s);
   }
   *partials = p.nblk;
+  {
+    // N = M_P K (K form) or A = M_P T, N = A T^T (factor form, rank columns)
+    ProfScope ps(KC_RECON, s);
+    const dim3 gb(256);
+    const dim3 gg((p.m + 31) / 32, (p.nH + 31) / 32);
+    if (p.kw) {
+      hipLaunchKernelGGL(k_recon_gemm, gg, gb, 0, s, p.m, p.nH, p.nH, a.MPcur, p.ldmp, a.Kw, p.nHp, a.Nbuf, p.ldmp,
+                         nullptr, nullptr);
+    } else {
+      const int* rk = &a.st->rank;
+      hipLaunchKernelGGL(k_recon_gemm, gg, gb, 0, s, p.m, p.nH, p.nH, a.MPcur, p.ldmp, a.T, p.nHp, a.Abuf, p.ldmp,
+                         nullptr, rk);
+      hipLaunchKernelGGL(k_recon_gemm, gg, gb, 0, s, p.m, p.nH, p.nH, a.Abuf, p.ldmp, a.Tt, p.nHp, a.Nbuf, p.ldmp,
+                         rk, nullptr);
+    }
+    MLPCP_HIP(hipGetLastError());
+  }
   const dim3 g(p.nblk), b(kThreads);
   if (p.plain) {
     if (p.masked)
@@ -1182,6 +1287,15 @@ int launch_epilogue(const Plan& p, const EpiArgs& a, const double* K, int nnz, h
   }
   MLPCP_HIP(hipGetLastError());
   return MLPCP_OK;
+}
+
+// The reconstruction operands and products of the wide epilogue.
+void bind_recon(const Plan& p, const WS& w, EpiArgs& a) {
+  a.T = w.at<double>(p.off_T);
+  a.Tt = w.at<double>(p.off_Tt);
+  a.Kw = p.kw ? w.at<double>(p.off_Kw) : nullptr;
+  a.Nbuf = p.tall ? nullptr : w.at<float>(p.off_N);
+  a.Abuf = (p.tall || p.kw) ? nullptr : w.at<float>(p.off_A);
 }
 
 int launch_init(const Plan& p, const Operator& op, const float* D, int ldd, const uint32_t* bits,
@@ -1313,6 +1427,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   double trace_prev = INFINITY;
   int bf16_iters = 0, split_iters = 0;
   EigState es;
+  es.ms_on = o.svt_method == 0 && p.ms;
   for (t = 0; t < o.max_iter; ++t) {
     const double mu_next = std::min(o.rho * mu, mu_max);
     const int gp = gram_prec_for(o.prec, 1.0 / mu, trace_prev, m, p.nH);
@@ -1323,7 +1438,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
     a.MPcur = mp[t & 1]; a.MPnext = mp[(t + 1) & 1];
-    a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt); a.st = st;
+    bind_recon(p, w, a); a.st = st;
     a.Zin = S; a.Zout = S; a.Y0 = Y0;
     a.mu = (float)mu; a.inv_mu = (float)(1.0 / mu); a.mu_prev = (float)mu_prev;
     a.inv_mu_next = (float)(1.0 / mu_next); a.lam = lambda; a.thr = (float)(lambda / mu);
@@ -1350,6 +1465,15 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     if (!es.last_partial) es.rho = hs.lam_r > 0.0 ? std::max(hs.lam_65, 0.0) / hs.lam_r : 1.0;
     margin = hs.margin;
     trace_prev = hs.trace;
+    es.trace_prev = hs.trace;
+    if (hs.kform) {
+      es.ms_alpha = hs.msvt_alpha;
+      es.ms_beta = hs.msvt_beta;
+      if (hs.msvt_flag) {
+        ++es.ms_flags;
+        es.ms_on = false;
+      }
+    }
     if (info && info->fg_history && t < info->history_len) info->fg_history[t] = fg;
     if (info && info->rank_history && t < info->history_len) info->rank_history[t] = rank;
     if (info && info->sweeps_history && t < info->history_len) info->sweeps_history[t] = sweeps;
@@ -1374,7 +1498,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     a.m = m; a.n = n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
     a.D = D; a.ldd = ldd; a.bits = bits;
     a.MPcur = mp[last & 1]; a.MPnext = nullptr;
-    a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt); a.st = st;
+    bind_recon(p, w, a); a.st = st;
     a.Zin = S; a.Lout = L; a.Sout = S; a.Yout = Y;
     a.mu = (float)mu_last; a.lam = lambda; a.thr = (float)(lambda / mu_last);
     a.row_idx = op->row_idx; a.row_w = op->row_w;
@@ -1394,6 +1518,9 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     info->gram_bf16_iters = bf16_iters;
     info->gram_split_iters = split_iters;
     info->partial_eig_iters = es.partial_iters;
+    info->msvt_iters = es.ms_iters;
+    info->msvt_flags = es.ms_flags;
+    info->msvt_products = es.ms_products;
   }
   return status;
 }
@@ -1602,7 +1729,7 @@ int step_forward_core(const StepPlan& sp, const Operator& op, const WS& w, const
   MLPCP_TRY(coarse_svt(p, op, w, mp, 1.0 / mu, s, &sweeps, false, false));
   EpiArgs a{};
   a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
-  a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
+  a.MPcur = mp; bind_recon(p, w, a);
   a.st = w.at<IterStats>(p.off_stats);
   a.Lout = Lout;
   a.row_idx = op.row_idx; a.row_w = op.row_w;
@@ -1637,7 +1764,7 @@ int svt_prox_core(const Plan& p, const Operator& op, const WS& w, const float* M
   MLPCP_TRY(coarse_svt(p, op, w, mp, (double)tau, s, &sweeps, false, true));
   EpiArgs a{};
   a.m = p.m; a.n = p.n; a.nH = p.nH; a.TM = p.TM; a.ldp = p.ldmp; a.nw = p.nw; a.ldT = p.nHp;
-  a.MPcur = mp; a.T = w.at<double>(p.off_T); a.Tt = w.at<double>(p.off_Tt);
+  a.MPcur = mp; bind_recon(p, w, a);
   a.st = w.at<IterStats>(p.off_stats);
   a.Lout = L;
   a.row_idx = op.row_idx; a.row_w = op.row_w;

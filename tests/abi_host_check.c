@@ -76,6 +76,10 @@ int main(void) {
   bad.check_every = 2;
   EXPECT(mlpcp_pcp_solve(20, 10, D, 10, 0.1f, 1.0, &bad, NULL, NULL, L, S, NULL, NULL, 0, NULL, NULL),
          MLPCP_E_UNSUPPORTED);
+  bad = o;
+  bad.svt_method = 5;
+  EXPECT(mlpcp_pcp_solve(20, 10, D, 10, 0.1f, 1.0, &bad, NULL, NULL, L, S, NULL, NULL, 0, NULL, NULL),
+         MLPCP_E_INVALID_ARG);
   EXPECT(mlpcp_pcp_solve(20, 10, D, 10, 0.1f, 1.0, NULL, NULL, NULL, L, S, NULL, ws, 16, NULL, NULL),
          MLPCP_E_WORKSPACE);
   EXPECT(mlpcp_cpcp_solve(20, 10, D, 10, NULL, 0.1f, 1.0, NULL, NULL, NULL, L, S, Y, NULL, 0, NULL, NULL),

@@ -44,8 +44,8 @@ def test_coarse_dim_rejects_bad_levels(n, levels):
 
 def test_default_opts():
     o = mlp.default_opts()
-    assert (o.levels, o.tol, o.max_iter, o.rho, o.mu_max_factor, o.prec, o.check_every, o.r_norm) == \
-        (0, 1e-6, 500, 1.5, 1e7, 0, 1, 0)
+    assert (o.levels, o.tol, o.max_iter, o.rho, o.mu_max_factor, o.prec, o.check_every, o.r_norm, o.svt_method) == \
+        (0, 1e-6, 500, 1.5, 1e7, 0, 1, 0, 0)
 
 
 def test_workspace_bytes():
@@ -56,7 +56,8 @@ def test_workspace_bytes():
     # the default-mu0 phase (Gram of P_Q D and two squaring buffers, 2048^2 doubles each)
     # shares the workspace, so it bounds the size from below
     assert a >= 3 * 2048 * 2048 * 8
-    assert mlp.workspace_bytes(262144, 200, mlp.default_opts(levels=4)) >= 262144 * 64 * 4 * 2
+    # two coarse-data buffers M_P, n_H = 13 columns at a leading dimension of 16
+    assert mlp.workspace_bytes(262144, 200, mlp.default_opts(levels=4)) >= 262144 * 16 * 4 * 2
     assert mlp.workspace_bytes(10, 20, o) == 0          # m < n
     assert mlp.workspace_bytes(100, 8, mlp.default_opts(levels=4)) == 0
 
@@ -89,6 +90,8 @@ def test_pcp_validation():
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(check_every=3)) == mlp.MLPCP_E_UNSUPPORTED
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(r_norm=3)) == mlp.MLPCP_E_UNSUPPORTED
     assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(r_norm=-1)) == mlp.MLPCP_E_UNSUPPORTED
+    assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(svt_method=2)) == mlp.MLPCP_E_INVALID_ARG
+    assert _pcp(20, 10, 10, 0.1, 1.0, opts=mlp.default_opts(svt_method=-1)) == mlp.MLPCP_E_INVALID_ARG
     assert _pcp(20, 10, 10, 0.1, 1.0, ws=FAKE, wsb=16) == mlp.MLPCP_E_WORKSPACE
     # L stages P_Q D for the default mu0, so it may not alias the initial S0 / Y0
     L_ = ctypes.c_void_p(12288)

@@ -228,3 +228,43 @@ def test_partial_eigensolve_matches_oracle(masked):
     _check(res, ref)
     assert res.rank_history == [h["rank"] for h in ref.history]
     assert res.partial_eig_iters >= 1
+
+
+@pytest.mark.parametrize("levels,masked,shape", [(2, False, (300, 300)), (0, False, (300, 300)),
+                                                 (3, True, (700, 520)), (1, True, (900, 500))])
+def test_matrix_function_svt_matches_oracle(levels, masked, shape):
+    """The matrix-function coarse SVT (f(G) from scaled Newton-Schulz products, no
+    eigenvectors) against the oracle's full-SVD solve and against the Jacobi path of the
+    same library: L and S within 1e-5 of the oracle, the same rank in every iteration,
+    the path taken in every iteration that follows a nonzero rank, and its norm bounds
+    within the growth its step counts assume.  Padded widths 128 (n_H = 75), 320 (the
+    plain 300-wide Gram), 128 (n_H = 65, one past the one-workgroup path) and 256
+    (n_H = 250)."""
+    m, n = shape
+    w = synth.gaussian_lowrank_plus_sparse(m, n, 10, seed=41 + levels, sparse_frac=0.06, sparse_kind="uniform",
+                                           sparse_amp=6.0, observed_frac=0.65 if masked else None, levels=levels)
+    ref = oracle.ialm(w.D, w.lam, w.mu0, Q=w.Q, levels=levels, tol=1e-6, record=True)
+    say("matrix-function svt", levels, masked, shape, ref.iters, ref.rank)
+    res = _run_gpu(w, levels, tol=1e-6)
+    assert res.status == mlp.MLPCP_OK and res.fg <= 1e-6
+    assert res.iters == ref.iters
+    _check(res, ref)
+    ranks = [h["rank"] for h in ref.history]
+    assert res.rank_history == ranks
+    # the path is taken in every iteration that follows a nonzero rank, and in those after
+    # a zero rank whose Gershgorin discs do not settle it
+    expect = sum(1 for i in range(1, len(ranks)) if ranks[i - 1] > 0)
+    say(f"   matrix-function iters {res.msvt_iters} (at least {expect}) products {res.msvt_products} "
+        f"flags {res.msvt_flags}")
+    assert expect <= res.msvt_iters <= res.iters and res.msvt_flags == 0
+    # the eigensolver path of the same solve
+    torch, dev = torch_dev()
+    D = to_dev(w.D)
+    kw = dict(levels=levels, tol=1e-6, history=600, svt_method=1)
+    if w.Q is None:
+        eig = mlp.pcp_solve(D, w.lam, w.mu0, **kw)
+    else:
+        eig = mlp.cpcp_solve(D, to_dev(w.Q.astype(np.uint8)), w.lam, w.mu0, **kw)
+    torch.cuda.synchronize()
+    assert eig.msvt_iters == 0 and eig.rank_history == ranks
+    assert rel(to_np(res.L), to_np(eig.L)) <= TOL32 and rel(to_np(res.S), to_np(eig.S)) <= TOL32
