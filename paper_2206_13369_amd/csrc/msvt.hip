@@ -26,8 +26,9 @@
 // sign phase; f is continuous with slope 1/(2 tau^2) there, so such an eigenvalue moves
 // the result by at most about l_0 alpha / (2 tau^2) in its direction, where M has a
 // singular value of about tau: l_0 is chosen so that this stays below kMsvtTarget
-// relative to ||M||_2.  The rank reported is the number of eigenvalues above tau^2,
-// (N + trace S) / 2 rounded.
+// relative to ||M||_2, and so that l_0 alpha is at most kMsvtRankRes tau^2.  The rank
+// reported is the number of eigenvalues above tau^2, (N + trace S) / 2 rounded: exact
+// for every eigenvalue farther than l_0 alpha from tau^2.
 #include <hip/hip_ext.h>
 
 #include <algorithm>
@@ -40,7 +41,9 @@ namespace mlpcp {
 
 namespace {
 
-constexpr double kMsvtTarget = 1.0e-7;   // bound on the relative error of M f(G) (see above)
+constexpr double kMsvtTarget = 1.0e-6;   // bound on the relative error of M f(G) (see above)
+constexpr double kMsvtRankRes = 1.0e-3;  // every eigenvalue farther than this times tau^2 from
+                                         // tau^2 is resolved (so the rank is exact there)
 constexpr double kMsvtTail = 1.0e-10;    // both iterations stop when 1 - l is below this
 constexpr double kMsvtKappa = 8.0;       // assumed ratio of the norm bound alpha to lambda_max
 constexpr int kMsvtMaxSteps = 64;
@@ -72,34 +75,65 @@ struct MmOp {
   const double* E;
   const double* sp;
   double ca, ce, ci;
+  int sym;   // the result is symmetric: upper tiles only, each written to both triangles
+  int at;    // A is exactly symmetric: read as A[k][i] (coalesced like B)
 };
 
-// Blocks [0, tiles) compute o0, blocks [tiles, 2 tiles) o1 (when two products are
+// Output tiles of one product: all nt^2, or the nt (nt + 1) / 2 upper ones when the
+// result is symmetric.
+__host__ __device__ inline int ms_tiles(int nt, int sym) { return sym ? nt * (nt + 1) / 2 : nt * nt; }
+
+// Blocks [0, tiles(o0)) compute o0, the next tiles(o1) blocks o1 (when two products are
 // independent they share one launch).  One 16 x 16 output tile per block; the four waves
 // take a quarter of K each with their MFMA operands loaded straight into registers
 // (v_mfma_f64_16x16x4f64: lane l holds A[l % 16][k + l / 16] and B[k + l / 16][l % 16]),
-// two accumulator chains each; partial tiles are summed in LDS.  The products here are
-// N <= 512 wide and one dependent chain: load latency, not MFMA throughput, bounds them.
+// two accumulator chains each; partial tiles are summed in LDS.  An exactly symmetric A
+// (a product written with sym set, or a symmetrised input) is read as A[k][i], each load
+// then covering four 128-byte rows as B's do.  The sign phase's results, symmetric in
+// exact arithmetic, are computed on the upper tiles and written to both triangles, which
+// keeps them exactly symmetric for the next product.  The coupled inverse square root
+// iteration must not be symmetrised that way (forcing Y T and T Z symmetric breaks the
+// relation between its two sequences, and the iteration then diverges on Grams of
+// condition number above about 1e5), so its products are computed in full.  The
+// products are N <= 512 wide and one dependent chain: load latency, not MFMA
+// throughput, bounds them.
 __global__ void __launch_bounds__(256) k_ms_mm(int N, MmOp o0, MmOp o1) {
   __shared__ double red[4][256];
-  const int nt = N / 16, tiles = nt * nt;
+  const int nt = N / 16;
+  const int t0 = ms_tiles(nt, o0.sym);
   const int b = blockIdx.x;
-  const MmOp& o = b < tiles ? o0 : o1;
-  const int tile = b < tiles ? b : b - tiles;
-  const int i0 = (tile / nt) * 16, j0 = (tile % nt) * 16;
+  const MmOp& o = b < t0 ? o0 : o1;
+  int tile = b < t0 ? b : b - t0;
+  int ti, tj;
+  if (o.sym) {   // upper tile number -> (ti, tj), ti <= tj, row by row
+    ti = 0;
+    while (tile >= nt - ti) {
+      tile -= nt - ti;
+      ++ti;
+    }
+    tj = ti + tile;
+  } else {
+    ti = tile / nt;
+    tj = tile % nt;
+  }
+  const int i0 = ti * 16, j0 = tj * 16;
   const int tid = threadIdx.x, lane = tid & 63, wave = tid >> 6;
   const int li = lane & 15, lk = lane >> 4;
   const int kw = N / 4, kb = wave * kw;   // kw is a multiple of 16 (N % 64 == 0)
   d4_t acc0 = {0.0, 0.0, 0.0, 0.0}, acc1 = {0.0, 0.0, 0.0, 0.0};
+  // A[i][k] at Ar[k] (rows), or A[k][i] at Ac[k N] (exactly symmetric A)
   const double* Ar = o.A + (size_t)(i0 + li) * N + kb + lk;
+  const double* Ac = o.A + (size_t)(kb + lk) * N + i0 + li;
   const double* Bc = o.B + (size_t)(kb + lk) * N + j0 + li;
+  const size_t astride = o.at ? (size_t)N : 1;
+  const double* Ap = o.at ? Ac : Ar;
   for (int k0 = 0; k0 < kw; k0 += 64) {
     double a[16], bb[16];
 #pragma unroll
     for (int s = 0; s < 16; ++s) {
       const int k = k0 + 4 * s;
       const bool in = k < kw;
-      a[s] = in ? Ar[k] : 0.0;
+      a[s] = in ? Ap[(size_t)k * astride] : 0.0;
       bb[s] = in ? Bc[(size_t)k * N] : 0.0;
     }
 #pragma unroll
@@ -114,12 +148,14 @@ __global__ void __launch_bounds__(256) k_ms_mm(int N, MmOp o0, MmOp o1) {
   __syncthreads();
   const int r = tid / 16, c = tid % 16;
   const int gi = i0 + r, gj = j0 + c;
+  if (o.sym && ti == tj && r > c) return;   // the diagonal tile's upper triangle is written twice
   const size_t off = (size_t)gi * N + gj;
   const double scale = o.sp ? *o.sp : 1.0;
   double v = o.ca * scale * ((red[0][tid] + red[1][tid]) + (red[2][tid] + red[3][tid]));
   if (o.E) v = fma(o.ce, o.E[off], v);
   if (gi == gj) v += o.ci;
   o.C[off] = v;
+  if (o.sym) o.C[(size_t)gj * N + gi] = v;
 }
 
 // Row statistics of A = G - t I over the padded N x N matrix (G zero beyond n_H, and
@@ -186,7 +222,7 @@ __global__ void __launch_bounds__(256) k_ms_scale(int N, int nH, const double* _
   __shared__ double red[768];
   double bound, trace;
   ms_bounds(N, rs, red, bound, trace);
-  const double alpha = fmax(bound, t);
+  const double alpha = fmax(bound, t) * (1.0 + 1e-12);   // above rounding in the bound
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[SC_ALPHA] = alpha;
     sc[SC_TRACE] = trace;
@@ -196,7 +232,8 @@ __global__ void __launch_bounds__(256) k_ms_scale(int N, int nH, const double* _
   const size_t total = (size_t)N * N;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / N), j = (int)(e % N);
-    const double g = (i < nH && j < nH) ? G[(size_t)i * ldg + j] : 0.0;
+    // symmetrised: the Gram of the coarse data is symmetric up to the rounding of C G C
+    const double g = (i < nH && j < nH) ? 0.5 * (G[(size_t)i * ldg + j] + G[(size_t)j * ldg + i]) : 0.0;
     const double x = g - (i == j ? t : 0.0);
     A[e] = x;
     X[e] = x * inv;
@@ -213,7 +250,7 @@ __global__ void __launch_bounds__(256) k_ms_ystart(int N, const double* __restri
   __shared__ double red[768];
   double bound, trace;
   ms_bounds(N, rs, red, bound, trace);
-  const double beta = fmax(bound, t);
+  const double beta = fmax(bound, t) * (1.0 + 1e-12);
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[SC_BETA] = beta;
     sc[SC_CF] = 1.0 / sqrt(beta);
@@ -242,12 +279,13 @@ __global__ void k_ms_plain_K(int N, int nH, const double* __restrict__ Z, const 
   }
 }
 
-// Cp (N x N) = C zero-padded (C: n_H x n_H, ld n_H).
+// Cp (N x N) = C zero-padded and symmetrised (C: n_H x n_H, ld n_H, symmetric up to the
+// rounding of its construction).
 __global__ void k_ms_padC(int N, int nH, const double* __restrict__ C, double* __restrict__ Cp) {
   const size_t total = (size_t)N * N;
   for (size_t e = (size_t)blockIdx.x * blockDim.x + threadIdx.x; e < total; e += (size_t)gridDim.x * blockDim.x) {
     const int i = (int)(e / N), j = (int)(e % N);
-    Cp[e] = (i < nH && j < nH) ? C[(size_t)i * nH + j] : 0.0;
+    Cp[e] = (i < nH && j < nH) ? 0.5 * (C[(size_t)i * nH + j] + C[(size_t)j * nH + i]) : 0.0;
   }
 }
 
@@ -342,9 +380,12 @@ MsLayout ms_layout(int N) {
   return l;
 }
 
-MmOp mm(const double* A, const double* B, double* C, double ca = 1.0, const double* E = nullptr, double ce = 0.0,
-        double ci = 0.0, const double* sp = nullptr) {
+// Product term; sym: symmetric result (upper tiles, mirrored), at: A exactly symmetric.
+MmOp mm(int sym, int at, const double* A, const double* B, double* C, double ca = 1.0, const double* E = nullptr,
+        double ce = 0.0, double ci = 0.0, const double* sp = nullptr) {
   MmOp o;
+  o.sym = sym;
+  o.at = at;
   o.A = A;
   o.B = B;
   o.C = C;
@@ -357,10 +398,10 @@ MmOp mm(const double* A, const double* B, double* C, double ca = 1.0, const doub
 }
 
 int launch_mm(int N, const MmOp& o0, const MmOp* o1, hipStream_t s, int* count) {
-  const int tiles = (N / 16) * (N / 16);
+  const int nt = N / 16;
+  const int blocks = ms_tiles(nt, o0.sym) + (o1 ? ms_tiles(nt, o1->sym) : 0);
   ProfKernel pk(KC_MSVT);
-  hipExtLaunchKernelGGL(k_ms_mm, dim3(o1 ? 2 * tiles : tiles), dim3(256), 0, s, pk.start, pk.stop, 0, N, o0,
-                        o1 ? *o1 : o0);
+  hipExtLaunchKernelGGL(k_ms_mm, dim3(blocks), dim3(256), 0, s, pk.start, pk.stop, 0, N, o0, o1 ? *o1 : o0);
   MLPCP_HIP(hipGetLastError());
   *count += o1 ? 2 : 1;
   return MLPCP_OK;
@@ -379,11 +420,15 @@ int msvt_plan(double tau, double alpha_est, double beta_est, MsvtPlan* mp) {
   if (!(t > 0.0) || !(alpha_est > 0.0) || !(beta_est > 0.0)) return MLPCP_E_INVALID_ARG;
   mp->alpha_cap = std::max(alpha_est, t);
   mp->beta_cap = std::max(beta_est, t);
-  // resolution l0 alpha in eigenvalue units; the error bound of the file header with
-  // lambda_max >= alpha / kappa
-  const double l0 = std::min(0.1, 2.0 * kMsvtTarget * std::sqrt(t / (kMsvtKappa * mp->alpha_cap)));
+  // resolution l0 alpha in eigenvalue units: the error bound of the file header (with
+  // lambda_max >= alpha / kappa), and at most kMsvtRankRes tau^2
+  const double l0 = std::min({0.1, 2.0 * kMsvtTarget * std::sqrt(t / (kMsvtKappa * mp->alpha_cap)),
+                              kMsvtRankRes * t / mp->alpha_cap});
   mp->n_sign = ns_schedule(l0, kMsvtTail, mp->a_sign, kMsvtMaxSteps);
-  const double l1 = std::min(0.999, 0.999 * std::sqrt(t / mp->beta_cap));
+  // Gt >= tau^2 / 2: a partly resolved eigenvalue l < tau^2 keeps the sign of l - tau^2
+  // (the iteration's polynomials are odd and positive on (0, 1]), so its value s in
+  // (-1, 0] gives tau^2 + (1 + s)(l - tau^2) / 2 >= (tau^2 + l) / 2
+  const double l1 = std::min(0.999, 0.999 * std::sqrt(0.5 * t / mp->beta_cap));
   mp->n_inv = ns_schedule(l1, kMsvtTail, mp->a_inv, kMsvtMaxSteps);
   return MLPCP_OK;
 }
@@ -438,7 +483,7 @@ int svt_msvt(int nH, int N, const double* G, int ldg, double tau, const double* 
       ProfScope ps(KC_SVT, s);
       hipLaunchKernelGGL(k_ms_padC, dim3(eg), dim3(256), 0, s, N, nH, C, Cp);
     }
-    MLPCP_TRY(launch_mm(N, mm(Cp, Cp, C2), nullptr, s, cnt));
+    MLPCP_TRY(launch_mm(N, mm(1, 1, Cp, Cp, C2), nullptr, s, cnt));
   }
   // 1. sign phase
   {
@@ -451,13 +496,13 @@ int svt_msvt(int nH, int N, const double* G, int ldg, double tau, const double* 
   int cur = 0;
   for (int k = 0; k < mp.n_sign; ++k) {
     const double a = mp.a_sign[k];
-    MLPCP_TRY(launch_mm(N, mm(X[cur], X[cur], P), nullptr, s, cnt));
-    MLPCP_TRY(launch_mm(N, mm(X[cur], P, X[cur ^ 1], -0.5 * a * a * a, X[cur], 1.5 * a), nullptr, s, cnt));
+    MLPCP_TRY(launch_mm(N, mm(1, 1, X[cur], X[cur], P), nullptr, s, cnt));
+    MLPCP_TRY(launch_mm(N, mm(1, 1, X[cur], P, X[cur ^ 1], -0.5 * a * a * a, X[cur], 1.5 * a), nullptr, s, cnt));
     cur ^= 1;
   }
   const double* S = X[cur];
   // 2. Gt = t I + (A + S A) / 2  (into P)
-  MLPCP_TRY(launch_mm(N, mm(S, A, P, 0.5, A, 0.5, t), nullptr, s, cnt));
+  MLPCP_TRY(launch_mm(N, mm(1, 1, S, A, P, 0.5, A, 0.5, t), nullptr, s, cnt));
   // 3. inverse square root phase: Y = Gt / beta, Z = I; first step T = c1 I + c2 Y
   {
     ProfScope ps(KC_SVT, s);
@@ -469,16 +514,16 @@ int svt_msvt(int nH, int N, const double* G, int ldg, double tau, const double* 
   // Z_1 = T (in Z[0]); Y_1 = Y_0 T
   int yc = 0, zc = 0;
   if (mp.n_inv > 1) {
-    MLPCP_TRY(launch_mm(N, mm(Y[0], Z[0], Y[1]), nullptr, s, cnt));
+    MLPCP_TRY(launch_mm(N, mm(0, 1, Y[0], Z[0], Y[1]), nullptr, s, cnt));
     yc = 1;
   }
   for (int k = 1; k < mp.n_inv; ++k) {
     const double a = mp.a_inv[k];
     // T = c1 I + c2 Z Y
-    MLPCP_TRY(launch_mm(N, mm(Z[zc], Y[yc], T, -0.5 * a * a * a, nullptr, 0.0, 1.5 * a), nullptr, s, cnt));
-    const MmOp oz = mm(T, Z[zc], Z[zc ^ 1]);
+    MLPCP_TRY(launch_mm(N, mm(0, 0, Z[zc], Y[yc], T, -0.5 * a * a * a, nullptr, 0.0, 1.5 * a), nullptr, s, cnt));
+    const MmOp oz = mm(0, 0, T, Z[zc], Z[zc ^ 1]);
     if (k + 1 < mp.n_inv) {
-      const MmOp oy = mm(Y[yc], T, Y[yc ^ 1]);
+      const MmOp oy = mm(0, 0, Y[yc], T, Y[yc ^ 1]);
       MLPCP_TRY(launch_mm(N, oz, &oy, s, cnt));
       yc ^= 1;
     } else {
@@ -487,11 +532,11 @@ int svt_msvt(int nH, int N, const double* G, int ldg, double tau, const double* 
     zc ^= 1;
   }
   const double* Zf = Z[zc];
-  // 4. K = C (I - tau beta^{-1/2} Z) C
+  // 4. K = C (I - tau beta^{-1/2} Z) C = C^2 - tau beta^{-1/2} C (Z C)
   if (C) {
     // Cp and C2 are zero beyond n_H, so K is too
-    MLPCP_TRY(launch_mm(N, mm(Cp, Zf, T), nullptr, s, cnt));
-    MLPCP_TRY(launch_mm(N, mm(T, Cp, K, -tau, C2, 1.0, 0.0, sc + SC_CF), nullptr, s, cnt));
+    MLPCP_TRY(launch_mm(N, mm(0, 0, Zf, Cp, T), nullptr, s, cnt));
+    MLPCP_TRY(launch_mm(N, mm(1, 1, Cp, T, K, -tau, C2, 1.0, 0.0, sc + SC_CF), nullptr, s, cnt));
   }
   {
     ProfScope ps(KC_SVT, s);

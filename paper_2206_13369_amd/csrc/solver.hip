@@ -1240,23 +1240,7 @@ int launch_tall_one(const Plan& p, const EpiArgs& a, const double* K, int nnz, i
 // Launches the epilogue of the given mode; returns the number of FG partials written.
 template <int MODE>
 int launch_epilogue(const Plan& p, const EpiArgs& a, const double* K, int nnz, hipStream_t s, int* partials) {
-  ProfScope ps(MODE == MODE_STEP ? KC_EPILOGUE : KC_FINAL, s);
-  if (p.tall) {
-    const int grid = p.grid_tall;
-    *partials = grid;
-    const bool vec = (p.n % 4 == 0) && aligned16(a.Lout) && aligned16(a.Zin) && aligned16(a.Zout) &&
-                     aligned16(a.Sout) && aligned16(a.Yout) && (MODE == MODE_RECON || (a.ldd % 4 == 0 && aligned16(a.D)));
-    EpiArgs b = a;
-    b.TM = p.TM_tall;
-    if (vec) {
-      if (p.masked) return launch_tall_one<MODE, true, true>(p, b, K, nnz, grid, s);
-      return launch_tall_one<MODE, false, true>(p, b, K, nnz, grid, s);
-    }
-    if (p.masked) return launch_tall_one<MODE, true, false>(p, b, K, nnz, grid, s);
-    return launch_tall_one<MODE, false, false>(p, b, K, nnz, grid, s);
-  }
-  *partials = p.nblk;
-  {
+  if (!p.tall) {
     // N = M_P K (K form) or A = M_P T, N = A T^T (factor form, rank columns)
     ProfScope ps(KC_RECON, s);
     const dim3 gb(256);
@@ -1273,6 +1257,22 @@ int launch_epilogue(const Plan& p, const EpiArgs& a, const double* K, int nnz, h
     }
     MLPCP_HIP(hipGetLastError());
   }
+  ProfScope ps(MODE == MODE_STEP ? KC_EPILOGUE : KC_FINAL, s);
+  if (p.tall) {
+    const int grid = p.grid_tall;
+    *partials = grid;
+    const bool vec = (p.n % 4 == 0) && aligned16(a.Lout) && aligned16(a.Zin) && aligned16(a.Zout) &&
+                     aligned16(a.Sout) && aligned16(a.Yout) && (MODE == MODE_RECON || (a.ldd % 4 == 0 && aligned16(a.D)));
+    EpiArgs b = a;
+    b.TM = p.TM_tall;
+    if (vec) {
+      if (p.masked) return launch_tall_one<MODE, true, true>(p, b, K, nnz, grid, s);
+      return launch_tall_one<MODE, false, true>(p, b, K, nnz, grid, s);
+    }
+    if (p.masked) return launch_tall_one<MODE, true, false>(p, b, K, nnz, grid, s);
+    return launch_tall_one<MODE, false, false>(p, b, K, nnz, grid, s);
+  }
+  *partials = p.nblk;
   const dim3 g(p.nblk), b(kThreads);
   if (p.plain) {
     if (p.masked)

@@ -268,3 +268,23 @@ def test_matrix_function_svt_matches_oracle(levels, masked, shape):
     torch.cuda.synchronize()
     assert eig.msvt_iters == 0 and eig.rank_history == ranks
     assert rel(to_np(res.L), to_np(eig.L)) <= TOL32 and rel(to_np(res.S), to_np(eig.S)) <= TOL32
+
+
+@pytest.mark.parametrize("levels", [2, 0])
+def test_matrix_function_svt_ill_conditioned(levels):
+    """A long fixed-iteration solve (mu grows by 1.5 per iteration, so the Gram's largest
+    eigenvalue ends about 1e10 times tau^2): the coupled inverse square root iteration
+    stays stable (its products are not symmetrised) and the result tracks the oracle's
+    full SVD, with the same rank in every iteration."""
+    w = synth.config("c1")
+    K = 36
+    ref = oracle.ialm(w.D, w.lam, w.mu0, levels=levels, fixed_iters=K, record=True)
+    say("ill-conditioned matrix-function svt", levels, K)
+    res = _run_gpu(w, levels, fixed=K)
+    assert res.iters == K
+    _check(res, ref)
+    ranks = [h["rank"] for h in ref.history]
+    assert res.rank_history == ranks
+    expect = sum(1 for i in range(1, K) if ranks[i - 1] > 0)
+    say(f"   matrix-function iters {res.msvt_iters} (at least {expect}) flags {res.msvt_flags}")
+    assert res.msvt_iters >= expect and res.msvt_flags == 0
