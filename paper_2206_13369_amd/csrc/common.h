@@ -177,6 +177,11 @@ bool msvt_eligible(int N);
 size_t msvt_workspace_bytes(int N);
 // Plan for threshold tau given estimates (upper bounds) of the two norm bounds.
 int msvt_plan(double tau, double alpha_est, double beta_est, MsvtPlan* mp);
+// G_H = C G C (N x N, ld N; G exactly symmetric, zero past n_H; C n_H x n_H, ld n_H) on
+// the matrix-function SVT's product kernel, the result exactly symmetric.  prep: (re)build
+// the padded C and C^2 first.  *products (nullable) += the products launched.  No sync.
+int msvt_cgc(int nH, int N, const double* G, const double* C, bool prep, double* GH, void* ws, hipStream_t s,
+             int* products);
 // Gershgorin certificate that every eigenvalue of G (n_H x n_H block, ld ldg) is below
 // tau^2 (then st takes rank 0 in factor form and a margin bound), and the largest
 // absolute row sum and the trace of G.  Synchronises `s`.

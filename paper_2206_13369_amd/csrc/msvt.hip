@@ -213,8 +213,8 @@ __device__ void ms_bounds(int N, const double* __restrict__ rs, double* red, dou
 }
 
 // A (N x N) = G - t I (padded), X = A / alpha, alpha = the norm bound (at least t, so a
-// zero G still scales to -I); block 0 stores alpha and trace(G).  flag |= 1 when alpha
-// exceeds alpha_cap (the bound the host's step count assumed).
+// zero G still scales to -I); block 0 stores alpha and trace(G), and sets flag to 1 when
+// alpha exceeds alpha_cap (the bound the host's step count assumed), else to 0.
 __global__ void __launch_bounds__(256) k_ms_scale(int N, int nH, const double* __restrict__ G, int ldg, double t,
                                                   const double* __restrict__ rs, double alpha_cap,
                                                   double* __restrict__ A, double* __restrict__ X,
@@ -226,7 +226,7 @@ __global__ void __launch_bounds__(256) k_ms_scale(int N, int nH, const double* _
   if (blockIdx.x == 0 && threadIdx.x == 0) {
     sc[SC_ALPHA] = alpha;
     sc[SC_TRACE] = trace;
-    if (alpha > alpha_cap) *flag |= 1;
+    *flag = alpha > alpha_cap ? 1 : 0;   // first writer of the SVT's flag
   }
   const double inv = 1.0 / alpha;
   const size_t total = (size_t)N * N;
@@ -287,10 +287,6 @@ __global__ void k_ms_padC(int N, int nH, const double* __restrict__ C, double* _
     const int i = (int)(e / N), j = (int)(e % N);
     Cp[e] = (i < nH && j < nH) ? 0.5 * (C[(size_t)i * nH + j] + C[(size_t)j * nH + i]) : 0.0;
   }
-}
-
-__global__ void k_ms_zero_flag(int* __restrict__ flag) {
-  if (threadIdx.x == 0) *flag = 0;
 }
 
 // Statistics of the result: rank = (N + trace S) / 2 rounded, the trace of G, the
@@ -433,6 +429,30 @@ int msvt_plan(double tau, double alpha_est, double beta_est, MsvtPlan* mp) {
   return MLPCP_OK;
 }
 
+int msvt_cgc(int nH, int N, const double* G, const double* C, bool prep, double* GH, void* ws, hipStream_t s,
+             int* products) {
+  if (!msvt_eligible(N) || nH < 1 || nH > N || !C) return MLPCP_E_INVALID_ARG;
+  const MsLayout l = ms_layout(N);
+  char* base = static_cast<char*>(ws);
+  auto at = [&](size_t off) { return reinterpret_cast<double*>(base + off); };
+  double* Cp = at(l.off_Cp);
+  double* C2 = at(l.off_C2);
+  double* T = at(l.off_T);
+  int np = 0;
+  if (prep) {
+    {
+      ProfScope ps(KC_SVT, s);
+      hipLaunchKernelGGL(k_ms_padC, dim3(elem_grid(N)), dim3(256), 0, s, N, nH, C, Cp);
+    }
+    MLPCP_TRY(launch_mm(N, mm(1, 1, Cp, Cp, C2), nullptr, s, &np));
+  }
+  // G is an exactly symmetric Gram (its lower triangle mirrored from the upper one)
+  MLPCP_TRY(launch_mm(N, mm(0, 1, G, Cp, T), nullptr, s, &np));
+  MLPCP_TRY(launch_mm(N, mm(1, 1, Cp, T, GH), nullptr, s, &np));
+  if (products) *products += np;
+  return MLPCP_OK;
+}
+
 int msvt_probe(int nH, int N, const double* G, int ldg, double tau, IterStats* st, void* ws, hipStream_t s,
                bool* certified, double* gmax, double* trace) {
   if (!msvt_eligible(N) || nH < 1 || nH > N || ldg < nH) return MLPCP_E_INVALID_ARG;
@@ -488,7 +508,6 @@ int svt_msvt(int nH, int N, const double* G, int ldg, double tau, const double* 
   // 1. sign phase
   {
     ProfScope ps(KC_SVT, s);
-    hipLaunchKernelGGL(k_ms_zero_flag, dim3(1), dim3(64), 0, s, flag);
     hipLaunchKernelGGL(k_ms_rowstats, dim3((N + 3) / 4), dim3(256), 0, s, N, nH, G, ldg, t, rs);
     hipLaunchKernelGGL(k_ms_scale, dim3(eg), dim3(256), 0, s, N, nH, G, ldg, t, rs, mp.alpha_cap, A, X[0], sc,
                        flag);

@@ -34,7 +34,10 @@ namespace mlpcp {
 namespace {
 
 constexpr int kThreads = 256;
-constexpr size_t kLdsBudget = 60 * 1024;
+// LDS per block of the wide epilogue and the initial pass (sets the rows per block):
+// small panels give more blocks per compute unit (c2, 2000 x 2000 at n_H = 250: two rows
+// per block, 0.70 ms of epilogue per solve against 0.83 ms at 28 KB and 1.35 ms at 60 KB)
+constexpr size_t kLdsBudget = 20 * 1024;
 // Below this width the full Jacobi eigensolver measured faster than the partial one
 // (a 256-wide plain Gram at rank 7-9: 125 ms per solve with the full solver, 142 ms with
 // the partial one, whose 64 x 64 Rayleigh-Ritz solve and Cholesky steps are latency
@@ -1122,19 +1125,26 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
                             p.tall ? w.at<double>(p.off_K) : (p.kw ? w.at<double>(p.off_Kw) : nullptr), st, s);
   }
   double* GH = G;
+  const bool ms_path = es && es->ms_on && p.ms && certify;
   if (!p.plain) {
-    ProfScope ps(KC_COARSE, s);
     GH = w.at<double>(p.off_GH);
-    double* tmp = w.at<double>(p.off_tmp);
-    MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
-    MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
+    if (ms_path) {
+      // on the matrix-function SVT's products (exactly symmetric result)
+      MLPCP_TRY(msvt_cgc(p.nH, p.nHp, G, op.C, !es->ms_prep, GH, w.at<void>(p.off_ms), s, &es->ms_products));
+      es->ms_prep = true;
+    } else {
+      ProfScope ps(KC_COARSE, s);
+      double* tmp = w.at<double>(p.off_tmp);
+      MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, op.C, p.nH, G, p.nHp, tmp, p.nHp, s));
+      MLPCP_TRY(gemm_f64(false, false, p.nH, p.nH, p.nH, 1.0, tmp, p.nHp, op.C, p.nH, GH, p.nHp, s));
+    }
   }
   // Matrix-function SVT (no eigenvectors).  After an iteration of rank 0 the Gershgorin
   // discs are tested first (one sync): when they put every eigenvalue below tau^2 the SVT
   // is zero; otherwise their bounds cap the norm bounds of the iteration's first phase.
   // After a nonzero rank the caps are the previous iteration's bounds times the allowed
   // growth, with no sync.
-  if (es && es->ms_on && p.ms && certify) {
+  if (ms_path) {
     const double t = tau * tau;
     double a_est, b_est;
     if (es->r_prev == 0 || !(es->ms_alpha > 0.0)) {
@@ -1156,9 +1166,8 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     }
     MsvtPlan mp;
     MLPCP_TRY(msvt_plan(tau, a_est, b_est, &mp));
-    MLPCP_TRY(svt_msvt(p.nH, p.nHp, GH, p.nHp, tau, p.plain ? nullptr : op.C, !es->ms_prep, mp,
-                       w.at<double>(p.off_Kw), p.nHp, st, w.at<void>(p.off_ms), s, &es->ms_products));
-    es->ms_prep = true;
+    MLPCP_TRY(svt_msvt(p.nH, p.nHp, GH, p.nHp, tau, p.plain ? nullptr : op.C, false, mp, w.at<double>(p.off_Kw),
+                       p.nHp, st, w.at<void>(p.off_ms), s, &es->ms_products));
     es->v_full = false;
     es->last_partial = false;
     ++es->ms_iters;
