@@ -44,7 +44,8 @@ namespace {
 constexpr double kMsvtTarget = 1.0e-6;   // bound on the relative error of M f(G) (see above)
 constexpr double kMsvtRankRes = 1.0e-3;  // every eigenvalue farther than this times tau^2 from
                                          // tau^2 is resolved (so the rank is exact there)
-constexpr double kMsvtTail = 1.0e-10;    // both iterations stop when 1 - l is below this
+constexpr double kMsvtSignTail = 1.0e-8;  // the sign phase stops when 1 - l is below this
+constexpr double kMsvtInvTail = 1.0e-10;  // the inverse square root phase likewise
 constexpr double kMsvtKappa = 8.0;       // assumed ratio of the norm bound alpha to lambda_max
 constexpr int kMsvtMaxSteps = 64;
 
@@ -420,12 +421,12 @@ int msvt_plan(double tau, double alpha_est, double beta_est, MsvtPlan* mp) {
   // lambda_max >= alpha / kappa), and at most kMsvtRankRes tau^2
   const double l0 = std::min({0.1, 2.0 * kMsvtTarget * std::sqrt(t / (kMsvtKappa * mp->alpha_cap)),
                               kMsvtRankRes * t / mp->alpha_cap});
-  mp->n_sign = ns_schedule(l0, kMsvtTail, mp->a_sign, kMsvtMaxSteps);
+  mp->n_sign = ns_schedule(l0, kMsvtSignTail, mp->a_sign, kMsvtMaxSteps);
   // Gt >= tau^2 / 2: a partly resolved eigenvalue l < tau^2 keeps the sign of l - tau^2
   // (the iteration's polynomials are odd and positive on (0, 1]), so its value s in
   // (-1, 0] gives tau^2 + (1 + s)(l - tau^2) / 2 >= (tau^2 + l) / 2
   const double l1 = std::min(0.999, 0.999 * std::sqrt(0.5 * t / mp->beta_cap));
-  mp->n_inv = ns_schedule(l1, kMsvtTail, mp->a_inv, kMsvtMaxSteps);
+  mp->n_inv = ns_schedule(l1, kMsvtInvTail, mp->a_inv, kMsvtMaxSteps);
   return MLPCP_OK;
 }
 
