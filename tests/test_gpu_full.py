@@ -6,7 +6,8 @@ error <= 1e-5 for the float32 solver, <= 1e-3 for the precision form (bfloat16 /
 split-bfloat16 products), with the final rank identical (and, for float32, the rank of
 every iteration and the iteration count).  Covered: the 2000 x 2000 compressive
 workload multilevel and plain, the 76800 x 400 video stand-in and the 262144 x 200
-hyperspectral stand-in (multilevel).  The converged points also satisfy Lemma 1's
+hyperspectral stand-in (multilevel; plain in float32 on a quarter of the rows, where
+their 448- and 256-wide Grams take the matrix-function SVT).  The converged points also satisfy Lemma 1's
 multiplier conditions and S = Y = 0 off Q."""
 import functools
 
@@ -98,3 +99,24 @@ def test_c2_plain_full_oracle():
 @pytest.mark.parametrize("name", ["c3", "c5"])
 def test_tall_workloads_to_tolerance(name, prec):
     _compare(name, _work(name).levels, prec)
+
+
+@pytest.mark.parametrize("name", ["c3", "c5"])
+def test_tall_workloads_plain_to_tolerance(name):
+    """The plain baselines of the tall workloads, on a quarter of the rows (the plain
+    oracle solves at full size take minutes of host time): every SVT after the first
+    nonzero rank comes from the matrix-function form (sign and inverse square root by
+    Newton-Schulz products) on the same 448 / 256-wide Gram as at full size; converged
+    L, S, the iteration count and every rank against the oracle's full SVDs."""
+    w = synth.config(name, scale=0.25)
+    say(f"{name} (quarter rows, {w.m} x {w.n}) plain oracle solve")
+    ref = oracle.ialm(w.D, w.lam, w.mu0, Q=w.Q, levels=0, tol=1e-6, record=True)
+    r = _solve(w, 0, 1e-6)
+    eL, eS = rel(to_np(r.L), ref.L), rel(to_np(r.S), ref.S)
+    say(f"   iters {r.iters}/{ref.iters} errL {eL:.2e} errS {eS:.2e} rank {r.rank}/{ref.rank} "
+        f"matrix-function iters {r.msvt_iters} flags {r.msvt_flags}")
+    assert r.status == mlp.MLPCP_OK and r.fg <= 1e-6
+    assert eL <= TOL["fp32"] and eS <= TOL["fp32"]
+    assert r.iters == ref.iters and r.rank_history == [h["rank"] for h in ref.history]
+    assert r.msvt_iters >= r.iters // 2 and r.msvt_flags == 0
+    _invariants(w, r)
