@@ -67,6 +67,12 @@ constexpr double kRelEps2 = 1.0e-24;  // (1e-12)^2
 // resolution; it stops sweeps that would only refine eigenvectors of clusters of
 // tiny eigenvalues to their own relative precision.
 constexpr double kAbsTol = 1.0e-14;
+// Perturbative path of the one-workgroup SVT: accepted when every off-diagonal entry of
+// the warm-started H is below kDkMaxCoupling sqrt(h_ii h_jj) (the neglected third-order
+// terms are then of relative size about kDkMaxCoupling^3); divided differences use the
+// derivative form for centres closer than kDkClose relative.
+constexpr double kDkMaxCoupling = 2.0e-3;
+constexpr double kDkClose = 1.0e-6;
 // Widths from which the threshold certificate takes its partial form: at N = 1024 an
 // outer round updates 120 + 256 tiles, more than the 256 compute units take at once.
 constexpr int kCertPartialMin = 1024;
@@ -941,6 +947,27 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double c
   }
 }
 
+// The SVT's spectral function on one class of eigenvalues: f(x) = 1 - tau / sqrt(x) above
+// tau^2, 0 below (the classes are separated by the Gershgorin test), and its first two
+// derivatives.
+struct SvtFn {
+  double tau;
+  __device__ double f(double x, bool up) const { return up ? 1.0 - tau / sqrt(x) : 0.0; }
+  __device__ double d1(double x, bool up) const { return up ? 0.5 * tau / (x * sqrt(x)) : 0.0; }
+  __device__ double d2(double x, bool up) const { return up ? -0.75 * tau / (x * x * sqrt(x)) : 0.0; }
+  // first divided difference f[a, b] (a, b in classes ua, ub)
+  __device__ double dd1(double a, bool ua, double b, bool ub) const {
+    if (ua == ub && fabs(a - b) <= kDkClose * fmax(fabs(a), fabs(b))) return d1(0.5 * (a + b), ua);
+    return (f(a, ua) - f(b, ub)) / (a - b);
+  }
+  // d/da f[a, b]
+  __device__ double dd1_da(double a, bool ua, double b, bool ub) const {
+    if (ua == ub && fabs(a - b) <= kDkClose * fmax(fabs(a), fabs(b))) return 0.5 * d2(a, ua);
+    const double h = a - b;
+    return (d1(a, ua) * h - (f(a, ua) - f(b, ub))) / (h * h);
+  }
+};
+
 __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, const double* __restrict__ G,
                                                       const double* __restrict__ C, double* __restrict__ V,
                                                       int warm, double tau, int certify, int max_sweeps,
@@ -1021,6 +1048,142 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
     __syncthreads();
   }
   const double fl = kAbsTol * red[0] + 1.0e-300;
+  const double trace_h = red[0];
+  // Perturbative path (warm start, K requested, SVT operator only).  In the previous
+  // basis H = V^T G_H V is close to its diagonal D = diag(h_i): when every Gershgorin disc
+  // [h_i - r_i, h_i + r_i] lies either above or below tau^2 (the rank is then the number
+  // above, each class holding that many eigenvalues) and every coupling |o_ij| is below
+  // kDkMaxCoupling sqrt(h_i h_j), the SVT operator f(H) (f(x) = 1 - tau / sqrt(x) above
+  // tau^2, 0 below) is taken from its second-order expansion around D (Daleckii and
+  // Krein's divided-difference series):
+  //   f(H)_ij ~ f(h_i) [i = j] + o_ij f[h_i, h_j] + sum_k o_ik o_kj f[h_i, h_k, h_j],
+  // the last term as ((A O - O A)_ij / (h_i - h_j)), A = O o f[.,.] (elementwise), and by
+  // its derivative form for centres within kDkClose.  Then K = C V f(H) V^T C; V stays
+  // (the next warm start); T, Tt, lam, perm, sw are not formed.  Otherwise the sweeps run.
+  if (warm && certify && K) {
+    const double t2 = tau * tau;
+    double cmax = 0.0;
+    int cls = 1;   // 1: disc above tau^2, 0: below, -1: straddles (or a centre not positive)
+    double mg = 1.0e300;
+    if (tid < nH) {
+      const double hi = sA[tid][tid];
+      double r = 0.0;
+      for (int j = 0; j < nH; ++j)
+        if (j != tid) {
+          const double o = fabs(sA[tid][j]);
+          r += o;
+          const double hj = sA[j][j];
+          cmax = (hi > 0.0 && hj > 0.0) ? fmax(cmax, o / sqrt(hi * hj)) : 1.0e300;
+        }
+      if (hi - r > t2 * (1.0 + 1.0e-12)) {
+        cls = 1;
+        mg = (sqrt(hi - r) - tau) / tau;
+      } else if (hi + r < t2 * (1.0 - 1.0e-12) && hi > 0.0) {
+        cls = 0;
+        mg = (tau - sqrt(hi + r)) / tau;
+      } else {
+        cls = -1;
+      }
+      swv[tid] = cls;   // class per index (reused below)
+    }
+    red[tid] = (cls < 0) ? 1.0e300 : cmax;
+    redi[tid] = (tid < nH && cls == 1) ? 1 : 0;
+    __syncthreads();
+    for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
+      if (tid < w) {
+        red[tid] = fmax(red[tid], red[tid + w]);
+        redi[tid] += redi[tid + w];
+      }
+      __syncthreads();
+    }
+    const double cm = red[0];
+    const int rank_dk = redi[0];
+    __syncthreads();
+    if (cm < kDkMaxCoupling) {
+      red[tid] = mg;
+      __syncthreads();
+      for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
+        if (tid < w) red[tid] = fmin(red[tid], red[tid + w]);
+        __syncthreads();
+      }
+      const double margin_dk = red[0];
+      const SvtFn fn{tau};
+      // the diagonal in gbs; O in sA (zero diagonal); A = O o f[h_i, h_j] in sC and
+      // B = O o d/dh_i f[h_i, h_j] in sW (elementwise)
+      if (tid < IN) gbs[tid] = tid < nH ? sA[tid][tid] : 0.0;
+      __syncthreads();
+      for (int it = tid; it < IN * IN; it += kSmallThreads) {
+        const int i = it / IN, j = it % IN;
+        double a = 0.0, b = 0.0;
+        if (i < nH && j < nH && i != j) {
+          const double o = sA[i][j];
+          const bool ui = swv[i] > 0.5, uj = swv[j] > 0.5;
+          a = o * fn.dd1(gbs[i], ui, gbs[j], uj);
+          b = o * fn.dd1_da(gbs[i], ui, gbs[j], uj);
+        }
+        sC[i][j] = a;
+        sW[i][j] = b;
+      }
+      __syncthreads();
+      if (tid < nH) sA[tid][tid] = 0.0;
+      __syncthreads();
+      // P3 = B O: the second-order term in derivative form, sum_k o_ik o_kj f[h_i, h_k, h_i]
+      // (the diagonal, and pairs of centres within kDkClose)
+      if (mm_on) mm64<false>(sW, sA, acc, km);
+      __syncthreads();
+      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+      __syncthreads();
+      // P1 = A O (O A = P1^T: both symmetric); the second-order term elsewhere is
+      // (P1 - P1^T)_ij / (h_i - h_j); P1 replaces A in sC (a_ij is recomputed from o_ij)
+      if (mm_on) mm64<false>(sC, sA, acc, km);
+      __syncthreads();
+      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sC[i][j] = v; });
+      __syncthreads();
+      // F (in sW): f(h_i) [i = j] + a_ij + the second-order term
+      for (int it = tid; it < IN * IN; it += kSmallThreads) {
+        const int i = it / IN, j = it % IN;
+        double x = 0.0;
+        if (i < nH && j < nH) {
+          const double hi = gbs[i], hj = gbs[j];
+          const bool ui = swv[i] > 0.5, uj = swv[j] > 0.5;
+          if (i == j)
+            x = fn.f(hi, ui) + sW[i][j];
+          else if (ui == uj && fabs(hi - hj) <= kDkClose * fmax(fabs(hi), fabs(hj)))
+            x = sA[i][j] * fn.dd1(hi, ui, hj, uj) + sW[i][j];
+          else
+            x = sA[i][j] * fn.dd1(hi, ui, hj, uj) + (sC[i][j] - sC[j][i]) / (hi - hj);
+        }
+        sW[i][j] = x;   // each entry read and written by one thread
+      }
+      __syncthreads();
+      // K = S'^T (F S'), S' = V^T C
+      for (int it = tid; it < IN * IN; it += kSmallThreads) {
+        const int i = it / IN, j = it % IN;
+        sC[i][j] = (i < nH && j < nH) ? (C ? C[(size_t)i * nH + j] : (i == j ? 1.0 : 0.0)) : 0.0;
+      }
+      __syncthreads();
+      if (mm_on) mm64<true>(sQ, sC, acc, km);
+      __syncthreads();
+      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+      __syncthreads();
+      if (mm_on) mm64<false>(sW, sA, acc, km);
+      __syncthreads();
+      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sC[i][j] = v; });
+      __syncthreads();
+      if (mm_on) {
+        mm64<true>(sA, sC, acc, km);
+        mm64_store(acc, [&](int i, int j, double v) { K[(size_t)i * IN + j] = v; });
+      }
+      if (tid == 0) {
+        st->rank = rank_dk;
+        st->kform = 0;
+        st->margin = margin_dk;
+        st->trace = trace_h;
+        st->sweeps = 0;
+      }
+      return;
+    }
+  }
   const int ne = nH + (nH & 1);
   int sweeps = 0;
   bool conv = false;
