@@ -832,9 +832,61 @@ __device__ __forceinline__ void sweep_sync() {
   }
 }
 
+// Gate of the perturbative SVT finish on H (sA, n_H x n_H): every Gershgorin disc
+// [h_i - r_i, h_i + r_i] lies above or below t2 = tau^2 and every coupling |h_ij| is below
+// kDkMaxCoupling sqrt(h_i h_j).  Writes each index's class (1: disc above t2, 0: below,
+// -1: straddles, or a centre not positive) to cls_out, the number above to rank, and this
+// thread's term of the margin (the relative distance of its disc from tau) to mg.  Every
+// thread of the block calls it.
+__device__ __forceinline__ bool dk_gate(int nH, double tau, LdsRow* sA, double* cls_out, double* red, int* redi,
+                                        double& mg, int& rank) {
+  const int tid = threadIdx.x;
+  const double t2 = tau * tau;
+  double cmax = 0.0;
+  int cls = 1;
+  mg = 1.0e300;
+  if (tid < nH) {
+    const double hi = sA[tid][tid];
+    double r = 0.0;
+    for (int j = 0; j < nH; ++j)
+      if (j != tid) {
+        const double o = fabs(sA[tid][j]);
+        r += o;
+        const double hj = sA[j][j];
+        cmax = (hi > 0.0 && hj > 0.0) ? fmax(cmax, o / sqrt(hi * hj)) : 1.0e300;
+      }
+    if (hi - r > t2 * (1.0 + 1.0e-12)) {
+      cls = 1;
+      mg = (sqrt(hi - r) - tau) / tau;
+    } else if (hi + r < t2 * (1.0 - 1.0e-12) && hi > 0.0) {
+      cls = 0;
+      mg = (tau - sqrt(hi + r)) / tau;
+    } else {
+      cls = -1;
+    }
+    cls_out[tid] = cls;
+  }
+  red[tid] = (cls < 0) ? 1.0e300 : cmax;
+  redi[tid] = (tid < nH && cls == 1) ? 1 : 0;
+  __syncthreads();
+  for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
+    if (tid < w) {
+      red[tid] = fmax(red[tid], red[tid + w]);
+      redi[tid] += redi[tid + w];
+    }
+    __syncthreads();
+  }
+  const double cm = red[0];
+  rank = redi[0];
+  __syncthreads();
+  return cm < kDkMaxCoupling;
+}
+
 template <int ACTIVE, int MT, int MQ, bool WAVE = false>
 __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double cert_tau2, int max_sweeps, double* pc,
-                             double* ps, double* pt, double* gbs, int& sweeps) {
+                             double* ps, double* pt, double* gbs, int& sweeps, int gate_n = 0, double gate_tau = 0.0,
+                             bool gate_first = false, double* gcls = nullptr, double* gred = nullptr,
+                             int* gredi = nullptr, bool* gate_hit = nullptr) {
   static_assert(!WAVE || ACTIVE == 64, "the wave form runs on one wave");
   constexpr int kPadCol = IN;
   const int tid = threadIdx.x, lane = tid & 63;
@@ -856,6 +908,17 @@ __device__ bool small_sweeps(LdsRow* sA, LdsRow* sQ, int ne, double fl, double c
     qb_[x] = qv_[x] ? e % np : 0;
   }
   for (sweeps = 0;; ++sweeps) {
+    // the perturbative finish's gate (gate_n > 0; block form only), before the first
+    // sweep only when gate_first: the sweeps converge quadratically, so its coupling
+    // bound is met a sweep or more before the rotation test below stops them
+    if (!WAVE && gate_n > 0 && (sweeps > 0 || gate_first)) {
+      double mg;
+      int rk;
+      if (dk_gate(gate_n, gate_tau, sA, gcls, gred, gredi, mg, rk)) {
+        *gate_hit = true;
+        return false;
+      }
+    }
     if (cert_tau2 > 0.0) {
       // Gershgorin bound of each row: 16 threads per row (blockDim = 1024 covers 64 rows);
       // the wave form: 4 lanes per row (16 rows)
@@ -1058,152 +1121,139 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   // Krein's divided-difference series):
   //   f(H)_ij ~ f(h_i) [i = j] + o_ij f[h_i, h_j] + sum_k o_ik o_kj f[h_i, h_k, h_j],
   // the last term as ((A O - O A)_ij / (h_i - h_j)), A = O o f[.,.] (elementwise), and by
-  // its derivative form for centres within kDkClose.  Then K = C V f(H) V^T C; V stays
-  // (the next warm start); T, Tt, lam, perm, sw are not formed.  Otherwise the sweeps run.
-  if (warm && certify && K) {
-    const double t2 = tau * tau;
-    double cmax = 0.0;
-    int cls = 1;   // 1: disc above tau^2, 0: below, -1: straddles (or a centre not positive)
-    double mg = 1.0e300;
-    if (tid < nH) {
-      const double hi = sA[tid][tid];
-      double r = 0.0;
-      for (int j = 0; j < nH; ++j)
-        if (j != tid) {
-          const double o = fabs(sA[tid][j]);
-          r += o;
-          const double hj = sA[j][j];
-          cmax = (hi > 0.0 && hj > 0.0) ? fmax(cmax, o / sqrt(hi * hj)) : 1.0e300;
-        }
-      if (hi - r > t2 * (1.0 + 1.0e-12)) {
-        cls = 1;
-        mg = (sqrt(hi - r) - tau) / tau;
-      } else if (hi + r < t2 * (1.0 - 1.0e-12) && hi > 0.0) {
-        cls = 0;
-        mg = (tau - sqrt(hi + r)) / tau;
-      } else {
-        cls = -1;
-      }
-      swv[tid] = cls;   // class per index (reused below)
-    }
-    red[tid] = (cls < 0) ? 1.0e300 : cmax;
-    redi[tid] = (tid < nH && cls == 1) ? 1 : 0;
+  // its derivative form for centres within kDkClose.  Then K = C V f(H) V^T C; T, Tt, lam,
+  // perm, sw are not formed.  It is tried on the warm start and after each Jacobi sweep
+  // (nsw: the sweeps run before it; their rotated basis V is the next warm start).
+  auto dk_try = [&](int nsw) -> bool {
+    double mg;
+    int rank_dk;
+    if (!dk_gate(nH, tau, sA, swv, red, redi, mg, rank_dk)) return false;
+    red[tid] = mg;
     __syncthreads();
     for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
-      if (tid < w) {
-        red[tid] = fmax(red[tid], red[tid + w]);
-        redi[tid] += redi[tid + w];
-      }
+      if (tid < w) red[tid] = fmin(red[tid], red[tid + w]);
       __syncthreads();
     }
-    const double cm = red[0];
-    const int rank_dk = redi[0];
+    const double margin_dk = red[0];
+    const SvtFn fn{tau};
+    // the diagonal in gbs; O in sA (zero diagonal); A = O o f[h_i, h_j] in sC and
+    // B = O o d/dh_i f[h_i, h_j] in sW (elementwise)
+    if (tid < IN) gbs[tid] = tid < nH ? sA[tid][tid] : 0.0;
     __syncthreads();
-    if (cm < kDkMaxCoupling) {
-      red[tid] = mg;
-      __syncthreads();
-      for (int w = kSmallThreads / 2; w > 0; w >>= 1) {
-        if (tid < w) red[tid] = fmin(red[tid], red[tid + w]);
-        __syncthreads();
+    for (int it = tid; it < IN * IN; it += kSmallThreads) {
+      const int i = it / IN, j = it % IN;
+      double a = 0.0, b = 0.0;
+      if (i < nH && j < nH && i != j) {
+        const double o = sA[i][j];
+        const bool ui = swv[i] > 0.5, uj = swv[j] > 0.5;
+        a = o * fn.dd1(gbs[i], ui, gbs[j], uj);
+        b = o * fn.dd1_da(gbs[i], ui, gbs[j], uj);
       }
-      const double margin_dk = red[0];
-      const SvtFn fn{tau};
-      // the diagonal in gbs; O in sA (zero diagonal); A = O o f[h_i, h_j] in sC and
-      // B = O o d/dh_i f[h_i, h_j] in sW (elementwise)
-      if (tid < IN) gbs[tid] = tid < nH ? sA[tid][tid] : 0.0;
-      __syncthreads();
-      for (int it = tid; it < IN * IN; it += kSmallThreads) {
-        const int i = it / IN, j = it % IN;
-        double a = 0.0, b = 0.0;
-        if (i < nH && j < nH && i != j) {
-          const double o = sA[i][j];
-          const bool ui = swv[i] > 0.5, uj = swv[j] > 0.5;
-          a = o * fn.dd1(gbs[i], ui, gbs[j], uj);
-          b = o * fn.dd1_da(gbs[i], ui, gbs[j], uj);
-        }
-        sC[i][j] = a;
-        sW[i][j] = b;
-      }
-      __syncthreads();
-      if (tid < nH) sA[tid][tid] = 0.0;
-      __syncthreads();
-      // P3 = B O: the second-order term in derivative form, sum_k o_ik o_kj f[h_i, h_k, h_i]
-      // (the diagonal, and pairs of centres within kDkClose)
-      if (mm_on) mm64<false>(sW, sA, acc, km);
-      __syncthreads();
-      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
-      __syncthreads();
-      // P1 = A O (O A = P1^T: both symmetric); the second-order term elsewhere is
-      // (P1 - P1^T)_ij / (h_i - h_j); P1 replaces A in sC (a_ij is recomputed from o_ij)
-      if (mm_on) mm64<false>(sC, sA, acc, km);
-      __syncthreads();
-      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sC[i][j] = v; });
-      __syncthreads();
-      // F (in sW): f(h_i) [i = j] + a_ij + the second-order term
-      for (int it = tid; it < IN * IN; it += kSmallThreads) {
-        const int i = it / IN, j = it % IN;
-        double x = 0.0;
-        if (i < nH && j < nH) {
-          const double hi = gbs[i], hj = gbs[j];
-          const bool ui = swv[i] > 0.5, uj = swv[j] > 0.5;
-          if (i == j)
-            x = fn.f(hi, ui) + sW[i][j];
-          else if (ui == uj && fabs(hi - hj) <= kDkClose * fmax(fabs(hi), fabs(hj)))
-            x = sA[i][j] * fn.dd1(hi, ui, hj, uj) + sW[i][j];
-          else
-            x = sA[i][j] * fn.dd1(hi, ui, hj, uj) + (sC[i][j] - sC[j][i]) / (hi - hj);
-        }
-        sW[i][j] = x;   // each entry read and written by one thread
-      }
-      __syncthreads();
-      // K = S'^T (F S'), S' = V^T C
-      for (int it = tid; it < IN * IN; it += kSmallThreads) {
-        const int i = it / IN, j = it % IN;
-        sC[i][j] = (i < nH && j < nH) ? (C ? C[(size_t)i * nH + j] : (i == j ? 1.0 : 0.0)) : 0.0;
-      }
-      __syncthreads();
-      if (mm_on) mm64<true>(sQ, sC, acc, km);
-      __syncthreads();
-      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
-      __syncthreads();
-      if (mm_on) mm64<false>(sW, sA, acc, km);
-      __syncthreads();
-      if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sC[i][j] = v; });
-      __syncthreads();
-      if (mm_on) {
-        mm64<true>(sA, sC, acc, km);
-        mm64_store(acc, [&](int i, int j, double v) { K[(size_t)i * IN + j] = v; });
-      }
-      if (tid == 0) {
-        st->rank = rank_dk;
-        st->kform = 0;
-        st->margin = margin_dk;
-        st->trace = trace_h;
-        st->sweeps = 0;
-      }
-      return;
+      sC[i][j] = a;
+      sW[i][j] = b;
     }
-  }
+    __syncthreads();
+    if (tid < nH) sA[tid][tid] = 0.0;
+    __syncthreads();
+    // P3 = B O: the second-order term in derivative form, sum_k o_ik o_kj f[h_i, h_k, h_i]
+    // (the diagonal, and pairs of centres within kDkClose)
+    if (mm_on) mm64<false>(sW, sA, acc, km);
+    __syncthreads();
+    if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
+    __syncthreads();
+    // P1 = A O (O A = P1^T: both symmetric); the second-order term elsewhere is
+    // (P1 - P1^T)_ij / (h_i - h_j); P1 replaces A in sC (a_ij is recomputed from o_ij)
+    if (mm_on) mm64<false>(sC, sA, acc, km);
+    __syncthreads();
+    if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sC[i][j] = v; });
+    __syncthreads();
+    // F (in sW): f(h_i) [i = j] + a_ij + the second-order term
+    for (int it = tid; it < IN * IN; it += kSmallThreads) {
+      const int i = it / IN, j = it % IN;
+      double x = 0.0;
+      if (i < nH && j < nH) {
+        const double hi = gbs[i], hj = gbs[j];
+        const bool ui = swv[i] > 0.5, uj = swv[j] > 0.5;
+        if (i == j)
+          x = fn.f(hi, ui) + sW[i][j];
+        else if (ui == uj && fabs(hi - hj) <= kDkClose * fmax(fabs(hi), fabs(hj)))
+          x = sA[i][j] * fn.dd1(hi, ui, hj, uj) + sW[i][j];
+        else
+          x = sA[i][j] * fn.dd1(hi, ui, hj, uj) + (sC[i][j] - sC[j][i]) / (hi - hj);
+      }
+      sW[i][j] = x;   // each entry read and written by one thread
+    }
+    __syncthreads();
+    // K = S'^T (F S'), S' = V^T C
+    for (int it = tid; it < IN * IN; it += kSmallThreads) {
+      const int i = it / IN, j = it % IN;
+      sC[i][j] = (i < nH && j < nH) ? (C ? C[(size_t)i * nH + j] : (i == j ? 1.0 : 0.0)) : 0.0;
+    }
+    __syncthreads();
+    if (mm_on) mm64<true>(sQ, sC, acc, km);
+    __syncthreads();
+    if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
+    __syncthreads();
+    if (mm_on) mm64<false>(sW, sA, acc, km);
+    __syncthreads();
+    if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sC[i][j] = v; });
+    __syncthreads();
+    if (mm_on) {
+      mm64<true>(sA, sC, acc, km);
+      mm64_store(acc, [&](int i, int j, double v) { K[(size_t)i * IN + j] = v; });
+    }
+    if (nsw > 0)   // the rotated basis is the next warm start
+      for (int it = tid; it < IN * IN; it += kSmallThreads) {
+        const int i = it / IN, j = it % IN;
+        V[(size_t)i * ld + j] = sQ[i][j];
+      }
+    if (tid == 0) {
+      st->rank = rank_dk;
+      st->kform = 0;
+      st->margin = margin_dk;
+      st->trace = trace_h;
+      st->sweeps = nsw;
+    }
+    return true;
+  };
   const int ne = nH + (nH & 1);
   int sweeps = 0;
   bool conv = false;
   const double ct2 = certify ? tau * tau : 0.0;
+  // the perturbative finish: tried on the warm start, and in the block forms after each
+  // sweep
+  const bool dk_on = certify && K;
+  const int gate_n = dk_on ? nH : 0;
+  bool hit = false;
   if (ne <= 16) {
-    __shared__ int wave_res[2];
-    if (tid < 64) {
-      const bool c = small_sweeps<64, 1, 2, true>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
-      if (tid == 0) {
-        wave_res[0] = c ? 1 : 0;
-        wave_res[1] = sweeps;
-      }
+    if (dk_on && warm) {
+      double mg;
+      int rk;
+      hit = dk_gate(nH, tau, sA, swv, red, redi, mg, rk);
     }
-    __syncthreads();
-    conv = wave_res[0] != 0;
-    sweeps = wave_res[1];
+    if (!hit) {
+      __shared__ int wave_res[2];
+      if (tid < 64) {
+        const bool c = small_sweeps<64, 1, 2, true>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
+        if (tid == 0) {
+          wave_res[0] = c ? 1 : 0;
+          wave_res[1] = sweeps;
+        }
+      }
+      __syncthreads();
+      conv = wave_res[0] != 0;
+      sweeps = wave_res[1];
+    }
   } else if (ne <= 32)
-    conv = small_sweeps<256, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
+    conv = small_sweeps<256, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps, gate_n, tau, warm, swv,
+                                   red, redi, &hit);
   else
-    conv = small_sweeps<kSmallThreads, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps);
+    conv = small_sweeps<kSmallThreads, 1, 2>(sA, sQ, ne, fl, ct2, max_sweeps, pc, ps, pt, gbs, sweeps, gate_n, tau,
+                                             warm, swv, red, redi, &hit);
+  if (hit) {
+    if (dk_try(sweeps)) return;
+    conv = false;   // not reached: the finish applies the same gate to the same matrix
+  }
   // eigenvalues, descending order (ties by index), weights, rank, margin, trace
   double li = 0.0;
   if (tid < IN) {
