@@ -118,6 +118,17 @@ struct IterStats {
   double msvt_alpha, msvt_beta;   // those norm bounds
 };
 
+// A record the device publishes to pinned, host-mapped memory: the values first, then,
+// behind a system-scope fence, the sequence number of the request that wrote them.
+struct ProbeRecord {
+  double v[3];
+  unsigned long long seq;
+};
+
+// Spins on host memory until *seqp == want; every 1024 polls a stream query ends the wait
+// with MLPCP_E_HIP on an error, or when the stream has drained without publishing.
+int wait_seq(const unsigned long long* seqp, unsigned long long want, hipStream_t s);
+
 // Sweep count placeholder: the count is in IterStats::sweeps after the next sync.
 constexpr int kSweepsOnDevice = -100;
 
@@ -188,7 +199,8 @@ int msvt_cgc(int nH, int N, const double* G, const double* C, bool prep, double*
 // tau^2 (then st takes rank 0 in factor form and a margin bound), and the largest
 // absolute row sum and the trace of G.  Synchronises `s`.
 int msvt_probe(int nH, int N, const double* G, int ldg, double tau, IterStats* st, void* ws, hipStream_t s,
-               bool* certified, double* gmax, double* trace);
+               bool* certified, double* gmax, double* trace, ProbeRecord* pub_host = nullptr,
+               ProbeRecord* pub_dev = nullptr, unsigned long long seq = 0);
 // K (N x N, ld ldk == N) = C f(G) C with f(l) = (1 - tau / sqrt(l))_+ on the eigenvalues
 // of G (n_H x n_H block of an N x N buffer, ld ldg; C n_H x n_H, ld n_H, or null for the
 // identity), zero beyond n_H; st: rank, trace, kform = 1, the flags and bounds.  prep:

@@ -322,7 +322,8 @@ __global__ void k_ms_stats(int N, const double* __restrict__ S, const double* __
 // 1 when certified, pr[1] = the largest row sum, pr[2] = trace G; when certified, st
 // takes rank 0 in factor form and the margin (tau - sqrt(max sum)) / tau.
 __global__ void __launch_bounds__(256) k_ms_probe(int N, const double* __restrict__ rs, double t, double tau,
-                                                  double* __restrict__ pr, IterStats* __restrict__ st) {
+                                                  double* __restrict__ pr, IterStats* __restrict__ st,
+                                                  ProbeRecord* pub, unsigned long long seq) {
   __shared__ double red[768];
   double bound, trace;
   ms_bounds(N, rs, red, bound, trace);   // bound = min(max row sum, ||G||_F)
@@ -340,6 +341,13 @@ __global__ void __launch_bounds__(256) k_ms_probe(int N, const double* __restric
       st->lam_r = 0.0;
       st->lam_65 = 0.0;
       st->msvt_flag = 0;
+    }
+    if (pub) {   // the same three values for the host, the sequence number last
+      pub->v[0] = pr[0];
+      pub->v[1] = gmax;
+      pub->v[2] = trace;
+      __threadfence_system();
+      *reinterpret_cast<volatile unsigned long long*>(&pub->seq) = seq;
     }
   }
 }
@@ -455,7 +463,8 @@ int msvt_cgc(int nH, int N, const double* G, const double* C, bool prep, double*
 }
 
 int msvt_probe(int nH, int N, const double* G, int ldg, double tau, IterStats* st, void* ws, hipStream_t s,
-               bool* certified, double* gmax, double* trace) {
+               bool* certified, double* gmax, double* trace, ProbeRecord* pub_host, ProbeRecord* pub_dev,
+               unsigned long long seq) {
   if (!msvt_eligible(N) || nH < 1 || nH > N || ldg < nH) return MLPCP_E_INVALID_ARG;
   const MsLayout l = ms_layout(N);
   char* base = static_cast<char*>(ws);
@@ -464,12 +473,18 @@ int msvt_probe(int nH, int N, const double* G, int ldg, double tau, IterStats* s
   {
     ProfScope ps(KC_SVT, s);
     hipLaunchKernelGGL(k_ms_rowstats, dim3((N + 3) / 4), dim3(256), 0, s, N, nH, G, ldg, 0.0, rs);
-    hipLaunchKernelGGL(k_ms_probe, dim3(1), dim3(256), 0, s, N, rs, tau * tau, tau, pr, st);
+    hipLaunchKernelGGL(k_ms_probe, dim3(1), dim3(256), 0, s, N, rs, tau * tau, tau, pr, st,
+                       pub_host ? pub_dev : nullptr, seq);
   }
   MLPCP_HIP(hipGetLastError());
   double h[3];
-  MLPCP_HIP(hipMemcpyAsync(h, pr, sizeof(h), hipMemcpyDeviceToHost, s));
-  MLPCP_HIP(hipStreamSynchronize(s));
+  if (pub_host) {   // published to host memory: no copy, no stream synchronisation
+    MLPCP_TRY(wait_seq(&pub_host->seq, seq, s));
+    for (int i = 0; i < 3; ++i) h[i] = pub_host->v[i];
+  } else {
+    MLPCP_HIP(hipMemcpyAsync(h, pr, sizeof(h), hipMemcpyDeviceToHost, s));
+    MLPCP_HIP(hipStreamSynchronize(s));
+  }
   *certified = h[0] != 0.0;
   *gmax = h[1];
   *trace = h[2];

@@ -27,6 +27,7 @@
 
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <vector>
 
 namespace mlpcp {
@@ -869,6 +870,78 @@ __global__ void __launch_bounds__(kThreads) k_reduce(const double* __restrict__ 
   if (threadIdx.x == 0) *out = t;
 }
 
+// The per-iteration record the host's stop test reads: the iteration statistics and,
+// written after them, the sequence number of the iteration that filled them in.
+struct HostStats {
+  IterStats st;
+  unsigned long long seq;
+};
+
+// k_reduce (sum of the blocks' residual partials into st->fg2), then the whole iteration
+// record copied to host-mapped memory with its sequence number last, behind a
+// system-scope fence: the host can read the record as soon as it sees the number,
+// without a copy or a stream synchronisation.
+__global__ void __launch_bounds__(kThreads) k_reduce_publish(const double* __restrict__ partial, int cnt,
+                                                             IterStats* __restrict__ st, HostStats* host,
+                                                             unsigned long long seq) {
+  __shared__ double red[kThreads];
+  double s = 0.0;
+  for (int i = threadIdx.x; i < cnt; i += kThreads) s += partial[i];
+  const double t = block_sum(s, red);
+  if (threadIdx.x == 0) {
+    st->fg2 = t;
+    IterStats c = *st;
+    c.fg2 = t;
+    host->st = c;
+    __threadfence_system();
+    *reinterpret_cast<volatile unsigned long long*>(&host->seq) = seq;
+  }
+}
+
+// One page of pinned, host-mapped memory per host thread for the records the host waits
+// on (allocated on the thread's first solve, kept until the process ends; a solve runs to
+// completion on its calling thread, so the page is never shared).  Null when the
+// allocation fails: the values then come back by a copy and a stream synchronisation.
+struct HostPage {
+  HostStats stats;
+  ProbeRecord probe;
+};
+
+struct HostSlot {
+  HostPage* host = nullptr;   // host address
+  HostPage* dev = nullptr;    // the same memory as the device addresses it
+  unsigned long long next = 0;
+};
+
+HostSlot* host_slot() {
+  thread_local HostSlot slot;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, sizeof(HostPage), hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) ==
+        hipSuccess) {
+      HostPage* pg = static_cast<HostPage*>(h);
+      pg->stats.seq = 0;
+      pg->probe.seq = 0;
+      if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
+        slot.host = pg;
+        slot.dev = static_cast<HostPage*>(d);
+      }
+    }
+    (void)hipGetLastError();
+  }
+  return slot.host ? &slot : nullptr;
+}
+
+// The record with sequence number want, once published.
+int wait_published(const HostStats* h, unsigned long long want, hipStream_t s, IterStats* out) {
+  MLPCP_TRY(wait_seq(&h->seq, want, s));
+  std::memcpy(out, const_cast<const IterStats*>(&h->st), sizeof(IterStats));
+  return MLPCP_OK;
+}
+
 unsigned grid_for(size_t total) {
   size_t b = (total + kThreads - 1) / kThreads;
   if (b > 65536) b = 65536;
@@ -952,6 +1025,22 @@ int gram_prec_for(int prec, double tau, double trace_prev, int m, int nH) {
   if (rho >= rho_split) return 2;
   return 0;
 }
+
+}  // namespace
+
+int wait_seq(const unsigned long long* seqp, unsigned long long want, hipStream_t s) {
+  for (unsigned spins = 1;; ++spins) {
+    if (__atomic_load_n(seqp, __ATOMIC_ACQUIRE) == want) return MLPCP_OK;
+    if ((spins & 1023u) == 0u) {
+      const hipError_t q = hipStreamQuery(s);
+      if (q == hipSuccess) return __atomic_load_n(seqp, __ATOMIC_ACQUIRE) == want ? MLPCP_OK : MLPCP_E_HIP;
+      if (q != hipErrorNotReady) return MLPCP_E_HIP;
+    }
+    __builtin_ia32_pause();
+  }
+}
+
+namespace {
 
 int make_plan(int m, int n, int levels, bool masked, Plan& p, int prec = MLPCP_FP32, bool partial = false) {
   p.m = m;
@@ -1150,7 +1239,10 @@ int coarse_svt(const Plan& p, const Operator& op, const WS& w, const float* mp, 
     if (es->r_prev == 0 || !(es->ms_alpha > 0.0)) {
       bool cert = false;
       double gmax = 0.0, trace = 0.0;
-      MLPCP_TRY(msvt_probe(p.nH, p.nHp, GH, p.nHp, tau, st, w.at<void>(p.off_ms), s, &cert, &gmax, &trace));
+      HostSlot* hsl = host_slot();
+      const unsigned long long want = hsl ? ++hsl->next : 0;
+      MLPCP_TRY(msvt_probe(p.nH, p.nHp, GH, p.nHp, tau, st, w.at<void>(p.off_ms), s, &cert, &gmax, &trace,
+                           hsl ? &hsl->host->probe : nullptr, hsl ? &hsl->dev->probe : nullptr, want));
       if (cert) {
         es->v_full = false;
         *sweeps = 0;
@@ -1437,6 +1529,7 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
   int bf16_iters = 0, split_iters = 0;
   EigState es;
   es.ms_on = o.svt_method == 0 && p.ms;
+  HostSlot* slot = host_slot();
   for (t = 0; t < o.max_iter; ++t) {
     const double mu_next = std::min(o.rho * mu, mu_max);
     const int gp = gram_prec_for(o.prec, 1.0 / mu, trace_prev, m, p.nH);
@@ -1458,13 +1551,24 @@ int solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lambda,
     a.partial = part;
     int nparts = 0;
     MLPCP_TRY(launch_epilogue<MODE_STEP>(p, a, w.at<double>(p.off_K), op->nnz, s, &nparts));
-    {
-      ProfScope ps(KC_REDUCE, s);
-      hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, nparts, &st->fg2);
+    if (slot) {
+      const unsigned long long want = ++slot->next;
+      {
+        ProfScope ps(KC_REDUCE, s);
+        hipLaunchKernelGGL(k_reduce_publish, dim3(1), dim3(kThreads), 0, s, part, nparts, st, &slot->dev->stats,
+                           want);
+      }
+      MLPCP_HIP(hipGetLastError());
+      MLPCP_TRY(wait_published(&slot->host->stats, want, s, &hs));
+    } else {
+      {
+        ProfScope ps(KC_REDUCE, s);
+        hipLaunchKernelGGL(k_reduce, dim3(1), dim3(kThreads), 0, s, part, nparts, &st->fg2);
+      }
+      MLPCP_HIP(hipGetLastError());
+      MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
+      MLPCP_HIP(hipStreamSynchronize(s));
     }
-    MLPCP_HIP(hipGetLastError());
-    MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-    MLPCP_HIP(hipStreamSynchronize(s));
     prof_drain();
     MLPCP_TRY(resolve_sweeps(sweeps, hs));
     fg = std::sqrt(hs.fg2) / nrmD;
