@@ -139,9 +139,10 @@ constexpr int kSweepsOnDevice = -100;
 // Buffers are kEigInner x kEigInner with leading dimension ld (= kEigInner).
 // certify: the threshold certificate of eig_sym at tau^2 (a matrix whose rows all have
 // Gershgorin bounds below tau^2 is not diagonalised; the margin is then taken from
-// the bounds).  With warm, certify and K, the SVT operator may instead come from the
-// second-order perturbation expansion around the warm-started diagonal (no sweep; V,
-// T, Tt, lam, perm, sw are then left as they are and st->sweeps is 0).
+// the bounds).  With certify and K, the SVT operator may instead come from the
+// second-order perturbation expansion around the current diagonal, tested on the warm
+// start and after every Jacobi sweep (T, Tt, lam, perm, sw are then left as they are;
+// V holds the rotated basis and st->sweeps the sweeps run before it).
 int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V, bool warm, double tau,
                      bool certify, double* lam, int* perm, double* sw, double* T, double* Tt, double* K,
                      IterStats* st, hipStream_t stream);
