@@ -27,6 +27,7 @@
 // iterations G^T G x (4 bytes per entry each) for its top singular pair.
 #include <algorithm>
 #include <cmath>
+#include <cstring>
 #include <map>
 #include <memory>
 #include <mutex>
@@ -45,7 +46,7 @@ constexpr int kNTerms = 7;        // S1..S4, and (multilevel) T5..T7 per block
 constexpr int kPowMax = 500;      // power-iteration steps per FW iteration (cap)
 constexpr double kPowEps = 1e-6;  // ||v_new - v_old|| that ends the power iteration
 
-// Device state of one solve, read by the kernels and copied to the host once per
+// Device state of one solve, read by the kernels and brought to the host once per
 // iteration.
 struct FwState {
   double f, t_L, t_S, U_L, U_S;
@@ -58,6 +59,69 @@ struct FwState {
   int pow_active, pow_steps;
   double pow_delta;
 };
+
+// The state as the host reads it, with the sequence number of the request written last.
+struct FwRecord {
+  FwState st;
+  unsigned long long seq;
+};
+
+// Copies the state to pinned, host-mapped memory, then, behind a system-scope fence, the
+// sequence number: the host reads the state as soon as it sees the number, without a copy
+// or a stream synchronisation.
+__global__ void k_fw_publish(const FwState* __restrict__ st, FwRecord* rec, unsigned long long seq) {
+  if (threadIdx.x == 0 && blockIdx.x == 0) {
+    rec->st = *st;
+    __threadfence_system();
+    *reinterpret_cast<volatile unsigned long long*>(&rec->seq) = seq;
+  }
+}
+
+// One pinned, host-mapped record per host thread (allocated on the thread's first solve,
+// kept until the process ends; a solve runs to completion on its calling thread, so the
+// record is never shared).  Null when the allocation fails: the state then comes back by
+// a copy and a stream synchronisation.
+struct FwSlot {
+  FwRecord* host = nullptr;   // host address
+  FwRecord* dev = nullptr;    // the same memory as the device addresses it
+  unsigned long long next = 0;
+};
+
+FwSlot* fw_slot() {
+  thread_local FwSlot slot;
+  thread_local bool tried = false;
+  if (!tried) {
+    tried = true;
+    void* h = nullptr;
+    void* d = nullptr;
+    if (hipHostMalloc(&h, sizeof(FwRecord), hipHostMallocMapped | hipHostMallocCoherent | hipHostMallocPortable) ==
+        hipSuccess) {
+      static_cast<FwRecord*>(h)->seq = 0;
+      if (hipHostGetDevicePointer(&d, h, 0) == hipSuccess) {
+        slot.host = static_cast<FwRecord*>(h);
+        slot.dev = static_cast<FwRecord*>(d);
+      }
+    }
+    (void)hipGetLastError();
+  }
+  return slot.host ? &slot : nullptr;
+}
+
+// The device state st (after the work queued on s) into hs: published when a slot is
+// there, else copied.
+int read_state(FwSlot* sl, const FwState* st, FwState* hs, hipStream_t s) {
+  if (sl) {
+    const unsigned long long want = ++sl->next;
+    hipLaunchKernelGGL(k_fw_publish, dim3(1), dim3(64), 0, s, st, sl->dev, want);
+    MLPCP_HIP(hipGetLastError());
+    MLPCP_TRY(wait_seq(&sl->host->seq, want, s));
+    std::memcpy(hs, const_cast<const FwState*>(&sl->host->st), sizeof(FwState));
+    return MLPCP_OK;
+  }
+  MLPCP_HIP(hipMemcpyAsync(hs, st, sizeof(FwState), hipMemcpyDeviceToHost, s));
+  MLPCP_HIP(hipStreamSynchronize(s));
+  return MLPCP_OK;
+}
 
 __device__ __forceinline__ float shrinkf(float x, float t) {
   const float a = fabsf(x) - t;
@@ -1598,8 +1662,8 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
   MLPCP_TRY(pass(false));
   MLPCP_TRY(finalize(false));
   FwState hs;
-  MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-  MLPCP_HIP(hipStreamSynchronize(s));
+  FwSlot* slot = fw_slot();
+  MLPCP_TRY(read_state(slot, st, &hs, s));
   prof_drain();
   double f_prev = hs.f;
   int k = 0;
@@ -1645,8 +1709,7 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
           for (int b = 0; b < pow_batch; ++b)
             MLPCP_TRY(p.VEC == 4 ? launch_power_step<4>(p, pa, s) : launch_power_step<1>(p, pa, s));
         }
-        MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-        MLPCP_HIP(hipStreamSynchronize(s));
+        MLPCP_TRY(read_state(slot, st, &hs, s));
         prof_drain();
         done_steps = hs.pow_steps;
         if (!hs.pow_active) break;
@@ -1691,8 +1754,7 @@ int fwt_solve(int m, int n, const float* D, int ldd, const uint8_t* Q, float lam
     MLPCP_TRY(pass(true));
     MLPCP_TRY(finalize(true));
     thr = true;
-    MLPCP_HIP(hipMemcpyAsync(&hs, st, sizeof(hs), hipMemcpyDeviceToHost, s));
-    MLPCP_HIP(hipStreamSynchronize(s));
+    MLPCP_TRY(read_state(slot, st, &hs, s));
     prof_drain();
     ++k;
     rel = f_prev > 0.0 ? std::fabs(f_prev - hs.f) / f_prev : 0.0;
