@@ -26,6 +26,7 @@
 #include "profile.h"
 
 #include <algorithm>
+#include <atomic>
 #include <cmath>
 #include <cstring>
 #include <vector>
@@ -974,15 +975,15 @@ struct Plan {
 };
 
 int device_cus() {
-  static int cached[64] = {0};
+  static std::atomic<int> cached[64];   // 0 until the first query (zero-initialised static)
   int dev = 0;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= 64) return 256;
-  if (!cached[dev]) {
-    int cus = 0;
-    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || cus < 1) cus = 256;
-    cached[dev] = cus;
+  int c = cached[dev].load(std::memory_order_relaxed);
+  if (!c) {
+    if (hipDeviceGetAttribute(&c, hipDeviceAttributeMultiprocessorCount, dev) != hipSuccess || c < 1) c = 256;
+    cached[dev].store(c, std::memory_order_relaxed);
   }
-  return cached[dev];
+  return c;
 }
 
 // Precision form (mlpcp_opts.prec) -> (Gram, reconstruction) kernel precisions.  The

@@ -288,3 +288,54 @@ def test_matrix_function_svt_ill_conditioned(levels):
     expect = sum(1 for i in range(1, K) if ranks[i - 1] > 0)
     say(f"   matrix-function iters {res.msvt_iters} (at least {expect}) flags {res.msvt_flags}")
     assert res.msvt_iters >= expect and res.msvt_flags == 0
+
+
+def test_concurrent_solves_from_host_threads():
+    """Three solves at once from three host threads, each on a stream of its own: a tall
+    PCP (one-workgroup coarse SVT), a wide CPCP (matrix-function SVT with its Gershgorin
+    probe) and an ML-FWT solve.  Each thread's stop tests read the records its own
+    pinned page receives, so the results equal, bit for bit, those of the same solves
+    run one after the other."""
+    import threading
+
+    torch, dev = torch_dev()
+    wa = synth.gaussian_lowrank_plus_sparse(300, 256, 6, seed=51, sparse_frac=0.05, levels=2)
+    wb = synth.gaussian_lowrank_plus_sparse(600, 512, 8, seed=52, sparse_frac=0.05, levels=1, observed_frac=0.7)
+    wc = synth.fw_cpcp(1200, 400, 2, seed=53, levels=3, observed_frac=0.8)
+    Da, Db, Dc = to_dev(wa.D), to_dev(wb.D), to_dev(wc.D)
+    Qb, Qc = to_dev(wb.Q.astype(np.uint8)), to_dev(wc.Q.astype(np.uint8))
+    torch.cuda.synchronize()
+
+    def run(k):
+        if k == 0:
+            r = mlp.pcp_solve(Da, wa.lam, wa.mu0, levels=2, tol=1e-6, history=600)
+            return r.iters, to_np(r.L), to_np(r.S)
+        if k == 1:
+            r = mlp.cpcp_solve(Db, Qb, wb.lam, wb.mu0, levels=1, tol=1e-6, history=600)
+            return r.iters, to_np(r.L), to_np(r.S)
+        r = mlp.cpcp_fwt(Dc, Qc, wc.lam_L, wc.lam, levels=3, tol=1e-3, history=64)
+        return r.iters, to_np(r.L), to_np(r.S)
+
+    ref = [run(k) for k in range(3)]
+    say("concurrent: sequential iterations", [x[0] for x in ref])
+    out, errs = [None] * 3, []
+
+    def worker(k):
+        try:
+            st = torch.cuda.Stream(device=dev)
+            with torch.cuda.stream(st):
+                out[k] = run(k)
+            st.synchronize()
+        except Exception as e:   # reported below, in the main thread
+            errs.append(e)
+
+    threads = [threading.Thread(target=worker, args=(k,)) for k in range(3)]
+    for t in threads:
+        t.start()
+    for t in threads:
+        t.join(timeout=90)
+    assert not any(t.is_alive() for t in threads), "a solve did not finish"
+    assert not errs, errs
+    for k in range(3):
+        assert out[k][0] == ref[k][0]
+        assert np.array_equal(out[k][1], ref[k][1]) and np.array_equal(out[k][2], ref[k][2])
