@@ -32,6 +32,13 @@
  *    restrict / prolong / shrink are asynchronous on it.  The solvers and
  *    svt_prox synchronise it (the host loop reads the feasibility gap and the
  *    rank every iteration).
+ *  - The solvers' host loops read each iteration's statistics from a record
+ *    the device writes to pinned, host-mapped memory, spinning on the host
+ *    thread until it arrives: each host thread that runs a solver holds one
+ *    such record (a page of pinned memory) from its first solve until the
+ *    process ends.  If that allocation fails the statistics are copied back
+ *    instead.  Solves from different host threads on different streams may
+ *    run at the same time.
  */
 #ifndef MLPCP_H
 #define MLPCP_H
