@@ -142,7 +142,8 @@ constexpr int kSweepsOnDevice = -100;
 // the bounds).  With certify and K, the SVT operator may instead come from the
 // second-order perturbation expansion around the current diagonal, tested on the warm
 // start and after every Jacobi sweep (T, Tt, lam, perm, sw are then left as they are;
-// V holds the rotated basis and st->sweeps the sweeps run before it).
+// V holds the rotated basis and st->sweeps the sweeps run before it).  With certify the
+// basis in V (written, and read back by a warm start) is C V, not V; without it, V.
 int coarse_svt_small(int nH, int ld, const double* G, const double* C, double* V, bool warm, double tau,
                      bool certify, double* lam, int* perm, double* sw, double* T, double* Tt, double* K,
                      IterStats* st, hipStream_t stream);

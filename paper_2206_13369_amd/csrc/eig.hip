@@ -1048,6 +1048,10 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
   const int tid = threadIdx.x;
   const bool mm_on = tid < 256;   // the 64^3 products run on the first four waves
   const int km = min(IN, (nH + 15) / 16 * 16);   // beyond it the operands are zero (identity in V)
+  // With certify the basis kept in Q (and in V between calls) is S' = C V rather than V:
+  // H = V^T (C G C) V = S'^T G S', rotations act on S' as on V, T = C V_r diag(w) =
+  // S'_r diag(w) and K = S' F S'^T, so C G C and the products by C are not formed.
+  const bool cb = certify != 0;
   d4_t acc[2][2];
   {
     constexpr int PER = IN * IN / kSmallThreads;
@@ -1057,9 +1061,13 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
       const int it = tid + kSmallThreads * x;
       const int i = it / IN, j = it % IN;
       const bool in = i < nH && j < nH;
+      const double eye = i == j ? 1.0 : 0.0;
       rg[x] = in ? G[(size_t)i * ld + j] : 0.0;
       rc[x] = (C && in) ? C[(size_t)i * nH + j] : 0.0;
-      rv[x] = (warm && in) ? V[(size_t)i * ld + j] : (i == j ? 1.0 : 0.0);
+      if (warm)
+        rv[x] = in ? V[(size_t)i * ld + j] : eye;
+      else
+        rv[x] = (cb && C && in) ? C[(size_t)i * nH + j] : eye;   // the C V basis starts at C
     }
 #pragma unroll
     for (int x = 0; x < PER; ++x) {
@@ -1071,7 +1079,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
     }
   }
   __syncthreads();
-  if (C) {                                   // G_H = C G C
+  if (C && !cb) {                            // G_H = C G C
     if (mm_on) {
       mm64<false>(sA, sC, acc, km);
       mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
@@ -1082,7 +1090,7 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
     if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
     __syncthreads();
   }
-  if (warm) {                                // A <- V0^T A V0, Q = V0
+  if (warm || (cb && C)) {                   // A <- Q^T A Q (Q = V0, or S' = C V0)
     if (mm_on) {
       mm64<true>(sQ, sA, acc, km);
       mm64_store(acc, [&](int i, int j, double v) { sW[i][j] = v; });
@@ -1184,15 +1192,11 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
       sW[i][j] = x;   // each entry read and written by one thread
     }
     __syncthreads();
-    // K = S'^T (F S'), S' = V^T C
+    // K = R^T (F R), R = S'^T = V^T C (Q holds S' here: the finish runs with certify)
     for (int it = tid; it < IN * IN; it += kSmallThreads) {
       const int i = it / IN, j = it % IN;
-      sC[i][j] = (i < nH && j < nH) ? (C ? C[(size_t)i * nH + j] : (i == j ? 1.0 : 0.0)) : 0.0;
+      sA[i][j] = sQ[j][i];
     }
-    __syncthreads();
-    if (mm_on) mm64<true>(sQ, sC, acc, km);
-    __syncthreads();
-    if (mm_on) mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
     __syncthreads();
     if (mm_on) mm64<false>(sW, sA, acc, km);
     __syncthreads();
@@ -1317,14 +1321,15 @@ __global__ void __launch_bounds__(kSmallThreads) k_coarse_small(int nH, int ld, 
     st->trace = trace;
     st->sweeps = conv ? sweeps : -1;
   }
-  // W = V_sorted diag(sw) (columns k < rank), T = C W, Tt, K = T T^T
+  // W = Q_sorted diag(sw) (columns k < rank), T = C W (with the C V basis, W is T), Tt,
+  // K = T T^T
   for (int it = tid; it < IN * IN; it += kSmallThreads) {
     const int j = it / IN, k = it % IN;
     sW[j][k] = k < rank ? sQ[j][prm[k]] * swv[k] : 0.0;
   }
   __syncthreads();
   LdsRow* sT = sW;
-  if (C) {
+  if (C && !cb) {
     if (mm_on) {
       mm64<false>(sC, sW, acc, km);
       mm64_store(acc, [&](int i, int j, double v) { sA[i][j] = v; });
